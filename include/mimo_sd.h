@@ -1,0 +1,202 @@
+/* mimo_sd.h -- C ABI of the MI355X (gfx950) sphere-decoder library.
+ *
+ * Hot path of Dabah et al., "Performance / Complexity Trade-offs of the
+ * Sphere Decoder Algorithm for Massive MIMO Systems" (arXiv 2002.09561):
+ * detection of s in argmin ||y - H s||^2 over a square-QAM lattice after the
+ * QR transform z = Q^T y.
+ *
+ * General conventions (apply to every entry point below)
+ * -------------------------------------------------------
+ * Memory   All array arguments are DEVICE pointers owned by the caller; the
+ *          library never allocates, frees or retains them, and allocates no
+ *          device memory of its own except a workspace the caller passes in.
+ * Streams  `stream` is a hipStream_t passed as void* (NULL = the default
+ *          stream).  Every call only enqueues work on it and returns; no call
+ *          synchronises the host, so calls may be captured into a hipGraph.
+ *          Results are valid once the stream has reached the call.
+ * Errors   0 = MIMO_OK.  Negative codes are returned *before* any work is
+ *          enqueued when an argument is invalid (checked on the host, so the
+ *          checks run without a GPU); MIMO_ERR_HIP reports a failed launch.
+ *          mimo_last_error() returns a thread-local text for the last error.
+ *          B == 0 is a no-op that returns MIMO_OK.
+ * Frames   B frames of an N x M system (N = n_rx receive antennas, M = n_tx
+ *          transmit streams, M <= N).  The paper's system model is Sec. III-A
+ *          Eq. (1): y = H s + n.  H is [B][N][M] complex64 row-major, y is
+ *          [B][N] complex64 (complex64 = two floats, real first).
+ * Lattice  Square QAM with P = sqrt(|Omega|) points per real dimension,
+ *          pam = P in {2, 4, 8} (4-, 16-, 64-QAM); real amplitudes
+ *          (2i - (P-1)) c with c = sqrt(3 / (2 (|Omega| - 1))), i = 0..P-1
+ *          (unit average symbol energy).  The QAM index of a symbol is
+ *          i_re * P + i_im.  Symbol outputs `sym` are [B][M] int32 QAM indices.
+ * Real model  n = 2M real levels: x = [Re s0, Im s0, Re s1, Im s1, ...] and
+ *          each complex h becomes [[Re h, -Im h], [Im h, Re h]] (rows
+ *          [Re y0, Im y0, ...]).  Level k fixes x_k; searches start at level
+ *          n-1 and end at level 0 (Sec. III-B: one symbol per tree level).
+ * R layout "packed level order": row k of the upper-triangular n x n matrix R
+ *          (entries R_kk, R_k,k+1, ..., R_k,n-1) is stored contiguously at
+ *          offset (n-1-k)(n-k)/2, so the rows appear in the order the search
+ *          visits them; n(n+1)/2 floats per frame.  z is [B][n].
+ * Radius   Squared radius r2 (Sec. III-B "Sphere radius and pruning"): a node
+ *          is kept iff its partial distance is < r2.  A NULL radius pointer
+ *          means r2 = +infinity.
+ * Flags    per frame, OR of MIMO_FLAG_* below.
+ * Counters optional [B][4] int64, *overwritten*: nodes expanded (branched
+ *          on), partial distances evaluated (children), rounds (hybrid only,
+ *          else 0), pool nodes discarded as outside the sphere.
+ */
+#ifndef MIMO_SD_H
+#define MIMO_SD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define MIMO_OK 0
+#define MIMO_ERR_INVALID_ARG (-1)
+#define MIMO_ERR_UNSUPPORTED (-2)
+#define MIMO_ERR_WORKSPACE (-3)
+#define MIMO_ERR_HIP (-4)
+
+/* per-frame flags */
+#define MIMO_FLAG_FOUND 1u            /* a leaf inside the radius was found          */
+#define MIMO_FLAG_EMPTY_SPHERE 2u     /* the radius left no leaf (output undefined)  */
+#define MIMO_FLAG_BUDGET_EXHAUSTED 4u /* node budget reached; best leaf so far       */
+#define MIMO_FLAG_CERTIFIED 8u        /* hybrid pool drained within the budget        */
+#define MIMO_FLAG_LEARNED_FALLBACK 16u /* a learned survivor count was invalid        */
+
+/* limits */
+#define MIMO_MAX_TX 128   /* n_tx <= 128, i.e. n <= 256 real levels */
+#define MIMO_MAX_RX 128
+#define MIMO_MAX_K 256    /* K-best survivors: K * pam <= 1024 */
+#define MIMO_MAX_WORKERS 15
+#define MIMO_HYB_MAX_CAND 64 /* hybrid worker: k_worker * pam <= 64 */
+
+#define MIMO_MLP_IN 4
+#define MIMO_MLP_HIDDEN 128
+/* flat parameter vector: W1[128][4], b1[128], W2[128][128], b2[128], w3[128], b3 */
+#define MIMO_MLP_NPARAM (128 * 4 + 128 + 128 * 128 + 128 + 128 + 1)
+
+const char* mimo_last_error(void);
+int32_t mimo_version(void);
+
+/* ---------------------------------------------------------------------
+ * QR preprocessing (Sec. III-B): H = Q R with R_kk > 0 and z = Q^H y,
+ * emitted for the real model in packed level order.  resid[b] receives
+ * ||y||^2 - ||z||^2 (the constant the search drops; 0 when N = M), or pass
+ * NULL.  Limits: 1 <= n_tx <= n_rx <= 128.
+ * H [B][n_rx][n_tx] c64, y [B][n_rx] c64 -> R [B][n(n+1)/2], z [B][n] f32.
+ * ------------------------------------------------------------------- */
+int32_t mimo_qr_preprocess(const float* H, const float* y, int32_t B, int32_t n_rx, int32_t n_tx,
+                           float* R, float* z, float* resid, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Batched K-best (Sec. VI, the K-best algorithm): level by level from the
+ * root, all P children of every survivor are evaluated with the
+ * incremental partial distance of Eq. (inc), children outside the radius
+ * are dropped, and the K_t best by (pd, parent rank, child index) survive;
+ * the best leaf is returned.  K_t = k_sched[b * k_sched_stride + k] at level
+ * k (clamped to [1, K]) when k_sched is not NULL, else K.  k_sched_stride is
+ * 0 (one schedule for all frames) or n (one per frame).
+ * R, z as produced by mimo_qr_preprocess; radius2 [B] or NULL.
+ * Outputs: sym [B][n_tx], pd [B] (float search metric), flags [B],
+ * counters [B][4] or NULL.  1 <= K <= MIMO_MAX_K, K * pam <= 1024.
+ * ------------------------------------------------------------------- */
+int32_t kbest_detect(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam,
+                     int32_t K, const int32_t* k_sched, int32_t k_sched_stride,
+                     const float* radius2, int32_t* sym, float* pd, uint32_t* flags,
+                     int64_t* counters, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Learned-pruning labels: K-best with K survivors in which the given path
+ * (normally the ML path) is forced to survive; rank[b][k] receives the
+ * 1-based rank of that path's prefix among the sorted candidates of level k.
+ * force_sym [B][n_tx] QAM indices; rank [B][n] int32.
+ * ------------------------------------------------------------------- */
+int32_t kbest_rank_labels(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam,
+                          int32_t K, const int32_t* force_sym, int32_t* rank, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Hybrid SD / K-best (Sec. VI, SD-K-best): a Best-FS sphere-decoder master
+ * (Alg. 1 with the Best-FS list of Sec. IV-A) feeds the right-most pool
+ * nodes to n_workers K-best workers that keep k_worker survivors (or
+ * k_sched[k] when k_sched is not NULL) inside the shared radius.  Run in
+ * deterministic rounds: (1) the master takes the left-most node inside the
+ * radius and expands it (leaf children become candidates, the others go to
+ * the left of the pool, best left-most); (2) idle workers, in order, take
+ * the right-most node while the pool holds >= 2 nodes; (3) busy workers
+ * advance one level; (4) the best candidate by (pd, source, rank) shrinks
+ * the radius.  The run ends when the pool is empty and all workers are idle
+ * (flag CERTIFIED) or after node_budget expansions (> 0; flag
+ * BUDGET_EXHAUSTED, best leaf so far).  n_workers = 0 is the exact Best-FS
+ * SD (maximum likelihood within the radius); master_off != 0 hands the root
+ * to worker 0 instead (K-best within the radius).
+ * Limits: 0 <= n_workers <= MIMO_MAX_WORKERS, k_worker * pam <= 64.
+ * ------------------------------------------------------------------- */
+int32_t sd_hybrid_detect(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam,
+                         const float* radius2, int32_t n_workers, int32_t k_worker,
+                         const int32_t* k_sched, int32_t k_sched_stride, int32_t master_off,
+                         int64_t node_budget, int32_t* sym, float* pd, uint32_t* flags,
+                         int64_t* counters, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Metric epilogue: metric[b] = ||y_b - H_b s_b||^2 in FP64 from the
+ * complex64 H, y and QAM indices sym [B][n_tx] (Eq. (2) objective).
+ * ------------------------------------------------------------------- */
+int32_t mimo_metric(const float* H, const float* y, const int32_t* sym, int32_t B, int32_t n_rx,
+                    int32_t n_tx, int32_t pam, double* metric, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Error counts: counts[0] += Gray-coded bit errors, counts[1] += symbol
+ * errors between sym and ref ([B][n_tx] QAM indices), counts[2] += frames
+ * with any error.  Bits of a symbol: Gray(i_re) || Gray(i_im), with
+ * Gray(i) = i ^ (i >> 1).  counts [3] uint64 (caller zeroes it).
+ * ------------------------------------------------------------------- */
+int32_t mimo_error_count(const int32_t* sym, const int32_t* ref, int32_t B, int32_t n_tx,
+                         int32_t pam, uint64_t* counts, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Learned pruning, per-level state of each frame (the paper leaves the
+ * "very close" extra-survivor rule of Sec. VI unspecified; this library
+ * replaces it with a learned survivor count).  From the successive-
+ * cancellation path (K-best with K = 1), for every level k:
+ *   f0 = k / n,
+ *   f1 = distance of the cancellation centre b_k / R_kk to the nearest
+ *        decision boundary, in units of the point spacing 2c,
+ *   f2 = log2(R_kk * 2c / sigma_r), sigma_r = sqrt(sigma2[b] / 2),
+ *   f3 = pd of the path after level k / ((n - k) sigma_r^2).
+ * sigma2 [B] is the complex noise variance.  feat [B][n][4] f32.
+ * ------------------------------------------------------------------- */
+int32_t prune_features(const float* R, const float* z, const float* sigma2, int32_t B,
+                       int32_t n_tx, int32_t pam, float* feat, void* stream);
+
+/* MLP 4 -> 128 -> 128 -> 1 (ReLU) forward over S states: out[s] = f(X[s]).
+ * w [MIMO_MLP_NPARAM] f32, X [S][4], out [S]. */
+int32_t prune_mlp_forward(const float* w, const float* X, int64_t S, float* out, void* stream);
+
+/* Forward plus survivor schedule: k_sched[s] = clamp(ceil(2^(f(X[s]) + margin)),
+ * k_min, k_max); a non-finite prediction gives k_max and sets
+ * MIMO_FLAG_LEARNED_FALLBACK in flags[s / n] when flags is not NULL
+ * (n = levels per frame, used only for that index). */
+int32_t prune_mlp_schedule(const float* w, const float* X, int64_t S, float margin,
+                           int32_t k_min, int32_t k_max, int32_t n, int32_t* k_sched,
+                           uint32_t* flags, void* stream);
+
+/* Mean pinball loss at quantile tau over S states and its gradient.
+ * grad [MIMO_MLP_NPARAM] and loss [1] are overwritten.  ws is a device
+ * workspace of at least prune_mlp_workspace_bytes(S) bytes. */
+size_t prune_mlp_workspace_bytes(int64_t S);
+int32_t prune_mlp_loss_grad(const float* w, const float* X, const float* y, int64_t S, float tau,
+                            float* grad, float* loss, void* ws, size_t ws_bytes, void* stream);
+
+/* One Adam step on w with moments m, v (all [np] f32), step t >= 1. */
+int32_t prune_mlp_adam_step(float* w, float* m, float* v, const float* grad, int32_t np, int32_t t,
+                            float lr, float beta1, float beta2, float eps, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

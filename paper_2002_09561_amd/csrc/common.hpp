@@ -1,0 +1,105 @@
+// Shared device/host helpers of the gfx950 sphere-decoder library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mimo_sd.h"
+
+namespace mimo {
+
+constexpr int WAVE = 64;
+
+// error reporting (thread-local text behind mimo_last_error)
+int32_t fail(int32_t code, const char* fmt, ...);
+int32_t check_launch(const char* what);
+
+// PAM spacing scale c = sqrt(3 / (2 (P^2 - 1))) of a unit-energy square QAM.
+__host__ __device__ inline float pam_scale(int P)
+{
+    return P == 2 ? 0.70710678118654752f : (P == 4 ? 0.31622776601683794f : 0.15430334996209191f);
+}
+
+// offset of row k of the packed level-order R (n real levels)
+__host__ __device__ inline int64_t r_row_off(int n, int k)
+{
+    return (int64_t)(n - 1 - k) * (n - k) / 2;
+}
+
+__host__ __device__ inline int64_t r_packed_size(int n) { return (int64_t)n * (n + 1) / 2; }
+
+__device__ inline float shfl_f(float v, int src) { return __shfl(v, src, WAVE); }
+__device__ inline float shfl_xor_f(float v, int m) { return __shfl_xor(v, m, WAVE); }
+
+__device__ inline uint64_t shfl_xor_u64(uint64_t v, int m)
+{
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    lo = __shfl_xor(lo, m, WAVE);
+    hi = __shfl_xor(hi, m, WAVE);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline uint64_t shfl_u64(uint64_t v, int src)
+{
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    lo = __shfl(lo, src, WAVE);
+    hi = __shfl(hi, src, WAVE);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline float wave_sum(float v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += shfl_xor_f(v, m);
+    return v;
+}
+
+__device__ inline uint64_t wave_min_u64(uint64_t v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        uint64_t o = shfl_xor_u64(v, m);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+// In-wave bitonic sort of 64*E keys, ascending by position e*64 + lane.
+template <int E>
+__device__ inline void bitonic_sort(uint64_t (&key)[E], int lane)
+{
+    constexpr int N = WAVE * E;
+#pragma unroll
+    for (int size = 2; size <= N; size <<= 1) {
+#pragma unroll
+        for (int j = size >> 1; j > 0; j >>= 1) {
+            if (j >= WAVE) {
+                const int je = j / WAVE;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int pe = e ^ je;
+                    if (pe > e) {
+                        const bool asc = (((e * WAVE + lane) & size) == 0);
+                        uint64_t a = key[e], b = key[pe];
+                        bool sw = asc ? (a > b) : (a < b);
+                        key[e] = sw ? b : a;
+                        key[pe] = sw ? a : b;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    uint64_t o = shfl_xor_u64(key[e], j);
+                    const bool asc = (((e * WAVE + lane) & size) == 0);
+                    const bool lower = (lane & j) == 0;
+                    const bool take_min = (asc == lower);
+                    uint64_t mn = o < key[e] ? o : key[e];
+                    uint64_t mx = o < key[e] ? key[e] : o;
+                    key[e] = take_min ? mn : mx;
+                }
+            }
+        }
+    }
+}
+
+}  // namespace mimo

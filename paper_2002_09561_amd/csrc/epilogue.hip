@@ -1,0 +1,153 @@
+// Epilogues of the detection path: FP64 metric ||y - H s||^2 (the Eq. (2)
+// objective), Gray bit / symbol error counts, and the per-level state of the
+// successive-cancellation path used by the learned survivor count.
+#include "common.hpp"
+
+namespace mimo {
+
+__device__ inline double amp_d(int P, int i)
+{
+    return (double)(2 * i - (P - 1)) * sqrt(3.0 / (2.0 * (double)(P * P - 1)));
+}
+
+// one workgroup per frame, one thread per receive antenna (N <= 128)
+__global__ void __launch_bounds__(128) metric_kernel(const float2* __restrict__ H, const float2* __restrict__ y,
+                                                     const int32_t* __restrict__ sym, int N, int M, int P,
+                                                     double* __restrict__ out)
+{
+    __shared__ double part[2];
+    const int f = blockIdx.x, i = threadIdx.x;
+    double acc = 0.0;
+    if (i < N) {
+        const float2* h = H + ((size_t)f * N + i) * M;
+        const int32_t* s = sym + (size_t)f * M;
+        float2 yy = y[(size_t)f * N + i];
+        double er = yy.x, ei = yy.y;
+        for (int j = 0; j < M; ++j) {
+            const int q = s[j];
+            const double sr = amp_d(P, q / P), si = amp_d(P, q % P);
+            const float2 hv = h[j];
+            er -= (double)hv.x * sr - (double)hv.y * si;
+            ei -= (double)hv.x * si + (double)hv.y * sr;
+        }
+        acc = er * er + ei * ei;
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, WAVE);
+    if ((i & 63) == 0) part[i >> 6] = acc;
+    __syncthreads();
+    if (i == 0) out[f] = part[0] + (blockDim.x > 64 ? part[1] : 0.0);
+}
+
+// one wave per frame
+__global__ void __launch_bounds__(256) errors_kernel(const int32_t* __restrict__ sym, const int32_t* __restrict__ ref,
+                                                     int B, int M, int P, unsigned long long* __restrict__ counts)
+{
+    const int lane = threadIdx.x & 63;
+    const int f = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x >> 6);
+    if (f >= B) return;
+    unsigned bits = 0, syms = 0;
+    for (int m = lane; m < M; m += WAVE) {
+        const int a = sym[(size_t)f * M + m], b = ref[(size_t)f * M + m];
+        const int ar = a / P, ai = a % P, br = b / P, bi = b % P;
+        const unsigned ga = (unsigned)(((ar ^ (ar >> 1)) * P) | (ai ^ (ai >> 1)));
+        const unsigned gb = (unsigned)(((br ^ (br >> 1)) * P) | (bi ^ (bi >> 1)));
+        bits += __popc(ga ^ gb);
+        syms += (a != b);
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        bits += __shfl_xor(bits, m, WAVE);
+        syms += __shfl_xor(syms, m, WAVE);
+    }
+    if (lane == 0 && syms) {
+        atomicAdd(&counts[0], (unsigned long long)bits);
+        atomicAdd(&counts[1], (unsigned long long)syms);
+        atomicAdd(&counts[2], 1ull);
+    }
+}
+
+// one wave per frame: the K = 1 path and its per-level state
+__global__ void __launch_bounds__(64) features_kernel(const float* __restrict__ R, const float* __restrict__ z,
+                                                      const float* __restrict__ sigma2, int n, int P,
+                                                      float* __restrict__ feat)
+{
+    __shared__ float xa[256];
+    const int f = blockIdx.x, lane = threadIdx.x;
+    const float* Rf = R + (size_t)f * r_packed_size(n);
+    const float* zf = z + (size_t)f * n;
+    const float c = pam_scale(P);
+    const float sr = sqrtf(sigma2[f] * 0.5f);
+    float pd = 0.f;
+    for (int k = n - 1; k >= 0; --k) {
+        const float* rk = Rf + r_row_off(n, k);
+        float acc = 0.f;
+        for (int t = 1 + lane; t < n - k; t += WAVE) acc = fmaf(rk[t], xa[k + t], acc);
+        acc = wave_sum(acc);
+        const float rkk = rk[0];
+        const float b = zf[k] - acc;
+        const float u = b / rkk;
+        int i = (int)floorf((u / c + (float)(P - 1)) * 0.5f + 0.5f);
+        i = i < 0 ? 0 : (i > P - 1 ? P - 1 : i);
+        const float a = (float)(2 * i - (P - 1)) * c;
+        const float e = fmaf(-rkk, a, b);
+        pd = fmaf(e, e, pd);
+        const float v = u / c;
+        float nb = 2.f * floorf(v * 0.5f + 0.5f);
+        nb = fminf(fmaxf(nb, -(float)(P - 2)), (float)(P - 2));
+        if (lane == 0) {
+            xa[k] = a;
+            float* o = feat + ((size_t)f * n + k) * 4;
+            o[0] = (float)k / (float)n;
+            o[1] = fabsf(v - nb) * 0.5f;
+            o[2] = log2f(rkk * 2.f * c / sr);
+            o[3] = pd / ((float)(n - k) * sr * sr);
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace mimo
+
+extern "C" int32_t mimo_metric(const float* H, const float* y, const int32_t* sym, int32_t B, int32_t n_rx,
+                               int32_t n_tx, int32_t pam, double* metric, void* stream)
+{
+    using namespace mimo;
+    if (B < 0 || n_tx < 1 || n_rx < n_tx) return fail(MIMO_ERR_INVALID_ARG, "mimo_metric: bad sizes");
+    if (pam != 2 && pam != 4 && pam != 8) return fail(MIMO_ERR_INVALID_ARG, "mimo_metric: pam must be 2, 4 or 8");
+    if (n_rx > MIMO_MAX_RX || n_tx > MIMO_MAX_TX) return fail(MIMO_ERR_UNSUPPORTED, "mimo_metric: size limit");
+    if (B == 0) return MIMO_OK;
+    if (!H || !y || !sym || !metric) return fail(MIMO_ERR_INVALID_ARG, "mimo_metric: null pointer");
+    const int threads = n_rx > 64 ? 128 : 64;
+    hipLaunchKernelGGL(metric_kernel, dim3(B), dim3(threads), 0, (hipStream_t)stream,
+                       reinterpret_cast<const float2*>(H), reinterpret_cast<const float2*>(y), sym, n_rx, n_tx,
+                       pam, metric);
+    return check_launch("mimo_metric");
+}
+
+extern "C" int32_t mimo_error_count(const int32_t* sym, const int32_t* ref, int32_t B, int32_t n_tx, int32_t pam,
+                                    uint64_t* counts, void* stream)
+{
+    using namespace mimo;
+    if (B < 0 || n_tx < 1) return fail(MIMO_ERR_INVALID_ARG, "mimo_error_count: bad sizes");
+    if (pam != 2 && pam != 4 && pam != 8) return fail(MIMO_ERR_INVALID_ARG, "mimo_error_count: bad pam");
+    if (B == 0) return MIMO_OK;
+    if (!sym || !ref || !counts) return fail(MIMO_ERR_INVALID_ARG, "mimo_error_count: null pointer");
+    hipLaunchKernelGGL(errors_kernel, dim3((B + 3) / 4), dim3(256), 0, (hipStream_t)stream, sym, ref, B, n_tx, pam,
+                       reinterpret_cast<unsigned long long*>(counts));
+    return check_launch("mimo_error_count");
+}
+
+extern "C" int32_t prune_features(const float* R, const float* z, const float* sigma2, int32_t B, int32_t n_tx,
+                                  int32_t pam, float* feat, void* stream)
+{
+    using namespace mimo;
+    if (B < 0 || n_tx < 1) return fail(MIMO_ERR_INVALID_ARG, "prune_features: bad sizes");
+    if (pam != 2 && pam != 4 && pam != 8) return fail(MIMO_ERR_INVALID_ARG, "prune_features: bad pam");
+    if (n_tx > MIMO_MAX_TX) return fail(MIMO_ERR_UNSUPPORTED, "prune_features: n_tx > %d", MIMO_MAX_TX);
+    if (B == 0) return MIMO_OK;
+    if (!R || !z || !sigma2 || !feat) return fail(MIMO_ERR_INVALID_ARG, "prune_features: null pointer");
+    hipLaunchKernelGGL(features_kernel, dim3(B), dim3(64), 0, (hipStream_t)stream, R, z, sigma2, 2 * n_tx, pam,
+                       feat);
+    return check_launch("prune_features");
+}

@@ -1,0 +1,259 @@
+// Learned survivor count: MLP 4 -> 128 -> 128 -> 1 (ReLU), its pinball-loss
+// backward pass and an Adam step.
+//
+// One thread per state.  The weights are read at wave-uniform addresses, so
+// they arrive as scalar operands of the FMAs and the hidden activations stay
+// in registers.  The backward pass writes the per-state activations and
+// deltas feature-major ([128][S]) and a second kernel reduces the weight
+// gradients over the states in a fixed order (deterministic).
+#include "common.hpp"
+
+namespace mimo {
+
+constexpr int HID = MIMO_MLP_HIDDEN;
+constexpr int NIN = MIMO_MLP_IN;
+constexpr int OW1 = 0, OB1 = OW1 + HID * NIN, OW2 = OB1 + HID, OB2 = OW2 + HID * HID, OW3 = OB2 + HID,
+              OB3 = OW3 + HID;
+
+// h1 = relu(W1 x + b1)
+__device__ inline void mlp_layer1(const float* __restrict__ w, const float x[NIN], float h1[HID])
+{
+#pragma unroll
+    for (int i = 0; i < HID; ++i) {
+        float s = w[OB1 + i];
+#pragma unroll
+        for (int j = 0; j < NIN; ++j) s = fmaf(w[OW1 + i * NIN + j], x[j], s);
+        h1[i] = fmaxf(s, 0.f);
+    }
+}
+
+// out = w3 . relu(W2 h1 + b2) + b3 ; optionally records the layer-2 mask
+__device__ inline float mlp_rest(const float* __restrict__ w, const float h1[HID], uint32_t mask2[HID / 32])
+{
+    float out = w[OB3];
+#pragma unroll 2
+    for (int i = 0; i < HID; ++i) {
+        float s = w[OB2 + i];
+#pragma unroll
+        for (int j = 0; j < HID; ++j) s = fmaf(w[OW2 + i * HID + j], h1[j], s);
+        if (mask2) {
+            if (s > 0.f) mask2[i >> 5] |= 1u << (i & 31);
+        }
+        out = fmaf(w[OW3 + i], fmaxf(s, 0.f), out);
+    }
+    return out;
+}
+
+__global__ void __launch_bounds__(256) mlp_forward_kernel(const float* __restrict__ w, const float* __restrict__ X,
+                                                          int64_t S, float* __restrict__ out)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    float x[NIN], h1[HID];
+#pragma unroll
+    for (int j = 0; j < NIN; ++j) x[j] = X[s * NIN + j];
+    mlp_layer1(w, x, h1);
+    out[s] = mlp_rest(w, h1, nullptr);
+}
+
+__global__ void __launch_bounds__(256) mlp_schedule_kernel(const float* __restrict__ w, const float* __restrict__ X,
+                                                           int64_t S, float margin, int kmin, int kmax, int n,
+                                                           int32_t* __restrict__ ks, uint32_t* __restrict__ flags)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    float x[NIN], h1[HID];
+#pragma unroll
+    for (int j = 0; j < NIN; ++j) x[j] = X[s * NIN + j];
+    mlp_layer1(w, x, h1);
+    const float yhat = mlp_rest(w, h1, nullptr);
+    int k;
+    if (!isfinite(yhat)) {
+        k = kmax;
+        if (flags) atomicOr(&flags[s / n], MIMO_FLAG_LEARNED_FALLBACK);
+    } else {
+        const float e = fminf(yhat + margin, 30.f);
+        const float kk = ceilf(exp2f(e));
+        k = kk < (float)kmin ? kmin : (kk > (float)kmax ? kmax : (int)kk);
+    }
+    ks[s] = k;
+}
+
+// per state: activations and deltas, feature-major in the workspace
+__global__ void __launch_bounds__(256) mlp_backward_states(const float* __restrict__ w, const float* __restrict__ X,
+                                                           const float* __restrict__ y, int64_t S, float tau,
+                                                           float* __restrict__ H1, float* __restrict__ H2,
+                                                           float* __restrict__ D2, float* __restrict__ D1,
+                                                           float* __restrict__ dout, float* __restrict__ lpart)
+{
+    __shared__ float red[4];
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float loss = 0.f;
+    if (s < S) {
+        float x[NIN], h1[HID];
+#pragma unroll
+        for (int j = 0; j < NIN; ++j) x[j] = X[s * NIN + j];
+        mlp_layer1(w, x, h1);
+        float out = w[OB3];
+        uint32_t m2[HID / 32] = {0, 0, 0, 0};
+#pragma unroll 2
+        for (int i = 0; i < HID; ++i) {
+            float a = w[OB2 + i];
+#pragma unroll
+            for (int j = 0; j < HID; ++j) a = fmaf(w[OW2 + i * HID + j], h1[j], a);
+            const float h = fmaxf(a, 0.f);
+            if (a > 0.f) m2[i >> 5] |= 1u << (i & 31);
+            H2[(int64_t)i * S + s] = h;
+            out = fmaf(w[OW3 + i], h, out);
+        }
+        const float r = y[s] - out;
+        loss = r > 0.f ? tau * r : (tau - 1.f) * r;
+        const float dz = (r > 0.f ? -tau : 1.f - tau) / (float)S;
+        dout[s] = dz;
+        float d1[HID];
+#pragma unroll
+        for (int j = 0; j < HID; ++j) d1[j] = 0.f;
+#pragma unroll 2
+        for (int i = 0; i < HID; ++i) {
+            const float d2 = ((m2[i >> 5] >> (i & 31)) & 1u) ? dz * w[OW3 + i] : 0.f;
+            D2[(int64_t)i * S + s] = d2;
+#pragma unroll
+            for (int j = 0; j < HID; ++j) d1[j] = fmaf(w[OW2 + i * HID + j], d2, d1[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < HID; ++j) {
+            D1[(int64_t)j * S + s] = h1[j] > 0.f ? d1[j] : 0.f;
+            H1[(int64_t)j * S + s] = h1[j];
+        }
+    }
+    // deterministic loss partial per block
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) loss += __shfl_xor(loss, m, WAVE);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = loss;
+    __syncthreads();
+    if (threadIdx.x == 0) lpart[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// gradient reduction: one thread per parameter, states summed in order
+__global__ void __launch_bounds__(256) mlp_backward_reduce(const float* __restrict__ X, int64_t S,
+                                                           const float* __restrict__ H1, const float* __restrict__ H2,
+                                                           const float* __restrict__ D2, const float* __restrict__ D1,
+                                                           const float* __restrict__ dout,
+                                                           const float* __restrict__ lpart, int nlpart,
+                                                           float* __restrict__ grad, float* __restrict__ loss)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= MIMO_MLP_NPARAM + 1) return;
+    float acc = 0.f;
+    if (p < OB1) {  // W1[i][j] = sum_s D1[i][s] X[s][j]
+        const int i = p / NIN, j = p % NIN;
+        for (int64_t s = 0; s < S; ++s) acc = fmaf(D1[(int64_t)i * S + s], X[s * NIN + j], acc);
+    } else if (p < OW2) {
+        const int i = p - OB1;
+        for (int64_t s = 0; s < S; ++s) acc += D1[(int64_t)i * S + s];
+    } else if (p < OB2) {
+        const int i = (p - OW2) / HID, j = (p - OW2) % HID;
+        const float* a = D2 + (int64_t)i * S;
+        const float* b = H1 + (int64_t)j * S;
+        for (int64_t s = 0; s < S; ++s) acc = fmaf(a[s], b[s], acc);
+    } else if (p < OW3) {
+        const int i = p - OB2;
+        for (int64_t s = 0; s < S; ++s) acc += D2[(int64_t)i * S + s];
+    } else if (p < OB3) {
+        const int j = p - OW3;
+        for (int64_t s = 0; s < S; ++s) acc = fmaf(dout[s], H2[(int64_t)j * S + s], acc);
+    } else if (p == OB3) {
+        for (int64_t s = 0; s < S; ++s) acc += dout[s];
+    } else {  // p == NPARAM: the loss
+        for (int b = 0; b < nlpart; ++b) acc += lpart[b];
+        *loss = acc / (float)S;
+        return;
+    }
+    grad[p] = acc;
+}
+
+__global__ void __launch_bounds__(256) adam_kernel(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                                                   const float* __restrict__ g, int np, float lr, float b1, float b2,
+                                                   float c1, float c2, float eps)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+}  // namespace mimo
+
+using namespace mimo;
+
+extern "C" int32_t prune_mlp_forward(const float* w, const float* X, int64_t S, float* out, void* stream)
+{
+    if (S < 0) return fail(MIMO_ERR_INVALID_ARG, "prune_mlp_forward: S < 0");
+    if (S == 0) return MIMO_OK;
+    if (!w || !X || !out) return fail(MIMO_ERR_INVALID_ARG, "prune_mlp_forward: null pointer");
+    hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, (hipStream_t)stream, w,
+                       X, S, out);
+    return check_launch("prune_mlp_forward");
+}
+
+extern "C" int32_t prune_mlp_schedule(const float* w, const float* X, int64_t S, float margin, int32_t k_min,
+                                      int32_t k_max, int32_t n, int32_t* k_sched, uint32_t* flags, void* stream)
+{
+    if (S < 0 || n < 1) return fail(MIMO_ERR_INVALID_ARG, "prune_mlp_schedule: S < 0 or n < 1");
+    if (k_min < 1 || k_max < k_min || k_max > MIMO_MAX_K)
+        return fail(MIMO_ERR_INVALID_ARG, "prune_mlp_schedule: need 1 <= k_min <= k_max <= %d", MIMO_MAX_K);
+    if (S == 0) return MIMO_OK;
+    if (!w || !X || !k_sched) return fail(MIMO_ERR_INVALID_ARG, "prune_mlp_schedule: null pointer");
+    hipLaunchKernelGGL(mlp_schedule_kernel, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, (hipStream_t)stream, w,
+                       X, S, margin, k_min, k_max, n, k_sched, flags);
+    return check_launch("prune_mlp_schedule");
+}
+
+extern "C" size_t prune_mlp_workspace_bytes(int64_t S)
+{
+    if (S < 0) S = 0;
+    const int64_t nblk = (S + 255) / 256;
+    return sizeof(float) * (size_t)(4 * HID * S + S + nblk + 64);
+}
+
+extern "C" int32_t prune_mlp_loss_grad(const float* w, const float* X, const float* y, int64_t S, float tau,
+                                       float* grad, float* loss, void* ws, size_t ws_bytes, void* stream)
+{
+    if (S < 1) return fail(MIMO_ERR_INVALID_ARG, "prune_mlp_loss_grad: S < 1");
+    if (!(tau > 0.f && tau < 1.f)) return fail(MIMO_ERR_INVALID_ARG, "prune_mlp_loss_grad: tau in (0, 1)");
+    if (!w || !X || !y || !grad || !loss || !ws) return fail(MIMO_ERR_INVALID_ARG, "prune_mlp_loss_grad: null pointer");
+    if (ws_bytes < prune_mlp_workspace_bytes(S))
+        return fail(MIMO_ERR_WORKSPACE, "prune_mlp_loss_grad: workspace %zu < %zu", ws_bytes,
+                    prune_mlp_workspace_bytes(S));
+    float* f = static_cast<float*>(ws);
+    float* H1 = f;
+    float* H2 = H1 + HID * S;
+    float* D2 = H2 + HID * S;
+    float* D1 = D2 + HID * S;
+    float* dout = D1 + HID * S;
+    float* lpart = dout + S;
+    const int nblk = (int)((S + 255) / 256);
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(mlp_backward_states, dim3(nblk), dim3(256), 0, st, w, X, y, S, tau, H1, H2, D2, D1, dout,
+                       lpart);
+    int32_t rc = check_launch("prune_mlp_loss_grad");
+    if (rc) return rc;
+    hipLaunchKernelGGL(mlp_backward_reduce, dim3((MIMO_MLP_NPARAM + 1 + 255) / 256), dim3(256), 0, st, X, S, H1, H2,
+                       D2, D1, dout, lpart, nblk, grad, loss);
+    return check_launch("prune_mlp_loss_grad");
+}
+
+extern "C" int32_t prune_mlp_adam_step(float* w, float* m, float* v, const float* grad, int32_t np, int32_t t,
+                                       float lr, float beta1, float beta2, float eps, void* stream)
+{
+    if (np < 1 || t < 1) return fail(MIMO_ERR_INVALID_ARG, "prune_mlp_adam_step: np < 1 or t < 1");
+    if (!w || !m || !v || !grad) return fail(MIMO_ERR_INVALID_ARG, "prune_mlp_adam_step: null pointer");
+    const float c1 = 1.f - powf(beta1, (float)t), c2 = 1.f - powf(beta2, (float)t);
+    hipLaunchKernelGGL(adam_kernel, dim3((np + 255) / 256), dim3(256), 0, (hipStream_t)stream, w, m, v, grad, np, lr,
+                       beta1, beta2, c1, c2, eps);
+    return check_launch("prune_mlp_adam_step");
+}

@@ -1,0 +1,234 @@
+"""Python binding of the C ABI in include/mimo_sd.h (libmimo_sd.so).
+
+Argument marshalling only: every step of the detection path runs in the HIP
+kernels of the library.  Tensors must be CUDA (HIP) tensors on the current
+device, contiguous and of the dtype stated; outputs are allocated here with
+torch and filled by the library on torch's current stream.  There is no CPU
+fallback: if the library is not built, or the GPU is missing, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmimo_sd.so")
+
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP = 0, -1, -2, -3, -4
+FLAG_FOUND, FLAG_EMPTY_SPHERE, FLAG_BUDGET_EXHAUSTED, FLAG_CERTIFIED, FLAG_LEARNED_FALLBACK = 1, 2, 4, 8, 16
+MLP_IN, MLP_HIDDEN = 4, 128
+MLP_NPARAM = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
+MAX_WORKERS = 15
+
+# exported symbols and their C signatures (argument types, return type)
+_P, _I32, _I64, _F, _SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_size_t
+SIGNATURES = {
+    "mimo_last_error": ([], ctypes.c_char_p),
+    "mimo_version": ([], _I32),
+    "mimo_qr_preprocess": ([_P, _P, _I32, _I32, _I32, _P, _P, _P, _P], _I32),
+    "kbest_detect": ([_P, _P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P, _P], _I32),
+    "kbest_rank_labels": ([_P, _P, _I32, _I32, _I32, _I32, _P, _P, _P], _I32),
+    "sd_hybrid_detect": ([_P, _P, _I32, _I32, _I32, _P, _I32, _I32, _P, _I32, _I32, _I64, _P, _P, _P, _P,
+                          _P], _I32),
+    "mimo_metric": ([_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P], _I32),
+    "mimo_error_count": ([_P, _P, _I32, _I32, _I32, _P, _P], _I32),
+    "prune_features": ([_P, _P, _P, _I32, _I32, _I32, _P, _P], _I32),
+    "prune_mlp_forward": ([_P, _P, _I64, _P, _P], _I32),
+    "prune_mlp_schedule": ([_P, _P, _I64, _F, _I32, _I32, _I32, _P, _P, _P], _I32),
+    "prune_mlp_workspace_bytes": ([_I64], _SZ),
+    "prune_mlp_loss_grad": ([_P, _P, _P, _I64, _F, _P, _P, _P, _SZ, _P], _I32),
+    "prune_mlp_adam_step": ([_P, _P, _P, _P, _I32, _I32, _F, _F, _F, _F, _P], _I32),
+}
+
+
+class MimoError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load libmimo_sd.so (built by paper_2002_09561_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is not built; run paper_2002_09561_amd.build.build() first")
+    lib = ctypes.CDLL(p)
+    for name, (args, res) in SIGNATURES.items():
+        fn = getattr(lib, name, None)
+        if fn is None:
+            continue
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise MimoError(rc, load().mimo_last_error().decode())
+
+
+def _ptr(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def packed_size(n: int) -> int:
+    return n * (n + 1) // 2
+
+
+# ------------------------------------------------------------------ QR
+def qr_preprocess(H: torch.Tensor, y: torch.Tensor, want_resid: bool = False, out=None, stream=None):
+    """H [B,N,M] complex64, y [B,N] complex64 -> R [B, n(n+1)/2], z [B, n] (and resid [B])."""
+    B, N, M = H.shape
+    n = 2 * M
+    dev = H.device
+    if out is None:
+        R = torch.empty(B, packed_size(n), device=dev, dtype=torch.float32)
+        z = torch.empty(B, n, device=dev, dtype=torch.float32)
+        resid = torch.empty(B, device=dev, dtype=torch.float32) if want_resid else None
+    else:
+        R, z, resid = out
+    _check(load().mimo_qr_preprocess(_ptr(H, torch.complex64, "H"), _ptr(y, torch.complex64, "y"), B, N, M,
+                                     _ptr(R, torch.float32, "R"), _ptr(z, torch.float32, "z"),
+                                     _ptr(resid, torch.float32, "resid"), _stream(stream)))
+    return (R, z, resid) if want_resid else (R, z)
+
+
+# ------------------------------------------------------------------ detectors
+def _det_outputs(B, n_tx, dev, want_counters):
+    sym = torch.empty(B, n_tx, device=dev, dtype=torch.int32)
+    pd = torch.empty(B, device=dev, dtype=torch.float32)
+    flags = torch.empty(B, device=dev, dtype=torch.int32)
+    ctr = torch.empty(B, 4, device=dev, dtype=torch.int64) if want_counters else None
+    return sym, pd, flags, ctr
+
+
+def _sched(k_sched, n):
+    if k_sched is None:
+        return None, 0
+    if k_sched.dim() == 1:
+        return k_sched, 0
+    return k_sched, n
+
+
+def kbest_detect(R, z, n_tx: int, pam: int, K: int, k_sched=None, radius2=None, want_counters=False,
+                 out=None, stream=None):
+    """Batched K-best.  Returns (sym [B,n_tx] int32, pd [B] f32, flags [B] int32[, counters])."""
+    B = z.shape[0]
+    n = 2 * n_tx
+    sym, pd, flags, ctr = out if out is not None else _det_outputs(B, n_tx, z.device, want_counters)
+    ks, stride = _sched(k_sched, n)
+    _check(load().kbest_detect(_ptr(R, torch.float32, "R"), _ptr(z, torch.float32, "z"), B, n_tx, pam, K,
+                               _ptr(ks, torch.int32, "k_sched"), stride, _ptr(radius2, torch.float32, "radius2"),
+                               _ptr(sym), _ptr(pd), _ptr(flags), _ptr(ctr), _stream(stream)))
+    return (sym, pd, flags, ctr) if want_counters else (sym, pd, flags)
+
+
+def kbest_rank_labels(R, z, n_tx: int, pam: int, K: int, force_sym, stream=None):
+    B = z.shape[0]
+    rank = torch.empty(B, 2 * n_tx, device=z.device, dtype=torch.int32)
+    _check(load().kbest_rank_labels(_ptr(R, torch.float32, "R"), _ptr(z, torch.float32, "z"), B, n_tx, pam, K,
+                                    _ptr(force_sym, torch.int32, "force_sym"), _ptr(rank), _stream(stream)))
+    return rank
+
+
+def sd_hybrid_detect(R, z, n_tx: int, pam: int, n_workers: int, k_worker: int, radius2=None, k_sched=None,
+                     master_off=False, node_budget: int = 0, want_counters=False, out=None, stream=None):
+    B = z.shape[0]
+    n = 2 * n_tx
+    sym, pd, flags, ctr = out if out is not None else _det_outputs(B, n_tx, z.device, want_counters)
+    ks, stride = _sched(k_sched, n)
+    _check(load().sd_hybrid_detect(_ptr(R, torch.float32, "R"), _ptr(z, torch.float32, "z"), B, n_tx, pam,
+                                   _ptr(radius2, torch.float32, "radius2"), n_workers, k_worker,
+                                   _ptr(ks, torch.int32, "k_sched"), stride, int(bool(master_off)),
+                                   int(node_budget), _ptr(sym), _ptr(pd), _ptr(flags), _ptr(ctr),
+                                   _stream(stream)))
+    return (sym, pd, flags, ctr) if want_counters else (sym, pd, flags)
+
+
+# ------------------------------------------------------------------ epilogues
+def metric(H, y, sym, pam: int, out=None, stream=None):
+    B, N, M = H.shape
+    m = out if out is not None else torch.empty(B, device=H.device, dtype=torch.float64)
+    _check(load().mimo_metric(_ptr(H, torch.complex64, "H"), _ptr(y, torch.complex64, "y"),
+                              _ptr(sym, torch.int32, "sym"), B, N, M, pam, _ptr(m, torch.float64), _stream(stream)))
+    return m
+
+
+def error_count(sym, ref, pam: int, counts=None, stream=None):
+    """counts (int64 [3], accumulated): bit errors, symbol errors, frames in error."""
+    B, M = sym.shape
+    c = counts if counts is not None else torch.zeros(3, device=sym.device, dtype=torch.int64)
+    _check(load().mimo_error_count(_ptr(sym, torch.int32, "sym"), _ptr(ref, torch.int32, "ref"), B, M, pam,
+                                   _ptr(c, torch.int64, "counts"), _stream(stream)))
+    return c
+
+
+def prune_features(R, z, sigma2, n_tx: int, pam: int, out=None, stream=None):
+    B = z.shape[0]
+    f = out if out is not None else torch.empty(B, 2 * n_tx, 4, device=z.device, dtype=torch.float32)
+    _check(load().prune_features(_ptr(R, torch.float32, "R"), _ptr(z, torch.float32, "z"),
+                                 _ptr(sigma2, torch.float32, "sigma2"), B, n_tx, pam, _ptr(f), _stream(stream)))
+    return f
+
+
+# ------------------------------------------------------------------ MLP
+def mlp_forward(w, X, out=None, stream=None):
+    S = X.shape[0]
+    o = out if out is not None else torch.empty(S, device=X.device, dtype=torch.float32)
+    _check(load().prune_mlp_forward(_ptr(w, torch.float32, "w"), _ptr(X, torch.float32, "X"), S, _ptr(o),
+                                    _stream(stream)))
+    return o
+
+
+def mlp_schedule(w, X, n: int, margin: float, k_min: int, k_max: int, flags=None, out=None, stream=None):
+    S = X.shape[0]
+    ks = out if out is not None else torch.empty(S, device=X.device, dtype=torch.int32)
+    _check(load().prune_mlp_schedule(_ptr(w, torch.float32, "w"), _ptr(X, torch.float32, "X"), S, float(margin),
+                                     int(k_min), int(k_max), int(n), _ptr(ks), _ptr(flags, torch.int32, "flags"),
+                                     _stream(stream)))
+    return ks
+
+
+def mlp_workspace_bytes(S: int) -> int:
+    return int(load().prune_mlp_workspace_bytes(S))
+
+
+def mlp_loss_grad(w, X, y, tau: float, ws=None, grad=None, loss=None, stream=None):
+    S = X.shape[0]
+    nb = mlp_workspace_bytes(S)
+    if ws is None:
+        ws = torch.empty(nb, device=X.device, dtype=torch.uint8)
+    g = grad if grad is not None else torch.empty(w.numel(), device=X.device, dtype=torch.float32)
+    l = loss if loss is not None else torch.empty(1, device=X.device, dtype=torch.float32)
+    _check(load().prune_mlp_loss_grad(_ptr(w, torch.float32, "w"), _ptr(X, torch.float32, "X"),
+                                      _ptr(y, torch.float32, "y"), S, float(tau), _ptr(g), _ptr(l), _ptr(ws),
+                                      ws.numel() * ws.element_size(), _stream(stream)))
+    return l, g
+
+
+def mlp_adam_step(w, m, v, g, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(load().prune_mlp_adam_step(_ptr(w, torch.float32, "w"), _ptr(m, torch.float32, "m"),
+                                      _ptr(v, torch.float32, "v"), _ptr(g, torch.float32, "g"), w.numel(), int(t),
+                                      float(lr), float(beta1), float(beta2), float(eps), _stream(stream)))

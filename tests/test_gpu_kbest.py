@@ -1,0 +1,231 @@
+"""GPU parity: QR preprocessing, batched K-best, labels and epilogues against
+the FP64 oracle on the same seeded frames."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2002_09561_amd.framegen import gen_frames
+from tests.parity_util import compare_symbols, near_tie_tol, pack_level_order
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(frames):
+    import torch
+
+    return (torch.from_numpy(frames.H).cuda(), torch.from_numpy(frames.y).cuda(),
+            torch.from_numpy(frames.s_idx).cuda())
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+# ----------------------------------------------------------------- QR
+@pytest.mark.parametrize("N,M,q,B", [(4, 4, 4, 37), (16, 16, 16, 130), (20, 12, 64, 9), (32, 32, 16, 64),
+                                     (100, 100, 64, 6), (128, 128, 4, 3), (1, 1, 16, 5)])
+def test_qr_parity(gpu, orc, N, M, q, B):
+    f = gen_frames(N, M, q, 18.0, B, seed=1000 + N + M)
+    H, y, _ = _dev(f)
+    R, z, resid = gpu.qr_preprocess(H, y, want_resid=True)
+    Ro, zo, reso = orc.qr(f.H, f.y)
+    Rp = pack_level_order(Ro)
+    n = 2 * M
+    # Householder in FP32 is backward stable: ||dR|| <= c n u ||H||
+    u = 2.0 ** -24
+    hn = np.sqrt((np.abs(f.H.astype(np.complex128)) ** 2).sum(axis=(1, 2)) * 2)
+    err_R = np.sqrt(((_np(R) - Rp) ** 2).sum(axis=1))
+    err_z = np.sqrt(((_np(z) - zo) ** 2).sum(axis=1))
+    yn = np.sqrt((np.abs(f.y.astype(np.complex128)) ** 2).sum(axis=1))
+    print(f"QR {N}x{M}: max ||dR||/||H|| = {np.max(err_R / hn):.2e}, max ||dz||/||y|| = {np.max(err_z / yn):.2e}")
+    assert np.all(err_R <= 8 * n * u * hn)
+    assert np.all(err_z <= 8 * n * u * (yn + hn))
+    assert np.all(np.abs(_np(resid) - reso) <= 8 * n * u * yn ** 2 + 1e-6)
+    # exact zeros of the interleaved structure: R_{2k,2k+1} = 0
+    Rg = _np(R)
+    for k in range(0, n, 2):
+        off = (n - 1 - k) * (n - k) // 2
+        assert np.all(Rg[:, off + 1] == 0.0)
+
+
+# ----------------------------------------------------------------- K-best
+def _kbest_case(gpu, orc, N, M, q, snr, B, K, seed, radius=None, sched=None):
+    import torch
+
+    f = gen_frames(N, M, q, snr, B, seed=seed)
+    P = math.isqrt(q)
+    n = 2 * M
+    H, y, _ = _dev(f)
+    R, z = gpu.qr_preprocess(H, y)
+    r2 = None if radius is None else torch.from_numpy(radius.astype(np.float32)).cuda()
+    ks = None if sched is None else torch.from_numpy(sched.astype(np.int32)).cuda()
+    sym, pd, flags, ctr = gpu.kbest_detect(R, z, M, P, K, k_sched=ks, radius2=r2, want_counters=True)
+    Ro, zo, reso = orc.qr(f.H, f.y)
+    out = orc.kbest(Ro, zo, P, K, k_sched=sched, r2=math.inf if radius is None else 0.0) if radius is None \
+        else None
+    if radius is not None:
+        # per-frame radius: run the oracle frame by frame
+        xs, pds, mgs, fls = [], [], [], []
+        for b in range(B):
+            o = orc.kbest(Ro[b:b + 1], zo[b:b + 1], P, K, k_sched=None if sched is None else sched[b:b + 1],
+                          r2=float(np.float32(radius[b])))
+            xs.append(o["x"][0]); pds.append(o["pd"][0]); mgs.append(o["margin"][0]); fls.append(o["flags"][0])
+        out = dict(x=np.array(xs), pd=np.array(pds), margin=np.array(mgs), flags=np.array(fls),
+                   counters=None)
+    return f, P, n, out, (sym, pd, flags, ctr), (Ro, zo, reso)
+
+
+@pytest.mark.parametrize("M,q,snr,B,K", [(4, 4, 10.0, 1000, 16), (16, 16, 4.0, 300, 64), (16, 16, 12.0, 300, 64),
+                                         (16, 16, 20.0, 257, 64), (8, 64, 18.0, 200, 5), (10, 16, 8.0, 150, 1),
+                                         (32, 16, 14.0, 100, 16), (6, 4, 6.0, 100, 256), (12, 64, 20.0, 61, 128),
+                                         (1, 16, 5.0, 50, 3)])
+def test_kbest_parity(gpu, orc, M, q, snr, B, K):
+    f, P, n, out, (sym, pd, flags, ctr), (Ro, zo, reso) = _kbest_case(gpu, orc, M, M, q, snr, B, K,
+                                                                      seed=2000 + M + K)
+    sym_o = orc.x_to_sym(out["x"], P)
+    tol = near_tie_tol(n)
+    nm, ne = compare_symbols(_np(sym), sym_o, out["margin"], tol, f"K-best {M}x{M} {q}-QAM K={K} {snr}dB")
+    assert nm <= max(3, B // 20)
+    assert np.all(_np(flags) & 1)
+    # node counters follow the closed form sum_t min(K, P^t)
+    expect = sum(min(K, P ** t) for t in range(n))
+    assert np.all(_np(ctr)[:, 0] == expect) and np.all(_np(ctr)[:, 1] == P * expect)
+    # FP32 search pd against the FP64 pd of the same leaf (matched frames)
+    same = np.all(_np(sym) == sym_o, axis=1)
+    rel = np.abs(_np(pd)[same] - out["pd"][same]) / np.maximum(out["pd"][same], 1e-30)
+    print(f"  FP32 search pd rel err: median {np.median(rel):.2e} max {rel.max():.2e}")
+    assert rel.max() < 1e-3
+    # FP64 metric epilogue of the same symbols
+    H, y, _ = _dev(f)
+    m_gpu = _np(gpu.metric(H, y, sym, P))
+    m_orc = orc.metric(f.H, f.y, _np(sym), q)
+    assert np.allclose(m_gpu, m_orc, rtol=1e-10, atol=1e-12)
+
+
+def test_kbest_full_K_is_ml_and_K1_is_sic(gpu, orc):
+    import torch
+
+    f = gen_frames(4, 4, 16, 8.0, 200, seed=2100)
+    H, y, _ = _dev(f)
+    R, z = gpu.qr_preprocess(H, y)
+    sb, _ = orc.brute_force(f.H, f.y, 16)
+    Ro, zo, _ = orc.qr(f.H, f.y)
+    ml = orc.kbest(Ro, zo, 4, 4 ** 7)
+    sym, _, _ = gpu.kbest_detect(R, z, 4, 4, 256)
+    compare_symbols(_np(sym), sb, ml["margin"], near_tie_tol(8), "K=256 vs brute force")
+    xs, _ = orc.zf_sic(Ro, zo, 4)
+    k1 = orc.kbest(Ro, zo, 4, 1)
+    sym1, _, _ = gpu.kbest_detect(R, z, 4, 4, 1)
+    compare_symbols(_np(sym1), orc.x_to_sym(xs, 4), k1["margin"], near_tie_tol(8), "K=1 vs SIC")
+
+
+def test_kbest_radius_and_empty_sphere(gpu, orc):
+    B = 120
+    f = gen_frames(8, 8, 16, 10.0, B, seed=2200)
+    Ro, zo, _ = orc.qr(f.H, f.y)
+    ml = orc.sesd(Ro, zo, 4)[1]
+    rng = np.random.default_rng(5)
+    radius = ml * rng.uniform(0.6, 2.0, size=B)  # some frames below the ML metric
+    f2, P, n, out, (sym, pd, flags, ctr), _ = _kbest_case(gpu, orc, 8, 8, 16, 10.0, B, 8, seed=2200,
+                                                          radius=radius)
+    fl = _np(flags)
+    of = out["flags"]
+    empty_o = (of & 2) != 0
+    empty_g = (fl & 2) != 0
+    near = out["margin"][:, 0] <= near_tie_tol(n)
+    assert np.all((empty_o == empty_g) | near)
+    ok = ~empty_o & ~empty_g
+    compare_symbols(_np(sym)[ok], orc.x_to_sym(out["x"], P)[ok], out["margin"][ok], near_tie_tol(n), "radius")
+    assert empty_o.any() and (~empty_o).any()
+
+
+def test_kbest_per_frame_schedule(gpu, orc):
+    B, M = 100, 16
+    rng = np.random.default_rng(6)
+    sched = rng.integers(1, 33, size=(B, 2 * M)).astype(np.int32)
+    f, P, n, out, (sym, pd, flags, ctr), _ = _kbest_case(gpu, orc, M, M, 16, 10.0, B, 32, seed=2300, sched=sched)
+    compare_symbols(_np(sym), orc.x_to_sym(out["x"], P), out["margin"], near_tie_tol(n), "schedule")
+    # expanded nodes follow the schedule: 1 + sum over levels of min(K_t, P * previous)
+    exp = np.zeros(B, np.int64)
+    for b in range(B):
+        cnt = 1
+        for k in range(n - 1, -1, -1):
+            exp[b] += cnt
+            cnt = min(sched[b, k], cnt * P)
+    assert np.array_equal(_np(ctr)[:, 0], exp)
+
+
+def test_rank_labels_parity(gpu, orc):
+    import torch
+
+    B, M, q = 80, 8, 16
+    f = gen_frames(M, M, q, 8.0, B, seed=2400)
+    P = 4
+    Ro, zo, _ = orc.qr(f.H, f.y)
+    ml = orc.sesd(Ro, zo, P)[0]
+    out = orc.kbest(Ro, zo, P, 16, force_path=ml)
+    H, y, _ = _dev(f)
+    R, z = gpu.qr_preprocess(H, y)
+    rank = _np(gpu.kbest_rank_labels(R, z, M, P, 16, torch.from_numpy(orc.x_to_sym(ml, P)).cuda()))
+    same = rank == out["rank"]
+    print(f"rank labels equal: {same.mean():.4f}")
+    assert same.mean() >= 0.99
+    assert np.all(np.abs(rank - out["rank"]) <= 2)
+
+
+# ----------------------------------------------------------------- epilogues
+def test_error_count_parity(gpu, orc):
+    import torch
+
+    rng = np.random.default_rng(7)
+    for q, M, B in ((4, 4, 100), (16, 16, 333), (64, 100, 40)):
+        P = math.isqrt(q)
+        ref = rng.integers(0, q, size=(B, M)).astype(np.int32)
+        hat = ref.copy()
+        flip = rng.random((B, M)) < 0.05
+        hat[flip] = rng.integers(0, q, size=flip.sum())
+        c = _np(gpu.error_count(torch.from_numpy(hat).cuda(), torch.from_numpy(ref).cuda(), P))
+        bits, syms = orc.error_counts(hat, ref, P)
+        assert c[0] == bits and c[1] == syms and c[2] == int(np.any(hat != ref, axis=1).sum())
+
+
+def test_prune_features_parity(gpu, orc):
+    import torch
+
+    B, M, q = 64, 16, 16
+    f = gen_frames(M, M, q, 14.0, B, seed=2500)
+    Ro, zo, _ = orc.qr(f.H, f.y)
+    fo = orc.prune_features(Ro, zo, 4, f.sigma2)
+    H, y, _ = _dev(f)
+    R, z = gpu.qr_preprocess(H, y)
+    s2 = torch.full((B,), f.sigma2, device="cuda", dtype=torch.float32)
+    fg = _np(gpu.prune_features(R, z, s2, M, 4))
+    # the cancellation path is the K = 1 path: compare where it agrees
+    xs, _ = orc.zf_sic(Ro, zo, 4)
+    sym1, _, _ = gpu.kbest_detect(R, z, M, 4, 1)
+    same = np.all(_np(sym1) == orc.x_to_sym(xs, 4), axis=1)
+    assert same.mean() > 0.9
+    d = np.abs(fg[same] - fo[same])
+    assert np.all(d[..., 0] < 1e-6)
+    assert np.all(d[..., 1] < 1e-3)
+    assert np.all(d[..., 2] < 1e-4)
+    assert np.all(d[..., 3] < 1e-3 * np.maximum(1.0, np.abs(fo[same][..., 3])))
+
+
+# ----------------------------------------------------------------- full size, sampled
+def test_kbest_100x100_64qam_sampled(gpu, orc):
+    """The benchmark's shape (100x100 64-QAM, K = 16) in its launch
+    configuration; a sample of frames is checked against the oracle."""
+    B = 512
+    f = gen_frames(100, 100, 64, 20.0, B, seed=2600)
+    H, y, _ = _dev(f)
+    R, z = gpu.qr_preprocess(H, y)
+    sym, pd, flags = gpu.kbest_detect(R, z, 100, 8, 16)
+    idx = np.arange(0, B, 16)
+    Ro, zo, _ = orc.qr(f.H[idx], f.y[idx])
+    out = orc.kbest(Ro, zo, 8, 16)
+    compare_symbols(_np(sym)[idx], orc.x_to_sym(out["x"], 8), out["margin"], near_tie_tol(200), "100x100 K=16")
+    m = _np(gpu.metric(H, y, sym, 8))
+    mo = orc.metric(f.H[idx], f.y[idx], _np(sym)[idx], 64)
+    assert np.allclose(m[idx], mo, rtol=1e-10)
