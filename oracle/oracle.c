@@ -356,10 +356,7 @@ uint32_t orc_kbest(int n, int P, const double* R, const double* z, int K, const 
                    double* margin_out, int* rank_out, int64_t* counters)
 {
     if (J < 1 || n % J != 0) return 0;
-    int kmax = K;
-    if (k_sched)
-        for (int k = 0; k < n; ++k)
-            if (k_sched[k] > kmax) kmax = k_sched[k];
+    const int kmax = K < 1 ? 1 : K; /* K is the capacity; schedule values are clamped to it */
     const int nc = ipow(P, J);
     int* path = (int*)calloc((size_t)kmax * n, sizeof(int));
     int* npath = (int*)calloc((size_t)kmax * n, sizeof(int));
@@ -379,6 +376,7 @@ uint32_t orc_kbest(int n, int P, const double* R, const double* z, int K, const 
     for (int t = 0; t < n; t += J) {
         int k_hi = n - 1 - t, k_lo = k_hi - J + 1;
         int Kt = k_sched ? k_sched[k_lo] : K;
+        if (Kt > kmax) Kt = kmax;
         if (Kt < 1) Kt = 1;
         int m = 0;
         for (int r = 0; r < cnt; ++r) {
@@ -497,11 +495,7 @@ uint32_t orc_hybrid(int n, int P, const double* R, const double* z, double r2, i
                     const int* k_sched, int master_off, int64_t budget, int* x_out, double* pd_out,
                     double* margin_out, int64_t* counters)
 {
-    int kmax = Kw;
-    if (k_sched)
-        for (int k = 0; k < n; ++k)
-            if (k_sched[k] > kmax) kmax = k_sched[k];
-    if (kmax < 1) kmax = 1;
+    const int kmax = Kw < 1 ? 1 : Kw; /* Kw is the capacity; schedule values are clamped to it */
     const int cap = n * P + 8;
     int* qt = (int*)malloc(sizeof(int) * cap);
     double* qpd = (double*)malloc(sizeof(double) * cap);
@@ -640,6 +634,7 @@ uint32_t orc_hybrid(int n, int P, const double* R, const double* z, double r2, i
             if (!wbusy[w]) continue;
             int t = wt[w], k = n - 1 - t;
             int Kt = k_sched ? k_sched[k] : Kw;
+            if (Kt > kmax) Kt = kmax;
             if (Kt < 1) Kt = 1;
             double* spd = wpd + (size_t)w * kmax;
             int* sp = wpath + (size_t)w * kmax * n;

@@ -72,7 +72,7 @@ uint32_t orc_sesd(int n, int P, const double* R, const double* z, double r2, int
 
 /* K-best (Sec. VI): level-synchronous, keeps the first K_t candidates by
  * (pd, parent rank, child index).  J = symbols fixed per step (1, or 2 for
- * complex-symbol branching), K_t = k_sched[k_lo] if k_sched else K.
+ * complex-symbol branching), K_t = k_sched[k_lo] clamped to [1, K] if k_sched else K.
  * force_path (or NULL): a complete path whose prefix is kept at every step
  * (label generation); its 1-based rank among the sorted candidates of each
  * step goes to rank_out[k_lo] (if rank_out).  margin_out (or NULL) receives
@@ -82,7 +82,7 @@ uint32_t orc_kbest(int n, int P, const double* R, const double* z, int K, const 
                    double* margin_out, int* rank_out, int64_t* counters);
 
 /* Hybrid SD-K-best (Sec. VI) in deterministic rounds; W workers each keep
- * Kw survivors (or k_sched[k] when k_sched is not NULL).  master_off hands
+ * Kw survivors (or k_sched[k] clamped to [1, Kw] when k_sched is not NULL).  master_off hands
  * the root to worker 0 and never expands (the K-best special case). */
 uint32_t orc_hybrid(int n, int P, const double* R, const double* z, double r2, int W, int Kw,
                     const int* k_sched, int master_off, int64_t budget, int* x_out, double* pd_out,

@@ -1,0 +1,516 @@
+// Hybrid SD / K-best detection (Sec. VI, SD-K-best) in deterministic rounds,
+// one workgroup per frame: wave 0 is the Best-FS sphere-decoder master
+// (Alg. 1 with the Best-FS list of Sec. IV-A), waves 1..W are K-best workers.
+//
+// The master's list is a depth-first stack, so every pool node at depth d is
+// a child of the master's current path prefix at depth d-1.  The pool is
+// therefore kept as the master path (one byte per level) plus, per depth, a
+// short sorted list of remaining siblings (pd, symbol): the left-most node is
+// the best sibling of the deepest non-empty depth, the right-most node is
+// the worst sibling of the shallowest one.
+//
+// One round:
+//   A  master: pop left-most nodes until one lies inside the radius, expand
+//      it (dot product of the path with row k of R, P child partial
+//      distances, Eq. (inc)), sort the children, insert the ones inside the
+//      radius at depth d+1 (best left-most) or offer the best leaf;
+//   B  one thread hands right-most nodes to idle workers (pool >= 2 nodes);
+//   C  every busy worker advances its K-best one level (K_w * P candidates
+//      sorted in the wave by (pd bits, parent rank, child)); at the leaves it
+//      offers its best survivor;
+//   D  one thread takes the best offer by (pd, source) and shrinks the radius.
+// A-C use the radius of the start of the round.
+#include "common.hpp"
+
+namespace mimo {
+
+struct HybArgs {
+    const float* R;
+    const float* z;
+    int n;
+    int W;
+    int Kw;
+    const int32_t* k_sched;
+    int k_sched_stride;
+    const float* radius2;
+    int master_off;
+    int64_t budget;
+    int32_t* sym;
+    float* pd;
+    uint32_t* flags;
+    int64_t* counters;
+};
+
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct HybLayout {
+    int nw, stride, nd;  // words per path, padded stride, depths (n + 1)
+    size_t o_mpath, o_bpath, o_ppd, o_pc, o_lo, o_hi, o_mask, o_wst, o_wpath, o_wpd, o_sel, o_cand, o_sc, total;
+    __host__ __device__ HybLayout(int n, int W, int Kw, int P)
+    {
+        nw = (n + 3) / 4;
+        stride = nw + 1;
+        nd = n + 1;
+        const int Wc = W > 0 ? W : 1;
+        size_t o = 0;
+        o_mpath = o; o += 4 * nw;
+        o_bpath = o; o += 4 * nw;
+        o_ppd = o; o += 4 * (size_t)nd * P;
+        o_pc = o; o += 4 * (size_t)nd * P;
+        o_lo = o; o += 4 * nd;
+        o_hi = o; o += 4 * nd;
+        o_mask = o; o += 4 * 9;
+        o_wst = o; o += 4 * 8 * Wc;              // per worker: busy, depth, cnt, buf, isnew, newd, newc, newpd
+        o_wpath = o; o += 4 * (size_t)Wc * 2 * Kw * stride;
+        o_wpd = o; o += 4 * (size_t)Wc * 2 * Kw;
+        o_sel = o; o += 4 * (size_t)Wc * Kw;
+        o_cand = o; o += 4 * 3 * (Wc + 1);      // pd, ok, info per source
+        o_sc = o; o += 64;                      // scalars
+        total = o;
+    }
+};
+
+// scalar slots (int32 unless noted)
+enum { SC_R2 = 0, SC_FOUND, SC_PSIZE, SC_DONE, SC_FLAGS, SC_EXP_LO, SC_EXP_HI, SC_ROUNDS, SC_STALE, SC_WEXP };
+
+template <int P>
+__global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
+{
+    extern __shared__ unsigned char smem_hy[];
+    const int frame = blockIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int n = a.n, W = a.W, Kw = a.Kw;
+    const HybLayout Lo(n, W, Kw, P);
+    const int nw = Lo.nw, stride = Lo.stride;
+    uint32_t* mpath = reinterpret_cast<uint32_t*>(smem_hy + Lo.o_mpath);
+    uint32_t* bpath = reinterpret_cast<uint32_t*>(smem_hy + Lo.o_bpath);
+    float* ppd = reinterpret_cast<float*>(smem_hy + Lo.o_ppd);
+    int* pc = reinterpret_cast<int*>(smem_hy + Lo.o_pc);
+    int* plo = reinterpret_cast<int*>(smem_hy + Lo.o_lo);
+    int* phi = reinterpret_cast<int*>(smem_hy + Lo.o_hi);
+    uint32_t* pmask = reinterpret_cast<uint32_t*>(smem_hy + Lo.o_mask);
+    int* wst = reinterpret_cast<int*>(smem_hy + Lo.o_wst);
+    uint32_t* wpath = reinterpret_cast<uint32_t*>(smem_hy + Lo.o_wpath);
+    float* wpd = reinterpret_cast<float*>(smem_hy + Lo.o_wpd);
+    int* wsel = reinterpret_cast<int*>(smem_hy + Lo.o_sel);
+    float* cpd = reinterpret_cast<float*>(smem_hy + Lo.o_cand);
+    int* cok = reinterpret_cast<int*>(cpd + (W + 1));
+    int* cinfo = cok + (W + 1);
+    int* sc = reinterpret_cast<int*>(smem_hy + Lo.o_sc);
+    float* sc_r2 = reinterpret_cast<float*>(sc + SC_R2);
+
+    const float* Rf = a.R + (size_t)frame * r_packed_size(n);
+    const float* zf = a.z + (size_t)frame * n;
+    const float cs = pam_scale(P);
+    const int32_t* ks = a.k_sched ? a.k_sched + (size_t)frame * a.k_sched_stride : nullptr;
+
+    // ---- init
+    for (int i = threadIdx.x; i < Lo.nd; i += blockDim.x) {
+        plo[i] = 0;
+        phi[i] = 0;
+    }
+    for (int i = threadIdx.x; i < nw; i += blockDim.x) {
+        mpath[i] = 0;
+        bpath[i] = 0;
+    }
+    for (int i = threadIdx.x; i < 9; i += blockDim.x) pmask[i] = 0;
+    for (int i = threadIdx.x; i < 8 * (W > 0 ? W : 1); i += blockDim.x) wst[i] = 0;
+    for (int i = threadIdx.x; i <= W; i += blockDim.x) cok[i] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *sc_r2 = a.radius2 ? a.radius2[frame] : INFINITY;
+        sc[SC_FOUND] = 0;
+        sc[SC_DONE] = 0;
+        sc[SC_FLAGS] = 0;
+        sc[SC_EXP_LO] = 0;
+        sc[SC_EXP_HI] = 0;
+        sc[SC_ROUNDS] = 0;
+        sc[SC_STALE] = 0;
+        sc[SC_WEXP] = 0;
+        if (a.master_off) {
+            sc[SC_PSIZE] = 0;
+            if (W >= 1) {  // worker 0 starts at the root
+                wst[0] = 1;   // busy
+                wst[1] = 0;   // depth
+                wst[2] = 1;   // survivors
+                wst[3] = 0;   // buffer
+                wst[4] = 0;   // not new
+                wpd[0] = 0.f;
+            }
+        } else {  // the root is the only pool node (depth 0)
+            ppd[0] = 0.f;
+            pc[0] = 0;
+            plo[0] = 0;
+            phi[0] = 1;
+            pmask[0] = 1u;
+            sc[SC_PSIZE] = 1;
+        }
+    }
+    __syncthreads();
+
+    for (;;) {
+        // ---- termination (uniform: every thread reads the same LDS state)
+        int busy_any = 0;
+        for (int w = 0; w < W; ++w) busy_any |= wst[8 * w];
+        const int64_t expanded = ((int64_t)(uint32_t)sc[SC_EXP_HI] << 32) | (uint32_t)sc[SC_EXP_LO];
+        if (sc[SC_PSIZE] == 0 && !busy_any) {
+            if (threadIdx.x == 0) sc[SC_FLAGS] |= MIMO_FLAG_CERTIFIED;
+            break;
+        }
+        if (a.budget > 0 && expanded >= a.budget) {
+            if (threadIdx.x == 0) sc[SC_FLAGS] |= MIMO_FLAG_BUDGET_EXHAUSTED;
+            break;
+        }
+        const float r2r = *sc_r2;
+        __syncthreads();  // everyone has read the round-start state
+
+        // ---- A: master
+        if (wave == 0 && !a.master_off) {
+            int ok = 0, d = 0, c = 0;
+            float pd = 0.f;
+            if (lane == 0) {
+                int stale = 0;
+                while (sc[SC_PSIZE] > 0) {
+                    int dd = 0;
+                    for (int q = 8; q >= 0; --q)
+                        if (pmask[q]) {
+                            dd = 32 * q + 31 - __clz(pmask[q]);
+                            break;
+                        }
+                    const int i = plo[dd]++;
+                    if (plo[dd] == phi[dd]) pmask[dd >> 5] &= ~(1u << (dd & 31));
+                    sc[SC_PSIZE] -= 1;
+                    const float v = ppd[dd * P + i];
+                    if (v >= r2r) {
+                        ++stale;
+                        continue;
+                    }
+                    ok = 1;
+                    d = dd;
+                    c = pc[dd * P + i];
+                    pd = v;
+                    break;
+                }
+                sc[SC_STALE] += stale;
+            }
+            ok = __shfl(ok, 0, WAVE);
+            if (ok) {
+                d = __shfl(d, 0, WAVE);
+                c = __shfl(c, 0, WAVE);
+                pd = __shfl(pd, 0, WAVE);
+                const int lev = n - d;  // level of the node's own symbol (n for the root)
+                const int k = lev - 1;  // level its children fix
+                const float* rk = Rf + r_row_off(n, k);
+                float acc = 0.f, rsum = 0.f;
+                for (int t = 1 + lane; t < n - k; t += WAVE) {
+                    const int j = k + t;
+                    const int sym = (j == lev) ? c : (int)((mpath[j >> 2] >> (8 * (j & 3))) & 0xffu);
+                    const float r = cs * rk[t];
+                    acc = fmaf(r, (float)sym, acc);
+                    rsum += r;
+                }
+                acc = wave_sum(acc);
+                rsum = wave_sum(rsum);
+                const float b = zf[k] - (2.f * acc - (float)(P - 1) * rsum);
+                const float rkk = cs * rk[0];
+                float pdc = INFINITY;
+                if (lane < P) {
+                    const float ee = fmaf(-rkk, (float)(2 * lane - (P - 1)), b);
+                    pdc = fmaf(ee, ee, pd);
+                }
+                // rank of each child by (pd, index)
+                int rank = 0;
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    const float o = shfl_f(pdc, q);
+                    rank += (o < pdc) || (o == pdc && q < lane);
+                }
+                const bool keep = lane < P && pdc < r2r;
+                const int nk = __popcll(__ballot(keep));
+                if (k == 0) {
+                    if (keep && rank == 0) {
+                        cpd[0] = pdc;
+                        cinfo[0] = lane;
+                        cok[0] = 1;
+                    }
+                } else if (nk > 0) {
+                    const int dn = d + 1;
+                    if (keep) {
+                        ppd[dn * P + rank] = pdc;
+                        pc[dn * P + rank] = lane;
+                    }
+                    if (lane == 0) {
+                        plo[dn] = 0;
+                        phi[dn] = nk;
+                        pmask[dn >> 5] |= 1u << (dn & 31);
+                        sc[SC_PSIZE] += nk;
+                    }
+                }
+                if (lane == 0) {
+                    if (d > 0) {  // the popped node's symbol joins the master path
+                        const int sh = 8 * (lev & 3);
+                        mpath[lev >> 2] = (mpath[lev >> 2] & ~(0xffu << sh)) | ((uint32_t)c << sh);
+                    }
+                    uint32_t lo = (uint32_t)sc[SC_EXP_LO] + 1u;
+                    if (lo == 0u) sc[SC_EXP_HI] += 1;
+                    sc[SC_EXP_LO] = (int)lo;
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---- B: idle workers take right-most nodes
+        if (threadIdx.x == 0) {
+            int stale = 0;
+            for (int w = 0; w < W; ++w) {
+                int* st = wst + 8 * w;
+                if (st[0]) continue;
+                while (sc[SC_PSIZE] >= 2) {
+                    int dd = 0;
+                    for (int q = 0; q < 9; ++q)
+                        if (pmask[q]) {
+                            dd = 32 * q + __ffs(pmask[q]) - 1;
+                            break;
+                        }
+                    const int i = --phi[dd];
+                    if (plo[dd] == phi[dd]) pmask[dd >> 5] &= ~(1u << (dd & 31));
+                    sc[SC_PSIZE] -= 1;
+                    const float v = ppd[dd * P + i];
+                    if (v >= r2r) {
+                        ++stale;
+                        continue;
+                    }
+                    st[0] = 1;
+                    st[4] = 1;
+                    st[5] = dd;
+                    st[6] = pc[dd * P + i];
+                    reinterpret_cast<float*>(st)[7] = v;
+                    break;
+                }
+            }
+            sc[SC_STALE] += stale;
+        }
+        __syncthreads();
+
+        // ---- C: busy workers advance one level
+        if (wave >= 1 && wave <= W) {
+            const int w = wave - 1;
+            int* st = wst + 8 * w;
+            if (st[0]) {
+                uint32_t* wp = wpath + (size_t)w * 2 * Kw * stride;
+                float* wq = wpd + (size_t)w * 2 * Kw;
+                int* sel = wsel + (size_t)w * Kw;
+                if (st[4]) {  // new node: survivor 0 = master prefix + its symbol
+                    const int d = st[5], lev = n - d;
+                    uint32_t* dst = wp;  // buffer 0, survivor 0
+                    for (int i = lane; i < nw; i += WAVE) {
+                        uint32_t v = mpath[i];
+                        if (d > 0 && i == (lev >> 2)) {
+                            const int sh = 8 * (lev & 3);
+                            v = (v & ~(0xffu << sh)) | ((uint32_t)st[6] << sh);
+                        }
+                        dst[i] = v;
+                    }
+                    if (lane == 0) {
+                        wq[0] = reinterpret_cast<float*>(st)[7];
+                        st[1] = d;
+                        st[2] = 1;
+                        st[3] = 0;
+                        st[4] = 0;
+                    }
+                    wave_sync();
+                }
+                const int depth = st[1], cnt = st[2], buf = st[3];
+                const int k = n - depth - 1;
+                uint32_t* pcur = wp + buf * Kw * stride;
+                uint32_t* pnxt = wp + (buf ^ 1) * Kw * stride;
+                float* scur = wq + buf * Kw;
+                float* snxt = wq + (buf ^ 1) * Kw;
+                int Kt = ks ? ks[k] : Kw;
+                Kt = Kt > Kw ? Kw : (Kt < 1 ? 1 : Kt);
+                const float* rk = Rf + r_row_off(n, k);
+                // row sum (uniform) and per-survivor dot products: P lanes per survivor
+                float rsum = 0.f;
+                for (int t = 1 + lane; t < n - k; t += WAVE) rsum += cs * rk[t];
+                rsum = wave_sum(rsum);
+                const int s = lane / P, cc = lane % P;
+                float acc = 0.f;
+                if (s < cnt) {
+                    const uint32_t* prow = pcur + s * stride;
+                    for (int wd = (k + 1) / 4 + cc; wd < nw; wd += P) {
+                        const uint32_t dw = prow[wd];
+#pragma unroll
+                        for (int bb = 0; bb < 4; ++bb) {
+                            const int j = 4 * wd + bb;
+                            if (j > k && j < n) acc = fmaf(cs * rk[j - k], (float)((dw >> (8 * bb)) & 0xffu), acc);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int m = 1; m < P; m <<= 1) acc += shfl_xor_f(acc, m);
+                const float b = zf[k] - (2.f * acc - (float)(P - 1) * rsum);
+                const float rkk = cs * rk[0];
+                uint64_t key[1] = {~0ull};
+                if (s < cnt) {
+                    const float ee = fmaf(-rkk, (float)(2 * cc - (P - 1)), b);
+                    const float pdc = fmaf(ee, ee, scur[s]);
+                    if (pdc < r2r) key[0] = ((uint64_t)__float_as_uint(pdc) << 32) | (uint32_t)lane;
+                }
+                bitonic_sort<1>(key, lane);
+                const int nvalid = __popcll(__ballot(key[0] != ~0ull));
+                if (lane == 0) atomicAdd(&sc[SC_WEXP], cnt);
+                if (nvalid == 0) {
+                    if (lane == 0) st[0] = 0;
+                } else {
+                    const int keep = Kt < nvalid ? Kt : nvalid;
+                    if (lane < keep) {
+                        snxt[lane] = __uint_as_float((uint32_t)(key[0] >> 32));
+                        sel[lane] = (int)(uint32_t)key[0];
+                    }
+                    wave_sync();
+                    const int w0 = k / 4;
+                    for (int i = 0; i < keep; ++i) {
+                        const int m = sel[i];
+                        const uint32_t* src = pcur + (m / P) * stride;
+                        uint32_t* dst = pnxt + i * stride;
+                        for (int wd = w0 + lane; wd < nw; wd += WAVE) {
+                            uint32_t v = src[wd];
+                            if (wd == w0) {
+                                const int sh = 8 * (k & 3);
+                                v = (v & ~(0xffu << sh)) | ((uint32_t)(m % P) << sh);
+                            }
+                            dst[wd] = v;
+                        }
+                    }
+                    if (lane == 0) {
+                        st[2] = keep;
+                        st[3] = buf ^ 1;
+                        st[1] = depth + 1;
+                        if (k == 0) {  // leaves: offer the best survivor
+                            cpd[1 + w] = snxt[0];
+                            cinfo[1 + w] = buf ^ 1;
+                            cok[1 + w] = 1;
+                            st[0] = 0;
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---- D: merge offers, shrink the radius once
+        if (threadIdx.x == 0) {
+            int best = -1;
+            for (int q = 0; q <= W; ++q) {
+                if (!cok[q]) continue;
+                if (best < 0 || cpd[q] < cpd[best]) best = q;
+            }
+            if (best >= 0 && cpd[best] < *sc_r2) {
+                *sc_r2 = cpd[best];
+                sc[SC_FOUND] = 1;
+                if (best == 0) {
+                    for (int i = 0; i < nw; ++i) bpath[i] = mpath[i];
+                    bpath[0] = (bpath[0] & ~0xffu) | (uint32_t)cinfo[0];
+                } else {
+                    const int w = best - 1;
+                    const uint32_t* src = wpath + ((size_t)w * 2 + cinfo[best]) * Kw * stride;
+                    for (int i = 0; i < nw; ++i) bpath[i] = src[i];
+                }
+            }
+            for (int q = 0; q <= W; ++q) cok[q] = 0;
+            uint32_t lo = (uint32_t)sc[SC_EXP_LO];
+            const uint32_t add = (uint32_t)sc[SC_WEXP];
+            const uint32_t nlo = lo + add;
+            if (nlo < lo) sc[SC_EXP_HI] += 1;
+            sc[SC_EXP_LO] = (int)nlo;
+            sc[SC_WEXP] = 0;
+            sc[SC_ROUNDS] += 1;
+        }
+        __syncthreads();
+    }
+
+    __syncthreads();
+    const int found = sc[SC_FOUND];
+    if (threadIdx.x == 0) {
+        uint32_t fl = (uint32_t)sc[SC_FLAGS];
+        fl |= found ? MIMO_FLAG_FOUND : MIMO_FLAG_EMPTY_SPHERE;
+        if (a.flags) a.flags[frame] = fl;
+        if (a.pd) a.pd[frame] = found ? *sc_r2 : INFINITY;
+        if (a.counters) {
+            const int64_t e = ((int64_t)(uint32_t)sc[SC_EXP_HI] << 32) | (uint32_t)sc[SC_EXP_LO];
+            int64_t* c = a.counters + (size_t)frame * 4;
+            c[0] = e;
+            c[1] = e * P;
+            c[2] = sc[SC_ROUNDS];
+            c[3] = sc[SC_STALE];
+        }
+    }
+    if (a.sym) {
+        for (int m = threadIdx.x; m < n / 2; m += blockDim.x) {
+            int v = 0;
+            if (found) {
+                const int ire = (bpath[(2 * m) >> 2] >> (8 * ((2 * m) & 3))) & 0xff;
+                const int iim = (bpath[(2 * m + 1) >> 2] >> (8 * ((2 * m + 1) & 3))) & 0xff;
+                v = ire * P + iim;
+            }
+            a.sym[(size_t)frame * (n / 2) + m] = v;
+        }
+    }
+}
+
+template <int P>
+static int32_t launch_hybrid(const HybArgs& a, int B, hipStream_t st)
+{
+    const HybLayout Lo(a.n, a.W, a.Kw, P);
+    if (Lo.total > 160 * 1024)
+        return fail(MIMO_ERR_UNSUPPORTED, "sd_hybrid_detect: %zu bytes of LDS needed (n_workers * k_worker too large)",
+                    Lo.total);
+    if (Lo.total > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)hybrid_kernel<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)Lo.total);
+        if (e != hipSuccess) return fail(MIMO_ERR_HIP, "sd_hybrid_detect: LDS attribute: %s", hipGetErrorString(e));
+    }
+    const int threads = WAVE * (1 + a.W);
+    hipLaunchKernelGGL(hybrid_kernel<P>, dim3(B), dim3(threads), Lo.total, st, a);
+    return check_launch("sd_hybrid_detect");
+}
+
+}  // namespace mimo
+
+extern "C" int32_t sd_hybrid_detect(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam,
+                                    const float* radius2, int32_t n_workers, int32_t k_worker,
+                                    const int32_t* k_sched, int32_t k_sched_stride, int32_t master_off,
+                                    int64_t node_budget, int32_t* sym, float* pd, uint32_t* flags,
+                                    int64_t* counters, void* stream)
+{
+    using namespace mimo;
+    if (B < 0) return fail(MIMO_ERR_INVALID_ARG, "sd_hybrid_detect: B < 0");
+    if (pam != 2 && pam != 4 && pam != 8) return fail(MIMO_ERR_INVALID_ARG, "sd_hybrid_detect: pam must be 2, 4 or 8");
+    if (n_tx < 1) return fail(MIMO_ERR_INVALID_ARG, "sd_hybrid_detect: n_tx < 1");
+    if (n_tx > MIMO_MAX_TX) return fail(MIMO_ERR_UNSUPPORTED, "sd_hybrid_detect: n_tx > %d", MIMO_MAX_TX);
+    if (n_workers < 0 || n_workers > MIMO_MAX_WORKERS)
+        return fail(MIMO_ERR_INVALID_ARG, "sd_hybrid_detect: 0 <= n_workers <= %d", MIMO_MAX_WORKERS);
+    if (k_worker < 1 || k_worker * pam > MIMO_HYB_MAX_CAND)
+        return fail(MIMO_ERR_INVALID_ARG, "sd_hybrid_detect: need k_worker >= 1 and k_worker * pam <= %d",
+                    MIMO_HYB_MAX_CAND);
+    if (master_off && n_workers < 1) return fail(MIMO_ERR_INVALID_ARG, "sd_hybrid_detect: master_off needs a worker");
+    if (node_budget < 0) return fail(MIMO_ERR_INVALID_ARG, "sd_hybrid_detect: node_budget < 0");
+    const int n = 2 * n_tx;
+    if (k_sched && k_sched_stride != 0 && k_sched_stride != n)
+        return fail(MIMO_ERR_INVALID_ARG, "sd_hybrid_detect: k_sched_stride must be 0 or n = %d", n);
+    if (B == 0) return MIMO_OK;
+    if (!R || !z || !sym || !pd || !flags) return fail(MIMO_ERR_INVALID_ARG, "sd_hybrid_detect: null pointer");
+    HybArgs a{R, z, n, n_workers, k_worker, k_sched, k_sched_stride, radius2, master_off, node_budget,
+              sym, pd, flags, counters};
+    hipStream_t st = (hipStream_t)stream;
+    switch (pam) {
+    case 2: return launch_hybrid<2>(a, B, st);
+    case 4: return launch_hybrid<4>(a, B, st);
+    default: return launch_hybrid<8>(a, B, st);
+    }
+}
