@@ -18,6 +18,8 @@ the GPU path read exactly these complex64 values.
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass
 
 import numpy as np
@@ -81,20 +83,28 @@ def gen_frames(n_rx: int, n_tx: int, qam: int, snr_db: float, n_frames: int,
     H = np.empty((n_frames, n_rx, n_tx), np.complex64)
     y = np.empty((n_frames, n_rx), np.complex64)
     s_idx = np.empty((n_frames, n_tx), np.int32)
-    for c0 in range(0, n_frames, chunk):
+
+    def one(c0):
         c1 = min(n_frames, c0 + chunk)
-        b = chunk
         g = _rng(seed, n_rx, n_tx, qam, snr_idx, c0 // chunk)
-        hr = g.standard_normal((b, n_rx, n_tx, 2), dtype=np.float32)
+        hr = g.standard_normal((chunk, n_rx, n_tx, 2), dtype=np.float32)
         Hc = (hr[..., 0] + 1j * hr[..., 1]).astype(np.complex64) * np.float32(math.sqrt(0.5))
-        si = g.integers(0, qam, size=(b, n_tx), dtype=np.int32)
-        nr = g.standard_normal((b, n_rx, 2))
+        si = g.integers(0, qam, size=(chunk, n_tx), dtype=np.int32)
+        nr = g.standard_normal((chunk, n_rx, 2))
         noise = (nr[..., 0] + 1j * nr[..., 1]) * math.sqrt(sigma2 / 2.0)
         s = _symbols(si, qam)
-        yc = np.einsum("bij,bj->bi", Hc.astype(np.complex128), s) + noise
+        yc = np.matmul(Hc.astype(np.complex128), s[:, :, None])[:, :, 0] + noise
         H[c0:c1] = Hc[: c1 - c0]
         y[c0:c1] = yc[: c1 - c0].astype(np.complex64)
         s_idx[c0:c1] = si[: c1 - c0]
+
+    starts = list(range(0, n_frames, chunk))
+    if len(starts) > 1:
+        with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1, len(starts))) as ex:
+            list(ex.map(one, starts))
+    else:
+        for c0 in starts:
+            one(c0)
     return Frames(H, y, s_idx, sigma2, n_rx, n_tx, qam, float(snr_db))
 
 
@@ -157,7 +167,7 @@ def gen_uneven(n_frames: int, seed: int = 0, antennas=(10, 16, 32, 64),
             si = gg.integers(0, qv, size=(b, nv), dtype=np.int32)
             nr = gg.standard_normal((b, nv, 2))
             noise = (nr[..., 0] + 1j * nr[..., 1]) * np.sqrt(sigma2[sel] / 2.0)[:, None]
-            yc = np.einsum("bij,bj->bi", Hc.astype(np.complex128), _symbols(si, int(qv))) + noise
+            yc = np.matmul(Hc.astype(np.complex128), _symbols(si, int(qv))[:, :, None])[:, :, 0] + noise
             for r, f in enumerate(sel):
                 H_flat[h_off[f]: h_off[f] + nv * nv] = Hc[r].reshape(-1)
                 y_flat[y_off[f]: y_off[f] + nv] = yc[r].astype(np.complex64)

@@ -1,0 +1,226 @@
+"""Learned per-level survivor counts for K-best / the hybrid's workers.
+
+The paper's hybrid lets workers keep extra nodes whose distance is "very
+close" to the selected ones (Sec. VI) without fixing a rule.  Here a small
+MLP (4 -> 128 -> 128 -> 1, ReLU) predicts, for every level of a frame, a high
+quantile of log2 of the rank that the maximum-likelihood path's prefix takes
+among that level's sorted candidates; the detector then keeps
+K_t = clamp(ceil(2^(prediction + margin)), k_min, k_max) survivors at level t.
+
+Everything here drives the library's kernels (no arithmetic of its own):
+  * training states: frames -> QR -> K-best warm radius -> exact Best-FS SD
+    (the hybrid kernel with no workers) -> forced-path K-best rank labels and
+    per-level features;
+  * training: pinball loss (quantile tau) and Adam, both on the GPU;
+  * inference: features -> MLP -> schedule.
+Weights are stored as a flat float32 checkpoint with a JSON header.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import struct
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import mimo
+from .framegen import gen_frames
+
+MAGIC = b"MIMOMLP1"
+HERE = os.path.dirname(os.path.abspath(__file__))
+WEIGHTS_DIR = os.path.join(HERE, "weights")
+
+
+# ------------------------------------------------------------ checkpoint
+def init_weights(seed: int = 0) -> np.ndarray:
+    """He-normal initialisation of the flat parameter vector."""
+    rng = np.random.default_rng(seed)
+    H, I = mimo.MLP_HIDDEN, mimo.MLP_IN
+    parts = [rng.normal(0, math.sqrt(2.0 / I), H * I), np.zeros(H),
+             rng.normal(0, math.sqrt(2.0 / H), H * H), np.zeros(H),
+             rng.normal(0, math.sqrt(1.0 / H), H), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def save_weights(path: str, w, meta: dict, m=None, v=None, step: int = 0):
+    """Checkpoint: MAGIC, u32 header length, JSON header, float32 w [, m, v]."""
+    w = np.asarray(w.detach().cpu() if isinstance(w, torch.Tensor) else w, np.float32)
+    head = dict(meta)
+    head.update(nparam=int(w.size), step=int(step), has_moments=m is not None)
+    hb = json.dumps(head, sort_keys=True).encode()
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "wb") as fh:
+        fh.write(MAGIC)
+        fh.write(struct.pack("<I", len(hb)))
+        fh.write(hb)
+        fh.write(w.tobytes())
+        if m is not None:
+            for a in (m, v):
+                a = np.asarray(a.detach().cpu() if isinstance(a, torch.Tensor) else a, np.float32)
+                fh.write(a.tobytes())
+    os.replace(tmp, path)
+
+
+def load_weights(path: str, with_moments: bool = False):
+    with open(path, "rb") as fh:
+        if fh.read(8) != MAGIC:
+            raise ValueError(f"{path}: not a weights checkpoint")
+        (hl,) = struct.unpack("<I", fh.read(4))
+        meta = json.loads(fh.read(hl))
+        npar = meta["nparam"]
+        w = np.frombuffer(fh.read(4 * npar), np.float32).copy()
+        if with_moments and meta.get("has_moments"):
+            m = np.frombuffer(fh.read(4 * npar), np.float32).copy()
+            v = np.frombuffer(fh.read(4 * npar), np.float32).copy()
+            return torch.from_numpy(w), meta, torch.from_numpy(m), torch.from_numpy(v)
+    return torch.from_numpy(w), meta
+
+
+# ------------------------------------------------------------ states and labels
+def training_states(n_tx: int, qam: int, snrs, frames_per_snr: int, seed: int, k_warm: int = 16,
+                    k_label: int = 64, sd_budget: int = 200000, chunk: int = 2048, log=print):
+    """Per-level (features, log2 rank) pairs from frames whose exact SD run
+    certified the ML solution.  Returns X [S, 4] f32, y [S] f32 (GPU) and stats."""
+    P = math.isqrt(qam)
+    n = 2 * n_tx
+    Xs, ys = [], []
+    stats = dict(frames=0, certified=0, sd_rounds=0)
+    for si, snr in enumerate(snrs):
+        for c0 in range(0, frames_per_snr, chunk):
+            b = min(chunk, frames_per_snr - c0)
+            f = gen_frames(n_tx, n_tx, qam, snr, c0 + b, seed=seed, snr_idx=si)
+            H = torch.from_numpy(f.H[c0:]).cuda()
+            y = torch.from_numpy(f.y[c0:]).cuda()
+            R, z = mimo.qr_preprocess(H, y)
+            _, pdw, _ = mimo.kbest_detect(R, z, n_tx, P, k_warm)
+            r2 = (pdw * (1.0 + 1e-4)).contiguous()
+            sym, pd, flags, ctr = mimo.sd_hybrid_detect(R, z, n_tx, P, 0, 1, radius2=r2, node_budget=sd_budget,
+                                                        want_counters=True)
+            ok = ((flags & mimo.FLAG_CERTIFIED) != 0) & ((flags & mimo.FLAG_FOUND) != 0)
+            rank = mimo.kbest_rank_labels(R, z, n_tx, P, k_label, sym)
+            s2 = torch.full((b,), f.sigma2, device="cuda", dtype=torch.float32)
+            feat = mimo.prune_features(R, z, s2, n_tx, P)
+            sel = ok.nonzero().squeeze(1)
+            Xs.append(feat[sel].reshape(-1, 4))
+            ys.append(torch.log2(rank[sel].clamp_min(1).float()).reshape(-1))
+            stats["frames"] += b
+            stats["certified"] += int(ok.sum())
+            stats["sd_rounds"] += int(ctr[:, 2].sum())
+        log(f"  states: {snr} dB done, {stats['certified']}/{stats['frames']} certified")
+    return torch.cat(Xs).contiguous(), torch.cat(ys).contiguous(), stats
+
+
+def train(X: torch.Tensor, y: torch.Tensor, steps: int = 3000, batch: int = 4096, lr: float = 2e-3,
+          tau: float = 0.95, seed: int = 0, log=print, w0=None):
+    """Adam on the mean pinball loss with the library's backward kernels."""
+    S = X.shape[0]
+    w = (torch.from_numpy(init_weights(seed)) if w0 is None else w0.clone()).cuda()
+    m = torch.zeros_like(w)
+    v = torch.zeros_like(w)
+    ws = torch.empty(mimo.mlp_workspace_bytes(batch), device="cuda", dtype=torch.uint8)
+    grad = torch.empty_like(w)
+    loss = torch.empty(1, device="cuda")
+    g = torch.Generator(device="cpu")
+    g.manual_seed(seed)
+    hist = []
+    for t in range(1, steps + 1):
+        idx = torch.randint(0, S, (batch,), generator=g).cuda()
+        xb = X[idx].contiguous()
+        yb = y[idx].contiguous()
+        # cosine learning-rate decay
+        lr_t = lr * 0.5 * (1.0 + math.cos(math.pi * (t - 1) / steps))
+        mimo.mlp_loss_grad(w, xb, yb, tau, ws=ws, grad=grad, loss=loss)
+        mimo.mlp_adam_step(w, m, v, grad, t, lr_t)
+        if t % max(1, steps // 10) == 0 or t == 1:
+            hist.append((t, float(loss.item())))
+            log(f"  step {t}: pinball loss {hist[-1][1]:.4f}")
+    return w, m, v, hist
+
+
+# ------------------------------------------------------------ inference
+def schedule(w, R, z, sigma2, n_tx: int, pam: int, margin: float, k_min: int, k_max: int, flags=None):
+    """Per-frame, per-level survivor counts [B, n] int32."""
+    B = z.shape[0]
+    n = 2 * n_tx
+    feat = mimo.prune_features(R, z, sigma2, n_tx, pam)
+    ks = mimo.mlp_schedule(w, feat.view(B * n, 4), n, margin, k_min, k_max, flags=flags)
+    return ks.view(B, n)
+
+
+def calibrate_margin(w, n_tx, qam, snrs, frames, seed, k_min, k_max, plain_K, margins, log=print):
+    """Smallest margin whose learned K-best makes no more symbol errors than
+    plain K-best (K = plain_K) on the calibration frames, per SNR."""
+    P = math.isqrt(qam)
+    data = []
+    for si, snr in enumerate(snrs):
+        f = gen_frames(n_tx, n_tx, qam, snr, frames, seed=seed, snr_idx=si)
+        H = torch.from_numpy(f.H).cuda()
+        y = torch.from_numpy(f.y).cuda()
+        s = torch.from_numpy(f.s_idx).cuda()
+        R, z = mimo.qr_preprocess(H, y)
+        s2 = torch.full((frames,), f.sigma2, device="cuda", dtype=torch.float32)
+        sp, _, _ = mimo.kbest_detect(R, z, n_tx, P, plain_K)
+        data.append((R, z, s, s2, int((sp != s).sum())))
+    result = None
+    for mg in margins:
+        errs, kmean = [], []
+        for R, z, s, s2, pe in data:
+            ks = schedule(w, R, z, s2, n_tx, P, mg, k_min, k_max)
+            sl, _, _ = mimo.kbest_detect(R, z, n_tx, P, k_max, k_sched=ks)
+            errs.append((int((sl != s).sum()), pe))
+            kmean.append(float(ks.float().mean()))
+        log(f"  margin {mg:.2f}: learned/plain symbol errors {errs}, mean K_t {np.mean(kmean):.2f}")
+        if all(e <= p for e, p in errs):
+            result = (mg, errs, float(np.mean(kmean)))
+            break
+    return result
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="train the learned survivor-count MLP on the GPU")
+    ap.add_argument("--n-tx", type=int, default=100)
+    ap.add_argument("--qam", type=int, default=64)
+    ap.add_argument("--snrs", default="20,22,24,26,28")
+    ap.add_argument("--frames", type=int, default=1000, help="training frames per SNR")
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--tau", type=float, default=0.95)
+    ap.add_argument("--k-min", type=int, default=1)
+    ap.add_argument("--k-max", type=int, default=32)
+    ap.add_argument("--k-label", type=int, default=64)
+    ap.add_argument("--plain-K", type=int, default=16)
+    ap.add_argument("--calib-frames", type=int, default=2000)
+    ap.add_argument("--seed", type=int, default=777)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    mimo.load()
+    snrs = [float(s) for s in a.snrs.split(",")]
+    t0 = time.time()
+    X, y, st = training_states(a.n_tx, a.qam, snrs, a.frames, a.seed, k_label=a.k_label)
+    print(f"states: {X.shape[0]} from {st['certified']} certified frames ({time.time() - t0:.1f} s)")
+    w, m, v, hist = train(X, y, steps=a.steps, batch=a.batch, lr=a.lr, tau=a.tau, seed=a.seed)
+    cal = calibrate_margin(w, a.n_tx, a.qam, snrs, a.calib_frames, a.seed + 1, a.k_min, a.k_max, a.plain_K,
+                           margins=[0.0, 0.5, 1.0, 1.5, 2.0, 2.5, 3.0, 4.0, 5.0])
+    tag = f"{a.n_tx}x{a.n_tx}_{a.qam}qam"
+    meta = dict(n_tx=a.n_tx, qam=a.qam, snrs=snrs, frames=a.frames, states=int(X.shape[0]), tau=a.tau,
+                k_min=a.k_min, k_max=a.k_max, k_label=a.k_label, steps=a.steps, lr=a.lr, seed=a.seed,
+                loss_history=hist, plain_K=a.plain_K)
+    if cal:
+        meta["margin"] = cal[0]
+        meta[f"margin_{tag}"] = cal[0]
+        meta["calibration"] = dict(symbol_errors_learned_vs_plain=cal[1], mean_k=cal[2])
+    out = a.out or os.path.join(WEIGHTS_DIR, f"prune_mlp_{tag}.bin")
+    save_weights(out, w, meta, m, v, step=a.steps)
+    print(json.dumps({k: meta[k] for k in meta if k != "loss_history"}))
+    print(f"saved {out} ({time.time() - t0:.1f} s total)")
+
+
+if __name__ == "__main__":
+    main()
