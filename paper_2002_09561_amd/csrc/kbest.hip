@@ -2,18 +2,21 @@
 // per frame.
 //
 // Per level k (n-1 down to 0):
-//   * row k of R (scaled by the PAM spacing c) is staged in LDS;
+//   * row k of R (scaled by the PAM spacing c, zero at and below the
+//     diagonal) is staged in LDS;
 //   * every survivor's cancellation centre b = z_k - sum_{j>k} R_kj x_j is a
-//     dot product of that row with the survivor's path (PAM indices, one
-//     byte per level, in LDS), split over 64/KCAP lanes per survivor; the
-//     amplitude 2i-(P-1) is folded as 2 * sum(R i) - (P-1) * sum(R);
+//     dot product of that row with the survivor's path, held in LDS as packed
+//     fp16 amplitudes (exact small integers: one mixed-precision FMA per term,
+//     FP32 accumulation), split over 64/KCAP lanes per survivor;
 //   * each child c of survivor s gets pd' = pd_s + (b - R_kk a_c)^2 (FP32
 //     FMA) -- the incremental evaluation of Eq. (inc);
-//   * children outside the radius are dropped and the rest are sorted in the
-//     wave by the 64-bit key (pd bits, s * P + c), which orders them by
-//     (pd, parent rank, child index) because survivors stay sorted;
-//   * the first K_t keys become the next survivors; their paths are copied
-//     from the parents with the new symbol written at level k.
+//   * children outside the radius are dropped; the K_t smallest keys
+//     (pd bits, s * P + c) -- i.e. (pd, parent rank, child index), since the
+//     survivors are kept sorted -- are found by a bitwise binary search on
+//     the pd bits with ballot counts, compacted, and put in order by rank
+//     counting among the K_t kept keys only;
+//   * the survivors' paths are copied from their parents with the new
+//     amplitude written at level k.
 #include "common.hpp"
 
 namespace mimo {
@@ -42,17 +45,126 @@ struct KbestShape {
     static constexpr int SPL = KCAP >= WAVE ? KCAP / WAVE : 1; // survivors per lane
 };
 
-inline int kb_row_words(int n) { return (n + 3) / 4 + 1; }  // odd-ish stride against bank conflicts
+// words of a path: two fp16 amplitudes per 32-bit word; odd stride against bank conflicts
+__host__ __device__ inline int kb_words(int n) { return (n + 1) / 2; }
+__host__ __device__ inline int kb_stride(int n) { return kb_words(n) | 1; }
 
 template <int P, int E>
 __host__ __device__ inline size_t kbest_lds_bytes(int n)
 {
     using S = KbestShape<P, E>;
-    const int nw = (n + 3) / 4, stride = nw + 1;
-    return sizeof(uint32_t) * 2 * S::KCAP * stride  // paths
-           + sizeof(float) * 2 * S::KCAP           // survivor pd
-           + sizeof(float) * nw * 4                // staged R row
-           + sizeof(int32_t) * S::KCAP;            // selected candidate ids
+    return sizeof(uint32_t) * 2 * S::KCAP * kb_stride(n)  // paths
+           + sizeof(float) * 2 * S::KCAP                   // survivor pd
+           + sizeof(float) * (2 * kb_words(n) + 4)         // staged R row
+           + sizeof(int32_t) * S::KCAP                     // selected candidate ids
+           + sizeof(uint64_t) * S::KCAP;                   // compacted keys
+}
+
+__device__ inline float half_lo(uint32_t d) { return (float)__builtin_bit_cast(_Float16, (unsigned short)(d & 0xffffu)); }
+__device__ inline float half_hi(uint32_t d) { return (float)__builtin_bit_cast(_Float16, (unsigned short)(d >> 16)); }
+__device__ inline uint32_t half_bits(float a) { return (uint32_t)__builtin_bit_cast(unsigned short, (_Float16)a); }
+
+__device__ inline void kb_wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Selection of the `keep` smallest keys (pd bits kh, candidate index
+// e * 64 + lane) of one level, written in sorted order to sn (pd) and sel
+// (candidate index).  Label mode (fm >= 0): the forced candidate's rank among
+// all candidates is returned and the candidate is kept in the last slot if
+// it would be dropped.  Returns the number kept; *fpos_out receives the
+// forced candidate's 0-based rank (-1 when absent).
+template <int E>
+__device__ inline int kb_select(const uint32_t (&kh)[E], int nvalid, int Kt, int fm, int lane, float* sn,
+                                int32_t* sel, uint64_t* skey, int* fpos_out)
+{
+    int keep = Kt < nvalid ? Kt : nvalid;
+    int fpos = -1;
+    uint64_t fkey = 0;
+    bool add_forced = false;
+    if (fm >= 0) {
+        const int fe = fm / WAVE, fl = fm % WAVE;
+        uint32_t fh = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (e == fe) fh = __shfl(kh[e], fl, WAVE);
+        fkey = ((uint64_t)fh << 32) | (uint32_t)fm;
+        int below = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint64_t key = ((uint64_t)kh[e] << 32) | (uint32_t)(e * WAVE + lane);
+            below += __popcll(__ballot(kh[e] != ~0u && key < fkey));
+        }
+        fpos = (fh != ~0u) ? below : -1;
+        if (fpos >= keep) {  // select keep-1, then add the forced one
+            --keep;
+            add_forced = true;
+        }
+    }
+    bool take[E];
+    if (keep == nvalid) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) take[e] = kh[e] != ~0u;
+    } else {
+        // bitwise binary search for the keep-th smallest pd bits
+        uint32_t v = 0;
+        for (int bit = 30; bit >= 0; --bit) {
+            const uint32_t cand = v | (1u << bit);
+            int c = 0;
+#pragma unroll
+            for (int e = 0; e < E; ++e) c += __popcll(__ballot(kh[e] < cand));
+            if (c < keep) v = cand;
+        }
+        int clt = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            take[e] = kh[e] < v;
+            clt += __popcll(__ballot(take[e]));
+        }
+        // ties on the pd bits: lowest candidate indices first
+        for (int need = keep - clt; need > 0; --need) {
+            uint32_t mloc = ~0u;
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                if (kh[e] == v && !take[e]) mloc = min(mloc, (uint32_t)(e * WAVE + lane));
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) mloc = min(mloc, (uint32_t)__shfl_xor(mloc, m, WAVE));
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                if ((uint32_t)(e * WAVE + lane) == mloc) take[e] = true;
+        }
+    }
+    if (add_forced) {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if ((uint32_t)(e * WAVE + lane) == (uint32_t)fm) take[e] = true;
+        ++keep;
+    }
+    // compaction in candidate order
+    int base = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint64_t bal = __ballot(take[e]);
+        if (take[e]) {
+            const int slot = base + (int)__popcll(bal & ((1ull << lane) - 1ull));
+            skey[slot] = ((uint64_t)kh[e] << 32) | (uint32_t)(e * WAVE + lane);
+        }
+        base += (int)__popcll(bal);
+    }
+    kb_wave_sync();
+    // order the kept keys by rank counting; survivor slot = rank
+    for (int i = lane; i < keep; i += WAVE) {
+        const uint64_t ki = skey[i];
+        int r = 0;
+        for (int j = 0; j < keep; ++j) r += skey[j] < ki;
+        sn[r] = __uint_as_float((uint32_t)(ki >> 32));
+        sel[r] = (int32_t)(uint32_t)ki;
+    }
+    *fpos_out = fpos;
+    return keep;
 }
 
 // K-best of one frame by one wavefront; lds as sized by kbest_lds_bytes.
@@ -63,11 +175,12 @@ __device__ void kbest_frame(const KbestArgs& a, int frame, unsigned char* lds)
     constexpr int KCAP = S::KCAP, L = S::L, SPL = S::SPL;
     const int lane = threadIdx.x & 63;
     const int n = a.n;
-    const int nw = (n + 3) / 4, stride = nw + 1;
+    const int nw = kb_words(n), stride = kb_stride(n);
     uint32_t* path = reinterpret_cast<uint32_t*>(lds);
     float* spd = reinterpret_cast<float*>(path + 2 * KCAP * stride);
     float* rrow = spd + 2 * KCAP;
-    int32_t* sel = reinterpret_cast<int32_t*>(rrow + nw * 4);
+    int32_t* sel = reinterpret_cast<int32_t*>(rrow + 2 * nw + 4);
+    uint64_t* skey = reinterpret_cast<uint64_t*>(sel + KCAP + (KCAP & 1));
 
     const float* Rf = a.R + (size_t)frame * r_packed_size(n);
     const float* zf = a.z + (size_t)frame * n;
@@ -76,11 +189,26 @@ __device__ void kbest_frame(const KbestArgs& a, int frame, unsigned char* lds)
     const int32_t* ks = a.k_sched ? a.k_sched + (size_t)frame * a.k_sched_stride : nullptr;
     const int32_t* fsym = a.force_sym ? a.force_sym + (size_t)frame * (n / 2) : nullptr;
 
+    // zero paths: a half-word not yet written is multiplied by a zero of the
+    // staged row and must be a finite number
+    for (int i = lane; i < 2 * KCAP * stride; i += WAVE) path[i] = 0u;
     if (lane == 0) spd[0] = 0.f;
     int cnt = 1, fs = 0;
     int64_t expanded = 0;
     uint32_t flags = 0;
     __syncthreads();
+
+    // software pipeline: row k-1 of R is loaded while level k is processed
+    constexpr int RPL = 4;  // row entries per lane (n <= 256)
+    float rnext[RPL];
+    float rkk_next, zk_next;
+    {
+        const float* rk = Rf + r_row_off(n, n - 1);
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) rnext[i] = (lane + WAVE * i < 1) ? rk[lane + WAVE * i] : 0.f;
+        rkk_next = rk[0];
+        zk_next = zf[n - 1];
+    }
 
     for (int k = n - 1; k >= 0; --k) {
         const int cur = (n - 1 - k) & 1, nxt = cur ^ 1;
@@ -88,19 +216,27 @@ __device__ void kbest_frame(const KbestArgs& a, int frame, unsigned char* lds)
         uint32_t* pn = path + nxt * KCAP * stride;
         float* sc = spd + cur * KCAP;
         float* sn = spd + nxt * KCAP;
-        // stage row k: rrow[j] = c R_kj, j in [k, n)
-        const float* rk = Rf + r_row_off(n, k);
-        float rsum = 0.f;
-        for (int t = lane; t < n - k; t += WAVE) {
-            const float v = cs * rk[t];
-            rrow[k + t] = v;
-            if (t > 0) rsum += v;
+        // stage row k: rrow[j] = c R_kj for j > k, rrow[k] = 0
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int t = lane + WAVE * i;
+            if (t < n - k) rrow[k + t] = t == 0 ? 0.f : cs * rnext[i];
         }
-        rsum = wave_sum(rsum);
-        __syncthreads();
-        const float rkk = rrow[k];
-        const float zk = zf[k];
-        // cancellation centres
+        const float rkk = cs * rkk_next;
+        const float zk = zk_next;
+        if (k > 0) {  // issue the loads of row k-1
+            const float* rk = Rf + r_row_off(n, k - 1);
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int t = lane + WAVE * i;
+                rnext[i] = t < n - k + 1 ? rk[t] : 0.f;
+            }
+            rkk_next = rk[0];
+            zk_next = zf[k - 1];
+        }
+        kb_wave_sync();
+        // cancellation centres: words from the one holding level k+1
+        const int w0 = (k + 1) >> 1;
         float bu[SPL];
 #pragma unroll
         for (int u = 0; u < SPL; ++u) {
@@ -109,21 +245,19 @@ __device__ void kbest_frame(const KbestArgs& a, int frame, unsigned char* lds)
             float acc = 0.f;
             if (s < cnt) {
                 const uint32_t* prow = pc + s * stride;
-                for (int wd = (k + 1) / 4 + q; wd < nw; wd += L) {
+                for (int wd = w0 + q; wd < nw; wd += L) {
                     const uint32_t d = prow[wd];
-#pragma unroll
-                    for (int bb = 0; bb < 4; ++bb) {
-                        const int j = 4 * wd + bb;
-                        if (j > k && j < n) acc = fmaf(rrow[j], (float)((d >> (8 * bb)) & 0xffu), acc);
-                    }
+                    const float2 rr = *reinterpret_cast<const float2*>(rrow + 2 * wd);
+                    acc = fmaf(rr.x, half_lo(d), acc);
+                    acc = fmaf(rr.y, half_hi(d), acc);
                 }
             }
 #pragma unroll
             for (int m = 1; m < L; m <<= 1) acc += shfl_xor_f(acc, m);
-            bu[u] = zk - (2.f * acc - (float)(P - 1) * rsum);
+            bu[u] = zk - acc;
         }
-        // children and keys
-        uint64_t key[E];
+        // children: key = (pd bits, candidate index s * P + c)
+        uint32_t kh[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int m = e * WAVE + lane;
@@ -131,80 +265,59 @@ __device__ void kbest_frame(const KbestArgs& a, int frame, unsigned char* lds)
             const int u = (KCAP >= WAVE) ? (e / P) : 0;
             const int src = (KCAP >= WAVE) ? (s % WAVE) : (s * L);
             const float b = shfl_f(bu[u], src);
-            key[e] = ~0ull;
+            kh[e] = ~0u;
             if (s < cnt) {
                 const float ee = fmaf(-rkk, (float)(2 * c - (P - 1)), b);
                 const float pdc = fmaf(ee, ee, sc[s]);
-                if (pdc < r2) key[e] = ((uint64_t)__float_as_uint(pdc) << 32) | (uint32_t)m;
+                if (pdc < r2) kh[e] = __float_as_uint(pdc);
             }
         }
         expanded += cnt;
-        bitonic_sort<E>(key, lane);
         int nvalid = 0;
 #pragma unroll
-        for (int e = 0; e < E; ++e) nvalid += __popcll(__ballot(key[e] != ~0ull));
+        for (int e = 0; e < E; ++e) nvalid += __popcll(__ballot(kh[e] != ~0u));
         if (nvalid == 0) {
             flags |= MIMO_FLAG_EMPTY_SPHERE;
             cnt = 0;
             break;
         }
         int Kt = ks ? ks[k] : a.K;
-        if (Kt > a.K) Kt = a.K;
-        if (Kt < 1) Kt = 1;
-        const int keep = Kt < nvalid ? Kt : nvalid;
+        Kt = Kt > a.K ? a.K : (Kt < 1 ? 1 : Kt);
+
+        int fm = -1;
         if (fsym) {
-            // label mode: rank of the forced prefix; keep it in the last slot if needed
             const int sy = fsym[k >> 1];
-            const int fc = (k & 1) ? (sy % P) : (sy / P);
-            const uint32_t fm = (uint32_t)(fs * P + fc);
-            int pos = -1;
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const uint64_t bal = __ballot(key[e] != ~0ull && (uint32_t)key[e] == fm);
-                if (bal && pos < 0) pos = e * WAVE + (__ffsll((unsigned long long)bal) - 1);
-            }
-            if (lane == 0) a.rank[(size_t)frame * n + k] = pos + 1;
-            if (pos >= keep) {
-                const int pe = pos / WAVE, pl = pos % WAVE;
-                uint64_t fk = 0;
-#pragma unroll
-                for (int e = 0; e < E; ++e)
-                    if (e == pe) fk = shfl_u64(key[e], pl);
-                const int te = (keep - 1) / WAVE, tl = (keep - 1) % WAVE;
-#pragma unroll
-                for (int e = 0; e < E; ++e)
-                    if (e == te && lane == tl) key[e] = fk;
-                pos = keep - 1;
-            }
-            fs = pos;
+            fm = fs * P + ((k & 1) ? (sy % P) : (sy / P));
+            if (fs < 0) fm = -1;
         }
-        // new survivors: sorted positions 0 .. keep-1
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int i = e * WAVE + lane;
-            if (i < keep) {
-                sn[i] = __uint_as_float((uint32_t)(key[e] >> 32));
-                sel[i] = (int32_t)(uint32_t)key[e];
-            }
+        int fpos = -1;
+        const int keep = kb_select<E>(kh, nvalid, Kt, fm, lane, sn, sel, skey, &fpos);
+        if (fsym) {
+            if (lane == 0) a.rank[(size_t)frame * n + k] = fpos + 1;
+            fs = fpos >= 0 ? (fpos < keep ? fpos : keep - 1) : -1;
         }
-        __syncthreads();
-        // copy parent paths (levels >= k) and write symbol k
-        const int w0 = k / 4;
-        for (int i = 0; i < keep; ++i) {
+        kb_wave_sync();
+        // copy parent paths (words from the one holding level k) and write level k
+        const int wk = k >> 1;
+        const int nwk = nw - wk;
+        int g = 1;  // survivors copied per pass: 64 / (words rounded up to a power of two)
+        while (g * 2 * nwk <= WAVE && g < KCAP) g *= 2;
+        const int span = WAVE / g;
+        for (int i0 = 0; i0 < keep; i0 += g) {
+            const int i = i0 + lane / span;
+            if (i >= keep) continue;
             const int m = sel[i];
             const int s = m / P, c = m % P;
-            const uint32_t* src = pc + s * stride;
-            uint32_t* dst = pn + i * stride;
-            for (int wd = w0 + lane; wd < nw; wd += WAVE) {
-                uint32_t d = src[wd];
-                if (wd == w0) {
-                    const int sh = 8 * (k & 3);
-                    d = (d & ~(0xffu << sh)) | ((uint32_t)c << sh);
+            for (int wd = wk + lane % span; wd < nw; wd += span) {
+                uint32_t d = pc[s * stride + wd];
+                if (wd == wk) {
+                    const uint32_t hb = half_bits((float)(2 * c - (P - 1)));
+                    d = (k & 1) ? ((d & 0x0000ffffu) | (hb << 16)) : ((d & 0xffff0000u) | hb);
                 }
-                dst[wd] = d;
+                pn[i * stride + wd] = d;
             }
         }
-        __syncthreads();
+        kb_wave_sync();
         cnt = keep;
     }
 
@@ -226,12 +339,212 @@ __device__ void kbest_frame(const KbestArgs& a, int frame, unsigned char* lds)
     for (int m = lane; m < n / 2; m += WAVE) {
         int v = 0;
         if (cnt > 0) {
-            const int ire = (best[(2 * m) >> 2] >> (8 * ((2 * m) & 3))) & 0xff;
-            const int iim = (best[(2 * m + 1) >> 2] >> (8 * ((2 * m + 1) & 3))) & 0xff;
+            const uint32_t d = best[m];  // levels 2m (real part) and 2m+1 (imaginary part)
+            const int ire = ((int)half_lo(d) + (P - 1)) / 2;
+            const int iim = ((int)half_hi(d) + (P - 1)) / 2;
             v = ire * P + iim;
         }
         a.sym[(size_t)frame * (n / 2) + m] = v;
     }
+}
+
+// Register-path variant for KCAP <= 32 (L >= 2 lanes per survivor): lane
+// (s, q) holds the path words w = q + L i (two fp16 amplitudes each) of
+// survivor s in registers; after the selection each new survivor's lanes
+// fetch the live words of their parent with cross-lane shuffles.  LDS holds
+// only the staged row and the selection arrays.
+template <int NWMAX>
+__host__ __device__ inline size_t kbest_reg_lds_bytes(int kcap)
+{
+    return sizeof(float) * 2 * kcap + sizeof(float) * (2 * NWMAX + 8) + sizeof(int32_t) * kcap +
+           sizeof(uint64_t) * kcap;
+}
+
+template <int P, int E, int NWMAX>
+__device__ void kbest_frame_reg(const KbestArgs& a, int frame, unsigned char* lds)
+{
+    using S = KbestShape<P, E>;
+    constexpr int KCAP = S::KCAP, L = S::L;
+    static_assert(KCAP <= 32 && L >= 2, "register variant needs two or more lanes per survivor");
+    constexpr int NWL = NWMAX / L;  // path words per lane
+    const int lane = threadIdx.x & 63;
+    const int s_own = lane / L, q = lane % L;
+    const int n = a.n;
+    const int nw = n / 2;
+    float* spd = reinterpret_cast<float*>(lds);
+    float* rrow = spd + 2 * KCAP;
+    int32_t* sel = reinterpret_cast<int32_t*>(rrow + 2 * NWMAX + 8);
+    uint64_t* skey = reinterpret_cast<uint64_t*>(sel + KCAP);
+
+    const float* Rf = a.R + (size_t)frame * r_packed_size(n);
+    const float* zf = a.z + (size_t)frame * n;
+    const float r2 = a.radius2 ? a.radius2[frame] : INFINITY;
+    const float cs = pam_scale(P);
+    const int32_t* ks = a.k_sched ? a.k_sched + (size_t)frame * a.k_sched_stride : nullptr;
+    const int32_t* fsym = a.force_sym ? a.force_sym + (size_t)frame * (n / 2) : nullptr;
+
+    uint32_t pw[NWL];
+#pragma unroll
+    for (int i = 0; i < NWL; ++i) pw[i] = 0u;  // unassigned levels are amplitude 0
+    for (int t = lane; t < 2 * NWMAX + 8; t += WAVE) rrow[t] = 0.f;
+    if (lane == 0) spd[0] = 0.f;
+    int cnt = 1, fs = 0;
+    int64_t expanded = 0;
+    uint32_t flags = 0;
+    const int i_hi = (nw + L - 1) / L;  // words beyond nw read zero row entries
+
+    constexpr int RPL = 4;
+    float rnext[RPL];
+    float rkk_next, zk_next;
+    {
+        const float* rk = Rf + r_row_off(n, n - 1);
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) rnext[i] = (lane + WAVE * i < 1) ? rk[lane + WAVE * i] : 0.f;
+        rkk_next = rk[0];
+        zk_next = zf[n - 1];
+    }
+    __syncthreads();
+
+    for (int k = n - 1; k >= 0; --k) {
+        const int cur = (n - 1 - k) & 1, nxt = cur ^ 1;
+        float* sc = spd + cur * KCAP;
+        float* sn = spd + nxt * KCAP;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int t = lane + WAVE * i;
+            if (t < n - k) rrow[k + t] = t == 0 ? 0.f : cs * rnext[i];
+        }
+        const float rkk = cs * rkk_next;
+        const float zk = zk_next;
+        if (k > 0) {
+            const float* rk = Rf + r_row_off(n, k - 1);
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int t = lane + WAVE * i;
+                rnext[i] = t < n - k + 1 ? rk[t] : 0.f;
+            }
+            rkk_next = rk[0];
+            zk_next = zf[k - 1];
+        }
+        kb_wave_sync();
+        // centre of this lane's survivor: levels <= k hold amplitude 0 and
+        // rrow[k] = 0, so whole words can be summed from the one of level k+1
+        const int i_lo = ((k + 1) >> 1) / L;
+        float acc = 0.f;
+#pragma unroll
+        for (int i = 0; i < NWL; ++i) {
+            if (i >= i_lo && i < i_hi) {
+                const float2 rr = *reinterpret_cast<const float2*>(rrow + 2 * (q + L * i));
+                acc = fmaf(rr.x, half_lo(pw[i]), acc);
+                acc = fmaf(rr.y, half_hi(pw[i]), acc);
+            }
+        }
+#pragma unroll
+        for (int m = 1; m < L; m <<= 1) acc += shfl_xor_f(acc, m);
+        const float bown = zk - acc;
+        uint32_t kh[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int m = e * WAVE + lane;
+            const int s = m / P, c = m % P;
+            const float b = shfl_f(bown, s * L);
+            kh[e] = ~0u;
+            if (s < cnt) {
+                const float ee = fmaf(-rkk, (float)(2 * c - (P - 1)), b);
+                const float pdc = fmaf(ee, ee, sc[s]);
+                if (pdc < r2) kh[e] = __float_as_uint(pdc);
+            }
+        }
+        expanded += cnt;
+        int nvalid = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) nvalid += __popcll(__ballot(kh[e] != ~0u));
+        if (nvalid == 0) {
+            flags |= MIMO_FLAG_EMPTY_SPHERE;
+            cnt = 0;
+            break;
+        }
+        int Kt = ks ? ks[k] : a.K;
+        Kt = Kt > a.K ? a.K : (Kt < 1 ? 1 : Kt);
+        int fm = -1;
+        if (fsym && fs >= 0) {
+            const int sy = fsym[k >> 1];
+            fm = fs * P + ((k & 1) ? (sy % P) : (sy / P));
+        }
+        int fpos = -1;
+        const int keep = kb_select<E>(kh, nvalid, Kt, fm, lane, sn, sel, skey, &fpos);
+        if (fsym) {
+            if (lane == 0) a.rank[(size_t)frame * n + k] = fpos + 1;
+            fs = fpos >= 0 ? (fpos < keep ? fpos : keep - 1) : -1;
+        }
+        kb_wave_sync();
+        // new survivor s_own takes its parent's words (those holding levels >= k)
+        int src = lane, cnew = 0;
+        if (s_own < keep) {
+            const int m = sel[s_own];
+            src = (m / P) * L + q;
+            cnew = m % P;
+        }
+        const int wk = k >> 1, ik = wk / L;
+#pragma unroll
+        for (int i = 0; i < NWL; ++i)
+            if (i >= ik && i < i_hi) pw[i] = (uint32_t)__shfl((int)pw[i], src, WAVE);
+        if (s_own < keep && q == wk % L) {
+            const uint32_t hb = half_bits((float)(2 * cnew - (P - 1)));
+#pragma unroll
+            for (int i = 0; i < NWL; ++i)
+                if (i == ik) pw[i] = (k & 1) ? ((pw[i] & 0x0000ffffu) | (hb << 16)) : ((pw[i] & 0xffff0000u) | hb);
+        }
+        cnt = keep;
+    }
+
+    if (lane == 0) {
+        if (cnt > 0) flags |= MIMO_FLAG_FOUND;
+        if (a.flags) a.flags[frame] = flags;
+        if (a.pd) a.pd[frame] = cnt > 0 ? spd[(n & 1) * KCAP] : INFINITY;
+        if (a.counters) {
+            int64_t* c = a.counters + (size_t)frame * 4;
+            c[0] = expanded;
+            c[1] = expanded * P;
+            c[2] = 0;
+            c[3] = 0;
+        }
+    }
+    // survivor 0 (lanes 0 .. L-1) is the best leaf; word w holds symbol w
+    if (!a.sym || s_own != 0) return;
+#pragma unroll
+    for (int i = 0; i < NWL; ++i) {
+        const int w = q + L * i;
+        if (w < nw) {
+            int v = 0;
+            if (cnt > 0) {
+                const int ire = ((int)half_lo(pw[i]) + (P - 1)) / 2;
+                const int iim = ((int)half_hi(pw[i]) + (P - 1)) / 2;
+                v = ire * P + iim;
+            }
+            a.sym[(size_t)frame * nw + w] = v;
+        }
+    }
+}
+
+template <int P, int E, int NWMAX>
+__global__ void __launch_bounds__(64) kbest_reg_kernel(KbestArgs a)
+{
+    extern __shared__ unsigned char smem_kbr[];
+    kbest_frame_reg<P, E, NWMAX>(a, blockIdx.x, smem_kbr);
+}
+
+template <int P, int E>
+static int32_t launch_kbest_reg(const KbestArgs& a, int B, hipStream_t st)
+{
+    using S = KbestShape<P, E>;
+    if (a.n <= 64) {
+        hipLaunchKernelGGL((kbest_reg_kernel<P, E, 32>), dim3(B), dim3(WAVE), kbest_reg_lds_bytes<32>(S::KCAP), st, a);
+    } else {
+        hipLaunchKernelGGL((kbest_reg_kernel<P, E, 128>), dim3(B), dim3(WAVE), kbest_reg_lds_bytes<128>(S::KCAP), st,
+                           a);
+    }
+    return check_launch("kbest_detect");
 }
 
 template <int P, int E>
@@ -254,15 +567,22 @@ static int32_t launch_kbest(const KbestArgs& a, int B, hipStream_t st)
     return check_launch("kbest_detect");
 }
 
+template <int P, int E>
+static int32_t launch_kbest_any(const KbestArgs& a, int B, hipStream_t st)
+{
+    if constexpr (KbestShape<P, E>::KCAP <= 32) return launch_kbest_reg<P, E>(a, B, st);
+    else return launch_kbest<P, E>(a, B, st);
+}
+
 template <int P>
 static int32_t dispatch_kbest_p(const KbestArgs& a, int B, hipStream_t st)
 {
     const int need = a.K * P;  // candidates per level
-    if (need <= 64) return launch_kbest<P, 1>(a, B, st);
-    if (need <= 128) return launch_kbest<P, 2>(a, B, st);
-    if (need <= 256) return launch_kbest<P, 4>(a, B, st);
-    if (need <= 512) return launch_kbest<P, 8>(a, B, st);
-    return launch_kbest<P, 16>(a, B, st);
+    if (need <= 64) return launch_kbest_any<P, 1>(a, B, st);
+    if (need <= 128) return launch_kbest_any<P, 2>(a, B, st);
+    if (need <= 256) return launch_kbest_any<P, 4>(a, B, st);
+    if (need <= 512) return launch_kbest_any<P, 8>(a, B, st);
+    return launch_kbest_any<P, 16>(a, B, st);
 }
 
 static int32_t dispatch_kbest(const KbestArgs& a, int pam, int B, hipStream_t st)

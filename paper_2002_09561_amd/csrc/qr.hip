@@ -1,192 +1,240 @@
 // QR preprocessing (Sec. III-B): H = Q R, z = Q^H y, emitted for the real
 // model in packed level order.
 //
-// One workgroup per frame.  The N x (M+1) matrix [H | y] lives in registers:
-// lane l of wave w owns column j = (w % ncg) * 64 + l and the rows of chunk
-// r = w / ncg (32 rows per chunk).  Each Householder step k
-//   1. the owners of column k publish it (and partial norms) in LDS,
-//   2. every thread forms the reflector v = x - alpha e1 (alpha = -phase(x0) ||x||),
-//   3. phase 1: partial w_j = sum_i conj(v_i) A_ij over the thread's rows,
+// One workgroup per frame, one wave per chunk of QR_RB = 16 rows.  The
+// N x (M+1) matrix [H | y] lives in registers: lane l of every wave owns the
+// columns l, l + 64, ... (CB = ceil((M+1)/64) of them) for the rows of its
+// wave's chunk.  Householder step k:
+//   1. the owner lane of column k (in every wave) publishes its rows >= k and
+//      the chunk's partial squared norm in LDS;
+//   2. every thread forms the reflector v = x - alpha e1 with
+//      alpha = -phase(x0) ||x|| (wave-uniform scalars) and loads the v_i of
+//      its rows once into registers;
+//   3. phase 1: partial w_j = sum_i conj(v_i) A_ij over the chunk's rows;
 //   4. phase 2: w_j = sum of the chunk partials, A_ij -= tau v_i w_j.
-// The complex QR maps onto the real model blockwise: with R_kk made real
-// and positive, the real R has R_2k,2k+1 = 0 and R_2k,2k = R_2k+1,2k+1.
+// Rows outside [k, N) carry v_i = 0, so the updates need no row guards.
+// The complex QR maps onto the real model blockwise: with R_kk
+// made real positive, the real R has R_2k,2k+1 = 0 and R_2k,2k = R_2k+1,2k+1.
 #include "common.hpp"
 
 namespace mimo {
 
-constexpr int QR_CH = 32;  // rows per chunk held in registers
+constexpr int QR_RB = 16;  // rows per wave held in registers
 
 struct c32 {
     float x, y;
 };
 
 __device__ inline c32 cmul(c32 a, c32 b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
-__device__ inline c32 cmulc(c32 a, c32 b)  // conj(a) * b
-{
-    return {a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
-}
 
-__global__ void __launch_bounds__(768) qr_kernel(const float2* __restrict__ H, const float2* __restrict__ y,
-                                                 int N, int M, int ncg, int rc, float* __restrict__ R,
-                                                 float* __restrict__ z, float* __restrict__ resid)
+template <int CB>
+__global__ void __launch_bounds__(512, CB <= 2 ? 4 : 2) qr_kernel(const float2* __restrict__ H, const float2* __restrict__ y, int N,
+                                                 int M, float* __restrict__ R, float* __restrict__ z,
+                                                 float* __restrict__ resid)
 {
     extern __shared__ float smem_qr[];
     const int frame = blockIdx.x;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int cg = w % ncg, r = w / ncg;
-    const int j = cg * WAVE + lane;     // owned column (j == M is y)
-    const int row0 = r * QR_CH;
-    const int ncol = ncg * WAVE;
+    const int lane = threadIdx.x & 63;
+    const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave index = row chunk (uniform)
+    const int rc = blockDim.x >> 6;
+    const int row0 = r * QR_RB;
+    const int ncol = CB * WAVE;
     const int n = 2 * M;
 
-    // LDS: colv[2][N] c32, wpart[rc][ncol] c32, pnorm[2][rc] f32, alpha[M] c32
+    // LDS: colv[2][N + RB] c32, wpart[rc][ncol] c32, alpha[M] c32, pnorm[2][rc] f32
     c32* colv = reinterpret_cast<c32*>(smem_qr);
-    c32* wpart = colv + 2 * N;
-    float* pnorm = reinterpret_cast<float*>(wpart + rc * ncol);
-    c32* alpha_s = reinterpret_cast<c32*>(pnorm + 2 * rc + (2 * rc) % 2);
+    c32* wpart = colv + 2 * (N + QR_RB);
+    c32* alpha_s = wpart + rc * ncol;
+    float* pnorm = reinterpret_cast<float*>(alpha_s + M);
 
     const float2* Hf = H + (size_t)frame * N * M;
     const float2* yf = y + (size_t)frame * N;
 
-    c32 A[QR_CH];
+    c32 A[QR_RB][CB];
 #pragma unroll
-    for (int q = 0; q < QR_CH; ++q) {
+    for (int q = 0; q < QR_RB; ++q) {
         const int i = row0 + q;
-        float2 v = make_float2(0.f, 0.f);
-        if (i < N) {
-            if (j < M) v = Hf[(size_t)i * M + j];
-            else if (j == M) v = yf[i];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const int j = lane + cb * WAVE;
+            float2 v = make_float2(0.f, 0.f);
+            if (i < N) {
+                if (j < M) v = Hf[(size_t)i * M + j];
+                else if (j == M) v = yf[i];
+            }
+            A[q][cb] = {v.x, v.y};
         }
-        A[q] = {v.x, v.y};
     }
 
     for (int k = 0; k < M; ++k) {
         const int buf = k & 1;
-        c32* cv = colv + buf * N;
+        c32* cv = colv + buf * (N + QR_RB);
         float* pn = pnorm + buf * rc;
-        // 1. publish column k and the chunk's partial norm
-        if (j == k) {
+        const int kcb = k / WAVE, klane = k % WAVE;
+        // 1. publish column k (all rows of this chunk; only rows > k are read)
+        //    and the chunk's partial squared norm over rows >= k
+        if (lane == klane) {
             float s = 0.f;
 #pragma unroll
-            for (int q = 0; q < QR_CH; ++q) {
+            for (int q = 0; q < QR_RB; ++q) {
                 const int i = row0 + q;
-                if (i >= k && i < N) {
-                    cv[i] = A[q];
-                    s += A[q].x * A[q].x + A[q].y * A[q].y;
-                }
+                c32 x = A[q][0];
+#pragma unroll
+                for (int cb = 1; cb < CB; ++cb)
+                    if (cb == kcb) x = A[q][cb];
+                cv[i] = x;
+                s += (i >= k) ? x.x * x.x + x.y * x.y : 0.f;
             }
             pn[r] = s;
         }
         __syncthreads();
+        if (row0 + QR_RB <= k) {  // this chunk is finished: only the barrier remains
+            __syncthreads();
+            continue;
+        }
         // 2. reflector scalars (uniform)
         float norm2 = 0.f;
         for (int rr = 0; rr < rc; ++rr) norm2 += pn[rr];
         const c32 x0 = cv[k];
         const float ax0 = sqrtf(x0.x * x0.x + x0.y * x0.y);
         const float norm = sqrtf(norm2);
-        c32 ph = ax0 > 0.f ? c32{x0.x / ax0, x0.y / ax0} : c32{1.f, 0.f};
+        const c32 ph = ax0 > 0.f ? c32{x0.x / ax0, x0.y / ax0} : c32{1.f, 0.f};
         const c32 alpha = {-ph.x * norm, -ph.y * norm};
         const c32 v0 = {x0.x - alpha.x, x0.y - alpha.y};
         const float vn2 = norm2 - ax0 * ax0 + (v0.x * v0.x + v0.y * v0.y);
         const float tau = (norm > 0.f && vn2 > 0.f) ? 2.f / vn2 : 0.f;
-        // 3. phase 1: partial w_j over this chunk
-        const bool active = (j > k) && (j <= M);
-        if (active) {
+        // v_i of this chunk's rows: zero above row k and below row N-1, so the
+        // updates below are exact no-ops there
+        c32 vr[QR_RB];
+#pragma unroll
+        for (int q = 0; q < QR_RB; ++q) {
+            const int i = row0 + q;
+            const c32 t = cv[i];
+            vr[q] = (i > k && i < N) ? t : (i == k ? v0 : c32{0.f, 0.f});
+        }
+        // 3. phase 1: partial w_j = sum_i conj(v_i) A_ij over this chunk
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            if ((cb + 1) * WAVE <= k) continue;  // every column of this block is finished (uniform)
             c32 s = {0.f, 0.f};
 #pragma unroll
-            for (int q = 0; q < QR_CH; ++q) {
-                const int i = row0 + q;
-                if (i >= k && i < N) {
-                    const c32 vi = (i == k) ? v0 : cv[i];
-                    const c32 t = cmulc(vi, A[q]);
-                    s.x += t.x;
-                    s.y += t.y;
-                }
+            for (int q = 0; q < QR_RB; ++q) {
+                s.x = fmaf(vr[q].x, A[q][cb].x, s.x);
+                s.x = fmaf(vr[q].y, A[q][cb].y, s.x);
+                s.y = fmaf(vr[q].x, A[q][cb].y, s.y);
+                s.y = fmaf(-vr[q].y, A[q][cb].x, s.y);
             }
-            wpart[r * ncol + j] = s;
+            wpart[r * ncol + lane + cb * WAVE] = s;
         }
         __syncthreads();
-        // 4. phase 2: apply the reflector
-        if (active) {
+        // 4. phase 2: apply the reflector; the pivot column becomes alpha e_k
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            if ((cb + 1) * WAVE <= k) continue;
+            const int j = lane + cb * WAVE;
             c32 wj = {0.f, 0.f};
-            for (int rr = 0; rr < rc; ++rr) {
-                wj.x += wpart[rr * ncol + j].x;
-                wj.y += wpart[rr * ncol + j].y;
+            for (int rr = k / QR_RB; rr < rc; ++rr) {  // chunks with rows >= k wrote this step's partials
+                const c32 t = wpart[rr * ncol + j];
+                wj.x += t.x;
+                wj.y += t.y;
             }
             wj.x *= tau;
             wj.y *= tau;
+            // finished columns (j < k) have w_j = 0 exactly, so updating every
+            // column is exact; the pivot column is set below
 #pragma unroll
-            for (int q = 0; q < QR_CH; ++q) {
+            for (int q = 0; q < QR_RB; ++q) {
+                A[q][cb].x = fmaf(-vr[q].x, wj.x, A[q][cb].x);
+                A[q][cb].x = fmaf(vr[q].y, wj.y, A[q][cb].x);
+                A[q][cb].y = fmaf(-vr[q].x, wj.y, A[q][cb].y);
+                A[q][cb].y = fmaf(-vr[q].y, wj.x, A[q][cb].y);
+            }
+        }
+        // pivot column: exactly alpha e_k
+        if (lane == klane) {
+#pragma unroll
+            for (int q = 0; q < QR_RB; ++q) {
                 const int i = row0 + q;
-                if (i >= k && i < N) {
-                    const c32 vi = (i == k) ? v0 : cv[i];
-                    const c32 t = cmul(vi, wj);
-                    A[q].x -= t.x;
-                    A[q].y -= t.y;
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    if (cb != kcb) continue;
+                    if (tau > 0.f) {  // (tau == 0 left the column unchanged)
+                        if (i == k) A[q][cb] = alpha;
+                        else if (i > k) A[q][cb] = {0.f, 0.f};
+                    }
                 }
             }
-        } else if (j == k) {
-#pragma unroll
-            for (int q = 0; q < QR_CH; ++q) {
-                const int i = row0 + q;
-                if (i == k) {
-                    A[q] = (tau > 0.f) ? alpha : x0;
-                    alpha_s[k] = A[q];
-                } else if (i > k && i < N && tau > 0.f) {
-                    A[q] = {0.f, 0.f};
-                }
-            }
+            const int qk = k - row0;
+            if (qk >= 0 && qk < QR_RB) alpha_s[k] = (tau > 0.f) ? alpha : x0;
         }
     }
     __syncthreads();
 
-    // make R_kk real positive: scale row k by d_k = conj(a_k) / |a_k|, then
+    // make R_kk real positive: scale row i by d_i = conj(a_i) / |a_i|, then
     // write the real blocks [[a, -b], [b, a]] in packed level order
     float* Rf = R + (size_t)frame * r_packed_size(n);
     float* zf = z + (size_t)frame * n;
     float rs = 0.f;
 #pragma unroll
-    for (int q = 0; q < QR_CH; ++q) {
+    for (int q = 0; q < QR_RB; ++q) {
         const int i = row0 + q;
-        if (i < M && j >= i && j <= M) {
+        if (i < M) {
             const c32 a = alpha_s[i];
             const float aa = sqrtf(a.x * a.x + a.y * a.y);
-            const c32 d = aa > 0.f ? c32{a.x / aa, -a.y / aa} : c32{1.f, 0.f};
-            c32 v = cmul(d, A[q]);
-            if (j == i) v = {aa > 0.f ? aa : A[q].x, 0.f};
-            if (j == M) {
-                zf[2 * i] = v.x;
-                zf[2 * i + 1] = v.y;
-            } else {
-                const int re = 2 * i, im = 2 * i + 1;
-                float* row_re = Rf + r_row_off(n, re);
-                float* row_im = Rf + r_row_off(n, im);
-                row_re[2 * j - re] = v.x;
-                row_re[2 * j + 1 - re] = -v.y;
-                if (j > i) row_im[2 * j - im] = v.y;
-                row_im[2 * j + 1 - im] = v.x;
+            const float inv = aa > 0.f ? 1.f / aa : 0.f;
+            const c32 d = aa > 0.f ? c32{a.x * inv, -a.y * inv} : c32{1.f, 0.f};
+            float* row_re = Rf + r_row_off(n, 2 * i);
+            float* row_im = Rf + r_row_off(n, 2 * i + 1);
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                const int j = lane + cb * WAVE;
+                if (j < i || j > M) continue;
+                c32 v = cmul(d, A[q][cb]);
+                if (j == i) v = {aa > 0.f ? aa : A[q][cb].x, 0.f};
+                if (j == M) {
+                    zf[2 * i] = v.x;
+                    zf[2 * i + 1] = v.y;
+                } else {
+                    row_re[2 * (j - i)] = v.x;
+                    row_re[2 * (j - i) + 1] = -v.y;
+                    if (j > i) row_im[2 * (j - i) - 1] = v.y;
+                    row_im[2 * (j - i)] = v.x;
+                }
             }
         }
-        if (i >= M && i < N && j == M) rs += A[q].x * A[q].x + A[q].y * A[q].y;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+            if (i >= M && i < N && lane + cb * WAVE == M) rs += A[q][cb].x * A[q][cb].x + A[q][cb].y * A[q][cb].y;
     }
     if (resid) {
-        // rows >= M of the rotated y: only the threads owning column M contribute
-        float* red = pnorm;  // reuse: rc floats
+        // rows >= M of the rotated y: only the lanes owning column M contribute
         __syncthreads();
-        if (j == M) red[r] = rs;
+        float part = wave_sum(rs);
+        if (lane == 0) pnorm[r] = part;
         __syncthreads();
         if (threadIdx.x == 0) {
             float s = 0.f;
-            for (int rr = 0; rr < rc; ++rr) s += red[rr];
+            for (int rr = 0; rr < rc; ++rr) s += pnorm[rr];
             resid[frame] = s;
         }
     }
 }
 
+template <int CB>
+static int32_t launch_qr(const float* H, const float* y, int B, int N, int M, float* R, float* z, float* resid,
+                         hipStream_t st)
+{
+    const int rc = (N + QR_RB - 1) / QR_RB;
+    const size_t lds = sizeof(c32) * (2 * (N + QR_RB) + rc * CB * WAVE + M) + sizeof(float) * (2 * rc);
+    hipLaunchKernelGGL(qr_kernel<CB>, dim3(B), dim3(rc * WAVE), lds, st, reinterpret_cast<const float2*>(H),
+                       reinterpret_cast<const float2*>(y), N, M, R, z, resid);
+    return check_launch("mimo_qr_preprocess");
+}
+
 }  // namespace mimo
 
-extern "C" int32_t mimo_qr_preprocess(const float* H, const float* y, int32_t B, int32_t n_rx,
-                                      int32_t n_tx, float* R, float* z, float* resid, void* stream)
+extern "C" int32_t mimo_qr_preprocess(const float* H, const float* y, int32_t B, int32_t n_rx, int32_t n_tx,
+                                      float* R, float* z, float* resid, void* stream)
 {
     using namespace mimo;
     if (B < 0) return fail(MIMO_ERR_INVALID_ARG, "mimo_qr_preprocess: B < 0");
@@ -196,12 +244,9 @@ extern "C" int32_t mimo_qr_preprocess(const float* H, const float* y, int32_t B,
         return fail(MIMO_ERR_UNSUPPORTED, "mimo_qr_preprocess: n_rx, n_tx <= %d", MIMO_MAX_RX);
     if (B == 0) return MIMO_OK;
     if (!H || !y || !R || !z) return fail(MIMO_ERR_INVALID_ARG, "mimo_qr_preprocess: null pointer");
-    const int ncg = (n_tx + 1 + WAVE - 1) / WAVE;
-    const int rc = (n_rx + QR_CH - 1) / QR_CH;
-    const int threads = ncg * rc * WAVE;
-    const size_t lds = sizeof(c32) * (2 * n_rx + rc * ncg * WAVE + n_tx) + sizeof(float) * (2 * rc + 2);
-    hipLaunchKernelGGL(qr_kernel, dim3(B), dim3(threads), lds, (hipStream_t)stream,
-                       reinterpret_cast<const float2*>(H), reinterpret_cast<const float2*>(y), n_rx, n_tx, ncg,
-                       rc, R, z, resid);
-    return check_launch("mimo_qr_preprocess");
+    hipStream_t st = (hipStream_t)stream;
+    const int cols = n_tx + 1;
+    if (cols <= WAVE) return launch_qr<1>(H, y, B, n_rx, n_tx, R, z, resid, st);
+    if (cols <= 2 * WAVE) return launch_qr<2>(H, y, B, n_rx, n_tx, R, z, resid, st);
+    return launch_qr<3>(H, y, B, n_rx, n_tx, R, z, resid, st);
 }

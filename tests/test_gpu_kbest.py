@@ -156,7 +156,8 @@ def test_kbest_per_frame_schedule(gpu, orc):
     assert np.array_equal(_np(ctr)[:, 0], exp)
 
 
-def test_rank_labels_parity(gpu, orc):
+@pytest.mark.parametrize("K", [16, 64, 3])
+def test_rank_labels_parity(gpu, orc, K):
     import torch
 
     B, M, q = 80, 8, 16
@@ -164,10 +165,10 @@ def test_rank_labels_parity(gpu, orc):
     P = 4
     Ro, zo, _ = orc.qr(f.H, f.y)
     ml = orc.sesd(Ro, zo, P)[0]
-    out = orc.kbest(Ro, zo, P, 16, force_path=ml)
+    out = orc.kbest(Ro, zo, P, K, force_path=ml)
     H, y, _ = _dev(f)
     R, z = gpu.qr_preprocess(H, y)
-    rank = _np(gpu.kbest_rank_labels(R, z, M, P, 16, torch.from_numpy(orc.x_to_sym(ml, P)).cuda()))
+    rank = _np(gpu.kbest_rank_labels(R, z, M, P, K, torch.from_numpy(orc.x_to_sym(ml, P)).cuda()))
     same = rank == out["rank"]
     print(f"rank labels equal: {same.mean():.4f}")
     assert same.mean() >= 0.99
