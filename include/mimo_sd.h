@@ -111,6 +111,22 @@ int32_t kbest_detect(const float* R, const float* z, int32_t B, int32_t n_tx, in
                      int64_t* counters, void* stream);
 
 /* ---------------------------------------------------------------------
+ * Plain fallback of a learned detection (the plain K-best stays the
+ * reference method): frame b is detected again by plain K-best with K
+ * survivors, overwriting sym[b], pd[b], flags[b] (which then carry
+ * MIMO_FLAG_LEARNED_FALLBACK) and counters[b], iff its current flags hold
+ * MIMO_FLAG_LEARNED_FALLBACK or lack MIMO_FLAG_FOUND, or its search metric
+ * pd[b] exceeds (sigma2[b] / 2) (n + beta sqrt(2 n)) -- beta standard
+ * deviations above the mean of the noise energy a correct detection leaves
+ * (chi-square with n real degrees of freedom, sigma2 the complex noise
+ * variance).  Frames that keep their detection are not touched.  sym, pd,
+ * flags are the outputs of the first detection (in place); sigma2 [B].
+ * ------------------------------------------------------------------- */
+int32_t kbest_fallback(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam, int32_t K,
+                       const float* sigma2, float beta, int32_t* sym, float* pd, uint32_t* flags,
+                       int64_t* counters, void* stream);
+
+/* ---------------------------------------------------------------------
  * Learned-pruning labels: K-best with K survivors in which the given path
  * (normally the ML path) is forced to survive; rank[b][k] receives the
  * 1-based rank of that path's prefix among the sorted candidates of level k.

@@ -10,33 +10,52 @@ __device__ inline double amp_d(int P, int i)
     return (double)(2 * i - (P - 1)) * sqrt(3.0 / (2.0 * (double)(P * P - 1)));
 }
 
-// one workgroup per frame, one thread per receive antenna (N <= 128)
-__global__ void __launch_bounds__(128) metric_kernel(const float2* __restrict__ H, const float2* __restrict__ y,
-                                                     const int32_t* __restrict__ sym, int N, int M, int P,
+// one wave per frame: lanes run along a row of H (coalesced reads), the
+// row's residual y_i - sum_j h_ij s_j is reduced across the wave in FP64 in a
+// fixed order, and lane 0 accumulates |residual|^2 over the rows
+__global__ void __launch_bounds__(256) metric_kernel(const float2* __restrict__ H, const float2* __restrict__ y,
+                                                     const int32_t* __restrict__ sym, int B, int N, int M, int P,
                                                      double* __restrict__ out)
 {
-    __shared__ double part[2];
-    const int f = blockIdx.x, i = threadIdx.x;
-    double acc = 0.0;
-    if (i < N) {
-        const float2* h = H + ((size_t)f * N + i) * M;
-        const int32_t* s = sym + (size_t)f * M;
-        float2 yy = y[(size_t)f * N + i];
-        double er = yy.x, ei = yy.y;
-        for (int j = 0; j < M; ++j) {
-            const int q = s[j];
-            const double sr = amp_d(P, q / P), si = amp_d(P, q % P);
-            const float2 hv = h[j];
-            er -= (double)hv.x * sr - (double)hv.y * si;
-            ei -= (double)hv.x * si + (double)hv.y * sr;
-        }
-        acc = er * er + ei * ei;
-    }
+    const int lane = threadIdx.x & 63;
+    const int f = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x >> 6);
+    if (f >= B) return;
+    constexpr int CPL = (MIMO_MAX_TX + WAVE - 1) / WAVE;  // columns per lane
+    double sr[CPL], si[CPL];
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, WAVE);
-    if ((i & 63) == 0) part[i >> 6] = acc;
-    __syncthreads();
-    if (i == 0) out[f] = part[0] + (blockDim.x > 64 ? part[1] : 0.0);
+    for (int c = 0; c < CPL; ++c) {
+        const int j = lane + WAVE * c;
+        sr[c] = si[c] = 0.0;
+        if (j < M) {
+            const int q = sym[(size_t)f * M + j];
+            sr[c] = amp_d(P, q / P);
+            si[c] = amp_d(P, q % P);
+        }
+    }
+    const float2* Hf = H + (size_t)f * N * M;
+    const float2* yf = y + (size_t)f * N;
+    double acc = 0.0;
+    for (int i = 0; i < N; ++i) {
+        double pr = 0.0, pi = 0.0;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const int j = lane + WAVE * c;
+            if (j < M) {
+                const float2 h = Hf[(size_t)i * M + j];
+                pr += (double)h.x * sr[c] - (double)h.y * si[c];
+                pi += (double)h.x * si[c] + (double)h.y * sr[c];
+            }
+        }
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            pr += __shfl_xor(pr, m, WAVE);
+            pi += __shfl_xor(pi, m, WAVE);
+        }
+        const float2 yy = yf[i];
+        const double er = (double)yy.x - pr, ei = (double)yy.y - pi;
+        acc += er * er + ei * ei;
+    }
+    if (lane == 0) out[f] = acc;
 }
 
 // one wave per frame
@@ -118,9 +137,8 @@ extern "C" int32_t mimo_metric(const float* H, const float* y, const int32_t* sy
     if (n_rx > MIMO_MAX_RX || n_tx > MIMO_MAX_TX) return fail(MIMO_ERR_UNSUPPORTED, "mimo_metric: size limit");
     if (B == 0) return MIMO_OK;
     if (!H || !y || !sym || !metric) return fail(MIMO_ERR_INVALID_ARG, "mimo_metric: null pointer");
-    const int threads = n_rx > 64 ? 128 : 64;
-    hipLaunchKernelGGL(metric_kernel, dim3(B), dim3(threads), 0, (hipStream_t)stream,
-                       reinterpret_cast<const float2*>(H), reinterpret_cast<const float2*>(y), sym, n_rx, n_tx,
+    hipLaunchKernelGGL(metric_kernel, dim3((B + 3) / 4), dim3(256), 0, (hipStream_t)stream,
+                       reinterpret_cast<const float2*>(H), reinterpret_cast<const float2*>(y), sym, B, n_rx, n_tx,
                        pam, metric);
     return check_launch("mimo_metric");
 }

@@ -35,7 +35,23 @@ struct KbestArgs {
     float* pd;
     uint32_t* flags;
     int64_t* counters;
+    // fallback mode: only frames flagged LEARNED_FALLBACK, or whose search
+    // metric pd exceeds (sigma2/2) (n + beta sqrt(2n)), are detected again
+    const float* fb_sigma2;
+    float fb_beta;
 };
+
+// fallback mode: does frame `frame` keep its first detection?
+__device__ inline bool kb_keep_first(const KbestArgs& a, int frame)
+{
+    if (!a.fb_sigma2) return false;
+    const uint32_t fl = a.flags[frame];
+    if (fl & MIMO_FLAG_LEARNED_FALLBACK) return false;
+    if (!(fl & MIMO_FLAG_FOUND)) return false;
+    const float n = (float)a.n;
+    const float bound = 0.5f * a.fb_sigma2[frame] * (n + a.fb_beta * sqrtf(2.f * n));
+    return a.pd[frame] <= bound;
+}
 
 template <int P, int E>
 struct KbestShape {
@@ -78,9 +94,10 @@ __device__ inline void kb_wave_sync()
 // it would be dropped.  Returns the number kept; *fpos_out receives the
 // forced candidate's 0-based rank (-1 when absent).
 template <int E>
-__device__ inline int kb_select(const uint32_t (&kh)[E], int nvalid, int Kt, int fm, int lane, float* sn,
+__device__ inline int kb_select(const uint32_t (&kh)[E], int ncand, int nvalid, int Kt, int fm, int lane, float* sn,
                                 int32_t* sel, uint64_t* skey, int* fpos_out)
 {
+    // blocks e with e * 64 >= ncand hold no candidate (uniform skips)
     int keep = Kt < nvalid ? Kt : nvalid;
     int fpos = -1;
     uint64_t fkey = 0;
@@ -95,6 +112,7 @@ __device__ inline int kb_select(const uint32_t (&kh)[E], int nvalid, int Kt, int
         int below = 0;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
+            if (e * WAVE >= ncand) continue;
             const uint64_t key = ((uint64_t)kh[e] << 32) | (uint32_t)(e * WAVE + lane);
             below += __popcll(__ballot(kh[e] != ~0u && key < fkey));
         }
@@ -115,14 +133,15 @@ __device__ inline int kb_select(const uint32_t (&kh)[E], int nvalid, int Kt, int
             const uint32_t cand = v | (1u << bit);
             int c = 0;
 #pragma unroll
-            for (int e = 0; e < E; ++e) c += __popcll(__ballot(kh[e] < cand));
+            for (int e = 0; e < E; ++e)
+                if (e * WAVE < ncand) c += __popcll(__ballot(kh[e] < cand));
             if (c < keep) v = cand;
         }
         int clt = 0;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             take[e] = kh[e] < v;
-            clt += __popcll(__ballot(take[e]));
+            if (e * WAVE < ncand) clt += __popcll(__ballot(take[e]));
         }
         // ties on the pd bits: lowest candidate indices first
         for (int need = keep - clt; need > 0; --need) {
@@ -147,6 +166,7 @@ __device__ inline int kb_select(const uint32_t (&kh)[E], int nvalid, int Kt, int
     int base = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
+        if (e * WAVE >= ncand) continue;
         const uint64_t bal = __ballot(take[e]);
         if (take[e]) {
             const int slot = base + (int)__popcll(bal & ((1ull << lane) - 1ull));
@@ -275,7 +295,8 @@ __device__ void kbest_frame(const KbestArgs& a, int frame, unsigned char* lds)
         expanded += cnt;
         int nvalid = 0;
 #pragma unroll
-        for (int e = 0; e < E; ++e) nvalid += __popcll(__ballot(kh[e] != ~0u));
+        for (int e = 0; e < E; ++e)
+            if (e * WAVE < cnt * P) nvalid += __popcll(__ballot(kh[e] != ~0u));
         if (nvalid == 0) {
             flags |= MIMO_FLAG_EMPTY_SPHERE;
             cnt = 0;
@@ -291,7 +312,7 @@ __device__ void kbest_frame(const KbestArgs& a, int frame, unsigned char* lds)
             if (fs < 0) fm = -1;
         }
         int fpos = -1;
-        const int keep = kb_select<E>(kh, nvalid, Kt, fm, lane, sn, sel, skey, &fpos);
+        const int keep = kb_select<E>(kh, cnt * P, nvalid, Kt, fm, lane, sn, sel, skey, &fpos);
         if (fsym) {
             if (lane == 0) a.rank[(size_t)frame * n + k] = fpos + 1;
             fs = fpos >= 0 ? (fpos < keep ? fpos : keep - 1) : -1;
@@ -323,6 +344,7 @@ __device__ void kbest_frame(const KbestArgs& a, int frame, unsigned char* lds)
 
     if (lane == 0) {
         if (cnt > 0) flags |= MIMO_FLAG_FOUND;
+        if (a.fb_sigma2) flags |= MIMO_FLAG_LEARNED_FALLBACK;
         if (a.flags) a.flags[frame] = flags;
         if (a.pd) a.pd[frame] = cnt > 0 ? spd[(n & 1) * KCAP] : INFINITY;
         if (a.counters) {
@@ -348,7 +370,7 @@ __device__ void kbest_frame(const KbestArgs& a, int frame, unsigned char* lds)
     }
 }
 
-// Register-path variant for KCAP <= 32 (L >= 2 lanes per survivor): lane
+// Register-path variant for KCAP <= 64 (L >= 1 lanes per survivor): lane
 // (s, q) holds the path words w = q + L i (two fp16 amplitudes each) of
 // survivor s in registers; after the selection each new survivor's lanes
 // fetch the live words of their parent with cross-lane shuffles.  LDS holds
@@ -365,7 +387,7 @@ __device__ void kbest_frame_reg(const KbestArgs& a, int frame, unsigned char* ld
 {
     using S = KbestShape<P, E>;
     constexpr int KCAP = S::KCAP, L = S::L;
-    static_assert(KCAP <= 32 && L >= 2, "register variant needs two or more lanes per survivor");
+    static_assert(KCAP <= 64, "register variant holds at most one survivor per lane");
     constexpr int NWL = NWMAX / L;  // path words per lane
     const int lane = threadIdx.x & 63;
     const int s_own = lane / L, q = lane % L;
@@ -443,12 +465,14 @@ __device__ void kbest_frame_reg(const KbestArgs& a, int frame, unsigned char* ld
         for (int m = 1; m < L; m <<= 1) acc += shfl_xor_f(acc, m);
         const float bown = zk - acc;
         uint32_t kh[E];
+        const int ncand = cnt * P;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
+            kh[e] = ~0u;
+            if (e * WAVE >= ncand) continue;  // block without candidates (uniform)
             const int m = e * WAVE + lane;
             const int s = m / P, c = m % P;
             const float b = shfl_f(bown, s * L);
-            kh[e] = ~0u;
             if (s < cnt) {
                 const float ee = fmaf(-rkk, (float)(2 * c - (P - 1)), b);
                 const float pdc = fmaf(ee, ee, sc[s]);
@@ -458,7 +482,8 @@ __device__ void kbest_frame_reg(const KbestArgs& a, int frame, unsigned char* ld
         expanded += cnt;
         int nvalid = 0;
 #pragma unroll
-        for (int e = 0; e < E; ++e) nvalid += __popcll(__ballot(kh[e] != ~0u));
+        for (int e = 0; e < E; ++e)
+            if (e * WAVE < cnt * P) nvalid += __popcll(__ballot(kh[e] != ~0u));
         if (nvalid == 0) {
             flags |= MIMO_FLAG_EMPTY_SPHERE;
             cnt = 0;
@@ -472,7 +497,7 @@ __device__ void kbest_frame_reg(const KbestArgs& a, int frame, unsigned char* ld
             fm = fs * P + ((k & 1) ? (sy % P) : (sy / P));
         }
         int fpos = -1;
-        const int keep = kb_select<E>(kh, nvalid, Kt, fm, lane, sn, sel, skey, &fpos);
+        const int keep = kb_select<E>(kh, cnt * P, nvalid, Kt, fm, lane, sn, sel, skey, &fpos);
         if (fsym) {
             if (lane == 0) a.rank[(size_t)frame * n + k] = fpos + 1;
             fs = fpos >= 0 ? (fpos < keep ? fpos : keep - 1) : -1;
@@ -500,6 +525,7 @@ __device__ void kbest_frame_reg(const KbestArgs& a, int frame, unsigned char* ld
 
     if (lane == 0) {
         if (cnt > 0) flags |= MIMO_FLAG_FOUND;
+        if (a.fb_sigma2) flags |= MIMO_FLAG_LEARNED_FALLBACK;
         if (a.flags) a.flags[frame] = flags;
         if (a.pd) a.pd[frame] = cnt > 0 ? spd[(n & 1) * KCAP] : INFINITY;
         if (a.counters) {
@@ -531,6 +557,7 @@ template <int P, int E, int NWMAX>
 __global__ void __launch_bounds__(64) kbest_reg_kernel(KbestArgs a)
 {
     extern __shared__ unsigned char smem_kbr[];
+    if (kb_keep_first(a, blockIdx.x)) return;
     kbest_frame_reg<P, E, NWMAX>(a, blockIdx.x, smem_kbr);
 }
 
@@ -551,6 +578,7 @@ template <int P, int E>
 __global__ void __launch_bounds__(64) kbest_kernel(KbestArgs a)
 {
     extern __shared__ unsigned char smem_kb[];
+    if (kb_keep_first(a, blockIdx.x)) return;
     kbest_frame<P, E>(a, blockIdx.x, smem_kb);
 }
 
@@ -570,7 +598,7 @@ static int32_t launch_kbest(const KbestArgs& a, int B, hipStream_t st)
 template <int P, int E>
 static int32_t launch_kbest_any(const KbestArgs& a, int B, hipStream_t st)
 {
-    if constexpr (KbestShape<P, E>::KCAP <= 32) return launch_kbest_reg<P, E>(a, B, st);
+    if constexpr (KbestShape<P, E>::KCAP <= 64) return launch_kbest_reg<P, E>(a, B, st);
     else return launch_kbest<P, E>(a, B, st);
 }
 
@@ -621,7 +649,7 @@ extern "C" int32_t kbest_detect(const float* R, const float* z, int32_t B, int32
         return fail(MIMO_ERR_INVALID_ARG, "kbest_detect: k_sched_stride must be 0 or n = %d", n);
     if (B == 0) return MIMO_OK;
     if (!R || !z || !sym || !pd || !flags) return fail(MIMO_ERR_INVALID_ARG, "kbest_detect: null pointer");
-    KbestArgs a{R, z, n, K, k_sched, k_sched_stride, radius2, nullptr, nullptr, sym, pd, flags, counters};
+    KbestArgs a{R, z, n, K, k_sched, k_sched_stride, radius2, nullptr, nullptr, sym, pd, flags, counters, nullptr, 0.f};
     return dispatch_kbest(a, pam, B, (hipStream_t)stream);
 }
 
@@ -633,6 +661,20 @@ extern "C" int32_t kbest_rank_labels(const float* R, const float* z, int32_t B, 
     if (rc) return rc;
     if (B == 0) return MIMO_OK;
     if (!R || !z || !force_sym || !rank) return fail(MIMO_ERR_INVALID_ARG, "kbest_rank_labels: null pointer");
-    KbestArgs a{R, z, 2 * n_tx, K, nullptr, 0, nullptr, force_sym, rank, nullptr, nullptr, nullptr, nullptr};
+    KbestArgs a{R, z, 2 * n_tx, K, nullptr, 0, nullptr, force_sym, rank, nullptr, nullptr, nullptr, nullptr, nullptr, 0.f};
+    return dispatch_kbest(a, pam, B, (hipStream_t)stream);
+}
+
+extern "C" int32_t kbest_fallback(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam, int32_t K,
+                                  const float* sigma2, float beta, int32_t* sym, float* pd, uint32_t* flags,
+                                  int64_t* counters, void* stream)
+{
+    using namespace mimo;
+    int32_t rc = validate_common("kbest_fallback", B, n_tx, pam, K);
+    if (rc) return rc;
+    if (!(beta >= 0.f)) return fail(MIMO_ERR_INVALID_ARG, "kbest_fallback: beta must be >= 0");
+    if (B == 0) return MIMO_OK;
+    if (!R || !z || !sigma2 || !sym || !pd || !flags) return fail(MIMO_ERR_INVALID_ARG, "kbest_fallback: null pointer");
+    KbestArgs a{R, z, 2 * n_tx, K, nullptr, 0, nullptr, nullptr, nullptr, sym, pd, flags, counters, sigma2, beta};
     return dispatch_kbest(a, pam, B, (hipStream_t)stream);
 }

@@ -30,6 +30,7 @@ SIGNATURES = {
     "mimo_qr_preprocess": ([_P, _P, _I32, _I32, _I32, _P, _P, _P, _P], _I32),
     "kbest_detect": ([_P, _P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P, _P], _I32),
     "kbest_rank_labels": ([_P, _P, _I32, _I32, _I32, _I32, _P, _P, _P], _I32),
+    "kbest_fallback": ([_P, _P, _I32, _I32, _I32, _I32, _P, _F, _P, _P, _P, _P, _P], _I32),
     "sd_hybrid_detect": ([_P, _P, _I32, _I32, _I32, _P, _I32, _I32, _P, _I32, _I32, _I64, _P, _P, _P, _P,
                           _P], _I32),
     "mimo_metric": ([_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P], _I32),
@@ -143,6 +144,18 @@ def kbest_detect(R, z, n_tx: int, pam: int, K: int, k_sched=None, radius2=None, 
                                _ptr(ks, torch.int32, "k_sched"), stride, _ptr(radius2, torch.float32, "radius2"),
                                _ptr(sym), _ptr(pd), _ptr(flags), _ptr(ctr), _stream(stream)))
     return (sym, pd, flags, ctr) if want_counters else (sym, pd, flags)
+
+
+def kbest_fallback(R, z, n_tx: int, pam: int, K: int, sigma2, beta: float, out, counters=None, stream=None):
+    """Re-detect with plain K-best the frames of `out` = (sym, pd, flags) whose
+    learned detection is flagged or whose metric exceeds the noise bound."""
+    B = z.shape[0]
+    sym, pd, flags = out[:3]
+    _check(load().kbest_fallback(_ptr(R, torch.float32, "R"), _ptr(z, torch.float32, "z"), B, n_tx, pam, K,
+                                 _ptr(sigma2, torch.float32, "sigma2"), float(beta), _ptr(sym, torch.int32, "sym"),
+                                 _ptr(pd, torch.float32, "pd"), _ptr(flags, torch.int32, "flags"),
+                                 _ptr(counters, torch.int64, "counters"), _stream(stream)))
+    return sym, pd, flags
 
 
 def kbest_rank_labels(R, z, n_tx: int, pam: int, K: int, force_sym, stream=None):

@@ -230,3 +230,31 @@ def test_kbest_100x100_64qam_sampled(gpu, orc):
     m = _np(gpu.metric(H, y, sym, 8))
     mo = orc.metric(f.H[idx], f.y[idx], _np(sym)[idx], 64)
     assert np.allclose(m[idx], mo, rtol=1e-10)
+
+
+def test_kbest_fallback(gpu, orc):
+    """Frames whose first detection (here K = 1) is above the noise bound, or
+    flagged, are detected again by plain K-best; the others are untouched."""
+    import torch
+
+    B, M, q = 200, 16, 16
+    f = gen_frames(M, M, q, 10.0, B, seed=2700)
+    P, n = 4, 2 * M
+    H, y, _ = _dev(f)
+    R, z = gpu.qr_preprocess(H, y)
+    sym, pd, flags = gpu.kbest_detect(R, z, M, P, 1)
+    flags[:5] |= gpu.FLAG_LEARNED_FALLBACK  # forced fallback on the first frames
+    first = (_np(sym).copy(), _np(pd).copy(), _np(flags).copy())
+    s2 = torch.full((B,), f.sigma2, device="cuda", dtype=torch.float32)
+    beta = 3.0
+    gpu.kbest_fallback(R, z, M, P, 32, s2, beta, (sym, pd, flags))
+    bound = 0.5 * np.float32(f.sigma2) * (n + beta * np.sqrt(2 * n))
+    redo = ((first[2] & gpu.FLAG_LEARNED_FALLBACK) != 0) | (first[1] > bound)
+    assert redo.any() and (~redo).any()
+    fl = _np(flags)
+    assert np.all(((fl & gpu.FLAG_LEARNED_FALLBACK) != 0) == redo)
+    assert np.array_equal(_np(sym)[~redo], first[0][~redo])
+    assert np.array_equal(_np(pd)[~redo], first[1][~redo])
+    Ro, zo, _ = orc.qr(f.H, f.y)
+    kb = orc.kbest(Ro[redo], zo[redo], P, 32)
+    compare_symbols(_np(sym)[redo], orc.x_to_sym(kb["x"], P), kb["margin"], near_tie_tol(n), "fallback")
