@@ -150,11 +150,15 @@ def main():
     if det == "auto":
         det = "learned" if os.path.exists(WEIGHTS) else "kbest"
 
-    # ---------------- inputs (host generation, then resident in HBM)
+    # ---------------- inputs (host generation, then resident in HBM): one batch of
+    # all SNR points, frame i of SNR point j at index j * B + i
     t_gen = time.perf_counter()
     frames = [gen_frames(N_RX, N_TX, QAM, s, B, seed=args.seed, snr_idx=i) for i, s in enumerate(snrs)]
-    dev = [dict(H=torch.from_numpy(f.H).cuda(), y=torch.from_numpy(f.y).cuda(), s=torch.from_numpy(f.s_idx).cuda(),
-                sigma2=torch.full((B,), f.sigma2, device="cuda", dtype=torch.float32)) for f in frames]
+    NB = B * len(snrs)
+    H = torch.from_numpy(np.concatenate([f.H for f in frames])).cuda()
+    Y = torch.from_numpy(np.concatenate([f.y for f in frames])).cuda()
+    S_true = torch.from_numpy(np.concatenate([f.s_idx for f in frames])).cuda()
+    SIG2 = torch.from_numpy(np.repeat(np.array([f.sigma2 for f in frames], np.float32), B)).cuda()
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t_gen
 
@@ -167,13 +171,12 @@ def main():
     k_min, k_max = int(meta.get("k_min", 1)), int(meta.get("k_max", 64))
 
     # ---------------- preallocated buffers (nothing is allocated in the timed loop)
-    bufs = [dict(R=torch.empty(B, n * (n + 1) // 2, device="cuda"), z=torch.empty(B, n, device="cuda"),
-                 sym=torch.empty(B, M, device="cuda", dtype=torch.int32), pd=torch.empty(B, device="cuda"),
-                 flags=torch.empty(B, device="cuda", dtype=torch.int32),
-                 metric=torch.empty(B, device="cuda", dtype=torch.float64),
-                 counts=torch.zeros(3, device="cuda", dtype=torch.int64),
-                 feat=torch.empty(B, n, 4, device="cuda"), ks=torch.empty(B, n, device="cuda", dtype=torch.int32))
-            for _ in snrs]
+    o = dict(R=torch.empty(NB, n * (n + 1) // 2, device="cuda"), z=torch.empty(NB, n, device="cuda"),
+             sym=torch.empty(NB, M, device="cuda", dtype=torch.int32), pd=torch.empty(NB, device="cuda"),
+             flags=torch.empty(NB, device="cuda", dtype=torch.int32),
+             metric=torch.empty(NB, device="cuda", dtype=torch.float64),
+             counts=torch.zeros(len(snrs), 3, device="cuda", dtype=torch.int64),
+             feat=torch.empty(NB, n, 4, device="cuda"), ks=torch.empty(NB, n, device="cuda", dtype=torch.int32))
     stream = torch.cuda.current_stream()
     ev = {}
 
@@ -187,32 +190,29 @@ def main():
         ev.setdefault(tag, []).append((a, b))
 
     def step(detector, record):
-        for i in range(len(snrs)):
-            d, o = dev[i], bufs[i]
-            out3 = (o["sym"], o["pd"], o["flags"], None)
-            timed("qr", record, lambda: mimo.qr_preprocess(d["H"], d["y"], out=(o["R"], o["z"], None)))
-            if detector == "kbest":
-                timed("kbest", record, lambda: mimo.kbest_detect(o["R"], o["z"], M, P, args.K, out=out3))
-            elif detector == "hybrid":
-                timed("hybrid", record, lambda: mimo.sd_hybrid_detect(o["R"], o["z"], M, P, args.workers,
-                                                                      args.k_worker, out=out3))
-            else:
-                timed("features", record, lambda: mimo.prune_features(o["R"], o["z"], d["sigma2"], M, P,
-                                                                      out=o["feat"]))
-                timed("mlp", record, lambda: mimo.mlp_schedule(w, o["feat"].view(B * n, 4), n, margin, k_min, k_max,
-                                                               out=o["ks"].view(B * n)))
-                timed("kbest", record, lambda: mimo.kbest_detect(o["R"], o["z"], M, P, k_max, k_sched=o["ks"],
-                                                                 out=out3))
-                timed("fallback", record, lambda: mimo.kbest_fallback(o["R"], o["z"], M, P, args.K, d["sigma2"],
-                                                                      beta, out3))
-            timed("metric", record, lambda: mimo.metric(d["H"], d["y"], o["sym"], P, out=o["metric"]))
-            timed("errors", record, lambda: mimo.error_count(o["sym"], d["s"], P, counts=o["counts"]))
+        out3 = (o["sym"], o["pd"], o["flags"], None)
+        timed("qr", record, lambda: mimo.qr_preprocess(H, Y, out=(o["R"], o["z"], None)))
+        if detector == "kbest":
+            timed("kbest", record, lambda: mimo.kbest_detect(o["R"], o["z"], M, P, args.K, out=out3))
+        elif detector == "hybrid":
+            timed("hybrid", record, lambda: mimo.sd_hybrid_detect(o["R"], o["z"], M, P, args.workers, args.k_worker,
+                                                                  out=out3))
+        else:
+            timed("features", record, lambda: mimo.prune_features(o["R"], o["z"], SIG2, M, P, out=o["feat"]))
+            timed("mlp", record, lambda: mimo.mlp_schedule(w, o["feat"].view(NB * n, 4), n, margin, k_min, k_max,
+                                                           out=o["ks"].view(NB * n)))
+            timed("kbest", record, lambda: mimo.kbest_detect(o["R"], o["z"], M, P, k_max, k_sched=o["ks"],
+                                                             out=out3))
+            timed("fallback", record, lambda: mimo.kbest_fallback(o["R"], o["z"], M, P, args.K, SIG2, beta, out3))
+        timed("metric", record, lambda: mimo.metric(H, Y, o["sym"], P, out=o["metric"]))
+        for i in range(len(snrs)):  # per-SNR error counts
+            sl = slice(i * B, (i + 1) * B)
+            timed("errors", record, lambda: mimo.error_count(o["sym"][sl], S_true[sl], P, counts=o["counts"][i]))
 
     def run(detector, record):
         for _ in range(args.warmup):
             step(detector, False)
-        for o in bufs:
-            o["counts"].zero_()
+        o["counts"].zero_()
         ev.clear()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -220,15 +220,15 @@ def main():
             step(detector, record)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        counts = np.array([o["counts"].cpu().numpy() for o in bufs]) // max(1, args.steps)
+        counts = o["counts"].cpu().numpy() // max(1, args.steps)
         kavg = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in ev.items()}
         extra = {}
         if detector == "learned":
-            fl = np.array([o["flags"].cpu().numpy() for o in bufs])
+            fl = o["flags"].cpu().numpy()
             extra["fallback_fraction"] = float(((fl & mimo.FLAG_LEARNED_FALLBACK) != 0).mean())
-            ks = np.concatenate([o["ks"].cpu().numpy() for o in bufs])
+            ks = o["ks"].cpu().numpy()
             extra["mean_k_t"] = float(ks.mean())
-            extra["ks_first"] = bufs[0]["ks"].cpu().numpy()
+            extra["ks"] = ks
         return dt, counts, kavg, extra
 
     frames_per_step = B * len(snrs)
@@ -239,9 +239,9 @@ def main():
     # dominant kernel and its roofline
     dom = max(kavg, key=kavg.get)
     if dom == "qr":
-        flops, src, kname = qr_flops(N_RX, N_TX) * B, "qr.hip", "qr_kernel"
+        flops, src, kname = qr_flops(N_RX, N_TX) * NB, "qr.hip", "qr_kernel"
     elif dom == "kbest":
-        cnt = plain_counts(n, P, args.K) * B if det == "kbest" else sched_counts(extra["ks_first"], P)
+        cnt = plain_counts(n, P, args.K) * NB if det == "kbest" else sched_counts(extra["ks"], P)
         flops, src, kname = kbest_flops_from_counts(cnt, P), "kbest.hip", "kbest_reg_kernel"
     else:
         flops, src, kname = None, None, dom
@@ -251,14 +251,14 @@ def main():
         traffic = None
         if os.path.exists(TRAFFIC_FILE):
             ent = json.load(open(TRAFFIC_FILE)).get(kname)
-            if ent and ent.get("source_hash") == kernel_source_hash(src) and ent.get("frames") == B:
+            if ent and ent.get("source_hash") == kernel_source_hash(src) and ent.get("frames") == NB:
                 traffic = ent.get("bytes_per_launch")
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": traffic,
                     "kernel": kname, "avg_launch_ms": round(kavg[dom], 4), "algorithmic_flops_per_launch": flops}
 
     det_tags = [k for k in kavg if k not in ("qr", "metric", "errors")]
-    det_ms = sum(kavg[k] for k in det_tags) * len(snrs)
+    det_ms = sum(kavg[k] for k in det_tags)
     out = {
         "metric": METRIC, "value": round(fps, 1), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 3), "higher_is_better": True,
@@ -287,7 +287,7 @@ def main():
             if other == det:
                 continue
             odt, oc, okavg, _ = run(other, True)
-            det_ms_o = sum(v for k, v in okavg.items() if k not in ("qr", "metric", "errors")) * len(snrs)
+            det_ms_o = sum(v for k, v in okavg.items() if k not in ("qr", "metric", "errors"))
             out["plain_kbest" if other == "kbest" else "paper_hybrid"] = {
                 "detector": f"K-best K={args.K}" if other == "kbest" else
                 f"SD-K-best, {args.workers} workers x {args.k_worker} survivors",
@@ -296,21 +296,19 @@ def main():
                 "symbol_errors": oc[:, 1].tolist(), "bit_errors": oc[:, 0].tolist()}
     # ---------------- maximum-likelihood reference (untimed)
     if not args.no_ml:
-        ml_err, cert = [], 0
-        for i in range(len(snrs)):
-            d, o = dev[i], bufs[i]
-            mimo.qr_preprocess(d["H"], d["y"], out=(o["R"], o["z"], None))
-            sk, pk, _ = mimo.kbest_detect(o["R"], o["z"], M, P, args.K)
-            r2 = (pk * (1.0 + 1e-4)).contiguous()
-            sm, _, fm = mimo.sd_hybrid_detect(o["R"], o["z"], M, P, 0, 1, radius2=r2, node_budget=400000)
-            sm = torch.where(((fm & mimo.FLAG_FOUND) != 0)[:, None], sm, sk)
-            ml_err.append(int((sm != d["s"]).sum()))
-            cert += int(((fm & mimo.FLAG_CERTIFIED) != 0).sum())
+        mimo.qr_preprocess(H, Y, out=(o["R"], o["z"], None))
+        sk, pk, _ = mimo.kbest_detect(o["R"], o["z"], M, P, args.K)
+        r2 = (pk * (1.0 + 1e-4)).contiguous()
+        sm, _, fm = mimo.sd_hybrid_detect(o["R"], o["z"], M, P, 0, 1, radius2=r2, node_budget=400000)
+        sm = torch.where(((fm & mimo.FLAG_FOUND) != 0)[:, None], sm, sk)
+        err = (sm != S_true).view(len(snrs), B, M).sum(dim=(1, 2)).cpu().numpy()
+        ml_err = [int(e) for e in err]
+        cert = int(((fm & mimo.FLAG_CERTIFIED) != 0).sum())
         out["ml_reference"] = {"symbol_errors": ml_err, "certified_fraction": round(cert / frames_per_step, 5),
                                "method": f"exact Best-FS SD warm-started by K-best K={args.K} "
                                          "(node budget 4e5; uncertified frames keep the K-best result)"}
         mine = counts[:, 1]
-        out["matched_ber"] = bool(all(m <= 1.05 * r + 0.0 for m, r in zip(mine, ml_err)))
+        out["matched_ber"] = bool(all(m <= 1.05 * r for m, r in zip(mine, ml_err)))
     if args.copy_probe_mib:
         nbytes = args.copy_probe_mib << 20
         a = torch.empty(nbytes // 4, device="cuda")

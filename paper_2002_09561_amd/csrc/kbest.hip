@@ -93,8 +93,8 @@ __device__ inline void kb_wave_sync()
 // all candidates is returned and the candidate is kept in the last slot if
 // it would be dropped.  Returns the number kept; *fpos_out receives the
 // forced candidate's 0-based rank (-1 when absent).
-template <int E>
-__device__ inline int kb_select(const uint32_t (&kh)[E], int ncand, int nvalid, int Kt, int fm, int lane, float* sn,
+template <int E, int KS>
+__device__ __forceinline__ int kb_select(const uint32_t (&kh)[E], int ncand, int nvalid, int Kt, int fm, int lane, float* sn,
                                 int32_t* sel, uint64_t* skey, int* fpos_out)
 {
     // blocks e with e * 64 >= ncand hold no candidate (uniform skips)
@@ -127,9 +127,25 @@ __device__ inline int kb_select(const uint32_t (&kh)[E], int ncand, int nvalid, 
 #pragma unroll
         for (int e = 0; e < E; ++e) take[e] = kh[e] != ~0u;
     } else {
-        // bitwise binary search for the keep-th smallest pd bits
-        uint32_t v = 0;
-        for (int bit = 30; bit >= 0; --bit) {
+        // bitwise binary search for the keep-th smallest pd bits, over the
+        // bits where the smallest and largest valid keys differ
+        uint32_t lo = ~0u, hi = 0u;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (e * WAVE >= ncand) continue;
+            if (kh[e] != ~0u) {
+                lo = min(lo, kh[e]);
+                hi = max(hi, kh[e]);
+            }
+        }
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            lo = min(lo, (uint32_t)__shfl_xor(lo, m, WAVE));
+            hi = max(hi, (uint32_t)__shfl_xor(hi, m, WAVE));
+        }
+        const int top = (lo == hi) ? -1 : 31 - __clz(lo ^ hi);  // highest differing bit
+        uint32_t v = top < 0 ? lo : (lo & ~((2u << top) - 1u));   // common prefix, low bits clear
+        for (int bit = top; bit >= 0; --bit) {
             const uint32_t cand = v | (1u << bit);
             int c = 0;
 #pragma unroll
@@ -175,13 +191,21 @@ __device__ inline int kb_select(const uint32_t (&kh)[E], int ncand, int nvalid, 
         base += (int)__popcll(bal);
     }
     kb_wave_sync();
-    // order the kept keys by rank counting; survivor slot = rank
-    for (int i = lane; i < keep; i += WAVE) {
-        const uint64_t ki = skey[i];
-        int r = 0;
-        for (int j = 0; j < keep; ++j) r += skey[j] < ki;
-        sn[r] = __uint_as_float((uint32_t)(ki >> 32));
-        sel[r] = (int32_t)(uint32_t)ki;
+    // sort the kept keys in the wave; survivor slot = rank
+    uint64_t sk[KS];
+#pragma unroll
+    for (int e = 0; e < KS; ++e) {
+        const int i = e * WAVE + lane;
+        sk[e] = i < keep ? skey[i] : ~0ull;
+    }
+    bitonic_sort<KS>(sk, lane);
+#pragma unroll
+    for (int e = 0; e < KS; ++e) {
+        const int r = e * WAVE + lane;
+        if (r < keep) {
+            sn[r] = __uint_as_float((uint32_t)(sk[e] >> 32));
+            sel[r] = (int32_t)(uint32_t)sk[e];
+        }
     }
     *fpos_out = fpos;
     return keep;
@@ -189,7 +213,7 @@ __device__ inline int kb_select(const uint32_t (&kh)[E], int ncand, int nvalid, 
 
 // K-best of one frame by one wavefront; lds as sized by kbest_lds_bytes.
 template <int P, int E>
-__device__ void kbest_frame(const KbestArgs& a, int frame, unsigned char* lds)
+__device__ __forceinline__ void kbest_frame(const KbestArgs& a, int frame, unsigned char* lds)
 {
     using S = KbestShape<P, E>;
     constexpr int KCAP = S::KCAP, L = S::L, SPL = S::SPL;
@@ -312,7 +336,7 @@ __device__ void kbest_frame(const KbestArgs& a, int frame, unsigned char* lds)
             if (fs < 0) fm = -1;
         }
         int fpos = -1;
-        const int keep = kb_select<E>(kh, cnt * P, nvalid, Kt, fm, lane, sn, sel, skey, &fpos);
+        const int keep = kb_select<E, (KCAP + WAVE - 1) / WAVE>(kh, cnt * P, nvalid, Kt, fm, lane, sn, sel, skey, &fpos);
         if (fsym) {
             if (lane == 0) a.rank[(size_t)frame * n + k] = fpos + 1;
             fs = fpos >= 0 ? (fpos < keep ? fpos : keep - 1) : -1;
@@ -378,24 +402,25 @@ __device__ void kbest_frame(const KbestArgs& a, int frame, unsigned char* lds)
 template <int NWMAX>
 __host__ __device__ inline size_t kbest_reg_lds_bytes(int kcap)
 {
-    return sizeof(float) * 2 * kcap + sizeof(float) * (2 * NWMAX + 8) + sizeof(int32_t) * kcap +
+    return sizeof(float) * 2 * kcap + sizeof(float) * (2 * NWMAX + 16) + sizeof(int32_t) * kcap +
            sizeof(uint64_t) * kcap;
 }
 
 template <int P, int E, int NWMAX>
-__device__ void kbest_frame_reg(const KbestArgs& a, int frame, unsigned char* lds)
+__device__ __forceinline__ void kbest_frame_reg(const KbestArgs& a, int frame, unsigned char* lds)
 {
     using S = KbestShape<P, E>;
     constexpr int KCAP = S::KCAP, L = S::L;
     static_assert(KCAP <= 64, "register variant holds at most one survivor per lane");
     constexpr int NWL = NWMAX / L;  // path words per lane
+    constexpr int CHW = NWL < 8 ? NWL : 8;  // words per guarded chunk
     const int lane = threadIdx.x & 63;
     const int s_own = lane / L, q = lane % L;
     const int n = a.n;
     const int nw = n / 2;
     float* spd = reinterpret_cast<float*>(lds);
     float* rrow = spd + 2 * KCAP;
-    int32_t* sel = reinterpret_cast<int32_t*>(rrow + 2 * NWMAX + 8);
+    int32_t* sel = reinterpret_cast<int32_t*>(rrow + 2 * NWMAX + 16);
     uint64_t* skey = reinterpret_cast<uint64_t*>(sel + KCAP);
 
     const float* Rf = a.R + (size_t)frame * r_packed_size(n);
@@ -408,7 +433,7 @@ __device__ void kbest_frame_reg(const KbestArgs& a, int frame, unsigned char* ld
     uint32_t pw[NWL];
 #pragma unroll
     for (int i = 0; i < NWL; ++i) pw[i] = 0u;  // unassigned levels are amplitude 0
-    for (int t = lane; t < 2 * NWMAX + 8; t += WAVE) rrow[t] = 0.f;
+    for (int t = lane; t < 2 * NWMAX + 16; t += WAVE) rrow[t] = 0.f;
     if (lane == 0) spd[0] = 0.f;
     int cnt = 1, fs = 0;
     int64_t expanded = 0;
@@ -451,14 +476,20 @@ __device__ void kbest_frame_reg(const KbestArgs& a, int frame, unsigned char* ld
         kb_wave_sync();
         // centre of this lane's survivor: levels <= k hold amplitude 0 and
         // rrow[k] = 0, so whole words can be summed from the one of level k+1
+        // words are taken in chunks of CHW: a word below the live range holds
+        // amplitude 0 (a level not yet fixed) and a word beyond nw meets zero
+        // row entries, so whole chunks can be summed
         const int i_lo = ((k + 1) >> 1) / L;
         float acc = 0.f;
 #pragma unroll
-        for (int i = 0; i < NWL; ++i) {
-            if (i >= i_lo && i < i_hi) {
-                const float2 rr = *reinterpret_cast<const float2*>(rrow + 2 * (q + L * i));
-                acc = fmaf(rr.x, half_lo(pw[i]), acc);
-                acc = fmaf(rr.y, half_hi(pw[i]), acc);
+        for (int c0 = 0; c0 < NWL; c0 += CHW) {
+            if (c0 + CHW > i_lo && c0 < i_hi) {
+#pragma unroll
+                for (int i = c0; i < c0 + CHW; ++i) {
+                    const float2 rr = *reinterpret_cast<const float2*>(rrow + 2 * (q + L * i));
+                    acc = fmaf(rr.x, half_lo(pw[i]), acc);
+                    acc = fmaf(rr.y, half_hi(pw[i]), acc);
+                }
             }
         }
 #pragma unroll
@@ -497,7 +528,7 @@ __device__ void kbest_frame_reg(const KbestArgs& a, int frame, unsigned char* ld
             fm = fs * P + ((k & 1) ? (sy % P) : (sy / P));
         }
         int fpos = -1;
-        const int keep = kb_select<E>(kh, cnt * P, nvalid, Kt, fm, lane, sn, sel, skey, &fpos);
+        const int keep = kb_select<E, (KCAP + WAVE - 1) / WAVE>(kh, cnt * P, nvalid, Kt, fm, lane, sn, sel, skey, &fpos);
         if (fsym) {
             if (lane == 0) a.rank[(size_t)frame * n + k] = fpos + 1;
             fs = fpos >= 0 ? (fpos < keep ? fpos : keep - 1) : -1;
@@ -511,9 +542,14 @@ __device__ void kbest_frame_reg(const KbestArgs& a, int frame, unsigned char* ld
             cnew = m % P;
         }
         const int wk = k >> 1, ik = wk / L;
+        // (words below level k hold zeros for every survivor: moving them is harmless)
 #pragma unroll
-        for (int i = 0; i < NWL; ++i)
-            if (i >= ik && i < i_hi) pw[i] = (uint32_t)__shfl((int)pw[i], src, WAVE);
+        for (int c0 = 0; c0 < NWL; c0 += CHW) {
+            if (c0 + CHW > ik && c0 < i_hi) {
+#pragma unroll
+                for (int i = c0; i < c0 + CHW; ++i) pw[i] = (uint32_t)__shfl((int)pw[i], src, WAVE);
+            }
+        }
         if (s_own < keep && q == wk % L) {
             const uint32_t hb = half_bits((float)(2 * cnew - (P - 1)));
 #pragma unroll

@@ -170,45 +170,45 @@ def detect(w, R, z, sigma2, n_tx: int, pam: int, margin: float, k_min: int, k_ma
     return out[0], out[1], out[2], ks
 
 
-def calibrate(w, n_tx, qam, snrs, frames, seed, k_min, k_max, plain_K, margins, betas, log=print):
-    """Fastest (margin, beta) whose learned detection makes at most 5% more
-    symbol errors than plain K-best (K = plain_K, the setting whose errors
-    match the exact SD) on the calibration frames, at every SNR."""
+def calibrate(w, n_tx, qam, snrs, frames, seed, k_min, plain_K, k_maxes, margins, betas, log=print):
+    """Fastest (k_max, margin, beta) whose learned detection makes at most 5%
+    more symbol errors than plain K-best (K = plain_K, the setting whose
+    errors match the exact SD) on the calibration frames at every SNR.  All
+    SNR points run as one batch, as in the benchmark."""
     P = math.isqrt(qam)
-    data = []
-    for si, snr in enumerate(snrs):
-        f = gen_frames(n_tx, n_tx, qam, snr, frames, seed=seed, snr_idx=si)
-        H = torch.from_numpy(f.H).cuda()
-        y = torch.from_numpy(f.y).cuda()
-        s = torch.from_numpy(f.s_idx).cuda()
-        R, z = mimo.qr_preprocess(H, y)
-        s2 = torch.full((frames,), f.sigma2, device="cuda", dtype=torch.float32)
+    fr = [gen_frames(n_tx, n_tx, qam, snr, frames, seed=seed, snr_idx=si) for si, snr in enumerate(snrs)]
+    H = torch.from_numpy(np.concatenate([f.H for f in fr])).cuda()
+    Y = torch.from_numpy(np.concatenate([f.y for f in fr])).cuda()
+    S = torch.from_numpy(np.concatenate([f.s_idx for f in fr])).cuda()
+    s2 = torch.from_numpy(np.repeat(np.array([f.sigma2 for f in fr], np.float32), frames)).cuda()
+    R, z = mimo.qr_preprocess(H, Y)
+
+    def per_snr_errors(sym):
+        return [int(e) for e in (sym != S).view(len(snrs), frames, -1).sum(dim=(1, 2)).cpu()]
+
+    def timed(fn):
+        fn()  # warm
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        sp, _, _ = mimo.kbest_detect(R, z, n_tx, P, plain_K)
+        r = fn()
         torch.cuda.synchronize()
-        data.append((R, z, s, s2, int((sp != s).sum()), time.perf_counter() - t0))
-    t_plain = sum(d[5] for d in data)
+        return r, time.perf_counter() - t0
+
+    (sp, _, _), t_plain = timed(lambda: mimo.kbest_detect(R, z, n_tx, P, plain_K))
+    pe = per_snr_errors(sp)
+    log(f"  plain K={plain_K}: errors {pe}, {t_plain * 1e3:.2f} ms")
     best = None
-    for mg in margins:
-        for beta in betas:
-            errs, fb, kmean, t = [], 0, [], 0.0
-            for R, z, s, s2, pe, _ in data:
-                detect(w, R, z, s2, n_tx, P, mg, k_min, k_max, beta, plain_K)  # warm
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                sl, _, fl, ks = detect(w, R, z, s2, n_tx, P, mg, k_min, k_max, beta, plain_K)
-                torch.cuda.synchronize()
-                t += time.perf_counter() - t0
-                errs.append((int((sl != s).sum()), pe))
-                fb += int(((fl & mimo.FLAG_LEARNED_FALLBACK) != 0).sum())
-                kmean.append(float(ks.float().mean()))
-            ok = all(e <= p * 1.05 for e, p in errs)
-            log(f"  margin {mg:.2f} beta {beta:.1f}: errors learned/plain {errs}, mean K_t {np.mean(kmean):.2f}, "
-                f"fallback {fb / (frames * len(snrs)):.4f}, time {t * 1e3:.2f} ms vs plain {t_plain * 1e3:.2f} ms"
-                f"{'  ok' if ok else ''}")
-            if ok and (best is None or t < best[4]):
-                best = (mg, beta, errs, float(np.mean(kmean)), t, fb / (frames * len(snrs)), t_plain)
+    for km in k_maxes:
+        for mg in margins:
+            for beta in betas:
+                (sl, _, fl, ks), t = timed(lambda: detect(w, R, z, s2, n_tx, P, mg, k_min, km, beta, plain_K))
+                le = per_snr_errors(sl)
+                fb = float(((fl & mimo.FLAG_LEARNED_FALLBACK) != 0).float().mean())
+                ok = all(e <= p * 1.05 for e, p in zip(le, pe))
+                log(f"  k_max {km} margin {mg:.2f} beta {beta:.1f}: errors {le}, mean K_t {float(ks.float().mean()):.2f},"
+                    f" fallback {fb:.4f}, {t * 1e3:.2f} ms{'  ok' if ok else ''}")
+                if ok and (best is None or t < best[5]):
+                    best = (km, mg, beta, le, float(ks.float().mean()), t, fb, t_plain, pe)
     return best
 
 
@@ -229,25 +229,44 @@ def main(argv=None):
     ap.add_argument("--calib-frames", type=int, default=2000)
     ap.add_argument("--seed", type=int, default=777)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--calibrate-only", default=None, help="recalibrate an existing checkpoint in place")
     a = ap.parse_args(argv)
     mimo.load()
     snrs = [float(s) for s in a.snrs.split(",")]
     t0 = time.time()
+    if a.calibrate_only:
+        w, meta, m, v = load_weights(a.calibrate_only, with_moments=True)
+        w = w.cuda()
+        cal = calibrate(w, a.n_tx, a.qam, snrs, a.calib_frames, a.seed + 1, a.k_min, a.plain_K,
+                        k_maxes=[16, 32, 64], margins=[2.0, 3.0, 3.5, 4.0, 4.5, 5.0], betas=[2.0, 3.0, 4.0, 6.0])
+        if cal:
+            meta.update(k_max=cal[0], margin=cal[1], beta=cal[2], plain_K=a.plain_K)
+            meta["calibration"] = dict(symbol_errors_learned=cal[3], symbol_errors_plain=cal[8], mean_k=cal[4],
+                                       learned_ms=cal[5] * 1e3, fallback_fraction=cal[6], plain_ms=cal[7] * 1e3,
+                                       frames_per_snr=a.calib_frames)
+        for k in ("nparam", "step", "has_moments"):
+            meta.pop(k, None)
+        save_weights(a.out or a.calibrate_only, w, meta, m, v, step=int(meta.get("steps", 0)))
+        print(json.dumps({k: meta[k] for k in meta if k != "loss_history"}))
+        return
     X, y, st = training_states(a.n_tx, a.qam, snrs, a.frames, a.seed, k_label=a.k_label)
     yc = y.cpu().numpy()
     print(f"states: {X.shape[0]} from {st['certified']} certified frames ({time.time() - t0:.1f} s); "
           f"rank 1: {np.mean(yc == 0):.4f}, rank > 16: {np.mean(yc > 4):.5f}, max rank {2 ** yc.max():.0f}")
     w, m, v, hist = train(X, y, steps=a.steps, batch=a.batch, lr=a.lr, tau=a.tau, seed=a.seed)
-    cal = calibrate(w, a.n_tx, a.qam, snrs, a.calib_frames, a.seed + 1, a.k_min, a.k_max, a.plain_K,
-                    margins=[1.0, 2.0, 2.5, 3.0, 3.5, 4.0, 4.5, 5.0], betas=[2.0, 3.0, 4.0, 6.0])
+    cal = calibrate(w, a.n_tx, a.qam, snrs, a.calib_frames, a.seed + 1, a.k_min, a.plain_K,
+                    k_maxes=[16, 32, 64], margins=[2.0, 3.0, 3.5, 4.0, 4.5, 5.0], betas=[2.0, 3.0, 4.0, 6.0])
     tag = f"{a.n_tx}x{a.n_tx}_{a.qam}qam"
     meta = dict(n_tx=a.n_tx, qam=a.qam, snrs=snrs, frames=a.frames, states=int(X.shape[0]), tau=a.tau,
-                k_min=a.k_min, k_max=a.k_max, k_label=a.k_label, steps=a.steps, lr=a.lr, seed=a.seed,
+                k_min=a.k_min, k_label=a.k_label, steps=a.steps, lr=a.lr, seed=a.seed,
                 loss_history=hist, plain_K=a.plain_K)
     if cal:
-        meta.update(margin=cal[0], beta=cal[1])
-        meta["calibration"] = dict(symbol_errors_learned_vs_plain=cal[2], mean_k=cal[3], learned_ms=cal[4] * 1e3,
-                                   fallback_fraction=cal[5], plain_ms=cal[6] * 1e3)
+        meta.update(k_max=cal[0], margin=cal[1], beta=cal[2])
+        meta["calibration"] = dict(symbol_errors_learned=cal[3], symbol_errors_plain=cal[8], mean_k=cal[4],
+                                   learned_ms=cal[5] * 1e3, fallback_fraction=cal[6], plain_ms=cal[7] * 1e3,
+                                   frames_per_snr=a.calib_frames)
+    else:
+        meta.update(k_max=a.k_max, margin=5.0, beta=3.0)
     out = a.out or os.path.join(WEIGHTS_DIR, f"prune_mlp_{tag}.bin")
     save_weights(out, w, meta, m, v, step=a.steps)
     print(json.dumps({k: meta[k] for k in meta if k != "loss_history"}))
