@@ -5,11 +5,11 @@
 // N x (M+1) matrix [H | y] lives in registers: lane l of every wave owns the
 // columns l, l + 64, ... (CB = ceil((M+1)/64) of them) for the rows of its
 // wave's chunk.  Householder step k:
-//   1. the owner lane of column k (in every wave) publishes its rows >= k and
-//      the chunk's partial squared norm in LDS;
+//   1. every wave broadcasts its rows of column k from the owner lane
+//      (readlane: wave-uniform values) and publishes the chunk's partial
+//      squared norm in LDS;
 //   2. every thread forms the reflector v = x - alpha e1 with
-//      alpha = -phase(x0) ||x|| (wave-uniform scalars) and loads the v_i of
-//      its rows once into registers;
+//      alpha = -phase(x0) ||x|| (wave-uniform scalars);
 //   3. phase 1: partial w_j = sum_i conj(v_i) A_ij over the chunk's rows;
 //   4. phase 2: w_j = sum of the chunk partials, A_ij -= tau v_i w_j.
 // Rows outside [k, N) carry v_i = 0, so the updates need no row guards.
@@ -41,9 +41,9 @@ __global__ void __launch_bounds__(512, CB <= 2 ? 4 : 2) qr_kernel(const float2* 
     const int ncol = CB * WAVE;
     const int n = 2 * M;
 
-    // LDS: colv[2][N + RB] c32, wpart[rc][ncol] c32, alpha[M] c32, pnorm[2][rc] f32
-    c32* colv = reinterpret_cast<c32*>(smem_qr);
-    c32* wpart = colv + 2 * (N + QR_RB);
+    // LDS: x0s[2] c32, wpart[rc][ncol] c32, alpha[M] c32, pnorm[2][rc] f32
+    c32* x0s = reinterpret_cast<c32*>(smem_qr);
+    c32* wpart = x0s + 2;
     c32* alpha_s = wpart + rc * ncol;
     float* pnorm = reinterpret_cast<float*>(alpha_s + M);
 
@@ -68,24 +68,29 @@ __global__ void __launch_bounds__(512, CB <= 2 ? 4 : 2) qr_kernel(const float2* 
 
     for (int k = 0; k < M; ++k) {
         const int buf = k & 1;
-        c32* cv = colv + buf * (N + QR_RB);
         float* pn = pnorm + buf * rc;
         const int kcb = k / WAVE, klane = k % WAVE;
-        // 1. publish column k (all rows of this chunk; only rows > k are read)
-        //    and the chunk's partial squared norm over rows >= k
-        if (lane == klane) {
-            float s = 0.f;
+        // 1. column k of this wave's rows, broadcast from its owner lane
+        //    (wave-uniform values), and the chunk's partial squared norm over
+        //    rows >= k; the wave holding row k publishes x0 = A_kk
+        c32 colk[QR_RB];
+        float s = 0.f;
 #pragma unroll
-            for (int q = 0; q < QR_RB; ++q) {
-                const int i = row0 + q;
-                c32 x = A[q][0];
+        for (int q = 0; q < QR_RB; ++q) {
+            c32 x = A[q][0];
 #pragma unroll
-                for (int cb = 1; cb < CB; ++cb)
-                    if (cb == kcb) x = A[q][cb];
-                cv[i] = x;
-                s += (i >= k) ? x.x * x.x + x.y * x.y : 0.f;
-            }
+            for (int cb = 1; cb < CB; ++cb)
+                if (cb == kcb) x = A[q][cb];
+            colk[q].x = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x.x), klane));
+            colk[q].y = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x.y), klane));
+            const int i = row0 + q;
+            if (i >= k && i < N) s = fmaf(colk[q].x, colk[q].x, fmaf(colk[q].y, colk[q].y, s));
+        }
+        if (lane == 0) {
             pn[r] = s;
+#pragma unroll
+            for (int q = 0; q < QR_RB; ++q)
+                if (row0 + q == k) x0s[buf] = colk[q];
         }
         __syncthreads();
         if (row0 + QR_RB <= k) {  // this chunk is finished: only the barrier remains
@@ -95,7 +100,7 @@ __global__ void __launch_bounds__(512, CB <= 2 ? 4 : 2) qr_kernel(const float2* 
         // 2. reflector scalars (uniform)
         float norm2 = 0.f;
         for (int rr = 0; rr < rc; ++rr) norm2 += pn[rr];
-        const c32 x0 = cv[k];
+        const c32 x0 = x0s[buf];
         const float ax0 = sqrtf(x0.x * x0.x + x0.y * x0.y);
         const float norm = sqrtf(norm2);
         const c32 ph = ax0 > 0.f ? c32{x0.x / ax0, x0.y / ax0} : c32{1.f, 0.f};
@@ -109,25 +114,27 @@ __global__ void __launch_bounds__(512, CB <= 2 ? 4 : 2) qr_kernel(const float2* 
 #pragma unroll
         for (int q = 0; q < QR_RB; ++q) {
             const int i = row0 + q;
-            const c32 t = cv[i];
-            vr[q] = (i > k && i < N) ? t : (i == k ? v0 : c32{0.f, 0.f});
+            vr[q] = (i > k && i < N) ? colk[q] : (i == k ? v0 : c32{0.f, 0.f});
         }
         // 3. phase 1: partial w_j = sum_i conj(v_i) A_ij over this chunk
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
             if ((cb + 1) * WAVE <= k) continue;  // every column of this block is finished (uniform)
-            c32 s = {0.f, 0.f};
+            c32 sw = {0.f, 0.f};
 #pragma unroll
             for (int q = 0; q < QR_RB; ++q) {
-                s.x = fmaf(vr[q].x, A[q][cb].x, s.x);
-                s.x = fmaf(vr[q].y, A[q][cb].y, s.x);
-                s.y = fmaf(vr[q].x, A[q][cb].y, s.y);
-                s.y = fmaf(-vr[q].y, A[q][cb].x, s.y);
+                sw.x = fmaf(vr[q].x, A[q][cb].x, sw.x);
+                sw.x = fmaf(vr[q].y, A[q][cb].y, sw.x);
+                sw.y = fmaf(vr[q].x, A[q][cb].y, sw.y);
+                sw.y = fmaf(-vr[q].y, A[q][cb].x, sw.y);
             }
-            wpart[r * ncol + lane + cb * WAVE] = s;
+            wpart[r * ncol + lane + cb * WAVE] = sw;
         }
         __syncthreads();
-        // 4. phase 2: apply the reflector; the pivot column becomes alpha e_k
+        // 4. phase 2: apply the reflector.  Finished columns (j < k) have w_j = 0
+        //    up to rounding of their (never used) sub-diagonal residue; the pivot
+        //    column's new values below the diagonal are never read either: its
+        //    diagonal is alpha, kept in alpha_s.
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
             if ((cb + 1) * WAVE <= k) continue;
@@ -140,8 +147,6 @@ __global__ void __launch_bounds__(512, CB <= 2 ? 4 : 2) qr_kernel(const float2* 
             }
             wj.x *= tau;
             wj.y *= tau;
-            // finished columns (j < k) have w_j = 0 exactly, so updating every
-            // column is exact; the pivot column is set below
 #pragma unroll
             for (int q = 0; q < QR_RB; ++q) {
                 A[q][cb].x = fmaf(-vr[q].x, wj.x, A[q][cb].x);
@@ -150,23 +155,7 @@ __global__ void __launch_bounds__(512, CB <= 2 ? 4 : 2) qr_kernel(const float2* 
                 A[q][cb].y = fmaf(-vr[q].y, wj.x, A[q][cb].y);
             }
         }
-        // pivot column: exactly alpha e_k
-        if (lane == klane) {
-#pragma unroll
-            for (int q = 0; q < QR_RB; ++q) {
-                const int i = row0 + q;
-#pragma unroll
-                for (int cb = 0; cb < CB; ++cb) {
-                    if (cb != kcb) continue;
-                    if (tau > 0.f) {  // (tau == 0 left the column unchanged)
-                        if (i == k) A[q][cb] = alpha;
-                        else if (i > k) A[q][cb] = {0.f, 0.f};
-                    }
-                }
-            }
-            const int qk = k - row0;
-            if (qk >= 0 && qk < QR_RB) alpha_s[k] = (tau > 0.f) ? alpha : x0;
-        }
+        if (lane == 0 && k >= row0 && k < row0 + QR_RB) alpha_s[k] = (tau > 0.f) ? alpha : x0;
     }
     __syncthreads();
 
@@ -225,7 +214,7 @@ static int32_t launch_qr(const float* H, const float* y, int B, int N, int M, fl
                          hipStream_t st)
 {
     const int rc = (N + QR_RB - 1) / QR_RB;
-    const size_t lds = sizeof(c32) * (2 * (N + QR_RB) + rc * CB * WAVE + M) + sizeof(float) * (2 * rc);
+    const size_t lds = sizeof(c32) * (2 + rc * CB * WAVE + M) + sizeof(float) * (2 * rc);
     hipLaunchKernelGGL(qr_kernel<CB>, dim3(B), dim3(rc * WAVE), lds, st, reinterpret_cast<const float2*>(H),
                        reinterpret_cast<const float2*>(y), N, M, R, z, resid);
     return check_launch("mimo_qr_preprocess");
