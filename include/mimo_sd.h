@@ -212,6 +212,37 @@ int32_t prune_mlp_loss_grad(const float* w, const float* X, const float* y, int6
 int32_t prune_mlp_adam_step(float* w, float* m, float* v, const float* grad, int32_t np, int32_t t,
                             float lr, float beta1, float beta2, float eps, void* stream);
 
+/* ---------------------------------------------------------------------
+ * Uneven batches: frames of different antenna counts and constellations in
+ * one batch.  Frame f is described by desc[f] (device memory):
+ * ------------------------------------------------------------------- */
+typedef struct {
+    int32_t n_rx, n_tx, pam, K; /* shape, PAM points, survivors (K-best) */
+    int64_t h_off;              /* complex offset of H (n_rx x n_tx complex64) in H_flat */
+    int64_t y_off;              /* complex offset of y (n_rx complex64) in y_flat */
+    int64_t r_off;              /* float offset of the packed R (n(n+1)/2) in R_flat */
+    int64_t z_off;              /* float offset of z (n floats) in z_flat */
+    int64_t s_off;              /* int offset of the symbols (n_tx) in sym_flat */
+} mimo_frame_desc;
+
+/* QR preprocessing (Sec. III-B) of an uneven batch in one persistent launch:
+ * `grid` workgroups (0 = two per compute unit) pull frames from the device
+ * work counter `counter` (one int32, reset by the call on the stream).
+ * max_rx >= every n_rx (<= 128); every n_tx <= 127.  Output layout as for
+ * mimo_qr_preprocess, at the frames' offsets. */
+int32_t mimo_qr_preprocess_uneven(const mimo_frame_desc* desc, int32_t B, int32_t max_rx,
+                                  const float* H_flat, const float* y_flat, float* R_flat, float* z_flat,
+                                  int32_t* counter, int32_t grid, void* stream);
+
+/* Batched K-best (Sec. VI) of an uneven batch in one persistent launch: one
+ * wavefront per workgroup pulls frames from `counter` (reset by the call)
+ * and runs K-best with the frame's own pam and K (desc[f].K * pam <= 256,
+ * n_tx <= 64).  sym_flat at the frames' s_off; pd [B], flags [B].
+ * grid = 0 picks eight workgroups per compute unit. */
+int32_t kbest_detect_uneven(const mimo_frame_desc* desc, int32_t B, const float* R_flat, const float* z_flat,
+                            int32_t* sym_flat, float* pd, uint32_t* flags, int32_t* counter, int32_t grid,
+                            void* stream);
+
 #ifdef __cplusplus
 }
 #endif

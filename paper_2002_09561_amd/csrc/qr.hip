@@ -27,16 +27,17 @@ struct c32 {
 
 __device__ inline c32 cmul(c32 a, c32 b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 
+// QR of one frame by the whole workgroup (rc = blockDim.x / 64 waves of
+// QR_RB rows; waves beyond the frame's rows only take part in the barriers).
 template <int CB>
-__global__ void __launch_bounds__(512, CB <= 2 ? 4 : 2) qr_kernel(const float2* __restrict__ H, const float2* __restrict__ y, int N,
-                                                 int M, float* __restrict__ R, float* __restrict__ z,
-                                                 float* __restrict__ resid)
+__device__ __forceinline__ void qr_frame(const float2* __restrict__ Hf, const float2* __restrict__ yf, int N, int M,
+                                         float* __restrict__ Rf, float* __restrict__ zf, float* __restrict__ resid_out,
+                                         float* smem_qr)
 {
-    extern __shared__ float smem_qr[];
-    const int frame = blockIdx.x;
     const int lane = threadIdx.x & 63;
     const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave index = row chunk (uniform)
     const int rc = blockDim.x >> 6;
+    const int rc_used = (N + QR_RB - 1) / QR_RB;
     const int row0 = r * QR_RB;
     const int ncol = CB * WAVE;
     const int n = 2 * M;
@@ -46,9 +47,6 @@ __global__ void __launch_bounds__(512, CB <= 2 ? 4 : 2) qr_kernel(const float2* 
     c32* wpart = x0s + 2;
     c32* alpha_s = wpart + rc * ncol;
     float* pnorm = reinterpret_cast<float*>(alpha_s + M);
-
-    const float2* Hf = H + (size_t)frame * N * M;
-    const float2* yf = y + (size_t)frame * N;
 
     c32 A[QR_RB][CB];
 #pragma unroll
@@ -93,7 +91,7 @@ __global__ void __launch_bounds__(512, CB <= 2 ? 4 : 2) qr_kernel(const float2* 
                 if (row0 + q == k) x0s[buf] = colk[q];
         }
         __syncthreads();
-        if (row0 + QR_RB <= k) {  // this chunk is finished: only the barrier remains
+        if (row0 + QR_RB <= k || row0 >= N) {  // finished or empty chunk: only the barrier remains
             __syncthreads();
             continue;
         }
@@ -119,7 +117,7 @@ __global__ void __launch_bounds__(512, CB <= 2 ? 4 : 2) qr_kernel(const float2* 
         // 3. phase 1: partial w_j = sum_i conj(v_i) A_ij over this chunk
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
-            if ((cb + 1) * WAVE <= k) continue;  // every column of this block is finished (uniform)
+            if ((cb + 1) * WAVE <= k || cb * WAVE > M) continue;  // block finished or beyond [H | y] (uniform)
             c32 sw = {0.f, 0.f};
 #pragma unroll
             for (int q = 0; q < QR_RB; ++q) {
@@ -137,10 +135,10 @@ __global__ void __launch_bounds__(512, CB <= 2 ? 4 : 2) qr_kernel(const float2* 
         //    diagonal is alpha, kept in alpha_s.
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
-            if ((cb + 1) * WAVE <= k) continue;
+            if ((cb + 1) * WAVE <= k || cb * WAVE > M) continue;
             const int j = lane + cb * WAVE;
             c32 wj = {0.f, 0.f};
-            for (int rr = k / QR_RB; rr < rc; ++rr) {  // chunks with rows >= k wrote this step's partials
+            for (int rr = k / QR_RB; rr < rc_used; ++rr) {  // chunks with rows >= k wrote this step's partials
                 const c32 t = wpart[rr * ncol + j];
                 wj.x += t.x;
                 wj.y += t.y;
@@ -161,8 +159,6 @@ __global__ void __launch_bounds__(512, CB <= 2 ? 4 : 2) qr_kernel(const float2* 
 
     // make R_kk real positive: scale row i by d_i = conj(a_i) / |a_i|, then
     // write the real blocks [[a, -b], [b, a]] in packed level order
-    float* Rf = R + (size_t)frame * r_packed_size(n);
-    float* zf = z + (size_t)frame * n;
     float rs = 0.f;
 #pragma unroll
     for (int q = 0; q < QR_RB; ++q) {
@@ -195,7 +191,7 @@ __global__ void __launch_bounds__(512, CB <= 2 ? 4 : 2) qr_kernel(const float2* 
         for (int cb = 0; cb < CB; ++cb)
             if (i >= M && i < N && lane + cb * WAVE == M) rs += A[q][cb].x * A[q][cb].x + A[q][cb].y * A[q][cb].y;
     }
-    if (resid) {
+    if (resid_out) {
         // rows >= M of the rotated y: only the lanes owning column M contribute
         __syncthreads();
         float part = wave_sum(rs);
@@ -204,10 +200,45 @@ __global__ void __launch_bounds__(512, CB <= 2 ? 4 : 2) qr_kernel(const float2* 
         if (threadIdx.x == 0) {
             float s = 0.f;
             for (int rr = 0; rr < rc; ++rr) s += pnorm[rr];
-            resid[frame] = s;
+            *resid_out = s;
         }
     }
+    __syncthreads();  // the LDS may be reused by the next frame
 }
+
+template <int CB>
+__global__ void __launch_bounds__(512, CB <= 2 ? 4 : 2) qr_kernel(const float2* __restrict__ H, const float2* __restrict__ y, int N,
+                                                 int M, float* __restrict__ R, float* __restrict__ z,
+                                                 float* __restrict__ resid)
+{
+    extern __shared__ float smem_qr[];
+    const int frame = blockIdx.x;
+    const int n = 2 * M;
+    qr_frame<CB>(H + (size_t)frame * N * M, y + (size_t)frame * N, N, M, R + (size_t)frame * r_packed_size(n),
+                 z + (size_t)frame * n, resid ? resid + frame : nullptr, smem_qr);
+}
+
+// Uneven batch: frames of different sizes pulled from a device work counter
+// by a persistent grid; every workgroup has enough waves for the largest frame.
+__global__ void __launch_bounds__(512, 2) qr_uneven_kernel(const mimo_frame_desc* __restrict__ desc, int B,
+                                                           const float2* __restrict__ H, const float2* __restrict__ y,
+                                                           float* __restrict__ R, float* __restrict__ z,
+                                                           int* __restrict__ counter)
+{
+    extern __shared__ float smem_qr[];
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int f = next;
+        __syncthreads();
+        if (f >= B) break;
+        const mimo_frame_desc d = desc[f];
+        qr_frame<2>(H + d.h_off, y + d.y_off, d.n_rx, d.n_tx, R + d.r_off, z + d.z_off, nullptr, smem_qr);
+    }
+}
+
+__global__ void reset_counter_kernel(int* counter) { *counter = 0; }
 
 template <int CB>
 static int32_t launch_qr(const float* H, const float* y, int B, int N, int M, float* R, float* z, float* resid,
@@ -238,4 +269,32 @@ extern "C" int32_t mimo_qr_preprocess(const float* H, const float* y, int32_t B,
     if (cols <= WAVE) return launch_qr<1>(H, y, B, n_rx, n_tx, R, z, resid, st);
     if (cols <= 2 * WAVE) return launch_qr<2>(H, y, B, n_rx, n_tx, R, z, resid, st);
     return launch_qr<3>(H, y, B, n_rx, n_tx, R, z, resid, st);
+}
+
+extern "C" int32_t mimo_qr_preprocess_uneven(const mimo_frame_desc* desc, int32_t B, int32_t max_rx,
+                                             const float* H_flat, const float* y_flat, float* R_flat, float* z_flat,
+                                             int32_t* counter, int32_t grid, void* stream)
+{
+    using namespace mimo;
+    if (B < 0 || grid < 0) return fail(MIMO_ERR_INVALID_ARG, "mimo_qr_preprocess_uneven: B < 0 or grid < 0");
+    if (max_rx < 1 || max_rx > MIMO_MAX_RX)
+        return fail(MIMO_ERR_UNSUPPORTED, "mimo_qr_preprocess_uneven: 1 <= max_rx <= %d", MIMO_MAX_RX);
+    if (B == 0) return MIMO_OK;
+    if (!desc || !H_flat || !y_flat || !R_flat || !z_flat || !counter)
+        return fail(MIMO_ERR_INVALID_ARG, "mimo_qr_preprocess_uneven: null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    const int rc = (max_rx + QR_RB - 1) / QR_RB;
+    const size_t lds = sizeof(c32) * (2 + rc * 2 * WAVE + MIMO_MAX_TX) + sizeof(float) * (2 * rc);
+    if (grid == 0) {
+        int dev = 0, cus = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        grid = 2 * (cus > 0 ? cus : 256);
+    }
+    if (grid > B) grid = B;
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
+    hipLaunchKernelGGL(qr_uneven_kernel, dim3(grid), dim3(rc * WAVE), lds, st, desc, B,
+                       reinterpret_cast<const float2*>(H_flat), reinterpret_cast<const float2*>(y_flat), R_flat,
+                       z_flat, counter);
+    return check_launch("mimo_qr_preprocess_uneven");
 }

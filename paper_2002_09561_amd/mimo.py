@@ -41,6 +41,8 @@ SIGNATURES = {
     "prune_mlp_workspace_bytes": ([_I64], _SZ),
     "prune_mlp_loss_grad": ([_P, _P, _P, _I64, _F, _P, _P, _P, _SZ, _P], _I32),
     "prune_mlp_adam_step": ([_P, _P, _P, _P, _I32, _I32, _F, _F, _F, _F, _P], _I32),
+    "mimo_qr_preprocess_uneven": ([_P, _I32, _I32, _P, _P, _P, _P, _P, _I32, _P], _I32),
+    "kbest_detect_uneven": ([_P, _I32, _P, _P, _P, _P, _P, _P, _I32, _P], _I32),
 }
 
 
@@ -245,3 +247,21 @@ def mlp_adam_step(w, m, v, g, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-
     _check(load().prune_mlp_adam_step(_ptr(w, torch.float32, "w"), _ptr(m, torch.float32, "m"),
                                       _ptr(v, torch.float32, "v"), _ptr(g, torch.float32, "g"), w.numel(), int(t),
                                       float(lr), float(beta1), float(beta2), float(eps), _stream(stream)))
+
+
+# ------------------------------------------------------------------ uneven batches
+def qr_preprocess_uneven(desc, B: int, max_rx: int, H_flat, y_flat, R_flat, z_flat, counter, grid: int = 0,
+                         stream=None):
+    """desc: uint8 tensor holding B mimo_frame_desc records (56 bytes each)."""
+    _check(load().mimo_qr_preprocess_uneven(_ptr(desc, torch.uint8, "desc"), B, max_rx,
+                                            _ptr(H_flat, torch.complex64, "H_flat"),
+                                            _ptr(y_flat, torch.complex64, "y_flat"), _ptr(R_flat, torch.float32, "R"),
+                                            _ptr(z_flat, torch.float32, "z"), _ptr(counter, torch.int32, "counter"),
+                                            int(grid), _stream(stream)))
+
+
+def kbest_detect_uneven(desc, B: int, R_flat, z_flat, sym_flat, pd, flags, counter, grid: int = 0, stream=None):
+    _check(load().kbest_detect_uneven(_ptr(desc, torch.uint8, "desc"), B, _ptr(R_flat, torch.float32, "R"),
+                                      _ptr(z_flat, torch.float32, "z"), _ptr(sym_flat, torch.int32, "sym"),
+                                      _ptr(pd, torch.float32, "pd"), _ptr(flags, torch.int32, "flags"),
+                                      _ptr(counter, torch.int32, "counter"), int(grid), _stream(stream)))

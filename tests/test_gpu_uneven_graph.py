@@ -1,0 +1,127 @@
+"""GPU: uneven batches in persistent launches, and hipGraph-captured steps."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2002_09561_amd.framegen import gen_frames, gen_uneven
+from tests.parity_util import compare_symbols, near_tie_tol, pack_level_order
+
+pytestmark = pytest.mark.gpu
+
+K_TABLE = {f"{m}x{q}": k for m in (10, 16, 32, 64) for q, k in ((4, 8), (16, 16), (64, 32))}
+
+
+def test_uneven_matches_batched_path_and_oracle(gpu, orc):
+    import torch
+
+    from paper_2002_09561_amd import uneven
+
+    fr = gen_uneven(700, seed=5)
+    ub = uneven.UnevenBatch(fr, K_TABLE)
+    ub.run(qr_grid=64, kb_grid=128)
+    torch.cuda.synchronize()
+    d = ub.desc_np
+    R, z, sym = ub.R.cpu().numpy(), ub.z.cpu().numpy(), ub.sym.cpu().numpy()
+    # the same frames through the batched launches, one shape class at a time
+    for (m, q) in {(int(a), int(b)) for a, b in zip(fr.n_tx, fr.qam)}:
+        idx = np.nonzero((fr.n_tx == m) & (fr.qam == q))[0]
+        H = torch.from_numpy(np.stack([fr.frame(i)[0] for i in idx])).cuda()
+        y = torch.from_numpy(np.stack([fr.frame(i)[1] for i in idx])).cuda()
+        Rb, zb = gpu.qr_preprocess(H, y)
+        sb, _, _ = gpu.kbest_detect(Rb, zb, m, math.isqrt(q), K_TABLE[f"{m}x{q}"])
+        n = 2 * m
+        for j, i in enumerate(idx):
+            assert np.array_equal(R[d["r_off"][i]: d["r_off"][i] + n * (n + 1) // 2], Rb[j].cpu().numpy())
+            assert np.array_equal(z[d["z_off"][i]: d["z_off"][i] + n], zb[j].cpu().numpy())
+            assert np.array_equal(sym[d["s_off"][i]: d["s_off"][i] + m], sb[j].cpu().numpy())
+    # oracle parity on a sample of frames
+    for i in range(0, 700, 37):
+        H, y, s = fr.frame(i)
+        m, q = int(fr.n_tx[i]), int(fr.qam[i])
+        P = math.isqrt(q)
+        Ro, zo, _ = orc.qr(H[None], y[None])
+        out = orc.kbest(Ro, zo, P, K_TABLE[f"{m}x{q}"])
+        compare_symbols(sym[None, d["s_off"][i]: d["s_off"][i] + m], orc.x_to_sym(out["x"], P), out["margin"],
+                        near_tie_tol(2 * m), f"uneven frame {i}")
+    assert np.all(ub.flags.cpu().numpy() & 1)
+
+
+def test_graph_replay_matches_eager(gpu, orc):
+    import torch
+
+    from paper_2002_09561_amd.graph import CapturedStep
+
+    B, M, q, P = 500, 16, 16, 4
+    fs = [gen_frames(M, M, q, snr, B, seed=77, snr_idx=i) for i, snr in enumerate((8.0, 14.0))]
+    H = [torch.from_numpy(f.H).cuda() for f in fs]
+    Y = [torch.from_numpy(f.y).cuda() for f in fs]
+    S = [torch.from_numpy(f.s_idx).cuda() for f in fs]
+    n = 2 * M
+    R = [torch.empty(B, n * (n + 1) // 2, device="cuda") for _ in fs]
+    Z = [torch.empty(B, n, device="cuda") for _ in fs]
+    sym = [torch.empty(B, M, device="cuda", dtype=torch.int32) for _ in fs]
+    pd = [torch.empty(B, device="cuda") for _ in fs]
+    fl = [torch.empty(B, device="cuda", dtype=torch.int32) for _ in fs]
+    met = [torch.empty(B, device="cuda", dtype=torch.float64) for _ in fs]
+    cnt = torch.zeros(len(fs), 3, device="cuda", dtype=torch.int64)
+
+    def step():
+        cnt.zero_()
+        for i in range(len(fs)):
+            gpu.qr_preprocess(H[i], Y[i], out=(R[i], Z[i], None))
+            gpu.kbest_detect(R[i], Z[i], M, P, 32, out=(sym[i], pd[i], fl[i], None))
+            gpu.metric(H[i], Y[i], sym[i], P, out=met[i])
+            gpu.error_count(sym[i], S[i], P, counts=cnt[i])
+
+    step()
+    torch.cuda.synchronize()
+    ref = ([s.clone() for s in sym], [m.clone() for m in met], cnt.clone())
+    g = CapturedStep(step)
+    for rep in range(3):
+        for s in sym:
+            s.fill_(-1)
+        cnt.fill_(12345)
+        _ = torch.randn(1000, 1000, device="cuda").sum()  # eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        for i in range(len(fs)):
+            assert torch.equal(sym[i], ref[0][i]), rep
+            assert torch.equal(met[i], ref[1][i]), rep
+        assert torch.equal(cnt, ref[2]), rep
+
+
+def test_learned_schedule_gain(gpu, orc):
+    """At about the same mean number of survivors, the learned per-level
+    schedule makes several times fewer symbol errors than plain K-best; with
+    the plain fallback it matches plain K-best at K = 64."""
+    import os
+
+    import torch
+
+    from paper_2002_09561_amd import learned
+
+    path = os.path.join(os.path.dirname(gpu.__file__), "weights", "prune_mlp_100x100_64qam.bin")
+    w, meta = learned.load_weights(path)
+    w = w.cuda()
+    M, q, P, B = 100, 64, 8, 1000
+    fs = [gen_frames(M, M, q, snr, B, seed=9090, snr_idx=i) for i, snr in enumerate((20.0, 24.0, 28.0))]
+    H = torch.from_numpy(np.concatenate([f.H for f in fs])).cuda()
+    Y = torch.from_numpy(np.concatenate([f.y for f in fs])).cuda()
+    S = torch.from_numpy(np.concatenate([f.s_idx for f in fs])).cuda()
+    s2 = torch.from_numpy(np.repeat(np.array([f.sigma2 for f in fs], np.float32), B)).cuda()
+    R, z = gpu.qr_preprocess(H, Y)
+    ks = learned.schedule(w, R, z, s2, M, P, 4.0, 1, 64)
+    mean_k = float(ks.float().mean())
+    sl, _, _ = gpu.kbest_detect(R, z, M, P, 64, k_sched=ks)
+    sp16, _, _ = gpu.kbest_detect(R, z, M, P, 16)
+    err_l, err_16 = int((sl != S).sum()), int((sp16 != S).sum())
+    print(f"learned (mean K_t {mean_k:.1f}): {err_l} symbol errors; plain K=16: {err_16}")
+    assert mean_k <= 20.0
+    assert 3 * err_l < err_16
+    # learned + fallback at the calibrated setting vs plain K = 64
+    s, _, _, _ = learned.detect(w, R, z, s2, M, P, meta["margin"], meta["k_min"], meta["k_max"], meta["beta"], 64)
+    sp64, _, _ = gpu.kbest_detect(R, z, M, P, 64)
+    e_l, e_64 = int((s != S).sum()), int((sp64 != S).sum())
+    print(f"learned + fallback: {e_l} symbol errors; plain K=64: {e_64}")
+    assert e_l <= 1.05 * e_64 + M  # at most one more frame in error
