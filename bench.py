@@ -63,6 +63,10 @@ def parse():
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="also run a plain device copy of this size (counter calibration)")
     p.add_argument("--seed", type=int, default=2020)
+    p.add_argument("--no-graph", action="store_true", help="skip the hipGraph-replayed timing")
+    p.add_argument("--workload", default="c5", choices=["c5", "uneven"],
+                   help="c5: 100x100 64-QAM sweep (default); uneven: 1e5 mixed frames, persistent launches")
+    p.add_argument("--uneven-frames", type=int, default=100000)
     return p.parse_args()
 
 
@@ -130,8 +134,60 @@ def cpu_baseline(frames, K, budget_s):
                       f"FP64 QR + K-best K={K} + metric, {dt:.1f} s wall on {cores} threads"}
 
 
+def uneven_main(args):
+    """Config: 1e5 frames, M = N drawn from {10, 16, 32, 64}, QAM from {4, 16,
+    64}, SNR uniform 8-24 dB; QR and K-best each in one persistent launch,
+    K per class and grids from the autotuner's cache; the step is captured in
+    a hipGraph and replayed."""
+    import torch
+
+    from paper_2002_09561_amd import autotune, mimo, uneven
+    from paper_2002_09561_amd.framegen import gen_uneven
+    from paper_2002_09561_amd.graph import CapturedStep
+
+    torch.cuda.set_device(0)
+    mimo.load()
+    tune = autotune.load() or autotune.load("gfx950")
+    if tune is None:
+        raise SystemExit("no autotuner cache: run python -m paper_2002_09561_amd.autotune")
+    fr = gen_uneven(args.uneven_frames, seed=args.seed)
+    ub = uneven.UnevenBatch(fr, tune["k_table"])
+    step = lambda: ub.run(qr_grid=tune["qr_grid"], kb_grid=tune["kbest_grid"])
+    g = CapturedStep(step, warmup=max(1, args.warmup))
+    ev = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # per-launch times (eager, events)
+    a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    a.record()
+    mimo.qr_preprocess_uneven(ub.desc, ub.B, ub.max_rx, ub.H, ub.y, ub.R, ub.z, ub.counter[0:1], tune["qr_grid"])
+    b.record()
+    mimo.kbest_detect_uneven(ub.desc, ub.B, ub.R, ub.z, ub.sym, ub.pd, ub.flags, ub.counter[1:2], tune["kbest_grid"])
+    c.record()
+    torch.cuda.synchronize()
+    classes = {}
+    for m, q in zip(fr.n_tx, fr.qam):
+        classes[f"{m}x{q}"] = classes.get(f"{m}x{q}", 0) + 1
+    out = {"metric": "decoded frames/s, uneven batch (1e5 mixed frames), one MI355X", "value": round(ub.B * args.steps / dt, 1),
+           "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(dt / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "uneven: M = N in {10,16,32,64}, QAM in {4,16,64}, SNR U[8,24] dB",
+                      "frames": ub.B, "classes": classes, "k_table": tune["k_table"], "qr_grid": tune["qr_grid"],
+                      "kbest_grid": tune["kbest_grid"], "graph": True},
+           "kernel_ms": {"qr_uneven": round(a.elapsed_time(b), 4), "kbest_uneven": round(b.elapsed_time(c), 4)},
+           "symbol_error_rate": float(ub.symbol_errors()) / int(fr.n_tx.sum())}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.gpus == 1 and args.workload == "uneven":
+        return uneven_main(args)
     if args.gpus != 1:
         print(json.dumps({"error": "bench.py measures one GPU; runs on several GPUs are not part of this build",
                           "n_gpus": args.gpus}))
@@ -280,6 +336,19 @@ def main():
     if det == "learned":
         out["learned"] = {"mean_k_t": round(extra["mean_k_t"], 3),
                           "fallback_fraction": round(extra["fallback_fraction"], 5)}
+    if not args.no_graph:
+        from paper_2002_09561_amd.graph import CapturedStep
+
+        g = CapturedStep(lambda: (o["counts"].zero_(), step(det, False)))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.replay()
+        torch.cuda.synchronize()
+        gdt = time.perf_counter() - t0
+        out["graph_frames_per_s"] = round(frames_per_step * args.steps / gdt, 1)
+        out["graph_ms_per_step"] = round(gdt / args.steps * 1e3, 3)
+        del g
 
     # ---------------- comparison legs on the same frames
     if not args.no_compare:
