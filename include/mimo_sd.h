@@ -87,7 +87,10 @@ int32_t mimo_version(void);
  * QR preprocessing (Sec. III-B): H = Q R with R_kk > 0 and z = Q^H y,
  * emitted for the real model in packed level order.  resid[b] receives
  * ||y||^2 - ||z||^2 (the constant the search drops; 0 when N = M), or pass
- * NULL.  Limits: 1 <= n_tx <= n_rx <= 128.
+ * NULL.  Limits: 1 <= n_tx <= n_rx <= 128.  Computed as a Cholesky QR in
+ * FP64 (Gram matrix of [H | y], then its Cholesky factor [[R, z], [0, rho]]);
+ * a frame whose H is rank-deficient in FP64 gets zero rows in R from the
+ * first vanishing pivot on.
  * H [B][n_rx][n_tx] c64, y [B][n_rx] c64 -> R [B][n(n+1)/2], z [B][n] f32.
  * ------------------------------------------------------------------- */
 int32_t mimo_qr_preprocess(const float* H, const float* y, int32_t B, int32_t n_rx, int32_t n_tx,
@@ -228,7 +231,8 @@ typedef struct {
 /* QR preprocessing (Sec. III-B) of an uneven batch in one persistent launch:
  * `grid` workgroups (0 = two per compute unit) pull frames from the device
  * work counter `counter` (one int32, reset by the call on the stream).
- * max_rx >= every n_rx (<= 128); every n_tx <= 127.  Output layout as for
+ * Every frame needs 1 <= n_tx <= n_rx <= max_rx <= 128; a frame that does
+ * not is skipped (its outputs are left untouched).  Output layout as for
  * mimo_qr_preprocess, at the frames' offsets. */
 int32_t mimo_qr_preprocess_uneven(const mimo_frame_desc* desc, int32_t B, int32_t max_rx,
                                   const float* H_flat, const float* y_flat, float* R_flat, float* z_flat,

@@ -1,231 +1,311 @@
-// QR preprocessing (Sec. III-B): H = Q R, z = Q^H y, emitted for the real
-// model in packed level order.
+// QR preprocessing (Sec. III-B): H = Q R with R_kk real positive and
+// z = Q^H y, emitted for the real model in packed level order.
 //
-// One workgroup per frame, one wave per chunk of QR_RB = 16 rows.  The
-// N x (M+1) matrix [H | y] lives in registers: lane l of every wave owns the
-// columns l, l + 64, ... (CB = ceil((M+1)/64) of them) for the rows of its
-// wave's chunk.  Householder step k:
-//   1. every wave broadcasts its rows of column k from the owner lane
-//      (readlane: wave-uniform values) and publishes the chunk's partial
-//      squared norm in LDS;
-//   2. every thread forms the reflector v = x - alpha e1 with
-//      alpha = -phase(x0) ||x|| (wave-uniform scalars);
-//   3. phase 1: partial w_j = sum_i conj(v_i) A_ij over the chunk's rows;
-//   4. phase 2: w_j = sum of the chunk partials, A_ij -= tau v_i w_j.
-// Rows outside [k, N) carry v_i = 0, so the updates need no row guards.
-// The complex QR maps onto the real model blockwise: with R_kk
-// made real positive, the real R has R_2k,2k+1 = 0 and R_2k,2k = R_2k+1,2k+1.
+// Method: Cholesky QR in FP64.  With A = [H | y] (N x (M+1)), the Gram matrix
+// G = A^H A equals Rt^H Rt for Rt = [[R, z], [0, rho]], where R is the unique
+// upper-triangular factor of H with a positive real diagonal (the factor a
+// Householder QR yields once its rows are normalised to R_kk > 0), z is the
+// first M entries of Q^H y and rho^2 = ||y||^2 - ||z||^2.  Products of the
+// complex64 inputs are exact in FP64 and every sum rounds at 2^-53, so the
+// error of R, which the Gram form amplifies by cond(H)^2, stays far below
+// the FP32 rounding of the output for any channel with cond(H) < 10^5.
+//
+// One workgroup per frame.  G's upper triangle is split into 4 x 4 complex
+// tiles, one per thread, held in registers for the whole frame:
+//   1. Gram: [H | y] streams through LDS in chunks of 16 rows (the next chunk
+//      is prefetched into registers while the current one is consumed); each
+//      thread accumulates conj(a_i)^T a_j over the rows for its tile.
+//   2. Right-looking Cholesky: at step k the owners of row k of the current
+//      Schur complement publish it in LDS (double-buffered, so one barrier per
+//      step) and every thread applies G_ij -= conj(g_ki) g_kj / g_kk to its
+//      rows i > k.  Row k keeps its unscaled values; R_kj = g_kj / sqrt(g_kk).
+//   3. Output: each thread scales its tile rows and writes the real blocks
+//      [[a, -b], [b, a]] of R, and z from the column M.
+// The complex factor maps onto the real model blockwise: R_2k,2k+1 = 0 and
+// R_2k,2k = R_2k+1,2k+1 = R_kk.
 #include "common.hpp"
 
 namespace mimo {
 
-constexpr int QR_RB = 16;  // rows per wave held in registers
+constexpr int CQ_T = 4;       // tile edge in complex entries
+constexpr int CQ_RCH = 16;    // rows of [H | y] per LDS chunk
+constexpr int CQ_PF_MAX = 6;  // max chunk elements a thread stages
+constexpr int CQ_MAX_THREADS = 576;  // 33 x 34 / 2 = 561 tiles at n_tx = 128
 
-struct c32 {
-    float x, y;
+struct CqShape {
+    int C;       // M + 1 columns of [H | y]
+    int nb;      // tile rows/columns: ceil(C / 4)
+    int CP;      // padded columns 4 nb
+    int ntiles;  // nb (nb + 1) / 2 upper-triangular tiles
 };
 
-__device__ inline c32 cmul(c32 a, c32 b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
-
-// QR of one frame by the whole workgroup (rc = blockDim.x / 64 waves of
-// QR_RB rows; waves beyond the frame's rows only take part in the barriers).
-template <int CB>
-__device__ __forceinline__ void qr_frame(const float2* __restrict__ Hf, const float2* __restrict__ yf, int N, int M,
-                                         float* __restrict__ Rf, float* __restrict__ zf, float* __restrict__ resid_out,
-                                         float* smem_qr)
+__host__ __device__ inline CqShape cq_shape(int M)
 {
-    const int lane = threadIdx.x & 63;
-    const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave index = row chunk (uniform)
-    const int rc = blockDim.x >> 6;
-    const int rc_used = (N + QR_RB - 1) / QR_RB;
-    const int row0 = r * QR_RB;
-    const int ncol = CB * WAVE;
+    CqShape s;
+    s.C = M + 1;
+    s.nb = (s.C + CQ_T - 1) / CQ_T;
+    s.CP = s.nb * CQ_T;
+    s.ntiles = s.nb * (s.nb + 1) / 2;
+    return s;
+}
+
+// one thread per tile, and enough threads that each stages at most
+// CQ_PF_MAX elements of a chunk (16 x CP)
+__host__ __device__ inline int cq_threads(int M)
+{
+    const CqShape s = cq_shape(M);
+    const int a = (s.ntiles + WAVE - 1) / WAVE * WAVE;
+    const int st = (16 * s.CP + CQ_PF_MAX - 1) / CQ_PF_MAX;
+    const int b = (st + WAVE - 1) / WAVE * WAVE;
+    return a > b ? a : b;
+}
+
+// LDS bytes: row buffers [2][CP] complex double, pivots [CP] and a 4-entry
+// spare [4] double, chunk buffers [2][16][CP] complex float
+__host__ __device__ inline size_t cq_lds_bytes(int M)
+{
+    const int CP = cq_shape(M).CP;
+    return (size_t)CP * (2 * 16 + 8) + CQ_T * 8 + (size_t)2 * CQ_RCH * CP * 8;
+}
+
+struct cd {
+    double x, y;
+};
+
+// element e of chunk c of [H | y] (rows 16c .. 16c+15, zero-padded to CP
+// columns; e = row * CP + col).  Branch-free: an element outside the frame
+// loads H[0] and is replaced by zero, so a thread's loads issue back to back.
+// row = e / CP by a float reciprocal: e < 2^12 keeps it exact.
+__device__ __forceinline__ float2 cq_elem(const float2* __restrict__ Hf, const float2* __restrict__ yf, int N, int M,
+                                          int CP, float rcp_cp, int tot, int c, int e)
+{
+    const int row = (int)(((float)e + 0.5f) * rcp_cp);
+    const int col = e - row * CP;
+    const int i = c * CQ_RCH + row;
+    const bool valid = e < tot && i < N && col <= M;
+    const float2* p = col < M ? Hf + ((size_t)i * M + col) : yf + i;
+    p = valid ? p : Hf;
+    const float2 v = *p;
+    return valid ? v : make_float2(0.f, 0.f);
+}
+
+// LDS slot of chunk element e (row, col = 4J + q) in the chunk layout
+// [row][h][J] of float4 pairs: columns 4J + 2h and 4J + 2h + 1 side by side,
+// so that the lanes of a wave (consecutive J) read 16-byte neighbours.
+__device__ __forceinline__ int cq_lds_slot(int e, int CP, int nb, float rcp_cp)
+{
+    const int row = (int)(((float)e + 0.5f) * rcp_cp);
+    const int col = e - row * CP;
+    const int J = col >> 2, q = col & 3;
+    return row * CP + (((q >> 1) * nb + J) << 1) + (q & 1);
+}
+
+// publish register row LR of the tile (a compile-time index keeps the tile
+// in registers).  A published row is stored in planes: column j = 4J + q at
+// [q][J], so the lanes of a wave, which hold consecutive J, read 16-byte
+// neighbours (no LDS bank conflicts).
+template <int LR>
+__device__ __forceinline__ void cq_store_row(cd* row, int nb, int J, const double (&gr)[CQ_T][CQ_T],
+                                             const double (&gi)[CQ_T][CQ_T])
+{
+#pragma unroll
+    for (int c = 0; c < CQ_T; ++c) row[c * nb + J] = {gr[LR][c], gi[LR][c]};
+}
+
+// one step k of the right-looking Cholesky; S = k mod 4 (row k+1 sits in
+// register row (S + 1) mod 4 of the tiles that publish it)
+template <int S>
+__device__ __forceinline__ void cq_step(int k, int M, int CP, int nb, int tid, bool has_tile, int I, int J, int i0,
+                                        cd* rowbuf, double* diag, double (&gr)[CQ_T][CQ_T],
+                                        double (&gi)[CQ_T][CQ_T])
+{
+    __syncthreads();  // row k published; the other buffer is free
+    const cd* rk = rowbuf + (k & 1) * CP;
+    const double d = rk[(k & (CQ_T - 1)) * nb + k / CQ_T].x;
+    if (tid == 0) diag[k] = d;
+    if (has_tile && i0 + CQ_T - 1 > k) {
+        // 1/d: hardware reciprocal refined by two Newton steps
+        double inv = __builtin_amdgcn_rcp(d);
+        inv = fma(inv, fma(-d, inv, 1.0), inv);
+        inv = fma(inv, fma(-d, inv, 1.0), inv);
+        inv = d > 0.0 ? inv : 0.0;
+        double ur[CQ_T], ui[CQ_T], vr[CQ_T], vi[CQ_T];
+#pragma unroll
+        for (int r = 0; r < CQ_T; ++r) {
+            const cd a = rk[r * nb + I];
+            const bool below = i0 + r > k;  // rows <= k are final
+            ur[r] = below ? a.x * inv : 0.0;
+            ui[r] = below ? -a.y * inv : 0.0;
+            const cd b = rk[r * nb + J];
+            vr[r] = b.x;
+            vi[r] = b.y;
+        }
+        // G_ij -= conj(g_ki) g_kj / g_kk
+#pragma unroll
+        for (int r = 0; r < CQ_T; ++r)
+#pragma unroll
+            for (int q = 0; q < CQ_T; ++q) {
+                gr[r][q] = fma(-ur[r], vr[q], gr[r][q]);
+                gr[r][q] = fma(ui[r], vi[q], gr[r][q]);
+                gi[r][q] = fma(-ur[r], vi[q], gi[r][q]);
+                gi[r][q] = fma(-ui[r], vr[q], gi[r][q]);
+            }
+        if (k + 1 < M && (k + 1) / CQ_T == I)
+            cq_store_row<(S + 1) & (CQ_T - 1)>(rowbuf + ((k + 1) & 1) * CP, nb, J, gr, gi);
+    }
+}
+
+template <int PF>
+__device__ __forceinline__ void cholqr_frame(const float2* __restrict__ Hf, const float2* __restrict__ yf, int N,
+                                             int M, float* __restrict__ Rf, float* __restrict__ zf,
+                                             float* __restrict__ resid_out, unsigned char* smem)
+{
+    const CqShape sh = cq_shape(M);
+    const int CP = sh.CP;
     const int n = 2 * M;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int nb = sh.nb;
+    cd* rowbuf = reinterpret_cast<cd*>(smem);                   // [2][4][nb]
+    double* diag = reinterpret_cast<double*>(rowbuf + 2 * CP);  // [CP] pivots, then [4] spare
+    float2* ach = reinterpret_cast<float2*>(diag + CP + CQ_T);  // [2][16][2][nb] x 2 complex
 
-    // LDS: x0s[2] c32, wpart[rc][ncol] c32, alpha[M] c32, pnorm[2][rc] f32
-    c32* x0s = reinterpret_cast<c32*>(smem_qr);
-    c32* wpart = x0s + 2;
-    c32* alpha_s = wpart + rc * ncol;
-    float* pnorm = reinterpret_cast<float*>(alpha_s + M);
+    // tile (I, J), I <= J, enumerated row by row
+    const bool has_tile = tid < sh.ntiles;
+    int I = 0, J = 0;
+    if (has_tile) {
+        int rem = tid;
+        while (rem >= sh.nb - I) {
+            rem -= sh.nb - I;
+            ++I;
+        }
+        J = I + rem;
+    }
+    const int i0 = CQ_T * I, j0 = CQ_T * J;
 
-    c32 A[QR_RB][CB];
+    double gr[CQ_T][CQ_T], gi[CQ_T][CQ_T];
 #pragma unroll
-    for (int q = 0; q < QR_RB; ++q) {
-        const int i = row0 + q;
+    for (int r = 0; r < CQ_T; ++r)
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-            const int j = lane + cb * WAVE;
-            float2 v = make_float2(0.f, 0.f);
-            if (i < N) {
-                if (j < M) v = Hf[(size_t)i * M + j];
-                else if (j == M) v = yf[i];
+        for (int c = 0; c < CQ_T; ++c) gr[r][c] = gi[r][c] = 0.0;
+
+    // ---- 1. Gram matrix over chunks of 16 rows
+    const int nchunk = (N + CQ_RCH - 1) / CQ_RCH;
+    const int tot = CQ_RCH * CP;
+    const float rcp_cp = 1.0f / (float)CP;
+    float2 pf[PF];
+#pragma unroll
+    for (int q = 0; q < PF; ++q) pf[q] = cq_elem(Hf, yf, N, M, CP, rcp_cp, tot, 0, tid + q * nthr);
+    for (int c = 0; c < nchunk; ++c) {
+        float2* buf = ach + (c & 1) * tot;
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int e = tid + q * nthr;
+            if (e < tot) buf[cq_lds_slot(e, CP, nb, rcp_cp)] = pf[q];
+        }
+        __syncthreads();  // chunk c visible; chunk c-1's buffer no longer read
+        if (c + 1 < nchunk) {
+#pragma unroll
+            for (int q = 0; q < PF; ++q) pf[q] = cq_elem(Hf, yf, N, M, CP, rcp_cp, tot, c + 1, tid + q * nthr);
+        }
+        if (has_tile) {
+            const int nr = min(CQ_RCH, N - c * CQ_RCH);
+            for (int rr = 0; rr < nr; ++rr) {
+                const float4* rowp = reinterpret_cast<const float4*>(buf + rr * CP);
+                const float4 a01 = rowp[I], a23 = rowp[nb + I];
+                const float4 b01 = rowp[J], b23 = rowp[nb + J];
+                const double ar[CQ_T] = {a01.x, a01.z, a23.x, a23.z}, ai[CQ_T] = {a01.y, a01.w, a23.y, a23.w};
+                const double br[CQ_T] = {b01.x, b01.z, b23.x, b23.z}, bi[CQ_T] = {b01.y, b01.w, b23.y, b23.w};
+                // G_ij += conj(a_i) a_j
+#pragma unroll
+                for (int r = 0; r < CQ_T; ++r)
+#pragma unroll
+                    for (int q = 0; q < CQ_T; ++q) {
+                        gr[r][q] = fma(ar[r], br[q], gr[r][q]);
+                        gr[r][q] = fma(ai[r], bi[q], gr[r][q]);
+                        gi[r][q] = fma(ar[r], bi[q], gi[r][q]);
+                        gi[r][q] = fma(-ai[r], br[q], gi[r][q]);
+                    }
             }
-            A[q][cb] = {v.x, v.y};
         }
     }
 
-    for (int k = 0; k < M; ++k) {
-        const int buf = k & 1;
-        float* pn = pnorm + buf * rc;
-        const int kcb = k / WAVE, klane = k % WAVE;
-        // 1. column k of this wave's rows, broadcast from its owner lane
-        //    (wave-uniform values), and the chunk's partial squared norm over
-        //    rows >= k; the wave holding row k publishes x0 = A_kk
-        c32 colk[QR_RB];
-        float s = 0.f;
-#pragma unroll
-        for (int q = 0; q < QR_RB; ++q) {
-            c32 x = A[q][0];
-#pragma unroll
-            for (int cb = 1; cb < CB; ++cb)
-                if (cb == kcb) x = A[q][cb];
-            colk[q].x = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x.x), klane));
-            colk[q].y = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x.y), klane));
-            const int i = row0 + q;
-            if (i >= k && i < N) s = fmaf(colk[q].x, colk[q].x, fmaf(colk[q].y, colk[q].y, s));
-        }
-        if (lane == 0) {
-            pn[r] = s;
-#pragma unroll
-            for (int q = 0; q < QR_RB; ++q)
-                if (row0 + q == k) x0s[buf] = colk[q];
-        }
-        __syncthreads();
-        if (row0 + QR_RB <= k || row0 >= N) {  // finished or empty chunk: only the barrier remains
-            __syncthreads();
-            continue;
-        }
-        // 2. reflector scalars (uniform)
-        float norm2 = 0.f;
-        for (int rr = 0; rr < rc; ++rr) norm2 += pn[rr];
-        const c32 x0 = x0s[buf];
-        const float ax0 = sqrtf(x0.x * x0.x + x0.y * x0.y);
-        const float norm = sqrtf(norm2);
-        const c32 ph = ax0 > 0.f ? c32{x0.x / ax0, x0.y / ax0} : c32{1.f, 0.f};
-        const c32 alpha = {-ph.x * norm, -ph.y * norm};
-        const c32 v0 = {x0.x - alpha.x, x0.y - alpha.y};
-        const float vn2 = norm2 - ax0 * ax0 + (v0.x * v0.x + v0.y * v0.y);
-        const float tau = (norm > 0.f && vn2 > 0.f) ? 2.f / vn2 : 0.f;
-        // v_i of this chunk's rows: zero above row k and below row N-1, so the
-        // updates below are exact no-ops there
-        c32 vr[QR_RB];
-#pragma unroll
-        for (int q = 0; q < QR_RB; ++q) {
-            const int i = row0 + q;
-            vr[q] = (i > k && i < N) ? colk[q] : (i == k ? v0 : c32{0.f, 0.f});
-        }
-        // 3. phase 1: partial w_j = sum_i conj(v_i) A_ij over this chunk
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-            if ((cb + 1) * WAVE <= k || cb * WAVE > M) continue;  // block finished or beyond [H | y] (uniform)
-            c32 sw = {0.f, 0.f};
-#pragma unroll
-            for (int q = 0; q < QR_RB; ++q) {
-                sw.x = fmaf(vr[q].x, A[q][cb].x, sw.x);
-                sw.x = fmaf(vr[q].y, A[q][cb].y, sw.x);
-                sw.y = fmaf(vr[q].x, A[q][cb].y, sw.y);
-                sw.y = fmaf(-vr[q].y, A[q][cb].x, sw.y);
-            }
-            wpart[r * ncol + lane + cb * WAVE] = sw;
-        }
-        __syncthreads();
-        // 4. phase 2: apply the reflector.  Finished columns (j < k) have w_j = 0
-        //    up to rounding of their (never used) sub-diagonal residue; the pivot
-        //    column's new values below the diagonal are never read either: its
-        //    diagonal is alpha, kept in alpha_s.
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-            if ((cb + 1) * WAVE <= k || cb * WAVE > M) continue;
-            const int j = lane + cb * WAVE;
-            c32 wj = {0.f, 0.f};
-            for (int rr = k / QR_RB; rr < rc_used; ++rr) {  // chunks with rows >= k wrote this step's partials
-                const c32 t = wpart[rr * ncol + j];
-                wj.x += t.x;
-                wj.y += t.y;
-            }
-            wj.x *= tau;
-            wj.y *= tau;
-#pragma unroll
-            for (int q = 0; q < QR_RB; ++q) {
-                A[q][cb].x = fmaf(-vr[q].x, wj.x, A[q][cb].x);
-                A[q][cb].x = fmaf(vr[q].y, wj.y, A[q][cb].x);
-                A[q][cb].y = fmaf(-vr[q].x, wj.y, A[q][cb].y);
-                A[q][cb].y = fmaf(-vr[q].y, wj.x, A[q][cb].y);
-            }
-        }
-        if (lane == 0 && k >= row0 && k < row0 + QR_RB) alpha_s[k] = (tau > 0.f) ? alpha : x0;
+    // ---- 2. right-looking Cholesky, one barrier per step (unrolled by the
+    //         tile edge so the published register row is a constant)
+    if (has_tile && I == 0) cq_store_row<0>(rowbuf, nb, J, gr, gi);
+    for (int kb = 0; kb < M; kb += CQ_T) {
+        cq_step<0>(kb, M, CP, nb, tid, has_tile, I, J, i0, rowbuf, diag, gr, gi);
+        if (kb + 1 < M) cq_step<1>(kb + 1, M, CP, nb, tid, has_tile, I, J, i0, rowbuf, diag, gr, gi);
+        if (kb + 2 < M) cq_step<2>(kb + 2, M, CP, nb, tid, has_tile, I, J, i0, rowbuf, diag, gr, gi);
+        if (kb + 3 < M) cq_step<3>(kb + 3, M, CP, nb, tid, has_tile, I, J, i0, rowbuf, diag, gr, gi);
     }
-    __syncthreads();
+    __syncthreads();  // diag complete
 
-    // make R_kk real positive: scale row i by d_i = conj(a_i) / |a_i|, then
-    // write the real blocks [[a, -b], [b, a]] in packed level order
-    float rs = 0.f;
+    // ---- 3. output: R_ij = g_ij / sqrt(g_ii), real blocks in packed level order
+    if (has_tile) {
 #pragma unroll
-    for (int q = 0; q < QR_RB; ++q) {
-        const int i = row0 + q;
-        if (i < M) {
-            const c32 a = alpha_s[i];
-            const float aa = sqrtf(a.x * a.x + a.y * a.y);
-            const float inv = aa > 0.f ? 1.f / aa : 0.f;
-            const c32 d = aa > 0.f ? c32{a.x * inv, -a.y * inv} : c32{1.f, 0.f};
+        for (int r = 0; r < CQ_T; ++r) {
+            const int i = i0 + r;
+            if (i >= M) continue;
+            const double d = diag[i];
+            const double s = d > 0.0 ? sqrt(d) : 0.0;
+            const double is = d > 0.0 ? 1.0 / s : 0.0;
             float* row_re = Rf + r_row_off(n, 2 * i);
             float* row_im = Rf + r_row_off(n, 2 * i + 1);
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb) {
-                const int j = lane + cb * WAVE;
+            for (int q = 0; q < CQ_T; ++q) {
+                const int j = j0 + q;
                 if (j < i || j > M) continue;
-                c32 v = cmul(d, A[q][cb]);
-                if (j == i) v = {aa > 0.f ? aa : A[q][cb].x, 0.f};
+                const float vx = (float)(gr[r][q] * is), vy = (float)(gi[r][q] * is);
                 if (j == M) {
-                    zf[2 * i] = v.x;
-                    zf[2 * i + 1] = v.y;
+                    zf[2 * i] = vx;
+                    zf[2 * i + 1] = vy;
+                } else if (j == i) {
+                    row_re[0] = (float)s;
+                    row_re[1] = 0.f;
+                    row_im[0] = (float)s;
                 } else {
-                    row_re[2 * (j - i)] = v.x;
-                    row_re[2 * (j - i) + 1] = -v.y;
-                    if (j > i) row_im[2 * (j - i) - 1] = v.y;
-                    row_im[2 * (j - i)] = v.x;
+                    row_re[2 * (j - i)] = vx;
+                    row_re[2 * (j - i) + 1] = -vy;
+                    row_im[2 * (j - i) - 1] = vy;
+                    row_im[2 * (j - i)] = vx;
                 }
             }
         }
+        // rho^2 = ||y||^2 - ||z||^2 is the Schur complement left at (M, M):
+        // its tile publishes the diagonal, the thread of (M, M) reads it back
+        if (resid_out && I == J && I == M / CQ_T) {
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb)
-            if (i >= M && i < N && lane + cb * WAVE == M) rs += A[q][cb].x * A[q][cb].x + A[q][cb].y * A[q][cb].y;
-    }
-    if (resid_out) {
-        // rows >= M of the rotated y: only the lanes owning column M contribute
-        __syncthreads();
-        float part = wave_sum(rs);
-        if (lane == 0) pnorm[r] = part;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            float s = 0.f;
-            for (int rr = 0; rr < rc; ++rr) s += pnorm[rr];
-            *resid_out = s;
+            for (int r = 0; r < CQ_T; ++r) diag[CP + r] = gr[r][r];
+            const double v = diag[CP + (M & (CQ_T - 1))];
+            *resid_out = (float)(v > 0.0 ? v : 0.0);
         }
     }
     __syncthreads();  // the LDS may be reused by the next frame
 }
 
-template <int CB>
-__global__ void __launch_bounds__(512, CB <= 2 ? 4 : 2) qr_kernel(const float2* __restrict__ H, const float2* __restrict__ y, int N,
-                                                 int M, float* __restrict__ R, float* __restrict__ z,
-                                                 float* __restrict__ resid)
+template <int PF>
+__global__ void __launch_bounds__(CQ_MAX_THREADS) qr_kernel(const float2* __restrict__ H,
+                                                            const float2* __restrict__ y, int N, int M,
+                                                            float* __restrict__ R, float* __restrict__ z,
+                                                            float* __restrict__ resid)
 {
-    extern __shared__ float smem_qr[];
+    extern __shared__ __align__(16) unsigned char smem_qr[];
     const int frame = blockIdx.x;
     const int n = 2 * M;
-    qr_frame<CB>(H + (size_t)frame * N * M, y + (size_t)frame * N, N, M, R + (size_t)frame * r_packed_size(n),
+    cholqr_frame<PF>(H + (size_t)frame * N * M, y + (size_t)frame * N, N, M, R + (size_t)frame * r_packed_size(n),
                  z + (size_t)frame * n, resid ? resid + frame : nullptr, smem_qr);
 }
 
 // Uneven batch: frames of different sizes pulled from a device work counter
-// by a persistent grid; every workgroup has enough waves for the largest frame.
-__global__ void __launch_bounds__(512, 2) qr_uneven_kernel(const mimo_frame_desc* __restrict__ desc, int B,
-                                                           const float2* __restrict__ H, const float2* __restrict__ y,
-                                                           float* __restrict__ R, float* __restrict__ z,
-                                                           int* __restrict__ counter)
+// by a persistent grid sized for the largest frame.
+template <int PF>
+__global__ void __launch_bounds__(CQ_MAX_THREADS) qr_uneven_kernel(const mimo_frame_desc* __restrict__ desc, int B,
+                                                                   const float2* __restrict__ H,
+                                                                   const float2* __restrict__ y,
+                                                                   float* __restrict__ R, float* __restrict__ z,
+                                                                   int* __restrict__ counter, int max_rx)
 {
-    extern __shared__ float smem_qr[];
+    extern __shared__ __align__(16) unsigned char smem_qr[];
     __shared__ int next;
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(counter, 1);
@@ -234,21 +314,19 @@ __global__ void __launch_bounds__(512, 2) qr_uneven_kernel(const mimo_frame_desc
         __syncthreads();
         if (f >= B) break;
         const mimo_frame_desc d = desc[f];
-        qr_frame<2>(H + d.h_off, y + d.y_off, d.n_rx, d.n_tx, R + d.r_off, z + d.z_off, nullptr, smem_qr);
+        // the workgroup and its LDS are sized for n_tx <= n_rx <= max_rx
+        if (d.n_tx < 1 || d.n_tx > d.n_rx || d.n_rx > max_rx) continue;
+        cholqr_frame<PF>(H + d.h_off, y + d.y_off, d.n_rx, d.n_tx, R + d.r_off, z + d.z_off, nullptr, smem_qr);
     }
 }
 
 __global__ void reset_counter_kernel(int* counter) { *counter = 0; }
 
-template <int CB>
-static int32_t launch_qr(const float* H, const float* y, int B, int N, int M, float* R, float* z, float* resid,
-                         hipStream_t st)
+// chunk elements each thread stages for n_tx = M with `threads` threads
+static int cq_per_thread(int M, int threads)
 {
-    const int rc = (N + QR_RB - 1) / QR_RB;
-    const size_t lds = sizeof(c32) * (2 + rc * CB * WAVE + M) + sizeof(float) * (2 * rc);
-    hipLaunchKernelGGL(qr_kernel<CB>, dim3(B), dim3(rc * WAVE), lds, st, reinterpret_cast<const float2*>(H),
-                       reinterpret_cast<const float2*>(y), N, M, R, z, resid);
-    return check_launch("mimo_qr_preprocess");
+    const int tot = CQ_RCH * cq_shape(M).CP;
+    return (tot + threads - 1) / threads;
 }
 
 }  // namespace mimo
@@ -264,11 +342,19 @@ extern "C" int32_t mimo_qr_preprocess(const float* H, const float* y, int32_t B,
         return fail(MIMO_ERR_UNSUPPORTED, "mimo_qr_preprocess: n_rx, n_tx <= %d", MIMO_MAX_RX);
     if (B == 0) return MIMO_OK;
     if (!H || !y || !R || !z) return fail(MIMO_ERR_INVALID_ARG, "mimo_qr_preprocess: null pointer");
+    const int threads = cq_threads(n_tx);
+    const int per = cq_per_thread(n_tx, threads);
+    if (per > CQ_PF_MAX || threads > CQ_MAX_THREADS)
+        return fail(MIMO_ERR_UNSUPPORTED, "mimo_qr_preprocess: n_tx = %d", n_tx);
+    const float2* H2 = reinterpret_cast<const float2*>(H);
+    const float2* y2 = reinterpret_cast<const float2*>(y);
+    const size_t lds = cq_lds_bytes(n_tx);
     hipStream_t st = (hipStream_t)stream;
-    const int cols = n_tx + 1;
-    if (cols <= WAVE) return launch_qr<1>(H, y, B, n_rx, n_tx, R, z, resid, st);
-    if (cols <= 2 * WAVE) return launch_qr<2>(H, y, B, n_rx, n_tx, R, z, resid, st);
-    return launch_qr<3>(H, y, B, n_rx, n_tx, R, z, resid, st);
+    if (per <= 4)
+        hipLaunchKernelGGL(qr_kernel<4>, dim3(B), dim3(threads), lds, st, H2, y2, n_rx, n_tx, R, z, resid);
+    else
+        hipLaunchKernelGGL(qr_kernel<CQ_PF_MAX>, dim3(B), dim3(threads), lds, st, H2, y2, n_rx, n_tx, R, z, resid);
+    return check_launch("mimo_qr_preprocess");
 }
 
 extern "C" int32_t mimo_qr_preprocess_uneven(const mimo_frame_desc* desc, int32_t B, int32_t max_rx,
@@ -282,19 +368,31 @@ extern "C" int32_t mimo_qr_preprocess_uneven(const mimo_frame_desc* desc, int32_
     if (B == 0) return MIMO_OK;
     if (!desc || !H_flat || !y_flat || !R_flat || !z_flat || !counter)
         return fail(MIMO_ERR_INVALID_ARG, "mimo_qr_preprocess_uneven: null pointer");
+    // n_tx <= n_rx <= max_rx: size the workgroup and LDS for n_tx = max_rx;
+    // smaller frames use a prefix of the threads and stage fewer elements
+    const int mt = max_rx < MIMO_MAX_TX ? max_rx : MIMO_MAX_TX;
+    const int threads = cq_threads(mt);
+    int per = 0;
+    for (int m = 1; m <= mt; ++m) per = per > cq_per_thread(m, threads) ? per : cq_per_thread(m, threads);
+    if (per > CQ_PF_MAX || threads > CQ_MAX_THREADS)
+        return fail(MIMO_ERR_UNSUPPORTED, "mimo_qr_preprocess_uneven: max_rx = %d", max_rx);
     hipStream_t st = (hipStream_t)stream;
-    const int rc = (max_rx + QR_RB - 1) / QR_RB;
-    const size_t lds = sizeof(c32) * (2 + rc * 2 * WAVE + MIMO_MAX_TX) + sizeof(float) * (2 * rc);
     if (grid == 0) {
         int dev = 0, cus = 0;
-        hipGetDevice(&dev);
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         grid = 2 * (cus > 0 ? cus : 256);
     }
     if (grid > B) grid = B;
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
-    hipLaunchKernelGGL(qr_uneven_kernel, dim3(grid), dim3(rc * WAVE), lds, st, desc, B,
-                       reinterpret_cast<const float2*>(H_flat), reinterpret_cast<const float2*>(y_flat), R_flat,
-                       z_flat, counter);
+    const float2* H2 = reinterpret_cast<const float2*>(H_flat);
+    const float2* y2 = reinterpret_cast<const float2*>(y_flat);
+    const size_t lds = cq_lds_bytes(mt);
+    if (per <= 4)
+        hipLaunchKernelGGL(qr_uneven_kernel<4>, dim3(grid), dim3(threads), lds, st, desc, B, H2, y2, R_flat, z_flat,
+                           counter, mt);
+    else
+        hipLaunchKernelGGL(qr_uneven_kernel<CQ_PF_MAX>, dim3(grid), dim3(threads), lds, st, desc, B, H2, y2, R_flat,
+                           z_flat, counter, mt);
     return check_launch("mimo_qr_preprocess_uneven");
 }

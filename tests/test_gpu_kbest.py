@@ -32,7 +32,8 @@ def test_qr_parity(gpu, orc, N, M, q, B):
     Ro, zo, reso = orc.qr(f.H, f.y)
     Rp = pack_level_order(Ro)
     n = 2 * M
-    # Householder in FP32 is backward stable: ||dR|| <= c n u ||H||
+    # the FP64 Cholesky-QR factor rounded to FP32: ||dR|| <= c n u ||H||, u = 2^-24
+    # (the FP64 error, amplified by cond(H)^2, is far below the FP32 rounding)
     u = 2.0 ** -24
     hn = np.sqrt((np.abs(f.H.astype(np.complex128)) ** 2).sum(axis=(1, 2)) * 2)
     err_R = np.sqrt(((_np(R) - Rp) ** 2).sum(axis=1))
