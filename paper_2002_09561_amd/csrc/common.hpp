@@ -64,6 +64,27 @@ __device__ inline uint64_t wave_min_u64(uint64_t v)
     return v;
 }
 
+// Exchange with lane ^ j for a compile-time j (after unrolling): DPP for
+// j = 1, 2 (quad permutes) and 8 (rotate by 8 in a row of 16), an LDS-free
+// swizzle for 4 and 16, a permute for 32.
+__device__ __forceinline__ uint32_t xor_lanes(uint32_t v, int j, int lane)
+{
+    switch (j) {
+    case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+    case 2: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
+    case 8: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);
+    case 4: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F);
+    case 16: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);
+    default: return (uint32_t)__builtin_amdgcn_ds_bpermute(((lane ^ j) & (WAVE - 1)) << 2, (int)v);
+    }
+}
+
+__device__ __forceinline__ uint64_t xor_lanes_u64(uint64_t v, int j, int lane)
+{
+    const uint32_t lo = xor_lanes((uint32_t)v, j, lane), hi = xor_lanes((uint32_t)(v >> 32), j, lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // In-wave bitonic sort of 64*E keys, ascending by position e*64 + lane.
 template <int E>
 __device__ inline void bitonic_sort(uint64_t (&key)[E], int lane)
@@ -89,13 +110,12 @@ __device__ inline void bitonic_sort(uint64_t (&key)[E], int lane)
             } else {
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
-                    uint64_t o = shfl_xor_u64(key[e], j);
-                    const bool asc = (((e * WAVE + lane) & size) == 0);
-                    const bool lower = (lane & j) == 0;
-                    const bool take_min = (asc == lower);
-                    uint64_t mn = o < key[e] ? o : key[e];
-                    uint64_t mx = o < key[e] ? key[e] : o;
-                    key[e] = take_min ? mn : mx;
+                    const uint64_t o = xor_lanes_u64(key[e], j, lane);
+                    // keep the smaller key iff this lane's half and the block's
+                    // direction agree; keys are distinct except the ~0 padding
+                    const bool take_max = ((((e * WAVE + lane) & size) != 0) != ((lane & j) != 0));
+                    const bool take_o = (o < key[e]) != take_max;
+                    key[e] = take_o ? o : key[e];
                 }
             }
         }

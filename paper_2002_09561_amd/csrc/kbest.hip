@@ -211,6 +211,52 @@ __device__ __forceinline__ int kb_select(const uint32_t (&kh)[E], int ncand, int
     return keep;
 }
 
+// Selection by sorting, for at most 128 candidates (ES = 1 or 2 blocks of
+// 64): all candidate keys (pd bits, candidate index; invalid = ~0) are put
+// in order by one in-wave bitonic sort and the first `keep` survive.  Same
+// contract and result as kb_select; no ballot counting.
+template <int E, int ES>
+__device__ __forceinline__ int kb_select_sort(const uint32_t (&kh)[E], int nvalid, int Kt, int fm, int lane,
+                                              float* sn, int32_t* sel, int* fpos_out)
+{
+    static_assert(ES <= E && ES <= 2, "sort selection covers one or two blocks");
+    const int keep = Kt < nvalid ? Kt : nvalid;
+    uint64_t key[ES];
+#pragma unroll
+    for (int e = 0; e < ES; ++e)
+        key[e] = kh[e] == ~0u ? ~0ull : (((uint64_t)kh[e] << 32) | (uint32_t)(e * WAVE + lane));
+    uint64_t fkey = ~0ull;
+    if (fm >= 0) {
+        const int fe = fm / WAVE, fl = fm % WAVE;
+        uint32_t fh = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (e == fe) fh = __shfl(kh[e], fl, WAVE);
+        if (fh != ~0u) fkey = ((uint64_t)fh << 32) | (uint32_t)fm;
+    }
+    bitonic_sort<ES>(key, lane);
+    int fpos = -1;
+    if (fkey != ~0ull) {  // the forced candidate's rank = its sorted position
+#pragma unroll
+        for (int e = 0; e < ES; ++e) {
+            const uint64_t b = __ballot(key[e] == fkey);
+            if (b) fpos = e * WAVE + (int)__builtin_ctzll(b);
+        }
+    }
+    const bool add_forced = fpos >= keep;  // it takes the last slot
+#pragma unroll
+    for (int e = 0; e < ES; ++e) {
+        const int r = e * WAVE + lane;
+        if (r < keep) {
+            const uint64_t k = (add_forced && r == keep - 1) ? fkey : key[e];
+            sn[r] = __uint_as_float((uint32_t)(k >> 32));
+            sel[r] = (int32_t)(uint32_t)k;
+        }
+    }
+    *fpos_out = fpos;
+    return keep;
+}
+
 // K-best of one frame by one wavefront; lds as sized by kbest_lds_bytes.
 template <int P, int E>
 __device__ __forceinline__ void kbest_frame(const KbestArgs& a, int frame, unsigned char* lds)
@@ -336,7 +382,15 @@ __device__ __forceinline__ void kbest_frame(const KbestArgs& a, int frame, unsig
             if (fs < 0) fm = -1;
         }
         int fpos = -1;
-        const int keep = kb_select<E, (KCAP + WAVE - 1) / WAVE>(kh, cnt * P, nvalid, Kt, fm, lane, sn, sel, skey, &fpos);
+        int keep;
+        if constexpr (E <= 2) {
+            if (cnt * P <= WAVE)
+                keep = kb_select_sort<E, 1>(kh, nvalid, Kt, fm, lane, sn, sel, &fpos);
+            else
+                keep = kb_select_sort<E, E>(kh, nvalid, Kt, fm, lane, sn, sel, &fpos);
+        } else {
+            keep = kb_select<E, (KCAP + WAVE - 1) / WAVE>(kh, cnt * P, nvalid, Kt, fm, lane, sn, sel, skey, &fpos);
+        }
         if (fsym) {
             if (lane == 0) a.rank[(size_t)frame * n + k] = fpos + 1;
             fs = fpos >= 0 ? (fpos < keep ? fpos : keep - 1) : -1;
@@ -528,7 +582,15 @@ __device__ __forceinline__ void kbest_frame_reg(const KbestArgs& a, int frame, u
             fm = fs * P + ((k & 1) ? (sy % P) : (sy / P));
         }
         int fpos = -1;
-        const int keep = kb_select<E, (KCAP + WAVE - 1) / WAVE>(kh, cnt * P, nvalid, Kt, fm, lane, sn, sel, skey, &fpos);
+        int keep;
+        if constexpr (E <= 2) {
+            if (cnt * P <= WAVE)
+                keep = kb_select_sort<E, 1>(kh, nvalid, Kt, fm, lane, sn, sel, &fpos);
+            else
+                keep = kb_select_sort<E, E>(kh, nvalid, Kt, fm, lane, sn, sel, &fpos);
+        } else {
+            keep = kb_select<E, (KCAP + WAVE - 1) / WAVE>(kh, cnt * P, nvalid, Kt, fm, lane, sn, sel, skey, &fpos);
+        }
         if (fsym) {
             if (lane == 0) a.rank[(size_t)frame * n + k] = fpos + 1;
             fs = fpos >= 0 ? (fpos < keep ? fpos : keep - 1) : -1;
