@@ -70,6 +70,9 @@ def _declare(L):
     L.orc_batch_prune_features.argtypes = [_I, _I, _I, _P, _P, _P, _P]
     L.orc_path_terms.argtypes = [_I, _I, _P, _P, _P, _P]
     L.orc_mlp_forward.argtypes = [_P, _P, _I, _P]
+    L.orc_mlp_forward_f16.argtypes = [_P, _P, _I, _P]
+    L.orc_round_half.restype = _D
+    L.orc_round_half.argtypes = [_D]
     L.orc_mlp_loss_grad.restype = _D
     L.orc_mlp_loss_grad.argtypes = [_P, _P, _P, _I, _D, _P]
     L.orc_adam_step.argtypes = [_P, _P, _P, _P, _I, _I, _D, _D, _D, _D]
@@ -228,6 +231,20 @@ def mlp_forward(w, X) -> np.ndarray:
     out = np.zeros(X.shape[0])
     lib().orc_mlp_forward(_p(w), _p(X), X.shape[0], _p(out))
     return out
+
+
+def mlp_forward_f16(w, X) -> np.ndarray:
+    """Forward pass with ReLU(layer 1) and W2 rounded to binary16 (the rest
+    in FP64): the precision of the GPU library's inference."""
+    w = _c(w, np.float64)
+    X = _c(X, np.float64)
+    out = np.zeros(X.shape[0])
+    lib().orc_mlp_forward_f16(_p(w), _p(X), X.shape[0], _p(out))
+    return out
+
+
+def round_half(x: float) -> float:
+    return lib().orc_round_half(float(x))
 
 
 def mlp_loss_grad(w, X, y, tau: float = 0.95):

@@ -769,8 +769,25 @@ void orc_prune_features(int n, int P, const double* R, const double* z, double s
 /* ------------------------------------------------------------------ */
 /* MLP 4 -> 128 -> 128 -> 1 (ReLU), pinball loss, Adam                 */
 /* ------------------------------------------------------------------ */
+/* Nearest IEEE binary16 value of x, ties to even: 11 significant bits for
+ * normal values (|x| >= 2^-14), spacing 2^-24 below (subnormals), +-inf from
+ * 65520 = 65504 + half an ulp on. */
+double orc_round_half(double x)
+{
+    if (x == 0.0 || !isfinite(x)) return x;
+    const double ax = fabs(x);
+    if (ax >= 65520.0) return copysign(INFINITY, x);
+    int e;
+    frexp(ax, &e); /* ax in [2^(e-1), 2^e) */
+    const double ulp = (e - 1 < -14) ? ldexp(1.0, -24) : ldexp(1.0, e - 1 - 10);
+    return copysign(nearbyint(ax / ulp) * ulp, x); /* default rounding: nearest, ties to even */
+}
+
+/* One state through the MLP; f16 != 0 rounds the second layer's operands,
+ * ReLU(layer 1) and W2, to binary16 (the inference precision of the GPU
+ * library), everything else stays FP64. */
 static void mlp_one(const double* w, const double* x, double* a1, double* h1, double* a2,
-                    double* h2, double* out)
+                    double* h2, double* out, int f16)
 {
     const int H = ORC_MLP_H;
     for (int i = 0; i < H; ++i) {
@@ -778,10 +795,14 @@ static void mlp_one(const double* w, const double* x, double* a1, double* h1, do
         for (int j = 0; j < ORC_MLP_IN; ++j) s += w[ORC_MLP_W1 + i * ORC_MLP_IN + j] * x[j];
         a1[i] = s;
         h1[i] = s > 0.0 ? s : 0.0;
+        if (f16) h1[i] = orc_round_half(h1[i]);
     }
     for (int i = 0; i < H; ++i) {
         double s = w[ORC_MLP_B2 + i];
-        for (int j = 0; j < H; ++j) s += w[ORC_MLP_W2 + i * H + j] * h1[j];
+        for (int j = 0; j < H; ++j) {
+            const double wij = f16 ? orc_round_half(w[ORC_MLP_W2 + i * H + j]) : w[ORC_MLP_W2 + i * H + j];
+            s += wij * h1[j];
+        }
         a2[i] = s;
         h2[i] = s > 0.0 ? s : 0.0;
     }
@@ -793,7 +814,13 @@ static void mlp_one(const double* w, const double* x, double* a1, double* h1, do
 void orc_mlp_forward(const double* w, const double* X, int B, double* out)
 {
     double a1[ORC_MLP_H], h1[ORC_MLP_H], a2[ORC_MLP_H], h2[ORC_MLP_H];
-    for (int b = 0; b < B; ++b) mlp_one(w, X + (size_t)b * ORC_MLP_IN, a1, h1, a2, h2, out + b);
+    for (int b = 0; b < B; ++b) mlp_one(w, X + (size_t)b * ORC_MLP_IN, a1, h1, a2, h2, out + b, 0);
+}
+
+void orc_mlp_forward_f16(const double* w, const double* X, int B, double* out)
+{
+    double a1[ORC_MLP_H], h1[ORC_MLP_H], a2[ORC_MLP_H], h2[ORC_MLP_H];
+    for (int b = 0; b < B; ++b) mlp_one(w, X + (size_t)b * ORC_MLP_IN, a1, h1, a2, h2, out + b, 1);
 }
 
 double orc_mlp_loss_grad(const double* w, const double* X, const double* y, int B, double tau,
@@ -806,7 +833,7 @@ double orc_mlp_loss_grad(const double* w, const double* X, const double* y, int 
     for (int b = 0; b < B; ++b) {
         const double* x = X + (size_t)b * ORC_MLP_IN;
         double o;
-        mlp_one(w, x, a1, h1, a2, h2, &o);
+        mlp_one(w, x, a1, h1, a2, h2, &o, 0);
         double r = y[b] - o;
         loss += r > 0.0 ? tau * r : (tau - 1.0) * r;
         double dout = (r > 0.0 ? -tau : 1.0 - tau) / (double)B;

@@ -106,6 +106,12 @@ void orc_prune_features(int n, int P, const double* R, const double* z, double s
 #define ORC_MLP_NPARAM (ORC_MLP_B3 + 1)
 
 void orc_mlp_forward(const double* w, const double* X, int B, double* out);
+/* Nearest binary16 value (ties to even) of x, as a double. */
+double orc_round_half(double x);
+/* The forward pass with the second layer's operands (ReLU of layer 1 and W2)
+ * rounded to binary16, the rest in FP64: the precision in which the GPU
+ * library takes its survivor-count decisions. */
+void orc_mlp_forward_f16(const double* w, const double* X, int B, double* out);
 /* mean pinball loss at quantile tau; grad (NPARAM) of the mean loss. */
 double orc_mlp_loss_grad(const double* w, const double* X, const double* y, int B, double tau,
                          double* grad);

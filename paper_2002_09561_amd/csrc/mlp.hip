@@ -1,11 +1,21 @@
 // Learned survivor count: MLP 4 -> 128 -> 128 -> 1 (ReLU), its pinball-loss
 // backward pass and an Adam step.
 //
-// One thread per state.  The weights are read at wave-uniform addresses, so
-// they arrive as scalar operands of the FMAs and the hidden activations stay
-// in registers.  The backward pass writes the per-state activations and
-// deltas feature-major ([128][S]) and a second kernel reduces the weight
-// gradients over the states in a fixed order (deterministic).
+// Inference (forward and schedule) runs on the matrix cores, 16 states per
+// wavefront and step, in the transposed form H1^T = W1 X^T, H2^T = W2 H1^T:
+//   * layer 1: FP32 MFMA 16x16x4 (K = the 4 features), bias as the
+//     accumulator's initial value;
+//   * layer 2: FP16 MFMA 16x16x32 with FP32 accumulation: ReLU(h1) and W2 are
+//     rounded to binary16 (their products are exact in FP32); the W2
+//     fragments stay in registers for the whole kernel;
+//   * layer 3, biases and ReLU in FP32 on the vector ALUs.
+// The hidden units of layer 1 are computed in a permuted order so that its
+// result registers are already laid out as layer 2's B operand.
+// Training (loss and gradient) runs one thread per state in FP32: the weights
+// are read at wave-uniform addresses, so they arrive as scalar operands, and
+// the backward pass writes the per-state activations and deltas
+// feature-major ([128][S]); a second kernel reduces the weight gradients over
+// the states in a fixed order (deterministic).
 #include "common.hpp"
 
 namespace mimo {
@@ -27,56 +37,111 @@ __device__ inline void mlp_layer1(const float* __restrict__ w, const float x[NIN
     }
 }
 
-// out = w3 . relu(W2 h1 + b2) + b3 ; optionally records the layer-2 mask
-__device__ inline float mlp_rest(const float* __restrict__ w, const float h1[HID], uint32_t mask2[HID / 32])
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// hidden unit computed by row i (0..15) of layer-1 block hb (0..7): rows
+// 4g..4g+3 of blocks 2t and 2t+1 hold units 32t + 8g + (0..3) and
+// 32t + 8g + (4..7), i.e. the eight units that lane group g feeds to the
+// K = 32 step t of layer 2
+__host__ __device__ inline int mlp_perm(int hb, int i)
 {
-    float out = w[OB3];
-#pragma unroll 2
-    for (int i = 0; i < HID; ++i) {
-        float s = w[OB2 + i];
+    return 32 * (hb >> 1) + 8 * (i >> 2) + 4 * (hb & 1) + (i & 3);
+}
+
+// S states, 16 per wavefront and step; SCHED: K_t = clamp(ceil(2^(yhat +
+// margin)), kmin, kmax) into ks (non-finite yhat: kmax and the frame flagged
+// for fallback), else yhat into out
+template <bool SCHED>
+__global__ void __launch_bounds__(256) mlp_infer_kernel(const float* __restrict__ w, const float* __restrict__ X,
+                                                        int64_t S, float* __restrict__ out, float margin, int kmin,
+                                                        int kmax, int n, int32_t* __restrict__ ks,
+                                                        uint32_t* __restrict__ flags)
+{
+    __shared__ f32x4 cb1[8 * 4];  // b1 in the permuted order, [hb][g] -> rows 4g..4g+3
+    __shared__ f32x4 cb2[32];     // b2, [nb][g] -> units 16nb + 4g .. +3
+    __shared__ f32x4 cw3[32];     // w3, same layout
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int g = lane >> 4, s16 = lane & 15;
+    if (tid < HID) {
+        reinterpret_cast<float*>(cb1)[tid] = w[OB1 + mlp_perm(tid >> 4, tid & 15)];
+        reinterpret_cast<float*>(cb2)[tid] = w[OB2 + tid];
+        reinterpret_cast<float*>(cw3)[tid] = w[OW3 + tid];
+    }
+    // layer-1 A operand of block hb: row s16 (unit mlp_perm(hb, s16)), feature g
+    float a1[8];
 #pragma unroll
-        for (int j = 0; j < HID; ++j) s = fmaf(w[OW2 + i * HID + j], h1[j], s);
-        if (mask2) {
-            if (s > 0.f) mask2[i >> 5] |= 1u << (i & 31);
+    for (int hb = 0; hb < 8; ++hb) a1[hb] = w[OW1 + mlp_perm(hb, s16) * NIN + g];
+    // layer-2 A operand of output block nb, step t: W2[16nb + s16][32t + 8g + e]
+    half8 a2[8][4];
+#pragma unroll
+    for (int nb = 0; nb < 8; ++nb)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const float* row = w + OW2 + (16 * nb + s16) * HID + 32 * t + 8 * g;
+            const float4 lo = *reinterpret_cast<const float4*>(row), hi = *reinterpret_cast<const float4*>(row + 4);
+            a2[nb][t] = half8{(_Float16)lo.x, (_Float16)lo.y, (_Float16)lo.z, (_Float16)lo.w,
+                              (_Float16)hi.x, (_Float16)hi.y, (_Float16)hi.z, (_Float16)hi.w};
         }
-        out = fmaf(w[OW3 + i], fmaxf(s, 0.f), out);
+    const float b3 = w[OB3];
+    __syncthreads();
+
+    const int64_t ngrp = (S + 15) / 16;
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t grp = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (tid >> 6); grp < ngrp; grp += nwaves) {
+        const int64_t s = grp * 16 + s16;
+        const float xb = s < S ? X[s * NIN + g] : 0.f;  // layer-1 B operand: feature g of state s16
+        f32x4 d2[8];
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) d2[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const f32x4 h0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[2 * t], xb, cb1[(2 * t) * 4 + g], 0, 0, 0);
+            const f32x4 h1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[2 * t + 1], xb, cb1[(2 * t + 1) * 4 + g], 0, 0, 0);
+            const half8 bk = {(_Float16)fmaxf(h0[0], 0.f), (_Float16)fmaxf(h0[1], 0.f), (_Float16)fmaxf(h0[2], 0.f),
+                              (_Float16)fmaxf(h0[3], 0.f), (_Float16)fmaxf(h1[0], 0.f), (_Float16)fmaxf(h1[1], 0.f),
+                              (_Float16)fmaxf(h1[2], 0.f), (_Float16)fmaxf(h1[3], 0.f)};
+#pragma unroll
+            for (int nb = 0; nb < 8; ++nb) d2[nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a2[nb][t], bk, d2[nb], 0, 0, 0);
+        }
+        // lane (g, s16) holds units 16nb + 4g + r of state s16
+        float part = 0.f;
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) {
+            const f32x4 bb = cb2[nb * 4 + g], ww = cw3[nb * 4 + g];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) part = fmaf(ww[r], fmaxf(d2[nb][r] + bb[r], 0.f), part);
+        }
+        part += __builtin_bit_cast(float, xor_lanes(__builtin_bit_cast(uint32_t, part), 16, lane));
+        part += __builtin_bit_cast(float, xor_lanes(__builtin_bit_cast(uint32_t, part), 32, lane));
+        const float yhat = part + b3;
+        if (g == 0 && s < S) {
+            if (!SCHED) {
+                out[s] = yhat;
+            } else {
+                int k;
+                if (!isfinite(yhat)) {
+                    k = kmax;
+                    if (flags) atomicOr(&flags[s / n], MIMO_FLAG_LEARNED_FALLBACK);
+                } else {
+                    const float e = fminf(yhat + margin, 30.f);
+                    const float kk = ceilf(exp2f(e));
+                    k = kk < (float)kmin ? kmin : (kk > (float)kmax ? kmax : (int)kk);
+                }
+                ks[s] = k;
+            }
+        }
     }
-    return out;
 }
 
-__global__ void __launch_bounds__(256) mlp_forward_kernel(const float* __restrict__ w, const float* __restrict__ X,
-                                                          int64_t S, float* __restrict__ out)
+static int mlp_infer_grid(int64_t S)
 {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S) return;
-    float x[NIN], h1[HID];
-#pragma unroll
-    for (int j = 0; j < NIN; ++j) x[j] = X[s * NIN + j];
-    mlp_layer1(w, x, h1);
-    out[s] = mlp_rest(w, h1, nullptr);
-}
-
-__global__ void __launch_bounds__(256) mlp_schedule_kernel(const float* __restrict__ w, const float* __restrict__ X,
-                                                           int64_t S, float margin, int kmin, int kmax, int n,
-                                                           int32_t* __restrict__ ks, uint32_t* __restrict__ flags)
-{
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S) return;
-    float x[NIN], h1[HID];
-#pragma unroll
-    for (int j = 0; j < NIN; ++j) x[j] = X[s * NIN + j];
-    mlp_layer1(w, x, h1);
-    const float yhat = mlp_rest(w, h1, nullptr);
-    int k;
-    if (!isfinite(yhat)) {
-        k = kmax;
-        if (flags) atomicOr(&flags[s / n], MIMO_FLAG_LEARNED_FALLBACK);
-    } else {
-        const float e = fminf(yhat + margin, 30.f);
-        const float kk = ceilf(exp2f(e));
-        k = kk < (float)kmin ? kmin : (kk > (float)kmax ? kmax : (int)kk);
-    }
-    ks[s] = k;
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t want = ((S + 15) / 16 + 3) / 4;
+    const int64_t cap = 2 * (int64_t)(cus > 0 ? cus : 256);
+    return (int)(want < cap ? want : cap);
 }
 
 // per state: activations and deltas, feature-major in the workspace
@@ -195,8 +260,8 @@ extern "C" int32_t prune_mlp_forward(const float* w, const float* X, int64_t S, 
     if (S < 0) return fail(MIMO_ERR_INVALID_ARG, "prune_mlp_forward: S < 0");
     if (S == 0) return MIMO_OK;
     if (!w || !X || !out) return fail(MIMO_ERR_INVALID_ARG, "prune_mlp_forward: null pointer");
-    hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, (hipStream_t)stream, w,
-                       X, S, out);
+    hipLaunchKernelGGL(mlp_infer_kernel<false>, dim3(mlp_infer_grid(S)), dim3(256), 0, (hipStream_t)stream, w, X, S,
+                       out, 0.f, 1, 1, 1, nullptr, nullptr);
     return check_launch("prune_mlp_forward");
 }
 
@@ -208,8 +273,8 @@ extern "C" int32_t prune_mlp_schedule(const float* w, const float* X, int64_t S,
         return fail(MIMO_ERR_INVALID_ARG, "prune_mlp_schedule: need 1 <= k_min <= k_max <= %d", MIMO_MAX_K);
     if (S == 0) return MIMO_OK;
     if (!w || !X || !k_sched) return fail(MIMO_ERR_INVALID_ARG, "prune_mlp_schedule: null pointer");
-    hipLaunchKernelGGL(mlp_schedule_kernel, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, (hipStream_t)stream, w,
-                       X, S, margin, k_min, k_max, n, k_sched, flags);
+    hipLaunchKernelGGL(mlp_infer_kernel<true>, dim3(mlp_infer_grid(S)), dim3(256), 0, (hipStream_t)stream, w, X, S,
+                       nullptr, margin, k_min, k_max, n, k_sched, flags);
     return check_launch("prune_mlp_schedule");
 }
 

@@ -18,13 +18,23 @@ def test_mlp_forward_parity(gpu, orc):
     ref = orc.mlp_forward(w, X)
     out = gpu.mlp_forward(torch.tensor(w, dtype=torch.float32).cuda(),
                           torch.tensor(X, dtype=torch.float32).cuda()).cpu().numpy()
-    # FP32 inputs and weights, FP32 accumulation over 128 terms
+    # the library's inference precision: FP32 inputs and weights, layer 2 on
+    # binary16 operands (ReLU(h1), W2) with FP32 accumulation.  The oracle's
+    # binary16 mode rounds the same operands (from FP64 layer-1 values); what
+    # is left is FP32 accumulation over 128 terms and, rarely, an h1 that
+    # FP32 and FP64 round to neighbouring halves
     wr = w.astype(np.float32).astype(np.float64)
     Xr = X.astype(np.float32).astype(np.float64)
-    ref32 = orc.mlp_forward(wr, Xr)
-    scale = np.maximum(1.0, np.abs(ref32))
-    assert np.max(np.abs(out - ref32) / scale) < 1e-4
-    assert np.max(np.abs(out - ref) / scale) < 1e-3
+    ref16 = orc.mlp_forward_f16(wr, Xr)
+    scale = np.maximum(1.0, np.abs(ref16))
+    assert np.max(np.abs(out - ref16) / scale) < 2e-4
+    # against the FP64 definition: binary16 rounding of 128-term sums
+    # (relative 2^-11 per operand) bounds the difference
+    assert np.max(np.abs(out - ref) / np.maximum(1.0, np.abs(ref))) < 3e-2
+    # tails of the batch (S not a multiple of 16) are handled
+    out7 = gpu.mlp_forward(torch.tensor(w, dtype=torch.float32).cuda(),
+                           torch.tensor(X[:7], dtype=torch.float32).cuda()).cpu().numpy()
+    assert np.array_equal(out7, out[:7])
 
 
 def test_mlp_loss_grad_parity(gpu, orc):
@@ -82,3 +92,11 @@ def test_mlp_schedule_mapping(gpu, orc):
     # exp2 in FP32 may round a value that sits on an integer either way
     assert np.all(np.abs(ks - expect) <= 1)
     assert (ks == expect).mean() > 0.99
+    # the same decisions taken from the oracle's forward pass in the
+    # library's precision: equal except where yhat + margin lies within the
+    # FP32 accumulation error of log2 of an integer
+    ref16 = orc.mlp_forward_f16(w.astype(np.float32).astype(np.float64), X.astype(np.float32).astype(np.float64))
+    e = ref16 + 0.5
+    expect16 = np.clip(np.ceil(np.exp2(e)), 2, 40)
+    near = np.abs(np.exp2(e) - np.round(np.exp2(e))) < 2e-4 * np.exp2(e)
+    assert np.all((ks == expect16) | near)

@@ -353,6 +353,42 @@ def test_adam_first_step_is_signed_lr(orc):
     assert np.allclose(w0 - w, 1e-2 * np.sign(g), rtol=1e-12)
 
 
+def test_round_half_matches_ieee_binary16(orc):
+    """The oracle's binary16 rounding agrees with numpy's IEEE half conversion
+    (round to nearest, ties to even) over normals, subnormals, exact ties and
+    overflow."""
+    rng = np.random.default_rng(11)
+    xs = np.concatenate([rng.normal(size=2000) * 10.0 ** rng.integers(-9, 5, size=2000),
+                         # exact ties between neighbouring halves (odd and even last bit)
+                         (np.arange(1, 200) * 2 + 1) * 2.0 ** -11 / 2 + 1.0,
+                         np.arange(1, 50) * 2.0 ** -25,          # subnormal ties
+                         [65504.0, 65519.9, 65520.0, -7e4, 0.0, -0.0, 6.0e-8, 2.0 ** -24]])
+    got = np.array([orc.round_half(x) for x in xs])
+    ref = xs.astype(np.float16).astype(np.float64)
+    assert np.array_equal(got, ref)
+
+
+def test_mlp_forward_f16_is_exact_on_half_representable_operands(orc):
+    """With W2 and every ReLU(layer 1) value exactly representable in binary16,
+    the binary16 forward pass equals the FP64 definition bit for bit; with
+    general weights it differs by binary16 rounding only."""
+    rng = np.random.default_rng(12)
+    H = 128
+    w = np.zeros(17281)
+    w[0:512] = rng.integers(-3, 4, size=512)              # W1: small integers
+    w[512:640] = rng.integers(-4, 5, size=128)            # b1
+    w[640:640 + H * H] = rng.integers(-64, 65, size=H * H) / 64.0   # W2 on a 2^-6 grid
+    w[640 + H * H:640 + H * H + 128] = rng.normal(size=128)
+    w[640 + H * H + 128:640 + H * H + 256] = rng.normal(size=128)
+    w[-1] = 0.25
+    X = rng.integers(-3, 4, size=(50, 4)).astype(np.float64)  # h1: integers below 2^11
+    assert np.array_equal(orc.mlp_forward_f16(w, X), orc.mlp_forward(w, X))
+    w2 = rng.normal(0, 0.2, size=17281)
+    X2 = rng.normal(size=(200, 4))
+    a, b = orc.mlp_forward_f16(w2, X2), orc.mlp_forward(w2, X2)
+    assert 0 < np.max(np.abs(a - b)) < 2e-2 * max(1.0, np.max(np.abs(b)))
+
+
 # --------------------------------------------------------------- T11: Gray map
 @pytest.mark.parametrize("P", [2, 4, 8])
 def test_gray_adjacent_points_differ_in_one_bit(orc, P):
