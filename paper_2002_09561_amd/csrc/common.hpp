@@ -28,8 +28,35 @@ __host__ __device__ inline int64_t r_row_off(int n, int k)
 
 __host__ __device__ inline int64_t r_packed_size(int n) { return (int64_t)n * (n + 1) / 2; }
 
+// Exchange with lane ^ j for a compile-time j (after unrolling): DPP for
+// j = 1, 2 (quad permutes) and 8 (rotate by 8 in a row of 16), an LDS-free
+// swizzle for 4 and 16, a permute for 32.
+__device__ __forceinline__ uint32_t xor_lanes(uint32_t v, int j, int lane)
+{
+    switch (j) {
+    case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+    case 2: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
+    case 8: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);
+    case 4: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F);
+    case 16: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);
+    default: return (uint32_t)__builtin_amdgcn_ds_bpermute(((lane ^ j) & (WAVE - 1)) << 2, (int)v);
+    }
+}
+
+__device__ __forceinline__ uint64_t xor_lanes_u64(uint64_t v, int j, int lane)
+{
+    const uint32_t lo = xor_lanes((uint32_t)v, j, lane), hi = xor_lanes((uint32_t)(v >> 32), j, lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ inline float shfl_f(float v, int src) { return __shfl(v, src, WAVE); }
-__device__ inline float shfl_xor_f(float v, int m) { return __shfl_xor(v, m, WAVE); }
+// exchange with lane ^ m (all lanes active; DPP or swizzle when m is a
+// compile-time power of two below 32)
+__device__ __forceinline__ float shfl_xor_f(float v, int m)
+{
+    const int lane = __lane_id();
+    return __builtin_bit_cast(float, xor_lanes(__builtin_bit_cast(uint32_t, v), m, lane));
+}
 
 __device__ inline uint64_t shfl_xor_u64(uint64_t v, int m)
 {
@@ -62,27 +89,6 @@ __device__ inline uint64_t wave_min_u64(uint64_t v)
         v = o < v ? o : v;
     }
     return v;
-}
-
-// Exchange with lane ^ j for a compile-time j (after unrolling): DPP for
-// j = 1, 2 (quad permutes) and 8 (rotate by 8 in a row of 16), an LDS-free
-// swizzle for 4 and 16, a permute for 32.
-__device__ __forceinline__ uint32_t xor_lanes(uint32_t v, int j, int lane)
-{
-    switch (j) {
-    case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
-    case 2: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
-    case 8: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);
-    case 4: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F);
-    case 16: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);
-    default: return (uint32_t)__builtin_amdgcn_ds_bpermute(((lane ^ j) & (WAVE - 1)) << 2, (int)v);
-    }
-}
-
-__device__ __forceinline__ uint64_t xor_lanes_u64(uint64_t v, int j, int lane)
-{
-    const uint32_t lo = xor_lanes((uint32_t)v, j, lane), hi = xor_lanes((uint32_t)(v >> 32), j, lane);
-    return ((uint64_t)hi << 32) | lo;
 }
 
 // In-wave bitonic sort of 64*E keys, ascending by position e*64 + lane.

@@ -10,9 +10,15 @@ __device__ inline double amp_d(int P, int i)
     return (double)(2 * i - (P - 1)) * sqrt(3.0 / (2.0 * (double)(P * P - 1)));
 }
 
+__device__ __forceinline__ double xor_lanes_f64(double v, int m, int lane)
+{
+    return __builtin_bit_cast(double, xor_lanes_u64(__builtin_bit_cast(uint64_t, v), m, lane));
+}
+
 // one wave per frame: lanes run along a row of H (coalesced reads), the
 // row's residual y_i - sum_j h_ij s_j is reduced across the wave in FP64 in a
-// fixed order, and lane 0 accumulates |residual|^2 over the rows
+// fixed order, and lane 0 accumulates |residual|^2 over the rows; two rows
+// per iteration keep two loads and two reductions in flight
 __global__ void __launch_bounds__(256) metric_kernel(const float2* __restrict__ H, const float2* __restrict__ y,
                                                      const int32_t* __restrict__ sym, int B, int N, int M, int P,
                                                      double* __restrict__ out)
@@ -35,25 +41,37 @@ __global__ void __launch_bounds__(256) metric_kernel(const float2* __restrict__ 
     const float2* Hf = H + (size_t)f * N * M;
     const float2* yf = y + (size_t)f * N;
     double acc = 0.0;
-    for (int i = 0; i < N; ++i) {
-        double pr = 0.0, pi = 0.0;
+    for (int i0 = 0; i0 < N; i0 += 2) {
+        double pr[2] = {0.0, 0.0}, pi[2] = {0.0, 0.0};
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            const int j = lane + WAVE * c;
-            if (j < M) {
-                const float2 h = Hf[(size_t)i * M + j];
-                pr += (double)h.x * sr[c] - (double)h.y * si[c];
-                pi += (double)h.x * si[c] + (double)h.y * sr[c];
+        for (int u = 0; u < 2; ++u) {
+            const int i = i0 + u;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int j = lane + WAVE * c;
+                if (j < M && i < N) {
+                    const float2 h = Hf[(size_t)i * M + j];
+                    pr[u] += (double)h.x * sr[c] - (double)h.y * si[c];
+                    pi[u] += (double)h.x * si[c] + (double)h.y * sr[c];
+                }
             }
         }
 #pragma unroll
         for (int m = 32; m >= 1; m >>= 1) {
-            pr += __shfl_xor(pr, m, WAVE);
-            pi += __shfl_xor(pi, m, WAVE);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                pr[u] += xor_lanes_f64(pr[u], m, lane);
+                pi[u] += xor_lanes_f64(pi[u], m, lane);
+            }
         }
-        const float2 yy = yf[i];
-        const double er = (double)yy.x - pr, ei = (double)yy.y - pi;
-        acc += er * er + ei * ei;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (i0 + u < N) {
+                const float2 yy = yf[i0 + u];
+                const double er = (double)yy.x - pr[u], ei = (double)yy.y - pi[u];
+                acc += er * er + ei * ei;
+            }
+        }
     }
     if (lane == 0) out[f] = acc;
 }
@@ -86,7 +104,58 @@ __global__ void __launch_bounds__(256) errors_kernel(const int32_t* __restrict__
     }
 }
 
-// one wave per frame: the K = 1 path and its per-level state
+// Per-level state of the K = 1 (successive-cancellation) path, one wave per
+// frame.  Level k: centre b = z_k - sum_{t>0} R_k,k+t x_{k+t}, nearest PAM
+// point a, path metric pd += (b - R_kk a)^2; the features are k/n, the
+// centre's distance to the nearest decision boundary in units of the
+// spacing, log2(R_kk 2c / sigma_r) and pd / ((n - k) sigma_r^2).  The R rows
+// of the next two levels are loaded while the current one is used.
+constexpr int FEAT_RPL = 4;  // row entries per lane: n <= 256
+
+__device__ __forceinline__ void feat_load(const float* __restrict__ Rf, const float* __restrict__ zf, int n, int k,
+                                          int lane, float (&r)[FEAT_RPL], float& zk)
+{
+    if (k < 0) return;
+    const float* rk = Rf + r_row_off(n, k);
+#pragma unroll
+    for (int i = 0; i < FEAT_RPL; ++i) {
+        const int t = lane + WAVE * i;
+        r[i] = t < n - k ? rk[t] : 0.f;
+    }
+    zk = zf[k];
+}
+
+__device__ __forceinline__ void feat_level(int k, int n, int P, float c, float sr, int lane,
+                                           const float (&r)[FEAT_RPL], float zk, float* xa, float& pd,
+                                           float* __restrict__ featf)
+{
+    float acc = 0.f;
+#pragma unroll
+    for (int i = 0; i < FEAT_RPL; ++i) {
+        const int t = lane + WAVE * i;
+        if (t >= 1 && t < n - k) acc = fmaf(r[i], xa[k + t], acc);
+    }
+    acc = wave_sum(acc);
+    const float rkk = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, r[0])));
+    const float b = zk - acc;
+    const float u = b / rkk;
+    int i = (int)floorf((u / c + (float)(P - 1)) * 0.5f + 0.5f);
+    i = i < 0 ? 0 : (i > P - 1 ? P - 1 : i);
+    const float a = (float)(2 * i - (P - 1)) * c;
+    const float e = fmaf(-rkk, a, b);
+    pd = fmaf(e, e, pd);
+    const float v = u / c;
+    float nb = 2.f * floorf(v * 0.5f + 0.5f);
+    nb = fminf(fmaxf(nb, -(float)(P - 2)), (float)(P - 2));
+    if (lane == 0) {
+        xa[k] = a;
+        *reinterpret_cast<float4*>(featf + (size_t)k * 4) =
+            make_float4((float)k / (float)n, fabsf(v - nb) * 0.5f, log2f(rkk * 2.f * c / sr),
+                        pd / ((float)(n - k) * sr * sr));
+    }
+    __syncthreads();  // xa[k] visible to the wave
+}
+
 __global__ void __launch_bounds__(64) features_kernel(const float* __restrict__ R, const float* __restrict__ z,
                                                       const float* __restrict__ sigma2, int n, int P,
                                                       float* __restrict__ feat)
@@ -95,34 +164,25 @@ __global__ void __launch_bounds__(64) features_kernel(const float* __restrict__ 
     const int f = blockIdx.x, lane = threadIdx.x;
     const float* Rf = R + (size_t)f * r_packed_size(n);
     const float* zf = z + (size_t)f * n;
+    float* featf = feat + (size_t)f * n * 4;
     const float c = pam_scale(P);
     const float sr = sqrtf(sigma2[f] * 0.5f);
     float pd = 0.f;
-    for (int k = n - 1; k >= 0; --k) {
-        const float* rk = Rf + r_row_off(n, k);
-        float acc = 0.f;
-        for (int t = 1 + lane; t < n - k; t += WAVE) acc = fmaf(rk[t], xa[k + t], acc);
-        acc = wave_sum(acc);
-        const float rkk = rk[0];
-        const float b = zf[k] - acc;
-        const float u = b / rkk;
-        int i = (int)floorf((u / c + (float)(P - 1)) * 0.5f + 0.5f);
-        i = i < 0 ? 0 : (i > P - 1 ? P - 1 : i);
-        const float a = (float)(2 * i - (P - 1)) * c;
-        const float e = fmaf(-rkk, a, b);
-        pd = fmaf(e, e, pd);
-        const float v = u / c;
-        float nb = 2.f * floorf(v * 0.5f + 0.5f);
-        nb = fminf(fmaxf(nb, -(float)(P - 2)), (float)(P - 2));
-        if (lane == 0) {
-            xa[k] = a;
-            float* o = feat + ((size_t)f * n + k) * 4;
-            o[0] = (float)k / (float)n;
-            o[1] = fabsf(v - nb) * 0.5f;
-            o[2] = log2f(rkk * 2.f * c / sr);
-            o[3] = pd / ((float)(n - k) * sr * sr);
-        }
-        __syncthreads();
+    float ra[FEAT_RPL], rb[FEAT_RPL], za = 0.f, zb = 0.f;
+    feat_load(Rf, zf, n, n - 1, lane, ra, za);
+    feat_load(Rf, zf, n, n - 2, lane, rb, zb);
+    // n = 2 n_tx is even: levels go in pairs (k, k-1) from buffers a and b
+    for (int k = n - 1; k >= 1; k -= 2) {
+        float rc[FEAT_RPL], zc = za;
+#pragma unroll
+        for (int i = 0; i < FEAT_RPL; ++i) rc[i] = ra[i];
+        feat_load(Rf, zf, n, k - 2, lane, ra, za);
+        feat_level(k, n, P, c, sr, lane, rc, zc, xa, pd, featf);
+#pragma unroll
+        for (int i = 0; i < FEAT_RPL; ++i) rc[i] = rb[i];
+        zc = zb;
+        feat_load(Rf, zf, n, k - 3, lane, rb, zb);
+        feat_level(k - 1, n, P, c, sr, lane, rc, zc, xa, pd, featf);
     }
 }
 
