@@ -614,9 +614,16 @@ __device__ __forceinline__ void kbest_frame_reg(const KbestArgs& a, int frame, u
         }
         if (s_own < keep && q == wk % L) {
             const uint32_t hb = half_bits((float)(2 * cnew - (P - 1)));
+            // only the chunk holding word ik is visited (uniform guard)
 #pragma unroll
-            for (int i = 0; i < NWL; ++i)
-                if (i == ik) pw[i] = (k & 1) ? ((pw[i] & 0x0000ffffu) | (hb << 16)) : ((pw[i] & 0xffff0000u) | hb);
+            for (int c0 = 0; c0 < NWL; c0 += CHW) {
+                if (ik >= c0 && ik < c0 + CHW) {
+#pragma unroll
+                    for (int i = c0; i < c0 + CHW; ++i)
+                        if (i == ik)
+                            pw[i] = (k & 1) ? ((pw[i] & 0x0000ffffu) | (hb << 16)) : ((pw[i] & 0xffff0000u) | hb);
+                }
+            }
         }
         cnt = keep;
     }
