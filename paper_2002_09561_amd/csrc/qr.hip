@@ -10,11 +10,14 @@
 // error of R, which the Gram form amplifies by cond(H)^2, stays far below
 // the FP32 rounding of the output for any channel with cond(H) < 10^5.
 //
-// One workgroup per frame.  G's upper triangle is split into 4 x 4 complex
-// tiles, one per thread, held in registers for the whole frame:
-//   1. Gram: [H | y] streams through LDS in chunks of 16 rows (the next chunk
-//      is prefetched into registers while the current one is consumed); each
-//      thread accumulates conj(a_i)^T a_j over the rows for its tile.
+// A frame takes one thread per 4 x 4 complex tile of G's upper triangle
+// (the tile stays in registers for the whole frame); frames of 4 to 6 waves
+// run two per workgroup.
+//   1. Gram: [H | y] streams through LDS in chunks of up to 16 rows (as many
+//      as let each thread stage at most 4 elements), converted to FP64 once
+//      when staged; the next chunk is prefetched into registers while the
+//      current one is consumed; each thread accumulates conj(a_i)^T a_j over
+//      the rows for its tile.
 //   2. Right-looking Cholesky: at step k the owners of row k of the current
 //      Schur complement publish it in LDS (double-buffered, so one barrier per
 //      step) and every thread applies G_ij -= conj(g_ki) g_kj / g_kk to its
@@ -28,9 +31,10 @@
 namespace mimo {
 
 constexpr int CQ_T = 4;       // tile edge in complex entries
-constexpr int CQ_RCH = 16;    // rows of [H | y] per LDS chunk
-constexpr int CQ_PF_MAX = 6;  // max chunk elements a thread stages
+constexpr int CQ_RCH_MAX = 16;  // rows of [H | y] per LDS chunk, at most
+constexpr int CQ_PF = 4;        // chunk elements a thread stages, at most
 constexpr int CQ_MAX_THREADS = 576;  // 33 x 34 / 2 = 561 tiles at n_tx = 128
+constexpr int CQ_MAX_WG = 768;       // two frames of up to 6 waves per workgroup
 
 struct CqShape {
     int C;       // M + 1 columns of [H | y]
@@ -49,39 +53,43 @@ __host__ __device__ inline CqShape cq_shape(int M)
     return s;
 }
 
-// one thread per tile, and enough threads that each stages at most
-// CQ_PF_MAX elements of a chunk (16 x CP)
+// one thread per tile (rounded up to whole waves)
 __host__ __device__ inline int cq_threads(int M)
 {
     const CqShape s = cq_shape(M);
-    const int a = (s.ntiles + WAVE - 1) / WAVE * WAVE;
-    const int st = (16 * s.CP + CQ_PF_MAX - 1) / CQ_PF_MAX;
-    const int b = (st + WAVE - 1) / WAVE * WAVE;
-    return a > b ? a : b;
+    return (s.ntiles + WAVE - 1) / WAVE * WAVE;
+}
+
+// rows of [H | y] per LDS chunk for nthr threads: as many as let every
+// thread stage at most CQ_PF elements, at most CQ_RCH_MAX
+__host__ __device__ inline int cq_rows(int M, int nthr)
+{
+    const int r = CQ_PF * nthr / cq_shape(M).CP;
+    return r < CQ_RCH_MAX ? (r < 1 ? 1 : r) : CQ_RCH_MAX;
 }
 
 // LDS bytes: row buffers [2][CP] complex double, pivots [CP] and a 4-entry
-// spare [4] double, chunk buffers [2][16][CP] complex float
-__host__ __device__ inline size_t cq_lds_bytes(int M)
+// spare [4] double, chunk buffers [2][rch][CP] complex double
+__host__ __device__ inline size_t cq_lds_bytes(int M, int rch)
 {
     const int CP = cq_shape(M).CP;
-    return (size_t)CP * (2 * 16 + 8) + CQ_T * 8 + (size_t)2 * CQ_RCH * CP * 8;
+    return (size_t)CP * (2 * 16 + 8) + CQ_T * 8 + (size_t)2 * rch * CP * 16;
 }
 
 struct cd {
     double x, y;
 };
 
-// element e of chunk c of [H | y] (rows 16c .. 16c+15, zero-padded to CP
-// columns; e = row * CP + col).  Branch-free: an element outside the frame
+// element e of chunk c of [H | y] (rows rch c .. rch c + rch - 1, zero-padded
+// to CP columns; e = row * CP + col).  Branch-free: an element outside the frame
 // loads H[0] and is replaced by zero, so a thread's loads issue back to back.
 // row = e / CP by a float reciprocal: e < 2^12 keeps it exact.
 __device__ __forceinline__ float2 cq_elem(const float2* __restrict__ Hf, const float2* __restrict__ yf, int N, int M,
-                                          int CP, float rcp_cp, int tot, int c, int e)
+                                          int CP, float rcp_cp, int tot, int rch, int c, int e)
 {
     const int row = (int)(((float)e + 0.5f) * rcp_cp);
     const int col = e - row * CP;
-    const int i = c * CQ_RCH + row;
+    const int i = c * rch + row;
     const bool valid = e < tot && i < N && col <= M;
     const float2* p = col < M ? Hf + ((size_t)i * M + col) : yf + i;
     p = valid ? p : Hf;
@@ -90,14 +98,14 @@ __device__ __forceinline__ float2 cq_elem(const float2* __restrict__ Hf, const f
 }
 
 // LDS slot of chunk element e (row, col = 4J + q) in the chunk layout
-// [row][h][J] of float4 pairs: columns 4J + 2h and 4J + 2h + 1 side by side,
-// so that the lanes of a wave (consecutive J) read 16-byte neighbours.
+// [row][q][J] of complex doubles, so that the lanes of a wave (consecutive J)
+// read 16-byte neighbours.
 __device__ __forceinline__ int cq_lds_slot(int e, int CP, int nb, float rcp_cp)
 {
     const int row = (int)(((float)e + 0.5f) * rcp_cp);
     const int col = e - row * CP;
     const int J = col >> 2, q = col & 3;
-    return row * CP + (((q >> 1) * nb + J) << 1) + (q & 1);
+    return row * CP + q * nb + J;
 }
 
 // publish register row LR of the tile (a compile-time index keeps the tile
@@ -155,19 +163,18 @@ __device__ __forceinline__ void cq_step(int k, int M, int CP, int nb, int tid, b
     }
 }
 
-template <int PF>
 __device__ __forceinline__ void cholqr_frame(const float2* __restrict__ Hf, const float2* __restrict__ yf, int N,
                                              int M, float* __restrict__ Rf, float* __restrict__ zf,
-                                             float* __restrict__ resid_out, unsigned char* smem)
+                                             float* __restrict__ resid_out, unsigned char* smem, int tid, int nthr,
+                                             bool live)
 {
     const CqShape sh = cq_shape(M);
     const int CP = sh.CP;
     const int n = 2 * M;
-    const int tid = threadIdx.x, nthr = blockDim.x;
     const int nb = sh.nb;
     cd* rowbuf = reinterpret_cast<cd*>(smem);                   // [2][4][nb]
     double* diag = reinterpret_cast<double*>(rowbuf + 2 * CP);  // [CP] pivots, then [4] spare
-    float2* ach = reinterpret_cast<float2*>(diag + CP + CQ_T);  // [2][16][2][nb] x 2 complex
+    cd* ach = reinterpret_cast<cd*>(diag + CP + CQ_T);           // [2][16][4][nb] complex
 
     // tile (I, J), I <= J, enumerated row by row
     const bool has_tile = tid < sh.ntiles;
@@ -189,32 +196,39 @@ __device__ __forceinline__ void cholqr_frame(const float2* __restrict__ Hf, cons
         for (int c = 0; c < CQ_T; ++c) gr[r][c] = gi[r][c] = 0.0;
 
     // ---- 1. Gram matrix over chunks of 16 rows
-    const int nchunk = (N + CQ_RCH - 1) / CQ_RCH;
-    const int tot = CQ_RCH * CP;
+    const int rch = cq_rows(M, nthr);
+    const int nchunk = (N + rch - 1) / rch;
+    const int tot = rch * CP;
     const float rcp_cp = 1.0f / (float)CP;
-    float2 pf[PF];
+    float2 pf[CQ_PF];
 #pragma unroll
-    for (int q = 0; q < PF; ++q) pf[q] = cq_elem(Hf, yf, N, M, CP, rcp_cp, tot, 0, tid + q * nthr);
+    for (int q = 0; q < CQ_PF; ++q) pf[q] = cq_elem(Hf, yf, N, M, CP, rcp_cp, tot, rch, 0, tid + q * nthr);
     for (int c = 0; c < nchunk; ++c) {
-        float2* buf = ach + (c & 1) * tot;
+        cd* buf = ach + (c & 1) * tot;
 #pragma unroll
-        for (int q = 0; q < PF; ++q) {
+        for (int q = 0; q < CQ_PF; ++q) {
             const int e = tid + q * nthr;
-            if (e < tot) buf[cq_lds_slot(e, CP, nb, rcp_cp)] = pf[q];
+            if (e < tot) buf[cq_lds_slot(e, CP, nb, rcp_cp)] = {(double)pf[q].x, (double)pf[q].y};
         }
         __syncthreads();  // chunk c visible; chunk c-1's buffer no longer read
         if (c + 1 < nchunk) {
 #pragma unroll
-            for (int q = 0; q < PF; ++q) pf[q] = cq_elem(Hf, yf, N, M, CP, rcp_cp, tot, c + 1, tid + q * nthr);
+            for (int q = 0; q < CQ_PF; ++q)
+                pf[q] = cq_elem(Hf, yf, N, M, CP, rcp_cp, tot, rch, c + 1, tid + q * nthr);
         }
         if (has_tile) {
-            const int nr = min(CQ_RCH, N - c * CQ_RCH);
+            const int nr = min(rch, N - c * rch);
             for (int rr = 0; rr < nr; ++rr) {
-                const float4* rowp = reinterpret_cast<const float4*>(buf + rr * CP);
-                const float4 a01 = rowp[I], a23 = rowp[nb + I];
-                const float4 b01 = rowp[J], b23 = rowp[nb + J];
-                const double ar[CQ_T] = {a01.x, a01.z, a23.x, a23.z}, ai[CQ_T] = {a01.y, a01.w, a23.y, a23.w};
-                const double br[CQ_T] = {b01.x, b01.z, b23.x, b23.z}, bi[CQ_T] = {b01.y, b01.w, b23.y, b23.w};
+                const cd* rowp = buf + rr * CP;
+                double ar[CQ_T], ai[CQ_T], br[CQ_T], bi[CQ_T];
+#pragma unroll
+                for (int q = 0; q < CQ_T; ++q) {
+                    const cd a = rowp[q * nb + I], b = rowp[q * nb + J];
+                    ar[q] = a.x;
+                    ai[q] = a.y;
+                    br[q] = b.x;
+                    bi[q] = b.y;
+                }
                 // G_ij += conj(a_i) a_j
 #pragma unroll
                 for (int r = 0; r < CQ_T; ++r)
@@ -241,7 +255,7 @@ __device__ __forceinline__ void cholqr_frame(const float2* __restrict__ Hf, cons
     __syncthreads();  // diag complete
 
     // ---- 3. output: R_ij = g_ij / sqrt(g_ii), real blocks in packed level order
-    if (has_tile) {
+    if (has_tile && live) {
 #pragma unroll
         for (int r = 0; r < CQ_T; ++r) {
             const int i = i0 + r;
@@ -283,22 +297,29 @@ __device__ __forceinline__ void cholqr_frame(const float2* __restrict__ Hf, cons
     __syncthreads();  // the LDS may be reused by the next frame
 }
 
-template <int PF>
-__global__ void __launch_bounds__(CQ_MAX_THREADS) qr_kernel(const float2* __restrict__ H,
-                                                            const float2* __restrict__ y, int N, int M,
-                                                            float* __restrict__ R, float* __restrict__ z,
-                                                            float* __restrict__ resid)
+// Frames of up to 6 waves are processed two per workgroup (12 waves, 3 per
+// SIMD): a workgroup of 6 waves at 3 waves per SIMD leaves the second
+// workgroup of a CU no room on the SIMDs that hold two of its waves.  tpf
+// threads per frame; a second half beyond the batch computes the last frame
+// again and stores nothing.
+__global__ void __launch_bounds__(CQ_MAX_WG) qr_kernel(const float2* __restrict__ H, const float2* __restrict__ y,
+                                                       int N, int M, float* __restrict__ R, float* __restrict__ z,
+                                                       float* __restrict__ resid, int B, int fpw, int tpf)
 {
     extern __shared__ __align__(16) unsigned char smem_qr[];
-    const int frame = blockIdx.x;
+    const int half = (int)threadIdx.x / tpf;
+    const int f = (int)blockIdx.x * fpw + half;
+    const bool live = f < B;
+    const int frame = live ? f : B - 1;
     const int n = 2 * M;
-    cholqr_frame<PF>(H + (size_t)frame * N * M, y + (size_t)frame * N, N, M, R + (size_t)frame * r_packed_size(n),
-                 z + (size_t)frame * n, resid ? resid + frame : nullptr, smem_qr);
+    const size_t lds = (cq_lds_bytes(M, cq_rows(M, tpf)) + 15) & ~(size_t)15;
+    cholqr_frame(H + (size_t)frame * N * M, y + (size_t)frame * N, N, M, R + (size_t)frame * r_packed_size(n),
+                     z + (size_t)frame * n, resid ? resid + frame : nullptr, smem_qr + half * lds,
+                     (int)threadIdx.x - half * tpf, tpf, live);
 }
 
 // Uneven batch: frames of different sizes pulled from a device work counter
 // by a persistent grid sized for the largest frame.
-template <int PF>
 __global__ void __launch_bounds__(CQ_MAX_THREADS) qr_uneven_kernel(const mimo_frame_desc* __restrict__ desc, int B,
                                                                    const float2* __restrict__ H,
                                                                    const float2* __restrict__ y,
@@ -316,18 +337,22 @@ __global__ void __launch_bounds__(CQ_MAX_THREADS) qr_uneven_kernel(const mimo_fr
         const mimo_frame_desc d = desc[f];
         // the workgroup and its LDS are sized for n_tx <= n_rx <= max_rx
         if (d.n_tx < 1 || d.n_tx > d.n_rx || d.n_rx > max_rx) continue;
-        cholqr_frame<PF>(H + d.h_off, y + d.y_off, d.n_rx, d.n_tx, R + d.r_off, z + d.z_off, nullptr, smem_qr);
+        cholqr_frame(H + d.h_off, y + d.y_off, d.n_rx, d.n_tx, R + d.r_off, z + d.z_off, nullptr, smem_qr,
+                         (int)threadIdx.x, (int)blockDim.x, true);
     }
 }
 
 __global__ void reset_counter_kernel(int* counter) { *counter = 0; }
 
-// chunk elements each thread stages for n_tx = M with `threads` threads
-static int cq_per_thread(int M, int threads)
+// dynamic LDS beyond 64 KB (n_tx > 100) must be allowed per kernel
+static int32_t cq_allow_lds(const void* kernel, size_t lds)
 {
-    const int tot = CQ_RCH * cq_shape(M).CP;
-    return (tot + threads - 1) / threads;
+    if (lds <= 64 * 1024) return MIMO_OK;
+    hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return fail(MIMO_ERR_HIP, "mimo_qr_preprocess: LDS attribute: %s", hipGetErrorString(e));
+    return MIMO_OK;
 }
+
 
 }  // namespace mimo
 
@@ -343,17 +368,17 @@ extern "C" int32_t mimo_qr_preprocess(const float* H, const float* y, int32_t B,
     if (B == 0) return MIMO_OK;
     if (!H || !y || !R || !z) return fail(MIMO_ERR_INVALID_ARG, "mimo_qr_preprocess: null pointer");
     const int threads = cq_threads(n_tx);
-    const int per = cq_per_thread(n_tx, threads);
-    if (per > CQ_PF_MAX || threads > CQ_MAX_THREADS)
-        return fail(MIMO_ERR_UNSUPPORTED, "mimo_qr_preprocess: n_tx = %d", n_tx);
+    if (threads > CQ_MAX_THREADS) return fail(MIMO_ERR_UNSUPPORTED, "mimo_qr_preprocess: n_tx = %d", n_tx);
     const float2* H2 = reinterpret_cast<const float2*>(H);
     const float2* y2 = reinterpret_cast<const float2*>(y);
-    const size_t lds = cq_lds_bytes(n_tx);
+    const int waves = threads / WAVE;
+    const int fpw = (waves >= 4 && waves <= 6) ? 2 : 1;
+    const size_t lds = fpw * ((cq_lds_bytes(n_tx, cq_rows(n_tx, threads)) + 15) & ~(size_t)15);
+    const int grid = (B + fpw - 1) / fpw;
     hipStream_t st = (hipStream_t)stream;
-    if (per <= 4)
-        hipLaunchKernelGGL(qr_kernel<4>, dim3(B), dim3(threads), lds, st, H2, y2, n_rx, n_tx, R, z, resid);
-    else
-        hipLaunchKernelGGL(qr_kernel<CQ_PF_MAX>, dim3(B), dim3(threads), lds, st, H2, y2, n_rx, n_tx, R, z, resid);
+    if (int32_t rc = cq_allow_lds((const void*)qr_kernel, lds)) return rc;
+    hipLaunchKernelGGL(qr_kernel, dim3(grid), dim3(fpw * threads), lds, st, H2, y2, n_rx, n_tx, R, z, resid, B, fpw,
+                       threads);
     return check_launch("mimo_qr_preprocess");
 }
 
@@ -372,10 +397,12 @@ extern "C" int32_t mimo_qr_preprocess_uneven(const mimo_frame_desc* desc, int32_
     // smaller frames use a prefix of the threads and stage fewer elements
     const int mt = max_rx < MIMO_MAX_TX ? max_rx : MIMO_MAX_TX;
     const int threads = cq_threads(mt);
-    int per = 0;
-    for (int m = 1; m <= mt; ++m) per = per > cq_per_thread(m, threads) ? per : cq_per_thread(m, threads);
-    if (per > CQ_PF_MAX || threads > CQ_MAX_THREADS)
-        return fail(MIMO_ERR_UNSUPPORTED, "mimo_qr_preprocess_uneven: max_rx = %d", max_rx);
+    if (threads > CQ_MAX_THREADS) return fail(MIMO_ERR_UNSUPPORTED, "mimo_qr_preprocess_uneven: max_rx = %d", max_rx);
+    size_t lds = 0;  // the largest need over the frame sizes the workgroup can meet
+    for (int m = 1; m <= mt; ++m) {
+        const size_t b = cq_lds_bytes(m, cq_rows(m, threads));
+        lds = b > lds ? b : lds;
+    }
     hipStream_t st = (hipStream_t)stream;
     if (grid == 0) {
         int dev = 0, cus = 0;
@@ -387,12 +414,8 @@ extern "C" int32_t mimo_qr_preprocess_uneven(const mimo_frame_desc* desc, int32_
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
     const float2* H2 = reinterpret_cast<const float2*>(H_flat);
     const float2* y2 = reinterpret_cast<const float2*>(y_flat);
-    const size_t lds = cq_lds_bytes(mt);
-    if (per <= 4)
-        hipLaunchKernelGGL(qr_uneven_kernel<4>, dim3(grid), dim3(threads), lds, st, desc, B, H2, y2, R_flat, z_flat,
-                           counter, mt);
-    else
-        hipLaunchKernelGGL(qr_uneven_kernel<CQ_PF_MAX>, dim3(grid), dim3(threads), lds, st, desc, B, H2, y2, R_flat,
-                           z_flat, counter, mt);
+    if (int32_t rc = cq_allow_lds((const void*)qr_uneven_kernel, lds)) return rc;
+    hipLaunchKernelGGL(qr_uneven_kernel, dim3(grid), dim3(threads), lds, st, desc, B, H2, y2, R_flat, z_flat, counter,
+                       mt);
     return check_launch("mimo_qr_preprocess_uneven");
 }
