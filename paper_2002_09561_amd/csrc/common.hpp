@@ -28,17 +28,31 @@ __host__ __device__ inline int64_t r_row_off(int n, int k)
 
 __host__ __device__ inline int64_t r_packed_size(int n) { return (int64_t)n * (n + 1) / 2; }
 
-// Exchange with lane ^ j for a compile-time j (after unrolling): DPP for
-// j = 1, 2 (quad permutes) and 8 (rotate by 8 in a row of 16), an LDS-free
-// swizzle for 4 and 16, a permute for 32.
+// Exchange with lane ^ j for a compile-time j (after unrolling), without
+// the LDS unit: DPP for j = 1, 2 (quad permutes), 4 (rotations by 12 and 4
+// within a row of 16: lane + 4 for lanes with bit 2 clear, lane - 4 for the
+// others) and 8 (rotation by 8 within a row); the gfx950 row swaps for 16
+// (permlane16_swap of v with itself: rows 0 and 1, 2 and 3 exchanged) and 32
+// (permlane32_swap: halves exchanged).  Any other j uses a permute.
 __device__ __forceinline__ uint32_t xor_lanes(uint32_t v, int j, int lane)
 {
     switch (j) {
     case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
     case 2: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
+    case 4: {
+        const uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x12C, 0xF, 0xF, false);
+        const uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x124, 0xF, 0xF, false);
+        return (lane & 4) ? dn : up;
+    }
     case 8: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);
-    case 4: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F);
-    case 16: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);
+    case 16: {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (lane & 16) ? r[0] : r[1];
+    }
+    case 32: {
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (lane & 32) ? r[0] : r[1];
+    }
     default: return (uint32_t)__builtin_amdgcn_ds_bpermute(((lane ^ j) & (WAVE - 1)) << 2, (int)v);
     }
 }

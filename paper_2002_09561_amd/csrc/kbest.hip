@@ -257,6 +257,83 @@ __device__ __forceinline__ int kb_select_sort(const uint32_t (&kh)[E], int nvali
     return keep;
 }
 
+// One compare-exchange stage with lane ^ j of a bitonic network on one
+// register of 64 keys (one per lane); keep_min: this lane keeps the smaller.
+__device__ __forceinline__ uint64_t kb_cx(uint64_t key, int j, bool keep_min, int lane)
+{
+    const uint64_t o = xor_lanes_u64(key, j, lane);
+    return ((o < key) == keep_min) ? o : key;
+}
+
+// Selection by sorting and merging, for KCAP <= 64 and E >= 2 blocks of 64
+// candidates.  Each non-empty block is sorted across the lanes (even blocks
+// ascending, odd ones descending); then pairs of sorted blocks are merged
+// with truncation: the lane-wise minimum of an ascending and a descending
+// block is a bitonic sequence holding the 64 smallest keys of the pair, which
+// six half-cleaner stages put in order (ascending or descending as the next
+// merge needs).  Block 0 ends with the 64 smallest keys in ascending order,
+// the first `keep` of which survive.  Keys are distinct, so the result is the
+// one of a full sort.  Same contract as kb_select.
+template <int E>
+__device__ __forceinline__ int kb_select_merge(const uint32_t (&kh)[E], int ncand, int nvalid, int Kt, int fm, int lane,
+                                               float* sn, int32_t* sel, int* fpos_out)
+{
+    const int keep = Kt < nvalid ? Kt : nvalid;  // <= 64
+    uint64_t key[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        key[e] = kh[e] == ~0u ? ~0ull : (((uint64_t)kh[e] << 32) | (uint32_t)(e * WAVE + lane));
+    uint64_t fkey = ~0ull;
+    int fpos = -1;
+    if (fm >= 0) {  // label mode: the forced candidate's rank among all candidates
+        const int fe = fm / WAVE, fl = fm % WAVE;
+        uint32_t fh = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (e == fe) fh = __shfl(kh[e], fl, WAVE);
+        if (fh != ~0u) {
+            fkey = ((uint64_t)fh << 32) | (uint32_t)fm;
+            int below = 0;
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                if (e * WAVE < ncand) below += __popcll(__ballot(key[e] < fkey));
+            fpos = below;
+        }
+    }
+    // 1. sort every block (branch-free: all E blocks are full at nearly every
+    //    level, and a block of padding is sorted already)
+#pragma unroll
+    for (int size = 2; size <= WAVE; size <<= 1) {
+#pragma unroll
+        for (int j = size >> 1; j > 0; j >>= 1) {
+            const bool asc_min = ((lane & size) == 0) == ((lane & j) == 0);
+#pragma unroll
+            for (int e = 0; e < E; ++e) key[e] = kb_cx(key[e], j, asc_min != (bool)(e & 1), lane);
+        }
+    }
+    // 2. merge with truncation: (e, e + w) -> e, direction by the parity of e / 2w
+#pragma unroll
+    for (int w = 1; w < E; w <<= 1) {
+#pragma unroll
+        for (int e = 0; e < E; e += 2 * w) {
+            const uint64_t b = key[e + w];
+            uint64_t c = b < key[e] ? b : key[e];
+            const bool desc = ((e / (2 * w)) & 1) != 0;
+#pragma unroll
+            for (int j = WAVE / 2; j > 0; j >>= 1) c = kb_cx(c, j, ((lane & j) == 0) != desc, lane);
+            key[e] = c;
+        }
+    }
+    const bool add_forced = fpos >= keep;  // it takes the last slot
+    if (lane < keep) {
+        const uint64_t k = (add_forced && lane == keep - 1) ? fkey : key[0];
+        sn[lane] = __uint_as_float((uint32_t)(k >> 32));
+        sel[lane] = (int32_t)(uint32_t)k;
+    }
+    *fpos_out = fpos;
+    return keep;
+}
+
 // K-best of one frame by one wavefront; lds as sized by kbest_lds_bytes.
 template <int P, int E>
 __device__ __forceinline__ void kbest_frame(const KbestArgs& a, int frame, unsigned char* lds)
@@ -589,7 +666,7 @@ __device__ __forceinline__ void kbest_frame_reg(const KbestArgs& a, int frame, u
             else
                 keep = kb_select_sort<E, E>(kh, nvalid, Kt, fm, lane, sn, sel, &fpos);
         } else {
-            keep = kb_select<E, (KCAP + WAVE - 1) / WAVE>(kh, cnt * P, nvalid, Kt, fm, lane, sn, sel, skey, &fpos);
+            keep = kb_select_merge<E>(kh, cnt * P, nvalid, Kt, fm, lane, sn, sel, &fpos);
         }
         if (fsym) {
             if (lane == 0) a.rank[(size_t)frame * n + k] = fpos + 1;
