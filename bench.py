@@ -111,6 +111,15 @@ def sched_counts(ks: np.ndarray, P: int) -> np.ndarray:
     return tot
 
 
+def kbest_roofline(flops, ms):
+    """FP32 roofline entry of the PD/expand (K-best) kernel: algorithmic flops
+    (centres and child PDs actually evaluated) over the launch time."""
+    achieved = flops / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 5), "avg_launch_ms": round(ms, 4),
+            "algorithmic_flops_per_launch": flops}
+
+
 def kernel_source_hash(name):
     h = hashlib.sha256()
     for f in ("common.hpp", name):
@@ -343,6 +352,11 @@ def main():
     if det == "learned":
         out["learned"] = {"mean_k_t": round(extra["mean_k_t"], 3),
                           "fallback_fraction": round(extra["fallback_fraction"], 5)}
+        out["kbest_roofline"] = {"learned": kbest_roofline(
+            kbest_flops_from_counts(sched_counts(extra["ks"], P), P), kavg["kbest"])}
+    elif det == "kbest":
+        out["kbest_roofline"] = {"plain": kbest_roofline(
+            kbest_flops_from_counts(plain_counts(n, P, args.K) * NB, P), kavg["kbest"])}
     if not args.no_graph:
         from paper_2002_09561_amd.graph import CapturedStep
 
@@ -364,6 +378,9 @@ def main():
                 continue
             odt, oc, okavg, _ = run(other, True)
             det_ms_o = sum(v for k, v in okavg.items() if k not in ("qr", "metric", "errors"))
+            if other == "kbest":
+                out.setdefault("kbest_roofline", {})["plain"] = kbest_roofline(
+                    kbest_flops_from_counts(plain_counts(n, P, args.K) * NB, P), okavg["kbest"])
             out["plain_kbest" if other == "kbest" else "paper_hybrid"] = {
                 "detector": f"K-best K={args.K}" if other == "kbest" else
                 f"SD-K-best, {args.workers} workers x {args.k_worker} survivors",
@@ -373,14 +390,22 @@ def main():
     # ---------------- maximum-likelihood reference (untimed)
     if not args.no_ml:
         mimo.qr_preprocess(H, Y, out=(o["R"], o["z"], None))
+        ea, eb, ec = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        ea.record(stream)
         sk, pk, _ = mimo.kbest_detect(o["R"], o["z"], M, P, args.K)
         r2 = (pk * (1.0 + 1e-4)).contiguous()
+        eb.record(stream)
         sm, _, fm = mimo.sd_hybrid_detect(o["R"], o["z"], M, P, 0, 1, radius2=r2, node_budget=400000)
+        ec.record(stream)
+        torch.cuda.synchronize()
+        sd_ms, warm_ms = eb.elapsed_time(ec), ea.elapsed_time(eb)
         sm = torch.where(((fm & mimo.FLAG_FOUND) != 0)[:, None], sm, sk)
         err = (sm != S_true).view(len(snrs), B, M).sum(dim=(1, 2)).cpu().numpy()
         ml_err = [int(e) for e in err]
         cert = int(((fm & mimo.FLAG_CERTIFIED) != 0).sum())
         out["ml_reference"] = {"symbol_errors": ml_err, "certified_fraction": round(cert / frames_per_step, 5),
+                               "sd_ms": round(sd_ms, 3), "warm_start_ms": round(warm_ms, 3),
+                               "detect_only_frames_per_s": round(frames_per_step / ((sd_ms + warm_ms) * 1e-3), 1),
                                "method": f"exact Best-FS SD warm-started by K-best K={args.K} "
                                          "(node budget 4e5; uncertified frames keep the K-best result)"}
         mine = counts[:, 1]
