@@ -62,6 +62,9 @@ def _declare(L):
     L.orc_batch_brute_force.argtypes = [_I, _I, _I, _I, _P, _P, _P, _P]
     L.orc_batch_metric.argtypes = [_I, _I, _I, _I, _P, _P, _P, _P]
     L.orc_batch_zf_sic.argtypes = [_I, _I, _I, _P, _P, _P, _P]
+    L.orc_batch_qr_mmse.argtypes = [_I, _I, _I, _P, _P, _P, _P, _P]
+    L.orc_batch_linear.argtypes = [_I, _I, _I, _P, _P, _P, _P]
+    L.orc_batch_mrc.argtypes = [_I, _I, _I, _I, _P, _P, _P, _P]
     L.orc_batch_sesd.argtypes = [_I, _I, _I, _P, _P, _P, _L, _P, _P, _P, _P, _P]
     L.orc_batch_kbest.argtypes = [_I, _I, _I, _P, _P, _I, _P, _I, _D, _I, _P, _P, _P, _P, _P,
                                   _P, _P]
@@ -139,6 +142,45 @@ def zf_sic(R, z, P: int):
     pd = np.zeros(B)
     lib().orc_batch_zf_sic(B, n, P, _p(R), _p(z), _p(x), _p(pd))
     return x, pd
+
+
+def qr_mmse(H, y, sigma2):
+    """MMSE preprocessing: QR of [H; sigma I], [y; 0] in the real model.
+    sigma2: scalar or [B] complex noise variances.  Returns R [B,n,n], z [B,n]
+    with R^T R = H_r^T H_r + sigma2 I and R^T z = H_r^T y_r."""
+    H = _c(H, np.complex64)
+    y = _c(y, np.complex64)
+    B, N, M = H.shape
+    n = 2 * M
+    s2 = _c(np.broadcast_to(np.asarray(sigma2, np.float64), (B,)), np.float64)
+    R = np.zeros((B, n, n))
+    z = np.zeros((B, n))
+    lib().orc_batch_qr_mmse(B, N, M, _p(H), _p(y), _p(s2), _p(R), _p(z))
+    return R, z
+
+
+def linear(R, z, P: int):
+    """Back-substitution without decision feedback (ZF on the plain QR,
+    linear MMSE on the MMSE QR).  Returns (x_idx [B,n] int32, u [B,n])."""
+    R = _c(R, np.float64)
+    z = _c(z, np.float64)
+    B, n = z.shape
+    x = np.zeros((B, n), np.int32)
+    u = np.zeros((B, n))
+    lib().orc_batch_linear(B, n, P, _p(R), _p(z), _p(x), _p(u))
+    return x, u
+
+
+def mrc(H, y, qam: int):
+    """Maximum-ratio combining.  Returns (s_idx [B,M] int32, u [B,2M]) with u
+    the interleaved (real, imaginary) estimates."""
+    H = _c(H, np.complex64)
+    y = _c(y, np.complex64)
+    B, N, M = H.shape
+    s = np.zeros((B, M), np.int32)
+    u = np.zeros((B, 2 * M))
+    lib().orc_batch_mrc(B, N, M, math.isqrt(qam), _p(H), _p(y), _p(s), _p(u))
+    return s, u
 
 
 def sesd(R, z, P: int, r2=None, budget: int = 0, x_init=None):

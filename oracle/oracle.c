@@ -56,17 +56,13 @@ void orc_real_model(int N, int M, const float* H, const float* y, double* Hr, do
     }
 }
 
-/* Householder triangularisation of [H_r | y_r]: the reflections that make
- * H_r upper triangular are applied to y_r as well, giving z = Q^T y_r; the
- * part of the rotated y_r below row n is the residual ||Q_2^T y||^2. */
-int orc_qr(int N, int M, const float* H, const float* y, double* R, double* z, double* resid)
+/* Householder triangularisation of a real system [A | b] (rows x n, rows >= n):
+ * the reflections that make A upper triangular are applied to b as well,
+ * giving z = Q^T b; the part of the rotated b below row n is the residual
+ * ||Q_2^T b||^2.  A and b are overwritten. */
+static void householder(int rows, int n, double* A, double* b, double* R, double* z, double* resid)
 {
-    const int rows = 2 * N, n = 2 * M;
-    if (M > N) return -1;
-    double* A = (double*)malloc(sizeof(double) * (size_t)rows * n);
-    double* b = (double*)malloc(sizeof(double) * rows);
     double* v = (double*)malloc(sizeof(double) * rows);
-    orc_real_model(N, M, H, y, A, b);
     for (int k = 0; k < n; ++k) {
         double norm2 = 0.0;
         for (int i = k; i < rows; ++i) norm2 += A[i * n + k] * A[i * n + k];
@@ -97,9 +93,40 @@ int orc_qr(int N, int M, const float* H, const float* y, double* R, double* z, d
     double r = 0.0;
     for (int i = n; i < rows; ++i) r += b[i] * b[i];
     if (resid) *resid = r;
+    free(v);
+}
+
+/* Sec. III-B: QR of the real model of H, z = Q^T y_r. */
+int orc_qr(int N, int M, const float* H, const float* y, double* R, double* z, double* resid)
+{
+    const int rows = 2 * N, n = 2 * M;
+    if (M > N) return -1;
+    double* A = (double*)malloc(sizeof(double) * (size_t)rows * n);
+    double* b = (double*)malloc(sizeof(double) * rows);
+    orc_real_model(N, M, H, y, A, b);
+    householder(rows, n, A, b, R, z, resid);
     free(A);
     free(b);
-    free(v);
+    return 0;
+}
+
+/* MMSE preprocessing (the linear baselines the paper compares against,
+ * Sec. III-A): the QR of the augmented system [H; sigma I_M], [y; 0], whose
+ * factor satisfies R^T R = H_r^T H_r + sigma^2 I and R^T z = H_r^T y_r, so
+ * back-substitution on (R, z) is the linear MMSE estimate and K = 1 on it is
+ * MMSE-SIC.  sigma2 is the complex noise variance (unit-energy symbols). */
+int orc_qr_mmse(int N, int M, const float* H, const float* y, double sigma2, double* R, double* z)
+{
+    const int n = 2 * M, rows = 2 * N + n;
+    if (M > N) return -1;
+    double* A = (double*)calloc((size_t)rows * n, sizeof(double));
+    double* b = (double*)calloc((size_t)rows, sizeof(double));
+    orc_real_model(N, M, H, y, A, b);
+    const double s = sqrt(sigma2);
+    for (int k = 0; k < n; ++k) A[(2 * N + k) * n + k] = s;
+    householder(rows, n, A, b, R, z, NULL);
+    free(A);
+    free(b);
     return 0;
 }
 
@@ -187,6 +214,38 @@ double orc_zf_sic(int n, int P, const double* R, const double* z, int* x_idx)
         pd += e * e;
     }
     return pd;
+}
+
+/* Linear detection by back-substitution without decision feedback:
+ * u = R^{-1} z in FP64, then each level sliced on its own.  With the plain
+ * QR this is zero forcing (u = H^+ y), with the MMSE QR linear MMSE. */
+void orc_linear(int n, int P, const double* R, const double* z, int* x_idx, double* u)
+{
+    for (int k = n - 1; k >= 0; --k) {
+        double b = z[k];
+        for (int j = k + 1; j < n; ++j) b -= R[k * n + j] * u[j];
+        u[k] = b / R[k * n + k];
+    }
+    for (int k = 0; k < n; ++k) x_idx[k] = slice(P, u[k]);
+}
+
+/* Maximum-ratio combining: u_j = h_j^H y / ||h_j||^2 per transmit stream,
+ * real and imaginary parts sliced on their own (QAM index i_re P + i_im). */
+void orc_mrc(int N, int M, int P, const float* H, const float* y, int* s_idx, double* u)
+{
+    for (int j = 0; j < M; ++j) {
+        double nr = 0.0, cr = 0.0, ci = 0.0;
+        for (int i = 0; i < N; ++i) {
+            double hr = H[2 * (i * M + j)], hi = H[2 * (i * M + j) + 1];
+            double yr = y[2 * i], yi = y[2 * i + 1];
+            nr += hr * hr + hi * hi;
+            cr += hr * yr + hi * yi; /* conj(h) y */
+            ci += hr * yi - hi * yr;
+        }
+        u[2 * j] = nr > 0.0 ? cr / nr : 0.0;
+        u[2 * j + 1] = nr > 0.0 ? ci / nr : 0.0;
+        s_idx[j] = slice(P, u[2 * j]) * P + slice(P, u[2 * j + 1]);
+    }
 }
 
 /* ------------------------------------------------------------------ */
@@ -882,6 +941,31 @@ void orc_batch_qr(int B, int N, int M, const float* H, const float* y, double* R
     for (int b = 0; b < B; ++b)
         orc_qr(N, M, H + (size_t)b * N * M * 2, y + (size_t)b * N * 2, R + (size_t)b * n * n,
                z + (size_t)b * n, resid ? resid + b : NULL);
+}
+
+void orc_batch_qr_mmse(int B, int N, int M, const float* H, const float* y, const double* sigma2, double* R,
+                       double* z)
+{
+    const int n = 2 * M;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int b = 0; b < B; ++b)
+        orc_qr_mmse(N, M, H + (size_t)b * N * M * 2, y + (size_t)b * N * 2, sigma2[b], R + (size_t)b * n * n,
+                    z + (size_t)b * n);
+}
+
+void orc_batch_linear(int B, int n, int P, const double* R, const double* z, int* x_idx, double* u)
+{
+#pragma omp parallel for schedule(static)
+    for (int b = 0; b < B; ++b)
+        orc_linear(n, P, R + (size_t)b * n * n, z + (size_t)b * n, x_idx + (size_t)b * n, u + (size_t)b * n);
+}
+
+void orc_batch_mrc(int B, int N, int M, int P, const float* H, const float* y, int* s_idx, double* u)
+{
+#pragma omp parallel for schedule(static)
+    for (int b = 0; b < B; ++b)
+        orc_mrc(N, M, P, H + (size_t)b * N * M * 2, y + (size_t)b * N * 2, s_idx + (size_t)b * M,
+                u + (size_t)b * 2 * M);
 }
 
 void orc_batch_brute_force(int B, int N, int M, int P, const float* H, const float* y, int* s_idx,

@@ -60,6 +60,9 @@ double orc_metric(int N, int M, int P, const float* H, const float* y, const int
 /* Successive interference cancellation with a rounding slicer (the K = 1
  * special case of K-best): x_idx [n], returns the path's pd. */
 double orc_zf_sic(int n, int P, const double* R, const double* z, int* x_idx);
+int orc_qr_mmse(int N, int M, const float* H, const float* y, double sigma2, double* R, double* z);
+void orc_linear(int n, int P, const double* R, const double* z, int* x_idx, double* u);
+void orc_mrc(int N, int M, int P, const float* H, const float* y, int* s_idx, double* u);
 
 /* Per-level partial distances of a complete path: g[k] = (z_k - sum_{j>=k} R_kj x_j)^2 */
 void orc_path_terms(int n, int P, const double* R, const double* z, const int* x_idx, double* g);
@@ -126,6 +129,10 @@ void orc_batch_brute_force(int B, int N, int M, int P, const float* H, const flo
                            double* metric);
 void orc_batch_metric(int B, int N, int M, int P, const float* H, const float* y,
                       const int* s_idx, double* metric);
+void orc_batch_qr_mmse(int B, int N, int M, const float* H, const float* y, const double* sigma2, double* R,
+                       double* z);
+void orc_batch_linear(int B, int n, int P, const double* R, const double* z, int* x_idx, double* u);
+void orc_batch_mrc(int B, int N, int M, int P, const float* H, const float* y, int* s_idx, double* u);
 void orc_batch_zf_sic(int B, int n, int P, const double* R, const double* z, int* x_idx, double* pd);
 void orc_batch_sesd(int B, int n, int P, const double* R, const double* z, const double* r2,
                     int64_t budget, const int* x_init, int* x_out, double* pd_out,

@@ -400,3 +400,101 @@ def test_gray_adjacent_points_differ_in_one_bit(orc, P):
             if abs(ia - ib) + abs(ja - jb) == 1:
                 assert (bits[a] != bits[b]).sum() == 1
     assert len({tuple(r) for r in bits}) == P * P
+
+
+# --------------------------------------------------------------- linear baselines and the paper's radius
+def _slice_np(u, P):
+    c = math.sqrt(3.0 / (2.0 * (P * P - 1)))
+    return np.clip(np.floor((u / c + (P - 1)) / 2.0 + 0.5), 0, P - 1).astype(np.int32)
+
+
+@pytest.mark.parametrize("N,M,q", [(6, 6, 16), (8, 5, 64)])
+def test_linear_zf_equals_least_squares(orc, N, M, q):
+    """Back-substitution on the plain QR is the least-squares (zero-forcing)
+    solution; checked against numpy's lstsq on the complex system."""
+    P = math.isqrt(q)
+    f = gen_frames(N, M, q, 12.0, 40, seed=41 + N)
+    R, z, _ = orc.qr(f.H, f.y)
+    x, u = orc.linear(R, z, P)
+    for b in range(len(f)):
+        s = np.linalg.lstsq(f.H[b].astype(np.complex128), f.y[b].astype(np.complex128), rcond=None)[0]
+        ur = np.stack([s.real, s.imag], -1).reshape(-1)
+        assert np.allclose(u[b], ur, atol=1e-10)
+        assert np.array_equal(x[b], _slice_np(ur, P))
+
+
+def test_mmse_qr_normal_equations(orc):
+    f = gen_frames(7, 5, 16, 6.0, 20, seed=5)
+    R, z = orc.qr_mmse(f.H, f.y, f.sigma2)
+    Hr, yr = real_model_np(f.H.astype(np.complex128), f.y.astype(np.complex128))
+    n = 10
+    for b in range(len(f)):
+        assert np.allclose(np.tril(R[b], -1), 0.0) and np.all(np.diag(R[b]) > 0)
+        assert np.allclose(R[b].T @ R[b], Hr[b].T @ Hr[b] + f.sigma2 * np.eye(n), atol=1e-10)
+        assert np.allclose(R[b].T @ z[b], Hr[b].T @ yr[b], atol=1e-10)
+
+
+def test_linear_mmse_equals_regularised_solve(orc):
+    P = 4
+    f = gen_frames(8, 8, 16, 8.0, 40, seed=17)
+    R, z = orc.qr_mmse(f.H, f.y, f.sigma2)
+    x, u = orc.linear(R, z, P)
+    for b in range(len(f)):
+        H = f.H[b].astype(np.complex128)
+        s = np.linalg.solve(H.conj().T @ H + f.sigma2 * np.eye(8), H.conj().T @ f.y[b].astype(np.complex128))
+        ur = np.stack([s.real, s.imag], -1).reshape(-1)
+        assert np.allclose(u[b], ur, atol=1e-10)
+        assert np.array_equal(x[b], _slice_np(ur, P))
+
+
+def test_mmse_limits(orc):
+    """sigma2 -> 0 gives the plain QR (zero forcing); on noiseless frames the
+    MMSE-SIC leaf (K = 1 on the MMSE QR) with a tiny load is the truth."""
+    f = gen_frames(6, 6, 64, 100.0, 30, seed=9)
+    R0, z0, _ = orc.qr(f.H, f.y)
+    R1, z1 = orc.qr_mmse(f.H, f.y, 1e-14)
+    assert np.allclose(R1, R0, atol=1e-6) and np.allclose(z1, z0, atol=1e-6)
+    amp = qam_amplitudes(64)
+    s = (amp[f.s_idx // 8] + 1j * amp[f.s_idx % 8]).astype(np.complex64)
+    y0 = np.einsum("bij,bj->bi", f.H, s).astype(np.complex64)
+    Rm, zm = orc.qr_mmse(f.H, y0, 1e-6)
+    out = orc.kbest(Rm, zm, 8, 1)
+    assert np.array_equal(orc.x_to_sym(out["x"], 8), f.s_idx)
+
+
+def test_mrc_orthogonal_channel_is_exact(orc):
+    """With orthogonal columns, matched filtering decouples the streams:
+    MRC equals zero forcing, and on noiseless frames it returns the truth."""
+    rng = np.random.default_rng(4)
+    B, N, M, q = 10, 8, 5, 16
+    H = np.empty((B, N, M), np.complex64)
+    for b in range(B):
+        Q, _ = np.linalg.qr(rng.standard_normal((N, M)) + 1j * rng.standard_normal((N, M)))
+        H[b] = (Q * rng.uniform(0.5, 2.0, M)).astype(np.complex64)
+    s_idx = rng.integers(0, q, (B, M)).astype(np.int32)
+    amp = qam_amplitudes(q)
+    s = amp[s_idx // 4] + 1j * amp[s_idx % 4]
+    y = np.einsum("bij,bj->bi", H.astype(np.complex128), s).astype(np.complex64)
+    sm, um = orc.mrc(H, y, q)
+    assert np.array_equal(sm, s_idx)
+    R, z, _ = orc.qr(H, y)
+    _, uz = orc.linear(R, z, 4)
+    assert np.allclose(um, uz, atol=1e-5)
+
+
+def test_paper_radius_keeps_ml_when_inside(orc):
+    """With the paper's radius r^2 = N M sigma^2 (squared, Sec. IV), the
+    radius-limited SD returns the ML vector on every frame whose ML metric
+    lies inside the sphere.  That radius is M times the expected noise energy
+    N sigma^2, so at this size every ML metric lies inside; a sphere half as
+    large as the smallest ML metric is empty on every frame."""
+    N = M = 6
+    f = gen_frames(N, M, 16, 4.0, 60, seed=23)
+    R, z, resid = orc.qr(f.H, f.y)
+    xs, pd_inf, _, _ = orc.sesd(R, z, 4)
+    r2 = np.full(len(f), N * M * f.sigma2)
+    xr, pd_r, fl, _ = orc.sesd(R, z, 4, r2=r2)
+    assert np.all(pd_inf < r2)
+    assert np.array_equal(xr, xs) and np.allclose(pd_r, pd_inf)
+    _, _, fl0, _ = orc.sesd(R, z, 4, r2=np.full(len(f), 0.5 * pd_inf.min()))
+    assert np.all((fl0 & orc.EMPTY_SPHERE) != 0)
