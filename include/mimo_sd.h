@@ -97,6 +97,19 @@ int32_t mimo_qr_preprocess(const float* H, const float* y, int32_t B, int32_t n_
                            float* R, float* z, float* resid, void* stream);
 
 /* ---------------------------------------------------------------------
+ * MMSE preprocessing for the linear and successive-cancellation baselines
+ * the paper compares against (Sec. III-A): the QR of the augmented system
+ * [H; sigma_b I], [y; 0], i.e. R^H R = H^H H + sigma2[b] I and
+ * R^H z = H^H y, emitted like mimo_qr_preprocess (same layout, limits and
+ * method: sigma2[b] is added to the first n_tx diagonal entries of the
+ * Gram matrix before the Cholesky factorisation).  Back-substitution on
+ * (R, z) (linear_detect) is the linear MMSE estimate; K-best with K = 1 on
+ * it is MMSE-SIC.  sigma2 [B] f32 complex noise variances (device).
+ * ------------------------------------------------------------------- */
+int32_t mimo_qr_preprocess_mmse(const float* H, const float* y, const float* sigma2, int32_t B, int32_t n_rx,
+                                int32_t n_tx, float* R, float* z, void* stream);
+
+/* ---------------------------------------------------------------------
  * Batched K-best (Sec. VI, the K-best algorithm): level by level from the
  * root, all P children of every survivor are evaluated with the
  * incremental partial distance of Eq. (inc), children outside the radius
@@ -160,6 +173,26 @@ int32_t sd_hybrid_detect(const float* R, const float* z, int32_t B, int32_t n_tx
                          const int32_t* k_sched, int32_t k_sched_stride, int32_t master_off,
                          int64_t node_budget, int32_t* sym, float* pd, uint32_t* flags,
                          int64_t* counters, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Linear detection (the zero-forcing / MMSE baselines of Sec. III-A):
+ * u = R^{-1} z by back-substitution in FP32 without decision feedback, then
+ * every real level sliced to the nearest PAM amplitude on its own.  With R, z
+ * from mimo_qr_preprocess this is zero forcing (u = H^+ y), from
+ * mimo_qr_preprocess_mmse linear MMSE.  sym [B][n_tx] QAM indices; xhat
+ * [B][n] f32 (interleaved real and imaginary estimates) or NULL.
+ * ------------------------------------------------------------------- */
+int32_t linear_detect(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam, int32_t* sym,
+                      float* xhat, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Maximum-ratio combining (Sec. III-A): u_j = h_j^H y / ||h_j||^2 per
+ * transmit stream, accumulated in FP64 from the complex64 H, y, the real and
+ * imaginary parts sliced on their own.  sym [B][n_tx]; xhat [B][2 n_tx] f32
+ * or NULL.  Limits as mimo_metric.
+ * ------------------------------------------------------------------- */
+int32_t mrc_detect(const float* H, const float* y, int32_t B, int32_t n_rx, int32_t n_tx, int32_t pam,
+                   int32_t* sym, float* xhat, void* stream);
 
 /* ---------------------------------------------------------------------
  * Metric epilogue: metric[b] = ||y_b - H_b s_b||^2 in FP64 from the

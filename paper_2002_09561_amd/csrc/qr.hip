@@ -108,35 +108,41 @@ __device__ __forceinline__ int cq_lds_slot(int e, int CP, int nb, float rcp_cp)
     return row * CP + q * nb + J;
 }
 
+// 1 / d for d > 0 (else 0): hardware reciprocal refined by two Newton steps
+__device__ __forceinline__ double cq_inv(double d)
+{
+    double inv = __builtin_amdgcn_rcp(d);
+    inv = fma(inv, fma(-d, inv, 1.0), inv);
+    inv = fma(inv, fma(-d, inv, 1.0), inv);
+    return d > 0.0 ? inv : 0.0;
+}
+
 // publish register row LR of the tile (a compile-time index keeps the tile
 // in registers).  A published row is stored in planes: column j = 4J + q at
 // [q][J], so the lanes of a wave, which hold consecutive J, read 16-byte
-// neighbours (no LDS bank conflicts).
+// neighbours (no LDS bank conflicts).  The owner of the diagonal entry also
+// publishes its reciprocal, which every thread of the next step needs.
 template <int LR>
-__device__ __forceinline__ void cq_store_row(cd* row, int nb, int J, const double (&gr)[CQ_T][CQ_T],
-                                             const double (&gi)[CQ_T][CQ_T])
+__device__ __forceinline__ void cq_store_row(cd* row, double* rinv, int nb, int I, int J,
+                                             const double (&gr)[CQ_T][CQ_T], const double (&gi)[CQ_T][CQ_T])
 {
 #pragma unroll
     for (int c = 0; c < CQ_T; ++c) row[c * nb + J] = {gr[LR][c], gi[LR][c]};
+    if (J == I) *rinv = cq_inv(gr[LR][LR]);
 }
 
 // one step k of the right-looking Cholesky; S = k mod 4 (row k+1 sits in
 // register row (S + 1) mod 4 of the tiles that publish it)
 template <int S>
 __device__ __forceinline__ void cq_step(int k, int M, int CP, int nb, int tid, bool has_tile, int I, int J, int i0,
-                                        cd* rowbuf, double* diag, double (&gr)[CQ_T][CQ_T],
+                                        cd* rowbuf, double* rinv, double* diag, double (&gr)[CQ_T][CQ_T],
                                         double (&gi)[CQ_T][CQ_T])
 {
     __syncthreads();  // row k published; the other buffer is free
     const cd* rk = rowbuf + (k & 1) * CP;
-    const double d = rk[(k & (CQ_T - 1)) * nb + k / CQ_T].x;
-    if (tid == 0) diag[k] = d;
+    if (tid == 0) diag[k] = rk[(k & (CQ_T - 1)) * nb + k / CQ_T].x;
     if (has_tile && i0 + CQ_T - 1 > k) {
-        // 1/d: hardware reciprocal refined by two Newton steps
-        double inv = __builtin_amdgcn_rcp(d);
-        inv = fma(inv, fma(-d, inv, 1.0), inv);
-        inv = fma(inv, fma(-d, inv, 1.0), inv);
-        inv = d > 0.0 ? inv : 0.0;
+        const double inv = rinv[k & 1];  // 1 / g_kk
         double ur[CQ_T], ui[CQ_T], vr[CQ_T], vi[CQ_T];
 #pragma unroll
         for (int r = 0; r < CQ_T; ++r) {
@@ -159,14 +165,14 @@ __device__ __forceinline__ void cq_step(int k, int M, int CP, int nb, int tid, b
                 gi[r][q] = fma(-ui[r], vr[q], gi[r][q]);
             }
         if (k + 1 < M && (k + 1) / CQ_T == I)
-            cq_store_row<(S + 1) & (CQ_T - 1)>(rowbuf + ((k + 1) & 1) * CP, nb, J, gr, gi);
+            cq_store_row<(S + 1) & (CQ_T - 1)>(rowbuf + ((k + 1) & 1) * CP, rinv + ((k + 1) & 1), nb, I, J, gr, gi);
     }
 }
 
 __device__ __forceinline__ void cholqr_frame(const float2* __restrict__ Hf, const float2* __restrict__ yf, int N,
                                              int M, float* __restrict__ Rf, float* __restrict__ zf,
-                                             float* __restrict__ resid_out, unsigned char* smem, int tid, int nthr,
-                                             bool live)
+                                             float* __restrict__ resid_out, const float* __restrict__ load,
+                                             unsigned char* smem, int tid, int nthr, bool live)
 {
     const CqShape sh = cq_shape(M);
     const int CP = sh.CP;
@@ -243,14 +249,24 @@ __device__ __forceinline__ void cholqr_frame(const float2* __restrict__ Hf, cons
         }
     }
 
+    // MMSE preprocessing: G + sigma^2 I on the first M diagonal entries (the
+    // Gram matrix of [H; sigma I], whose factor is the QR of that system)
+    if (load && has_tile && I == J) {
+        const double l = (double)*load;
+#pragma unroll
+        for (int r = 0; r < CQ_T; ++r)
+            if (i0 + r < M) gr[r][r] += l;
+    }
+
     // ---- 2. right-looking Cholesky, one barrier per step (unrolled by the
     //         tile edge so the published register row is a constant)
-    if (has_tile && I == 0) cq_store_row<0>(rowbuf, nb, J, gr, gi);
+    double* rinv = diag + CP;  // [2] reciprocal pivots of the published rows (the spare entries)
+    if (has_tile && I == 0) cq_store_row<0>(rowbuf, rinv, nb, I, J, gr, gi);
     for (int kb = 0; kb < M; kb += CQ_T) {
-        cq_step<0>(kb, M, CP, nb, tid, has_tile, I, J, i0, rowbuf, diag, gr, gi);
-        if (kb + 1 < M) cq_step<1>(kb + 1, M, CP, nb, tid, has_tile, I, J, i0, rowbuf, diag, gr, gi);
-        if (kb + 2 < M) cq_step<2>(kb + 2, M, CP, nb, tid, has_tile, I, J, i0, rowbuf, diag, gr, gi);
-        if (kb + 3 < M) cq_step<3>(kb + 3, M, CP, nb, tid, has_tile, I, J, i0, rowbuf, diag, gr, gi);
+        cq_step<0>(kb, M, CP, nb, tid, has_tile, I, J, i0, rowbuf, rinv, diag, gr, gi);
+        if (kb + 1 < M) cq_step<1>(kb + 1, M, CP, nb, tid, has_tile, I, J, i0, rowbuf, rinv, diag, gr, gi);
+        if (kb + 2 < M) cq_step<2>(kb + 2, M, CP, nb, tid, has_tile, I, J, i0, rowbuf, rinv, diag, gr, gi);
+        if (kb + 3 < M) cq_step<3>(kb + 3, M, CP, nb, tid, has_tile, I, J, i0, rowbuf, rinv, diag, gr, gi);
     }
     __syncthreads();  // diag complete
 
@@ -304,7 +320,8 @@ __device__ __forceinline__ void cholqr_frame(const float2* __restrict__ Hf, cons
 // again and stores nothing.
 __global__ void __launch_bounds__(CQ_MAX_WG) qr_kernel(const float2* __restrict__ H, const float2* __restrict__ y,
                                                        int N, int M, float* __restrict__ R, float* __restrict__ z,
-                                                       float* __restrict__ resid, int B, int fpw, int tpf)
+                                                       float* __restrict__ resid, const float* __restrict__ load,
+                                                       int B, int fpw, int tpf)
 {
     extern __shared__ __align__(16) unsigned char smem_qr[];
     const int half = (int)threadIdx.x / tpf;
@@ -314,7 +331,8 @@ __global__ void __launch_bounds__(CQ_MAX_WG) qr_kernel(const float2* __restrict_
     const int n = 2 * M;
     const size_t lds = (cq_lds_bytes(M, cq_rows(M, tpf)) + 15) & ~(size_t)15;
     cholqr_frame(H + (size_t)frame * N * M, y + (size_t)frame * N, N, M, R + (size_t)frame * r_packed_size(n),
-                     z + (size_t)frame * n, resid ? resid + frame : nullptr, smem_qr + half * lds,
+                     z + (size_t)frame * n, resid ? resid + frame : nullptr, load ? load + frame : nullptr,
+                     smem_qr + half * lds,
                      (int)threadIdx.x - half * tpf, tpf, live);
 }
 
@@ -337,7 +355,7 @@ __global__ void __launch_bounds__(CQ_MAX_THREADS) qr_uneven_kernel(const mimo_fr
         const mimo_frame_desc d = desc[f];
         // the workgroup and its LDS are sized for n_tx <= n_rx <= max_rx
         if (d.n_tx < 1 || d.n_tx > d.n_rx || d.n_rx > max_rx) continue;
-        cholqr_frame(H + d.h_off, y + d.y_off, d.n_rx, d.n_tx, R + d.r_off, z + d.z_off, nullptr, smem_qr,
+        cholqr_frame(H + d.h_off, y + d.y_off, d.n_rx, d.n_tx, R + d.r_off, z + d.z_off, nullptr, nullptr, smem_qr,
                          (int)threadIdx.x, (int)blockDim.x, true);
     }
 }
@@ -356,19 +374,20 @@ static int32_t cq_allow_lds(const void* kernel, size_t lds)
 
 }  // namespace mimo
 
-extern "C" int32_t mimo_qr_preprocess(const float* H, const float* y, int32_t B, int32_t n_rx, int32_t n_tx,
-                                      float* R, float* z, float* resid, void* stream)
+namespace mimo {
+
+static int32_t launch_qr(const char* who, const float* H, const float* y, const float* load, int32_t B, int32_t n_rx,
+                         int32_t n_tx, float* R, float* z, float* resid, void* stream)
 {
-    using namespace mimo;
-    if (B < 0) return fail(MIMO_ERR_INVALID_ARG, "mimo_qr_preprocess: B < 0");
+    if (B < 0) return fail(MIMO_ERR_INVALID_ARG, "%s: B < 0", who);
     if (n_tx < 1 || n_rx < n_tx)
-        return fail(MIMO_ERR_INVALID_ARG, "mimo_qr_preprocess: need 1 <= n_tx <= n_rx (got %d, %d)", n_tx, n_rx);
+        return fail(MIMO_ERR_INVALID_ARG, "%s: need 1 <= n_tx <= n_rx (got %d, %d)", who, n_tx, n_rx);
     if (n_tx > MIMO_MAX_TX || n_rx > MIMO_MAX_RX)
-        return fail(MIMO_ERR_UNSUPPORTED, "mimo_qr_preprocess: n_rx, n_tx <= %d", MIMO_MAX_RX);
+        return fail(MIMO_ERR_UNSUPPORTED, "%s: n_rx, n_tx <= %d", who, MIMO_MAX_RX);
     if (B == 0) return MIMO_OK;
-    if (!H || !y || !R || !z) return fail(MIMO_ERR_INVALID_ARG, "mimo_qr_preprocess: null pointer");
+    if (!H || !y || !R || !z) return fail(MIMO_ERR_INVALID_ARG, "%s: null pointer", who);
     const int threads = cq_threads(n_tx);
-    if (threads > CQ_MAX_THREADS) return fail(MIMO_ERR_UNSUPPORTED, "mimo_qr_preprocess: n_tx = %d", n_tx);
+    if (threads > CQ_MAX_THREADS) return fail(MIMO_ERR_UNSUPPORTED, "%s: n_tx = %d", who, n_tx);
     const float2* H2 = reinterpret_cast<const float2*>(H);
     const float2* y2 = reinterpret_cast<const float2*>(y);
     const int waves = threads / WAVE;
@@ -377,9 +396,24 @@ extern "C" int32_t mimo_qr_preprocess(const float* H, const float* y, int32_t B,
     const int grid = (B + fpw - 1) / fpw;
     hipStream_t st = (hipStream_t)stream;
     if (int32_t rc = cq_allow_lds((const void*)qr_kernel, lds)) return rc;
-    hipLaunchKernelGGL(qr_kernel, dim3(grid), dim3(fpw * threads), lds, st, H2, y2, n_rx, n_tx, R, z, resid, B, fpw,
-                       threads);
-    return check_launch("mimo_qr_preprocess");
+    hipLaunchKernelGGL(qr_kernel, dim3(grid), dim3(fpw * threads), lds, st, H2, y2, n_rx, n_tx, R, z, resid, load, B,
+                       fpw, threads);
+    return check_launch(who);
+}
+
+}  // namespace mimo
+
+extern "C" int32_t mimo_qr_preprocess(const float* H, const float* y, int32_t B, int32_t n_rx, int32_t n_tx,
+                                      float* R, float* z, float* resid, void* stream)
+{
+    return mimo::launch_qr("mimo_qr_preprocess", H, y, nullptr, B, n_rx, n_tx, R, z, resid, stream);
+}
+
+extern "C" int32_t mimo_qr_preprocess_mmse(const float* H, const float* y, const float* sigma2, int32_t B,
+                                           int32_t n_rx, int32_t n_tx, float* R, float* z, void* stream)
+{
+    if (B > 0 && !sigma2) return mimo::fail(MIMO_ERR_INVALID_ARG, "mimo_qr_preprocess_mmse: null sigma2");
+    return mimo::launch_qr("mimo_qr_preprocess_mmse", H, y, sigma2, B, n_rx, n_tx, R, z, nullptr, stream);
 }
 
 extern "C" int32_t mimo_qr_preprocess_uneven(const mimo_frame_desc* desc, int32_t B, int32_t max_rx,

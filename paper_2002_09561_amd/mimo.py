@@ -28,6 +28,9 @@ SIGNATURES = {
     "mimo_last_error": ([], ctypes.c_char_p),
     "mimo_version": ([], _I32),
     "mimo_qr_preprocess": ([_P, _P, _I32, _I32, _I32, _P, _P, _P, _P], _I32),
+    "mimo_qr_preprocess_mmse": ([_P, _P, _P, _I32, _I32, _I32, _P, _P, _P], _I32),
+    "linear_detect": ([_P, _P, _I32, _I32, _I32, _P, _P, _P], _I32),
+    "mrc_detect": ([_P, _P, _I32, _I32, _I32, _I32, _P, _P, _P], _I32),
     "kbest_detect": ([_P, _P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P, _P], _I32),
     "kbest_rank_labels": ([_P, _P, _I32, _I32, _I32, _I32, _P, _P, _P], _I32),
     "kbest_fallback": ([_P, _P, _I32, _I32, _I32, _I32, _P, _F, _P, _P, _P, _P, _P], _I32),
@@ -118,7 +121,49 @@ def qr_preprocess(H: torch.Tensor, y: torch.Tensor, want_resid: bool = False, ou
     return (R, z, resid) if want_resid else (R, z)
 
 
+def qr_preprocess_mmse(H: torch.Tensor, y: torch.Tensor, sigma2: torch.Tensor, out=None, stream=None):
+    """QR of [H; sigma I], [y; 0] (MMSE preprocessing).  sigma2 [B] float32.
+    Returns R [B, n(n+1)/2], z [B, n] as qr_preprocess."""
+    B, N, M = H.shape
+    n = 2 * M
+    if out is None:
+        R = torch.empty(B, packed_size(n), device=H.device, dtype=torch.float32)
+        z = torch.empty(B, n, device=H.device, dtype=torch.float32)
+    else:
+        R, z = out
+    _check(load().mimo_qr_preprocess_mmse(_ptr(H, torch.complex64, "H"), _ptr(y, torch.complex64, "y"),
+                                          _ptr(sigma2, torch.float32, "sigma2"), B, N, M,
+                                          _ptr(R, torch.float32, "R"), _ptr(z, torch.float32, "z"), _stream(stream)))
+    return R, z
+
+
+def paper_radius2(n_rx: int, n_tx: int, sigma2: torch.Tensor) -> torch.Tensor:
+    """The paper's sphere radius rule, squared: r^2 = N M sigma^2 per frame."""
+    return (float(n_rx * n_tx) * sigma2).to(torch.float32).contiguous()
+
+
 # ------------------------------------------------------------------ detectors
+def linear_detect(R, z, n_tx: int, pam: int, want_xhat: bool = False, stream=None):
+    """Back-substitution without decision feedback (ZF on the plain QR, linear
+    MMSE on the MMSE QR).  Returns sym [B, n_tx] int32 (and xhat [B, n])."""
+    B = z.shape[0]
+    sym = torch.empty(B, n_tx, device=z.device, dtype=torch.int32)
+    xh = torch.empty(B, 2 * n_tx, device=z.device, dtype=torch.float32) if want_xhat else None
+    _check(load().linear_detect(_ptr(R, torch.float32, "R"), _ptr(z, torch.float32, "z"), B, n_tx, pam, _ptr(sym),
+                                _ptr(xh), _stream(stream)))
+    return (sym, xh) if want_xhat else sym
+
+
+def mrc_detect(H, y, pam: int, want_xhat: bool = False, stream=None):
+    """Maximum-ratio combining.  Returns sym [B, M] int32 (and xhat [B, 2M])."""
+    B, N, M = H.shape
+    sym = torch.empty(B, M, device=H.device, dtype=torch.int32)
+    xh = torch.empty(B, 2 * M, device=H.device, dtype=torch.float32) if want_xhat else None
+    _check(load().mrc_detect(_ptr(H, torch.complex64, "H"), _ptr(y, torch.complex64, "y"), B, N, M, pam, _ptr(sym),
+                             _ptr(xh), _stream(stream)))
+    return (sym, xh) if want_xhat else sym
+
+
 def _det_outputs(B, n_tx, dev, want_counters):
     sym = torch.empty(B, n_tx, device=dev, dtype=torch.int32)
     pd = torch.empty(B, device=dev, dtype=torch.float32)

@@ -67,6 +67,15 @@ def test_host_validation_without_gpu(lib):
     assert lib.sd_hybrid_detect(P, P, 1, 4, 8, P, 2, 9, P, 0, 0, 0, P, P, P, P, P) == -1
     assert lib.sd_hybrid_detect(P, P, 1, 4, 8, P, 0, 1, P, 0, 1, 0, P, P, P, P, P) == -1
     assert lib.sd_hybrid_detect(P, P, 1, 4, 8, P, 2, 2, P, 0, 0, -5, P, P, P, P, P) == -1
+    # MMSE preprocessing and the linear baselines
+    assert lib.mimo_qr_preprocess_mmse(P, P, P, 2, 4, 4, P, P, P) == -1
+    assert "sigma2" in _err(lib)
+    assert lib.mimo_qr_preprocess_mmse(P, P, P, 0, 4, 4, P, P, P) == 0
+    assert lib.linear_detect(P, P, 2, 4, 3, P, P, P) == -1
+    assert lib.linear_detect(P, P, 2, 200, 4, P, P, P) == -2
+    assert lib.linear_detect(P, P, 2, 4, 4, P, P, P) == -1
+    assert lib.mrc_detect(P, P, 2, 300, 200, 4, P, P, P) == -2
+    assert lib.mrc_detect(P, P, 2, 8, 4, 4, P, P, P) == -1
     # MLP
     assert lib.prune_mlp_schedule(P, P, 10, 0.0, 0, 4, 8, P, P, P) == -1
     assert lib.prune_mlp_loss_grad(P, P, P, 10, 1.5, P, P, P, 0, P) == -1
