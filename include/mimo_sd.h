@@ -127,6 +127,24 @@ int32_t kbest_detect(const float* R, const float* z, int32_t B, int32_t n_tx, in
                      int64_t* counters, void* stream);
 
 /* ---------------------------------------------------------------------
+ * Batched K-best over complex levels, the tree of the paper's own figures
+ * (Sec. III-B branches on complex symbols: |Omega| = pam^2 children per
+ * level, n_tx levels; Sec. VI for K-best).  Complex level m fixes the
+ * imaginary part (real level 2m+1) and the real part (real level 2m) of
+ * symbol m together: child (i_im, i_re) of a survivor has
+ * pd' = pd + (b_2m+1 - R a_im)^2 + (b_2m - R a_re)^2, and the K_t best by
+ * (pd, parent rank, i_im pam + i_re) survive.  K_t = k_sched[... + 2m]
+ * (the level of the real part), clamped to [1, K].  Arguments, outputs and
+ * flags as kbest_detect; counters[b][0] = survivors expanded,
+ * counters[b][1] = real-level evaluations (2 per child).
+ * Limits: 1 <= K <= 64, K * pam^2 <= 1024.
+ * ------------------------------------------------------------------- */
+int32_t kbest_detect_complex(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam,
+                             int32_t K, const int32_t* k_sched, int32_t k_sched_stride,
+                             const float* radius2, int32_t* sym, float* pd, uint32_t* flags,
+                             int64_t* counters, void* stream);
+
+/* ---------------------------------------------------------------------
  * Plain fallback of a learned detection (the plain K-best stays the
  * reference method): frame b is detected again by plain K-best with K
  * survivors, overwriting sym[b], pd[b], flags[b] (which then carry

@@ -735,6 +735,265 @@ __device__ __forceinline__ void kbest_frame_reg(const KbestArgs& a, int frame, u
     }
 }
 
+// K-best over complex levels (the paper's own tree, Sec. III-B: one complex
+// symbol, i.e. P^2 children, per level).  Complex level m fixes the real
+// levels k_hi = 2m + 1 (imaginary part) and k_lo = 2m (real part); the
+// interleaved real model has R[k_lo][k_hi] = 0, so both centres depend on the
+// levels above k_hi only and are computed together.  Child c = i_im P + i_re
+// of survivor s has pd' = pd_s + (b_hi - R_hi a_im)^2 + (b_lo - R_lo a_re)^2
+// (added in that order); the key is (pd', s P^2 + c).  One wavefront per
+// frame, survivor paths in registers as in the real-level variant (lane
+// (s, q) holds words q + L i), candidate blocks of 64 selected by sorting and
+// merging.  K_t = k_sched[k_lo].
+template <int P, int E>
+struct KbestCplxShape {
+    static constexpr int PC = P * P;                       // children per survivor
+    static constexpr int KCAP = WAVE * E / PC;             // survivor capacity
+    static constexpr int L = WAVE / KCAP;                  // lanes per survivor
+};
+
+template <int NWMAX>
+__host__ __device__ inline size_t kbest_cplx_lds_bytes(int kcap)
+{
+    const int L = WAVE / kcap;
+    const int nwx = NWMAX > L ? NWMAX : L;
+    return sizeof(float) * 2 * kcap + sizeof(float) * 2 * (2 * nwx + 16) + sizeof(int32_t) * kcap;
+}
+
+template <int P, int E, int NWMAX>
+__device__ __forceinline__ void kbest_frame_cplx(const KbestArgs& a, int frame, unsigned char* lds)
+{
+    using S = KbestCplxShape<P, E>;
+    constexpr int PC = S::PC, KCAP = S::KCAP, L = S::L;
+    static_assert(KCAP >= 1 && KCAP <= 64, "one survivor per lane at most, one at least");
+    constexpr int NWX = NWMAX > L ? NWMAX : L;  // words covered by the lanes of a survivor
+    constexpr int NWL = NWX / L;                // path words per lane
+    constexpr int CHW = NWL < 8 ? NWL : 8;      // words per guarded chunk
+    constexpr int RW = 2 * NWX + 16;            // staged row length
+    const int lane = threadIdx.x & 63;
+    const int s_own = lane / L, q = lane % L;
+    const int n = a.n;
+    const int nw = n / 2;
+    float* spd = reinterpret_cast<float*>(lds);
+    float* rhi = spd + 2 * KCAP;  // c R[k_hi][j], zero at j <= k_hi
+    float* rlo = rhi + RW;        // c R[k_lo][j], zero at j <= k_hi
+    int32_t* sel = reinterpret_cast<int32_t*>(rlo + RW);
+
+    const float* Rf = a.R + (size_t)frame * r_packed_size(n);
+    const float* zf = a.z + (size_t)frame * n;
+    const float r2 = a.radius2 ? a.radius2[frame] : INFINITY;
+    const float cs = pam_scale(P);
+    const int32_t* ks = a.k_sched ? a.k_sched + (size_t)frame * a.k_sched_stride : nullptr;
+
+    uint32_t pw[NWL];
+#pragma unroll
+    for (int i = 0; i < NWL; ++i) pw[i] = 0u;  // unassigned levels are amplitude 0
+    for (int t = lane; t < 2 * RW; t += WAVE) rhi[t] = 0.f;
+    if (lane == 0) spd[0] = 0.f;
+    int cnt = 1;
+    int64_t expanded = 0;
+    uint32_t flags = 0;
+    const int i_hi = (nw + L - 1) / L;  // words beyond nw read zero row entries
+
+    // rows k_hi, k_lo of the next complex level are loaded while the current one is used
+    constexpr int RPL = 4;
+    float nh[RPL], nl[RPL];
+    float rkh_next, rkl_next, zh_next, zl_next;
+    auto load_rows = [&](int m) {
+        const float* rh = Rf + r_row_off(n, 2 * m + 1);
+        const float* rl = Rf + r_row_off(n, 2 * m);
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int t = lane + WAVE * i;
+            nh[i] = t < n - 2 * m - 1 ? rh[t] : 0.f;
+            nl[i] = t < n - 2 * m ? rl[t] : 0.f;
+        }
+        rkh_next = rh[0];
+        rkl_next = rl[0];
+        zh_next = zf[2 * m + 1];
+        zl_next = zf[2 * m];
+    };
+    load_rows(nw - 1);
+    __syncthreads();
+
+    for (int m = nw - 1; m >= 0; --m) {
+        const int k_hi = 2 * m + 1, k_lo = 2 * m;
+        const int cur = (nw - 1 - m) & 1, nxt = cur ^ 1;
+        float* sc = spd + cur * KCAP;
+        float* sn = spd + nxt * KCAP;
+        // stage: row k_hi from column k_hi, row k_lo from column k_lo (its
+        // entry at k_hi is the structural zero); entries at and below the
+        // complex level meet amplitude 0 in every path
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int t = lane + WAVE * i;
+            if (t < n - k_hi) rhi[k_hi + t] = t == 0 ? 0.f : cs * nh[i];
+            if (t < n - k_lo) rlo[k_lo + t] = t <= 1 ? 0.f : cs * nl[i];
+        }
+        const float rkh = cs * rkh_next, rkl = cs * rkl_next;
+        const float zh = zh_next, zl = zl_next;
+        if (m > 0) load_rows(m - 1);
+        kb_wave_sync();
+        // centres of this lane's survivor from the words above word m
+        const int i_lo = (m + 1) / L;
+        float ah = 0.f, al = 0.f;
+#pragma unroll
+        for (int c0 = 0; c0 < NWL; c0 += CHW) {
+            if (c0 + CHW > i_lo && c0 < i_hi) {
+#pragma unroll
+                for (int i = c0; i < c0 + CHW; ++i) {
+                    const int w = q + L * i;
+                    const float2 rh = *reinterpret_cast<const float2*>(rhi + 2 * w);
+                    const float2 rl = *reinterpret_cast<const float2*>(rlo + 2 * w);
+                    const float xl = half_lo(pw[i]), xh = half_hi(pw[i]);
+                    ah = fmaf(rh.x, xl, ah);
+                    ah = fmaf(rh.y, xh, ah);
+                    al = fmaf(rl.x, xl, al);
+                    al = fmaf(rl.y, xh, al);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 1; j < L; j <<= 1) {
+            ah += shfl_xor_f(ah, j);
+            al += shfl_xor_f(al, j);
+        }
+        const float bh_own = zh - ah, bl_own = zl - al;
+        uint32_t kh[E];
+        const int ncand = cnt * PC;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            kh[e] = ~0u;
+            if (e * WAVE >= ncand) continue;  // block without candidates (uniform)
+            const int mm = e * WAVE + lane;
+            const int s = mm / PC, c = mm % PC;
+            const float bh = shfl_f(bh_own, s * L), bl = shfl_f(bl_own, s * L);
+            if (s < cnt) {
+                const float eh = fmaf(-rkh, (float)(2 * (c / P) - (P - 1)), bh);
+                const float el = fmaf(-rkl, (float)(2 * (c % P) - (P - 1)), bl);
+                const float pdc = fmaf(el, el, fmaf(eh, eh, sc[s]));
+                if (pdc < r2) kh[e] = __float_as_uint(pdc);
+            }
+        }
+        expanded += cnt;
+        int nvalid = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (e * WAVE < ncand) nvalid += __popcll(__ballot(kh[e] != ~0u));
+        if (nvalid == 0) {
+            flags |= MIMO_FLAG_EMPTY_SPHERE;
+            cnt = 0;
+            break;
+        }
+        int Kt = ks ? ks[k_lo] : a.K;
+        Kt = Kt > a.K ? a.K : (Kt < 1 ? 1 : Kt);
+        int fpos = -1;
+        int keep;
+        if constexpr (E <= 2) {
+            if (ncand <= WAVE)
+                keep = kb_select_sort<E, 1>(kh, nvalid, Kt, -1, lane, sn, sel, &fpos);
+            else
+                keep = kb_select_sort<E, E>(kh, nvalid, Kt, -1, lane, sn, sel, &fpos);
+        } else {
+            keep = kb_select_merge<E>(kh, ncand, nvalid, Kt, -1, lane, sn, sel, &fpos);
+        }
+        kb_wave_sync();
+        // new survivor s_own takes its parent's words above word m and writes word m
+        int src = lane, cnew = 0;
+        if (s_own < keep) {
+            const int mm = sel[s_own];
+            src = (mm / PC) * L + q;
+            cnew = mm % PC;
+        }
+        const int im = m / L;
+#pragma unroll
+        for (int c0 = 0; c0 < NWL; c0 += CHW) {
+            if (c0 + CHW > im && c0 < i_hi) {
+#pragma unroll
+                for (int i = c0; i < c0 + CHW; ++i) pw[i] = (uint32_t)__shfl((int)pw[i], src, WAVE);
+            }
+        }
+        if (s_own < keep && q == m % L) {
+            const uint32_t wd = half_bits((float)(2 * (cnew % P) - (P - 1))) |
+                                (half_bits((float)(2 * (cnew / P) - (P - 1))) << 16);
+#pragma unroll
+            for (int c0 = 0; c0 < NWL; c0 += CHW) {
+                if (im >= c0 && im < c0 + CHW) {
+#pragma unroll
+                    for (int i = c0; i < c0 + CHW; ++i)
+                        if (i == im) pw[i] = wd;
+                }
+            }
+        }
+        cnt = keep;
+    }
+
+    if (lane == 0) {
+        if (cnt > 0) flags |= MIMO_FLAG_FOUND;
+        if (a.flags) a.flags[frame] = flags;
+        if (a.pd) a.pd[frame] = cnt > 0 ? spd[(nw & 1) * KCAP] : INFINITY;
+        if (a.counters) {
+            int64_t* c = a.counters + (size_t)frame * 4;
+            c[0] = expanded;
+            c[1] = expanded * PC * 2;  // real-level evaluations
+            c[2] = 0;
+            c[3] = 0;
+        }
+    }
+    // survivor 0 (lanes 0 .. L-1) is the best leaf; word w holds symbol w
+    if (!a.sym || s_own != 0) return;
+#pragma unroll
+    for (int i = 0; i < NWL; ++i) {
+        const int w = q + L * i;
+        if (w < nw) {
+            int v = 0;
+            if (cnt > 0) {
+                const int ire = ((int)half_lo(pw[i]) + (P - 1)) / 2;
+                const int iim = ((int)half_hi(pw[i]) + (P - 1)) / 2;
+                v = ire * P + iim;
+            }
+            a.sym[(size_t)frame * nw + w] = v;
+        }
+    }
+}
+
+template <int P, int E, int NWMAX>
+__global__ void __launch_bounds__(64) kbest_cplx_kernel(KbestArgs a)
+{
+    extern __shared__ unsigned char smem_kbc[];
+    kbest_frame_cplx<P, E, NWMAX>(a, blockIdx.x, smem_kbc);
+}
+
+template <int P, int E>
+static int32_t launch_kbest_cplx(const KbestArgs& a, int B, hipStream_t st)
+{
+    constexpr int KCAP = KbestCplxShape<P, E>::KCAP;
+    if (a.n <= 64)
+        hipLaunchKernelGGL((kbest_cplx_kernel<P, E, 32>), dim3(B), dim3(WAVE), kbest_cplx_lds_bytes<32>(KCAP), st, a);
+    else
+        hipLaunchKernelGGL((kbest_cplx_kernel<P, E, 128>), dim3(B), dim3(WAVE), kbest_cplx_lds_bytes<128>(KCAP), st,
+                           a);
+    return check_launch("kbest_detect_complex");
+}
+
+// smallest block count E (a power of two) with 64 E >= K P^2 candidates
+template <int P>
+static int32_t dispatch_kbest_cplx_p(const KbestArgs& a, int B, hipStream_t st)
+{
+    const int need = a.K * P * P;
+    if constexpr (P == 2) {
+        if (need <= 64) return launch_kbest_cplx<2, 1>(a, B, st);
+        if (need <= 128) return launch_kbest_cplx<2, 2>(a, B, st);
+        return launch_kbest_cplx<2, 4>(a, B, st);
+    } else {
+        if (need <= 64) return launch_kbest_cplx<P, 1>(a, B, st);
+        if (need <= 128) return launch_kbest_cplx<P, 2>(a, B, st);
+        if (need <= 256) return launch_kbest_cplx<P, 4>(a, B, st);
+        if (need <= 512) return launch_kbest_cplx<P, 8>(a, B, st);
+        return launch_kbest_cplx<P, 16>(a, B, st);
+    }
+}
+
 template <int P, int E, int NWMAX>
 __global__ void __launch_bounds__(64) kbest_reg_kernel(KbestArgs a)
 {
@@ -833,6 +1092,30 @@ extern "C" int32_t kbest_detect(const float* R, const float* z, int32_t B, int32
     if (!R || !z || !sym || !pd || !flags) return fail(MIMO_ERR_INVALID_ARG, "kbest_detect: null pointer");
     KbestArgs a{R, z, n, K, k_sched, k_sched_stride, radius2, nullptr, nullptr, sym, pd, flags, counters, nullptr, 0.f};
     return dispatch_kbest(a, pam, B, (hipStream_t)stream);
+}
+
+extern "C" int32_t kbest_detect_complex(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam,
+                                        int32_t K, const int32_t* k_sched, int32_t k_sched_stride,
+                                        const float* radius2, int32_t* sym, float* pd, uint32_t* flags,
+                                        int64_t* counters, void* stream)
+{
+    using namespace mimo;
+    int32_t rc = validate_common("kbest_detect_complex", B, n_tx, pam, K);
+    if (rc) return rc;
+    if (K > 64 || K * pam * pam > 1024)
+        return fail(MIMO_ERR_UNSUPPORTED, "kbest_detect_complex: K <= 64 and K * pam^2 <= 1024");
+    const int n = 2 * n_tx;
+    if (k_sched && k_sched_stride != 0 && k_sched_stride != n)
+        return fail(MIMO_ERR_INVALID_ARG, "kbest_detect_complex: k_sched_stride must be 0 or n = %d", n);
+    if (B == 0) return MIMO_OK;
+    if (!R || !z || !sym || !pd || !flags) return fail(MIMO_ERR_INVALID_ARG, "kbest_detect_complex: null pointer");
+    KbestArgs a{R, z, n, K, k_sched, k_sched_stride, radius2, nullptr, nullptr, sym, pd, flags, counters, nullptr, 0.f};
+    hipStream_t st = (hipStream_t)stream;
+    switch (pam) {
+    case 2: return dispatch_kbest_cplx_p<2>(a, B, st);
+    case 4: return dispatch_kbest_cplx_p<4>(a, B, st);
+    default: return dispatch_kbest_cplx_p<8>(a, B, st);
+    }
 }
 
 extern "C" int32_t kbest_rank_labels(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam,

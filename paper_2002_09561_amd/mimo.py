@@ -32,6 +32,7 @@ SIGNATURES = {
     "linear_detect": ([_P, _P, _I32, _I32, _I32, _P, _P, _P], _I32),
     "mrc_detect": ([_P, _P, _I32, _I32, _I32, _I32, _P, _P, _P], _I32),
     "kbest_detect": ([_P, _P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P, _P], _I32),
+    "kbest_detect_complex": ([_P, _P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P, _P], _I32),
     "kbest_rank_labels": ([_P, _P, _I32, _I32, _I32, _I32, _P, _P, _P], _I32),
     "kbest_fallback": ([_P, _P, _I32, _I32, _I32, _I32, _P, _F, _P, _P, _P, _P, _P], _I32),
     "sd_hybrid_detect": ([_P, _P, _I32, _I32, _I32, _P, _I32, _I32, _P, _I32, _I32, _I64, _P, _P, _P, _P,
@@ -190,6 +191,21 @@ def kbest_detect(R, z, n_tx: int, pam: int, K: int, k_sched=None, radius2=None, 
     _check(load().kbest_detect(_ptr(R, torch.float32, "R"), _ptr(z, torch.float32, "z"), B, n_tx, pam, K,
                                _ptr(ks, torch.int32, "k_sched"), stride, _ptr(radius2, torch.float32, "radius2"),
                                _ptr(sym), _ptr(pd), _ptr(flags), _ptr(ctr), _stream(stream)))
+    return (sym, pd, flags, ctr) if want_counters else (sym, pd, flags)
+
+
+def kbest_detect_complex(R, z, n_tx: int, pam: int, K: int, k_sched=None, radius2=None, want_counters=False,
+                         out=None, stream=None):
+    """Batched K-best over complex levels (pam^2 children per level).
+    Returns (sym [B,n_tx] int32, pd [B] f32, flags [B] int32[, counters])."""
+    B = z.shape[0]
+    n = 2 * n_tx
+    sym, pd, flags, ctr = out if out is not None else _det_outputs(B, n_tx, z.device, want_counters)
+    ks, stride = _sched(k_sched, n)
+    _check(load().kbest_detect_complex(_ptr(R, torch.float32, "R"), _ptr(z, torch.float32, "z"), B, n_tx, pam, K,
+                                       _ptr(ks, torch.int32, "k_sched"), stride,
+                                       _ptr(radius2, torch.float32, "radius2"), _ptr(sym), _ptr(pd), _ptr(flags),
+                                       _ptr(ctr), _stream(stream)))
     return (sym, pd, flags, ctr) if want_counters else (sym, pd, flags)
 
 

@@ -1,0 +1,87 @@
+"""GPU parity of the complex-level K-best (pam^2 children per complex symbol,
+the tree of the paper's figures) with the FP64 oracle's grouped K-best
+(J = 2 real levels per step)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2002_09561_amd.framegen import gen_frames
+from tests.parity_util import compare_symbols, near_tie_tol
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(gpu, orc, M, q, snr, B, K, seed, sched=None, radius=None):
+    import torch
+
+    f = gen_frames(M, M, q, snr, B, seed=seed)
+    P = math.isqrt(q)
+    H = torch.from_numpy(f.H).cuda()
+    y = torch.from_numpy(f.y).cuda()
+    R, z = gpu.qr_preprocess(H, y)
+    ks = None if sched is None else torch.from_numpy(sched.astype(np.int32)).cuda()
+    r2 = None if radius is None else torch.from_numpy(radius.astype(np.float32)).cuda()
+    print(f"complex K-best {M}x{M} {q}-QAM {snr} dB B={B} K={K}", flush=True)
+    sym, pd, flags, ctr = gpu.kbest_detect_complex(R, z, M, P, K, k_sched=ks, radius2=r2, want_counters=True)
+    Ro, zo, _ = orc.qr(f.H, f.y)
+    if radius is None:
+        out = orc.kbest(Ro, zo, P, K, k_sched=sched, J=2)
+    else:
+        parts = [orc.kbest(Ro[b:b + 1], zo[b:b + 1], P, K, k_sched=None if sched is None else sched[b:b + 1],
+                           r2=float(np.float32(radius[b])), J=2) for b in range(B)]
+        out = {k: np.concatenate([p[k] for p in parts]) for k in ("x", "pd", "margin", "flags", "counters")}
+    return f, P, out, sym.cpu().numpy(), pd.cpu().numpy(), flags.cpu().numpy(), ctr.cpu().numpy()
+
+
+def _check(f, P, out, sym, pd, flags, ctr, n, label):
+    tol = near_tie_tol(n)
+    found = (out["flags"] & 1) != 0
+    assert np.array_equal((flags & 1) != 0, found), label
+    compare_symbols(sym[found], orc_sym(out["x"], P)[found], out["margin"][found], tol, label)
+    clean = out["margin"][:, 0] > tol
+    assert np.array_equal(ctr[clean, :2], out["counters"][clean, :2]), label
+    ok = found & clean
+    assert np.allclose(pd[ok], out["pd"][ok], rtol=5e-5, atol=1e-6), label
+
+
+def orc_sym(x, P):
+    return (x[..., 0::2] * P + x[..., 1::2]).astype(np.int32)
+
+
+@pytest.mark.parametrize("M,q,snr,B,K", [(4, 16, 10.0, 300, 10), (16, 16, 12.0, 200, 10), (16, 64, 18.0, 150, 10),
+                                         (8, 64, 20.0, 100, 16), (32, 16, 14.0, 60, 64), (5, 4, 3.0, 100, 1),
+                                         (6, 4, 2.0, 100, 24), (100, 64, 24.0, 6, 10)])
+def test_kbest_complex_parity(gpu, orc, M, q, snr, B, K):
+    f, P, out, sym, pd, flags, ctr = _run(gpu, orc, M, q, snr, B, K, seed=8000 + M * 7 + K)
+    _check(f, P, out, sym, pd, flags, ctr, 2 * M, f"complex K-best {M}x{M} {q}-QAM K={K}")
+
+
+def test_kbest_complex_node_count_is_papers(gpu, orc):
+    """Survivors expanded per frame = 1 + (M - 1) K for K <= |Omega|: at
+    16x16 64-QAM with K = 10 that is the 151 visited nodes the paper prints."""
+    f, P, out, sym, pd, flags, ctr = _run(gpu, orc, 16, 64, 20.0, 50, 10, seed=8100)
+    assert np.all(ctr[:, 0] == 151)
+    assert np.all(out["counters"][:, 0] == 151)
+
+
+def test_kbest_complex_full_K_is_ml(gpu, orc):
+    """2x2 4-QAM with K = 16 keeps every prefix: the result is the exhaustive ML."""
+    f, P, out, sym, pd, flags, ctr = _run(gpu, orc, 2, 4, 4.0, 200, 16, seed=8200)
+    s_bf, _ = orc.brute_force(f.H, f.y, 4)
+    m_gpu = orc.metric(f.H, f.y, sym, 4)
+    m_bf = orc.metric(f.H, f.y, s_bf, 4)
+    assert np.allclose(m_gpu, m_bf, rtol=1e-9)
+
+
+def test_kbest_complex_schedule_and_radius(gpu, orc):
+    rng = np.random.default_rng(5)
+    M, q, B, K = 8, 16, 120, 16
+    f0 = gen_frames(M, M, q, 9.0, B, seed=8300)
+    R0, z0, _ = orc.qr(f0.H, f0.y)
+    ml = orc.sesd(R0, z0, 4)[1]
+    radius = ml * rng.uniform(0.7, 2.0, B)  # some spheres hold no K-best leaf
+    sched = rng.integers(1, K + 1, (B, 2 * M)).astype(np.int32)
+    f, P, out, sym, pd, flags, ctr = _run(gpu, orc, M, q, 9.0, B, K, seed=8300, sched=sched, radius=radius)
+    assert np.array_equal(flags & 2, out["flags"] & 2)  # EMPTY_SPHERE
+    _check(f, P, out, sym, pd, flags, ctr, 2 * M, "complex K-best schedule+radius")
