@@ -387,6 +387,36 @@ def main():
                 "frames_per_s": round(frames_per_step * args.steps / odt, 1),
                 "detect_only_frames_per_s": round(frames_per_step / (det_ms_o * 1e-3), 1),
                 "symbol_errors": oc[:, 1].tolist(), "bit_errors": oc[:, 0].tolist()}
+    # ---------------- the paper's other detectors on the same frames: linear
+    # baselines (Sec. III-A) and K-best over complex levels (its figures' tree)
+    if not args.no_compare:
+        qr_plain = lambda: mimo.qr_preprocess(H, Y, out=(o["R"], o["z"], None))
+        qr_mmse = lambda: mimo.qr_preprocess_mmse(H, Y, SIG2, out=(o["R"], o["z"]))
+        legs = {
+            "zf": (qr_plain, lambda: mimo.linear_detect(o["R"], o["z"], M, P)),
+            "mmse": (qr_mmse, lambda: mimo.linear_detect(o["R"], o["z"], M, P)),
+            "mmse_sic": (qr_mmse, lambda: mimo.kbest_detect(o["R"], o["z"], M, P, 1)[0]),
+            "mrc": (None, lambda: mimo.mrc_detect(H, Y, P)),
+            "complex_kbest_K10": (qr_plain, lambda: mimo.kbest_detect_complex(o["R"], o["z"], M, P, 10)[0]),
+        }
+        base = {}
+        for name, (pre, det_fn) in legs.items():
+            if pre:
+                pre()
+            det_fn()
+            ea, eb, ec = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            ea.record(stream)
+            if pre:
+                pre()
+            eb.record(stream)
+            s_hat = det_fn()
+            ec.record(stream)
+            torch.cuda.synchronize()
+            err = (s_hat != S_true).view(len(snrs), B, M).sum(dim=(1, 2)).cpu().numpy()
+            base[name] = {"frames_per_s": round(frames_per_step / (ea.elapsed_time(ec) * 1e-3), 1),
+                          "detect_only_frames_per_s": round(frames_per_step / (eb.elapsed_time(ec) * 1e-3), 1),
+                          "symbol_errors": [int(e) for e in err]}
+        out["baselines"] = base
     # ---------------- maximum-likelihood reference (untimed)
     if not args.no_ml:
         mimo.qr_preprocess(H, Y, out=(o["R"], o["z"], None))
