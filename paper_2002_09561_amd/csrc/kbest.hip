@@ -211,6 +211,22 @@ __device__ __forceinline__ int kb_select(const uint32_t (&kh)[E], int ncand, int
     return keep;
 }
 
+// Bitonic sort of one register of keys within groups of LIM lanes (LIM a
+// power of two <= 64), ascending in the group of lanes 0 .. LIM-1.
+template <int LIM>
+__device__ __forceinline__ void bitonic_sort_lim(uint64_t& key, int lane)
+{
+#pragma unroll
+    for (int size = 2; size <= LIM; size <<= 1) {
+#pragma unroll
+        for (int j = size >> 1; j > 0; j >>= 1) {
+            const uint64_t o = xor_lanes_u64(key, j, lane);
+            const bool take_max = ((lane & size) != 0) != ((lane & j) != 0);
+            key = ((o < key) != take_max) ? o : key;
+        }
+    }
+}
+
 // Selection by sorting, for at most 128 candidates (ES = 1 or 2 blocks of
 // 64): all candidate keys (pd bits, candidate index; invalid = ~0) are put
 // in order by one in-wave bitonic sort and the first `keep` survive.  Same
@@ -265,6 +281,82 @@ __device__ __forceinline__ uint64_t kb_cx(uint64_t key, int j, bool keep_min, in
     return ((o < key) == keep_min) ? o : key;
 }
 
+// Selection with a bound, when at least `keep` parents (groups of PC
+// candidates) were expanded.  Each parent's smallest child exists, so the
+// largest of those minima, T, is at least the keep-th smallest pd: no
+// candidate above T can survive.  The valid candidates with pd bits <= T are
+// compacted through LDS (skey, 128 entries) and sorted with the smallest
+// network that holds them; the result is that of sorting all candidates.
+// At high SNR a parent's second child lies far above the best children of
+// the others, so about `keep` candidates remain.  Returns -1 (nothing
+// written) when more than 128 remain.
+template <int E, int PC>
+__device__ __forceinline__ int kb_select_bounded(const uint32_t (&kh)[E], int ncand, int keep, int fm, int lane,
+                                                 float* sn, int32_t* sel, uint64_t* skey, int* fpos_out)
+{
+    uint32_t t = 0u;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        if (e * WAVE >= ncand) continue;  // uniform
+        uint32_t mn = kh[e];
+#pragma unroll
+        for (int j = 1; j < PC; j <<= 1) mn = min(mn, xor_lanes(mn, j, lane));
+        if (e * WAVE + lane < ncand) t = max(t, mn);  // groups of expanded parents only
+    }
+#pragma unroll
+    for (int j = 1; j < WAVE; j <<= 1) t = max(t, xor_lanes(t, j, lane));
+    int count = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        if (e * WAVE < ncand) count += __popcll(__ballot(kh[e] != ~0u && kh[e] <= t));
+    if (count > 2 * WAVE) return -1;
+    uint64_t fkey = ~0ull;
+    int fpos = -1;
+    if (fm >= 0) {  // label mode: the forced candidate's rank among all candidates
+        const int fe = fm / WAVE, fl = fm % WAVE;
+        uint32_t fh = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (e == fe) fh = __shfl(kh[e], fl, WAVE);
+        if (fh != ~0u) {
+            fkey = ((uint64_t)fh << 32) | (uint32_t)fm;
+            int below = 0;
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                if (e * WAVE < ncand)
+                    below += __popcll(__ballot(((((uint64_t)kh[e] << 32) | (uint32_t)(e * WAVE + lane)) < fkey) &&
+                                               kh[e] != ~0u));
+            fpos = below;
+        }
+    }
+    int base = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        if (e * WAVE >= ncand) continue;
+        const bool take = kh[e] != ~0u && kh[e] <= t;
+        const uint64_t bal = __ballot(take);
+        if (take) skey[base + (int)__popcll(bal & ((1ull << lane) - 1ull))] =
+            ((uint64_t)kh[e] << 32) | (uint32_t)(e * WAVE + lane);
+        base += (int)__popcll(bal);
+    }
+    kb_wave_sync();
+    uint64_t key[2];
+    key[0] = lane < count ? skey[lane] : ~0ull;
+    key[1] = WAVE + lane < count ? skey[WAVE + lane] : ~0ull;
+    if (count <= 16) bitonic_sort_lim<16>(key[0], lane);
+    else if (count <= 32) bitonic_sort_lim<32>(key[0], lane);
+    else if (count <= WAVE) bitonic_sort_lim<WAVE>(key[0], lane);
+    else bitonic_sort<2>(key, lane);
+    const bool add_forced = fpos >= keep;  // it takes the last slot
+    if (lane < keep) {
+        const uint64_t k = (add_forced && lane == keep - 1) ? fkey : key[0];
+        sn[lane] = __uint_as_float((uint32_t)(k >> 32));
+        sel[lane] = (int32_t)(uint32_t)k;
+    }
+    *fpos_out = fpos;
+    return keep;
+}
+
 // Selection by sorting and merging, for KCAP <= 64 and E >= 2 blocks of 64
 // candidates.  Each non-empty block is sorted across the lanes (even blocks
 // ascending, odd ones descending); then pairs of sorted blocks are merged
@@ -274,11 +366,15 @@ __device__ __forceinline__ uint64_t kb_cx(uint64_t key, int j, bool keep_min, in
 // merge needs).  Block 0 ends with the 64 smallest keys in ascending order,
 // the first `keep` of which survive.  Keys are distinct, so the result is the
 // one of a full sort.  Same contract as kb_select.
-template <int E>
+template <int E, int PC>
 __device__ __forceinline__ int kb_select_merge(const uint32_t (&kh)[E], int ncand, int nvalid, int Kt, int fm, int lane,
-                                               float* sn, int32_t* sel, int* fpos_out)
+                                               float* sn, int32_t* sel, uint64_t* skey, int* fpos_out)
 {
     const int keep = Kt < nvalid ? Kt : nvalid;  // <= 64
+    if (ncand / PC >= keep) {  // uniform: at least `keep` parents
+        const int k = kb_select_bounded<E, PC>(kh, ncand, keep, fm, lane, sn, sel, skey, fpos_out);
+        if (k >= 0) return k;
+    }
     uint64_t key[E];
 #pragma unroll
     for (int e = 0; e < E; ++e)
@@ -534,7 +630,7 @@ template <int NWMAX>
 __host__ __device__ inline size_t kbest_reg_lds_bytes(int kcap)
 {
     return sizeof(float) * 2 * kcap + sizeof(float) * (2 * NWMAX + 16) + sizeof(int32_t) * kcap +
-           sizeof(uint64_t) * kcap;
+           sizeof(uint64_t) * 2 * WAVE;  // compaction buffer of the bounded selection
 }
 
 template <int P, int E, int NWMAX>
@@ -666,7 +762,7 @@ __device__ __forceinline__ void kbest_frame_reg(const KbestArgs& a, int frame, u
             else
                 keep = kb_select_sort<E, E>(kh, nvalid, Kt, fm, lane, sn, sel, &fpos);
         } else {
-            keep = kb_select_merge<E>(kh, cnt * P, nvalid, Kt, fm, lane, sn, sel, &fpos);
+            keep = kb_select_merge<E, P>(kh, cnt * P, nvalid, Kt, fm, lane, sn, sel, skey, &fpos);
         }
         if (fsym) {
             if (lane == 0) a.rank[(size_t)frame * n + k] = fpos + 1;
@@ -757,7 +853,8 @@ __host__ __device__ inline size_t kbest_cplx_lds_bytes(int kcap)
 {
     const int L = WAVE / kcap;
     const int nwx = NWMAX > L ? NWMAX : L;
-    return sizeof(float) * 2 * kcap + sizeof(float) * 2 * (2 * nwx + 16) + sizeof(int32_t) * kcap;
+    return sizeof(uint64_t) * 2 * WAVE + sizeof(float) * 2 * kcap + sizeof(float) * 2 * (2 * nwx + 16) +
+           sizeof(int32_t) * kcap;
 }
 
 template <int P, int E, int NWMAX>
@@ -774,7 +871,8 @@ __device__ __forceinline__ void kbest_frame_cplx(const KbestArgs& a, int frame, 
     const int s_own = lane / L, q = lane % L;
     const int n = a.n;
     const int nw = n / 2;
-    float* spd = reinterpret_cast<float*>(lds);
+    uint64_t* skey = reinterpret_cast<uint64_t*>(lds);  // compaction buffer of the bounded selection
+    float* spd = reinterpret_cast<float*>(skey + 2 * WAVE);
     float* rhi = spd + 2 * KCAP;  // c R[k_hi][j], zero at j <= k_hi
     float* rlo = rhi + RW;        // c R[k_lo][j], zero at j <= k_hi
     int32_t* sel = reinterpret_cast<int32_t*>(rlo + RW);
@@ -895,7 +993,7 @@ __device__ __forceinline__ void kbest_frame_cplx(const KbestArgs& a, int frame, 
             else
                 keep = kb_select_sort<E, E>(kh, nvalid, Kt, -1, lane, sn, sel, &fpos);
         } else {
-            keep = kb_select_merge<E>(kh, ncand, nvalid, Kt, -1, lane, sn, sel, &fpos);
+            keep = kb_select_merge<E, PC>(kh, ncand, nvalid, Kt, -1, lane, sn, sel, skey, &fpos);
         }
         kb_wave_sync();
         // new survivor s_own takes its parent's words above word m and writes word m
