@@ -15,22 +15,24 @@ __device__ __forceinline__ double xor_lanes_f64(double v, int m, int lane)
     return __builtin_bit_cast(double, xor_lanes_u64(__builtin_bit_cast(uint64_t, v), m, lane));
 }
 
-// one wave per frame: lanes run along a row of H (coalesced reads), the
-// row's residual y_i - sum_j h_ij s_j is reduced across the wave in FP64 in a
-// fixed order, and lane 0 accumulates |residual|^2 over the rows; two rows
-// per iteration keep two loads and two reductions in flight
+// One wave per frame, four rows of H at a time: the 16 lanes of a row group
+// run along the row (coalesced 128-byte segments, up to 8 columns per lane),
+// the row's residual y_i - sum_j h_ij s_j is reduced over those 16 lanes in
+// FP64 in a fixed order (DPP exchanges only), and each group accumulates
+// |residual|^2 over its rows; the four group sums are added at the end.
 __global__ void __launch_bounds__(256) metric_kernel(const float2* __restrict__ H, const float2* __restrict__ y,
                                                      const int32_t* __restrict__ sym, int B, int N, int M, int P,
                                                      double* __restrict__ out)
 {
     const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, l = lane & 15;
     const int f = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x >> 6);
     if (f >= B) return;
-    constexpr int CPL = (MIMO_MAX_TX + WAVE - 1) / WAVE;  // columns per lane
+    constexpr int CPL = (MIMO_MAX_TX + 15) / 16;  // columns per lane
     double sr[CPL], si[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
-        const int j = lane + WAVE * c;
+        const int j = l + 16 * c;
         sr[c] = si[c] = 0.0;
         if (j < M) {
             const int q = sym[(size_t)f * M + j];
@@ -41,14 +43,14 @@ __global__ void __launch_bounds__(256) metric_kernel(const float2* __restrict__ 
     const float2* Hf = H + (size_t)f * N * M;
     const float2* yf = y + (size_t)f * N;
     double acc = 0.0;
-    for (int i0 = 0; i0 < N; i0 += 2) {
+    for (int i0 = 0; i0 < N; i0 += 8) {
         double pr[2] = {0.0, 0.0}, pi[2] = {0.0, 0.0};
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const int i = i0 + u;
+            const int i = i0 + 4 * u + g;
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
-                const int j = lane + WAVE * c;
+                const int j = l + 16 * c;
                 if (j < M && i < N) {
                     const float2 h = Hf[(size_t)i * M + j];
                     pr[u] += (double)h.x * sr[c] - (double)h.y * si[c];
@@ -57,7 +59,7 @@ __global__ void __launch_bounds__(256) metric_kernel(const float2* __restrict__ 
             }
         }
 #pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) {
+        for (int m = 8; m >= 1; m >>= 1) {
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 pr[u] += xor_lanes_f64(pr[u], m, lane);
@@ -66,13 +68,16 @@ __global__ void __launch_bounds__(256) metric_kernel(const float2* __restrict__ 
         }
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            if (i0 + u < N) {
-                const float2 yy = yf[i0 + u];
+            const int i = i0 + 4 * u + g;
+            if (i < N) {
+                const float2 yy = yf[i];
                 const double er = (double)yy.x - pr[u], ei = (double)yy.y - pi[u];
                 acc += er * er + ei * ei;
             }
         }
     }
+    acc += xor_lanes_f64(acc, 16, lane);
+    acc += xor_lanes_f64(acc, 32, lane);
     if (lane == 0) out[f] = acc;
 }
 
@@ -104,85 +109,101 @@ __global__ void __launch_bounds__(256) errors_kernel(const int32_t* __restrict__
     }
 }
 
-// Per-level state of the K = 1 (successive-cancellation) path, one wave per
-// frame.  Level k: centre b = z_k - sum_{t>0} R_k,k+t x_{k+t}, nearest PAM
-// point a, path metric pd += (b - R_kk a)^2; the features are k/n, the
-// centre's distance to the nearest decision boundary in units of the
-// spacing, log2(R_kk 2c / sigma_r) and pd / ((n - k) sigma_r^2).  The R rows
-// of the next two levels are loaded while the current one is used.
-constexpr int FEAT_RPL = 4;  // row entries per lane: n <= 256
+// Per-level state of the K = 1 (successive-cancellation) path.  Level k:
+// centre b = z_k - sum_{j>k} R_kj x_j, nearest PAM point a, path metric
+// pd += (b - R_kk a)^2; the features are k/n, the centre's distance to the
+// nearest decision boundary in units of the spacing, log2(R_kk 2c / sigma_r)
+// and pd / ((n - k) sigma_r^2).
+//
+// Four frames per wave, 16 lanes per frame: lane l of a frame holds the
+// decided amplitudes x_j of the levels j = l + 16 i in registers and loads
+// the matching entries R_kj of each row (coalesced 64-byte segments), so the
+// centre is 16 register FMAs and a 16-lane reduction (DPP); the R rows of the
+// next two levels are loaded while the current one is used.
+constexpr int FEAT_SLOTS = 16;  // levels per lane: n <= 256
 
 __device__ __forceinline__ void feat_load(const float* __restrict__ Rf, const float* __restrict__ zf, int n, int k,
-                                          int lane, float (&r)[FEAT_RPL], float& zk)
+                                          int l, float (&r)[FEAT_SLOTS], float& rkk, float& zk)
 {
     if (k < 0) return;
-    const float* rk = Rf + r_row_off(n, k);
+    const float* rk = Rf + r_row_off(n, k);  // rk[j - k] = R_kj
 #pragma unroll
-    for (int i = 0; i < FEAT_RPL; ++i) {
-        const int t = lane + WAVE * i;
-        r[i] = t < n - k ? rk[t] : 0.f;
+    for (int i = 0; i < FEAT_SLOTS; ++i) {
+        const int jj = l + 16 * i;
+        r[i] = (jj > k && jj < n) ? rk[jj - k] : 0.f;
     }
+    rkk = rk[0];
     zk = zf[k];
 }
 
-__device__ __forceinline__ void feat_level(int k, int n, int P, float c, float sr, int lane,
-                                           const float (&r)[FEAT_RPL], float zk, float* xa, float& pd,
-                                           float* __restrict__ featf)
+__device__ __forceinline__ void feat_level(int k, int n, int P, float c, float rc, float lc, float rs2, int lane,
+                                           const float (&r)[FEAT_SLOTS], float rkk, float zk,
+                                           float (&xr)[FEAT_SLOTS], float& pd, float* __restrict__ featf, bool live)
 {
     float acc = 0.f;
 #pragma unroll
-    for (int i = 0; i < FEAT_RPL; ++i) {
-        const int t = lane + WAVE * i;
-        if (t >= 1 && t < n - k) acc = fmaf(r[i], xa[k + t], acc);
-    }
-    acc = wave_sum(acc);
-    const float rkk = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, r[0])));
+    for (int i = 0; i < FEAT_SLOTS; ++i) acc = fmaf(r[i], xr[i], acc);
+#pragma unroll
+    for (int m = 8; m >= 1; m >>= 1) acc += shfl_xor_f(acc, m);
     const float b = zk - acc;
     const float u = b / rkk;
-    int i = (int)floorf((u / c + (float)(P - 1)) * 0.5f + 0.5f);
+    const float v = u * rc;  // u / c
+    int i = (int)floorf((v + (float)(P - 1)) * 0.5f + 0.5f);
     i = i < 0 ? 0 : (i > P - 1 ? P - 1 : i);
     const float a = (float)(2 * i - (P - 1)) * c;
     const float e = fmaf(-rkk, a, b);
     pd = fmaf(e, e, pd);
-    const float v = u / c;
     float nb = 2.f * floorf(v * 0.5f + 0.5f);
     nb = fminf(fmaxf(nb, -(float)(P - 2)), (float)(P - 2));
-    if (lane == 0) {
-        xa[k] = a;
+    const int l = lane & 15;
+    if (l == 0 && live)
         *reinterpret_cast<float4*>(featf + (size_t)k * 4) =
-            make_float4((float)k / (float)n, fabsf(v - nb) * 0.5f, log2f(rkk * 2.f * c / sr),
-                        pd / ((float)(n - k) * sr * sr));
-    }
-    __syncthreads();  // xa[k] visible to the wave
+            make_float4((float)k / (float)n, fabsf(v - nb) * 0.5f, log2f(rkk) + lc, pd * rs2 / (float)(n - k));
+    // level k's decision goes to lane k mod 16, slot k / 16 (uniform index)
+    const int slot = k >> 4;
+#pragma unroll
+    for (int q = 0; q < FEAT_SLOTS; ++q)
+        if (q == slot && l == (k & 15)) xr[q] = a;
 }
 
-__global__ void __launch_bounds__(64) features_kernel(const float* __restrict__ R, const float* __restrict__ z,
-                                                      const float* __restrict__ sigma2, int n, int P,
-                                                      float* __restrict__ feat)
+__global__ void __launch_bounds__(256) features_kernel(const float* __restrict__ R, const float* __restrict__ z,
+                                                       const float* __restrict__ sigma2, int B, int n, int P,
+                                                       float* __restrict__ feat)
 {
-    __shared__ float xa[256];
-    const int f = blockIdx.x, lane = threadIdx.x;
+    const int lane = threadIdx.x & 63, l = lane & 15;
+    const int fr = (blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x >> 6)) * 4 + (lane >> 4);
+    if ((fr & ~3) >= B) return;  // whole wave beyond the batch
+    const bool live = fr < B;
+    const int f = live ? fr : B - 1;  // a slot beyond the batch repeats the last frame, storing nothing
     const float* Rf = R + (size_t)f * r_packed_size(n);
     const float* zf = z + (size_t)f * n;
     float* featf = feat + (size_t)f * n * 4;
     const float c = pam_scale(P);
-    const float sr = sqrtf(sigma2[f] * 0.5f);
+    const float s2r = sigma2[f] * 0.5f;  // sigma_r^2
+    const float lc = log2f(2.f * c / sqrtf(s2r));
+    const float rs2 = 1.f / s2r;
+    const float rc = 1.f / c;
+    float xr[FEAT_SLOTS];
+#pragma unroll
+    for (int i = 0; i < FEAT_SLOTS; ++i) xr[i] = 0.f;
     float pd = 0.f;
-    float ra[FEAT_RPL], rb[FEAT_RPL], za = 0.f, zb = 0.f;
-    feat_load(Rf, zf, n, n - 1, lane, ra, za);
-    feat_load(Rf, zf, n, n - 2, lane, rb, zb);
+    float ra[FEAT_SLOTS], rb[FEAT_SLOTS], rka = 0.f, rkb = 0.f, za = 0.f, zb = 0.f;
+    feat_load(Rf, zf, n, n - 1, l, ra, rka, za);
+    feat_load(Rf, zf, n, n - 2, l, rb, rkb, zb);
     // n = 2 n_tx is even: levels go in pairs (k, k-1) from buffers a and b
     for (int k = n - 1; k >= 1; k -= 2) {
-        float rc[FEAT_RPL], zc = za;
+        float rcur[FEAT_SLOTS];
 #pragma unroll
-        for (int i = 0; i < FEAT_RPL; ++i) rc[i] = ra[i];
-        feat_load(Rf, zf, n, k - 2, lane, ra, za);
-        feat_level(k, n, P, c, sr, lane, rc, zc, xa, pd, featf);
+        for (int i = 0; i < FEAT_SLOTS; ++i) rcur[i] = ra[i];
+        float rk = rka, zk = za;
+        feat_load(Rf, zf, n, k - 2, l, ra, rka, za);
+        feat_level(k, n, P, c, rc, lc, rs2, lane, rcur, rk, zk, xr, pd, featf, live);
 #pragma unroll
-        for (int i = 0; i < FEAT_RPL; ++i) rc[i] = rb[i];
-        zc = zb;
-        feat_load(Rf, zf, n, k - 3, lane, rb, zb);
-        feat_level(k - 1, n, P, c, sr, lane, rc, zc, xa, pd, featf);
+        for (int i = 0; i < FEAT_SLOTS; ++i) rcur[i] = rb[i];
+        rk = rkb;
+        zk = zb;
+        feat_load(Rf, zf, n, k - 3, l, rb, rkb, zb);
+        feat_level(k - 1, n, P, c, rc, lc, rs2, lane, rcur, rk, zk, xr, pd, featf, live);
     }
 }
 
@@ -225,7 +246,7 @@ extern "C" int32_t prune_features(const float* R, const float* z, const float* s
     if (n_tx > MIMO_MAX_TX) return fail(MIMO_ERR_UNSUPPORTED, "prune_features: n_tx > %d", MIMO_MAX_TX);
     if (B == 0) return MIMO_OK;
     if (!R || !z || !sigma2 || !feat) return fail(MIMO_ERR_INVALID_ARG, "prune_features: null pointer");
-    hipLaunchKernelGGL(features_kernel, dim3(B), dim3(64), 0, (hipStream_t)stream, R, z, sigma2, 2 * n_tx, pam,
-                       feat);
+    hipLaunchKernelGGL(features_kernel, dim3((B + 15) / 16), dim3(256), 0, (hipStream_t)stream, R, z, sigma2, B,
+                       2 * n_tx, pam, feat);
     return check_launch("prune_features");
 }
