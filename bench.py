@@ -51,7 +51,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--frames", type=int, default=10000, help="frames per SNR point")
     p.add_argument("--snrs", default="20,22,24,26,28")
-    p.add_argument("--detector", default="auto", choices=["auto", "kbest", "learned", "hybrid"])
+    p.add_argument("--detector", default="auto", choices=["auto", "kbest", "learned", "hybrid", "fixed"])
+    p.add_argument("--fixed-k", type=int, default=0,
+                   help="ablation leg: plain K-best with this K plus the same fallback (0: the learned mean K_t, rounded)")
     p.add_argument("--K", type=int, default=64, help="plain K-best survivors (matched-BER setting)")
     p.add_argument("--workers", type=int, default=15)
     p.add_argument("--k-worker", type=int, default=8)
@@ -260,11 +262,16 @@ def main():
         b.record(stream)
         ev.setdefault(tag, []).append((a, b))
 
+    fixed_k = args.fixed_k
+
     def step(detector, record):
         out3 = (o["sym"], o["pd"], o["flags"], None)
         timed("qr", record, lambda: mimo.qr_preprocess(H, Y, out=(o["R"], o["z"], None)))
         if detector == "kbest":
             timed("kbest", record, lambda: mimo.kbest_detect(o["R"], o["z"], M, P, args.K, out=out3))
+        elif detector == "fixed":  # ablation: the learned detector without its network
+            timed("kbest", record, lambda: mimo.kbest_detect(o["R"], o["z"], M, P, fixed_k, out=out3))
+            timed("fallback", record, lambda: mimo.kbest_fallback(o["R"], o["z"], M, P, args.K, SIG2, beta, out3))
         elif detector == "hybrid":
             timed("hybrid", record, lambda: mimo.sd_hybrid_detect(o["R"], o["z"], M, P, args.workers, args.k_worker,
                                                                   out=out3))
@@ -387,6 +394,17 @@ def main():
                 "frames_per_s": round(frames_per_step * args.steps / odt, 1),
                 "detect_only_frames_per_s": round(frames_per_step / (det_ms_o * 1e-3), 1),
                 "symbol_errors": oc[:, 1].tolist(), "bit_errors": oc[:, 0].tolist()}
+    # ---------------- ablation: the learned detector's fallback with a constant K
+    if not args.no_compare and det == "learned":
+        fixed_k = args.fixed_k or max(1, int(round(extra["mean_k_t"])))
+        fdt, fc, fkavg, _ = run("fixed", True)
+        fl = o["flags"].cpu().numpy()
+        out["ablation_fixed_k"] = {
+            "detector": f"K-best K={fixed_k} (no network) + the same K={args.K} fallback",
+            "frames_per_s": round(frames_per_step * args.steps / fdt, 1),
+            "symbol_errors": fc[:, 1].tolist(),
+            "fallback_fraction": round(float(((fl & mimo.FLAG_LEARNED_FALLBACK) != 0).mean()), 5),
+            "kernel_avg_ms": {k: round(v, 4) for k, v in fkavg.items()}}
     # ---------------- the paper's other detectors on the same frames: linear
     # baselines (Sec. III-A) and K-best over complex levels (its figures' tree)
     if not args.no_compare:

@@ -170,7 +170,7 @@ def detect(w, R, z, sigma2, n_tx: int, pam: int, margin: float, k_min: int, k_ma
     return out[0], out[1], out[2], ks
 
 
-def calibrate(w, n_tx, qam, snrs, frames, seed, k_min, plain_K, k_maxes, margins, betas, log=print):
+def calibrate(w, n_tx, qam, snrs, frames, seed, k_min, plain_K, k_maxes, margins, betas, fixed_ks=(), log=print):
     """Fastest (k_max, margin, beta) whose learned detection makes at most 5%
     more symbol errors than plain K-best (K = plain_K, the setting whose
     errors match the exact SD) on the calibration frames at every SNR.  All
@@ -186,17 +186,34 @@ def calibrate(w, n_tx, qam, snrs, frames, seed, k_min, plain_K, k_maxes, margins
     def per_snr_errors(sym):
         return [int(e) for e in (sym != S).view(len(snrs), frames, -1).sum(dim=(1, 2)).cpu()]
 
-    def timed(fn):
+    def timed(fn, reps=3):
         fn()  # warm
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r = fn()
-        torch.cuda.synchronize()
-        return r, time.perf_counter() - t0
+        ts = []
+        for _ in range(reps):  # median of reps
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return r, sorted(ts)[reps // 2]
 
     (sp, _, _), t_plain = timed(lambda: mimo.kbest_detect(R, z, n_tx, P, plain_K))
     pe = per_snr_errors(sp)
     log(f"  plain K={plain_K}: errors {pe}, {t_plain * 1e3:.2f} ms")
+
+    def fixed(K, beta):  # ablation: constant K with the same fallback, no network
+        sym, pd, fl = mimo.kbest_detect(R, z, n_tx, P, K)
+        mimo.kbest_fallback(R, z, n_tx, P, plain_K, s2, beta, (sym, pd, fl))
+        return sym, fl
+
+    for K in fixed_ks:
+        for beta in betas:
+            (sf, ff), t = timed(lambda: fixed(K, beta))
+            fe = per_snr_errors(sf)
+            fb = float(((ff & mimo.FLAG_LEARNED_FALLBACK) != 0).float().mean())
+            ok = all(e <= p * 1.05 for e, p in zip(fe, pe))
+            log(f"  ablation fixed K={K} beta {beta:.1f}: errors {fe}, fallback {fb:.4f}, {t * 1e3:.2f} ms"
+                f"{'  ok' if ok else ''}")
     best = None
     for km in k_maxes:
         for mg in margins:
@@ -230,15 +247,23 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=777)
     ap.add_argument("--out", default=None)
     ap.add_argument("--calibrate-only", default=None, help="recalibrate an existing checkpoint in place")
+    ap.add_argument("--k-maxes", default="16,32,64", help="calibration grid: survivor caps")
+    ap.add_argument("--margins", default="2.0,3.0,3.5,4.0,4.5,5.0", help="calibration grid: margins")
+    ap.add_argument("--betas", default="2.0,3.0,4.0,6.0", help="calibration grid: fallback thresholds")
+    ap.add_argument("--fixed-ks", default="", help="ablation: constant K values logged beside the grid")
     a = ap.parse_args(argv)
     mimo.load()
     snrs = [float(s) for s in a.snrs.split(",")]
+    kms = [int(x) for x in a.k_maxes.split(",")]
+    mgs = [float(x) for x in a.margins.split(",")]
+    bts = [float(x) for x in a.betas.split(",")]
+    fks = [int(x) for x in a.fixed_ks.split(",") if x]
     t0 = time.time()
     if a.calibrate_only:
         w, meta, m, v = load_weights(a.calibrate_only, with_moments=True)
         w = w.cuda()
         cal = calibrate(w, a.n_tx, a.qam, snrs, a.calib_frames, a.seed + 1, a.k_min, a.plain_K,
-                        k_maxes=[16, 32, 64], margins=[2.0, 3.0, 3.5, 4.0, 4.5, 5.0], betas=[2.0, 3.0, 4.0, 6.0])
+                        k_maxes=kms, margins=mgs, betas=bts, fixed_ks=fks)
         if cal:
             meta.update(k_max=cal[0], margin=cal[1], beta=cal[2], plain_K=a.plain_K)
             meta["calibration"] = dict(symbol_errors_learned=cal[3], symbol_errors_plain=cal[8], mean_k=cal[4],
@@ -255,7 +280,7 @@ def main(argv=None):
           f"rank 1: {np.mean(yc == 0):.4f}, rank > 16: {np.mean(yc > 4):.5f}, max rank {2 ** yc.max():.0f}")
     w, m, v, hist = train(X, y, steps=a.steps, batch=a.batch, lr=a.lr, tau=a.tau, seed=a.seed)
     cal = calibrate(w, a.n_tx, a.qam, snrs, a.calib_frames, a.seed + 1, a.k_min, a.plain_K,
-                    k_maxes=[16, 32, 64], margins=[2.0, 3.0, 3.5, 4.0, 4.5, 5.0], betas=[2.0, 3.0, 4.0, 6.0])
+                    k_maxes=kms, margins=mgs, betas=bts, fixed_ks=fks)
     tag = f"{a.n_tx}x{a.n_tx}_{a.qam}qam"
     meta = dict(n_tx=a.n_tx, qam=a.qam, snrs=snrs, frames=a.frames, states=int(X.shape[0]), tau=a.tau,
                 k_min=a.k_min, k_label=a.k_label, steps=a.steps, lr=a.lr, seed=a.seed,
