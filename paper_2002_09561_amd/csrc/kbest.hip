@@ -707,18 +707,25 @@ __device__ __forceinline__ void kbest_frame_reg(const KbestArgs& a, int frame, u
         // amplitude 0 (a level not yet fixed) and a word beyond nw meets zero
         // row entries, so whole chunks can be summed
         const int i_lo = ((k + 1) >> 1) / L;
-        float acc = 0.f;
+        // four partial sums (by word parity and half) keep the FMA chains short
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
 #pragma unroll
         for (int c0 = 0; c0 < NWL; c0 += CHW) {
             if (c0 + CHW > i_lo && c0 < i_hi) {
 #pragma unroll
                 for (int i = c0; i < c0 + CHW; ++i) {
                     const float2 rr = *reinterpret_cast<const float2*>(rrow + 2 * (q + L * i));
-                    acc = fmaf(rr.x, half_lo(pw[i]), acc);
-                    acc = fmaf(rr.y, half_hi(pw[i]), acc);
+                    if (i & 1) {
+                        a2 = fmaf(rr.x, half_lo(pw[i]), a2);
+                        a3 = fmaf(rr.y, half_hi(pw[i]), a3);
+                    } else {
+                        a0 = fmaf(rr.x, half_lo(pw[i]), a0);
+                        a1 = fmaf(rr.y, half_hi(pw[i]), a1);
+                    }
                 }
             }
         }
+        float acc = (a0 + a1) + (a2 + a3);
 #pragma unroll
         for (int m = 1; m < L; m <<= 1) acc += shfl_xor_f(acc, m);
         const float bown = zk - acc;
@@ -934,7 +941,7 @@ __device__ __forceinline__ void kbest_frame_cplx(const KbestArgs& a, int frame, 
         kb_wave_sync();
         // centres of this lane's survivor from the words above word m
         const int i_lo = (m + 1) / L;
-        float ah = 0.f, al = 0.f;
+        float ah = 0.f, al = 0.f, ah2 = 0.f, al2 = 0.f;  // partial sums by half: shorter FMA chains
 #pragma unroll
         for (int c0 = 0; c0 < NWL; c0 += CHW) {
             if (c0 + CHW > i_lo && c0 < i_hi) {
@@ -945,12 +952,14 @@ __device__ __forceinline__ void kbest_frame_cplx(const KbestArgs& a, int frame, 
                     const float2 rl = *reinterpret_cast<const float2*>(rlo + 2 * w);
                     const float xl = half_lo(pw[i]), xh = half_hi(pw[i]);
                     ah = fmaf(rh.x, xl, ah);
-                    ah = fmaf(rh.y, xh, ah);
+                    ah2 = fmaf(rh.y, xh, ah2);
                     al = fmaf(rl.x, xl, al);
-                    al = fmaf(rl.y, xh, al);
+                    al2 = fmaf(rl.y, xh, al2);
                 }
             }
         }
+        ah += ah2;
+        al += al2;
 #pragma unroll
         for (int j = 1; j < L; j <<= 1) {
             ah += shfl_xor_f(ah, j);
