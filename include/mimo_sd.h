@@ -161,6 +161,16 @@ int32_t kbest_fallback(const float* R, const float* z, int32_t B, int32_t n_tx, 
                        int64_t* counters, void* stream);
 
 /* ---------------------------------------------------------------------
+ * The fallback's decision alone: sets MIMO_FLAG_LEARNED_FALLBACK in
+ * flags[b] for every frame that kbest_fallback (same sigma2, beta, n_tx)
+ * would detect again, and touches nothing else.  It lets the metric of the
+ * frames that keep their first detection run while the fallback runs
+ * (mimo_metric_select).  pd, flags, sigma2 [B] as for kbest_fallback.
+ * ------------------------------------------------------------------- */
+int32_t kbest_fallback_mark(const float* pd, uint32_t* flags, const float* sigma2, int32_t B, int32_t n_tx,
+                            float beta, void* stream);
+
+/* ---------------------------------------------------------------------
  * Learned-pruning labels: K-best with K survivors in which the given path
  * (normally the ML path) is forced to survive; rank[b][k] receives the
  * 1-based rank of that path's prefix among the sorted candidates of level k.
@@ -218,6 +228,15 @@ int32_t mrc_detect(const float* H, const float* y, int32_t B, int32_t n_rx, int3
  * ------------------------------------------------------------------- */
 int32_t mimo_metric(const float* H, const float* y, const int32_t* sym, int32_t B, int32_t n_rx,
                     int32_t n_tx, int32_t pam, double* metric, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Metric epilogue for a subset of frames: as mimo_metric, for the frames
+ * with (flags[b] & mask) == value only; metric[b] of the others is not
+ * written.  flags [B] (device).
+ * ------------------------------------------------------------------- */
+int32_t mimo_metric_select(const float* H, const float* y, const int32_t* sym, const uint32_t* flags,
+                           uint32_t mask, uint32_t value, int32_t B, int32_t n_rx, int32_t n_tx, int32_t pam,
+                           double* metric, void* stream);
 
 /* ---------------------------------------------------------------------
  * Error counts: counts[0] += Gray-coded bit errors, counts[1] += symbol

@@ -22,12 +22,14 @@ __device__ __forceinline__ double xor_lanes_f64(double v, int m, int lane)
 // |residual|^2 over its rows; the four group sums are added at the end.
 __global__ void __launch_bounds__(256) metric_kernel(const float2* __restrict__ H, const float2* __restrict__ y,
                                                      const int32_t* __restrict__ sym, int B, int N, int M, int P,
-                                                     double* __restrict__ out)
+                                                     const uint32_t* __restrict__ flags, uint32_t mask,
+                                                     uint32_t value, double* __restrict__ out)
 {
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4, l = lane & 15;
     const int f = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x >> 6);
     if (f >= B) return;
+    if (flags && (flags[f] & mask) != value) return;  // frame not selected (uniform per wave)
     constexpr int CPL = (MIMO_MAX_TX + 15) / 16;  // columns per lane
     double sr[CPL], si[CPL];
 #pragma unroll
@@ -209,19 +211,38 @@ __global__ void __launch_bounds__(256) features_kernel(const float* __restrict__
 
 }  // namespace mimo
 
+namespace mimo {
+
+static int32_t launch_metric(const char* who, const float* H, const float* y, const int32_t* sym, int32_t B,
+                             int32_t n_rx, int32_t n_tx, int32_t pam, const uint32_t* flags, uint32_t mask,
+                             uint32_t value, double* metric, void* stream)
+{
+    if (B < 0 || n_tx < 1 || n_rx < n_tx) return fail(MIMO_ERR_INVALID_ARG, "%s: bad sizes", who);
+    if (pam != 2 && pam != 4 && pam != 8) return fail(MIMO_ERR_INVALID_ARG, "%s: pam must be 2, 4 or 8", who);
+    if (n_rx > MIMO_MAX_RX || n_tx > MIMO_MAX_TX) return fail(MIMO_ERR_UNSUPPORTED, "%s: size limit", who);
+    if (B == 0) return MIMO_OK;
+    if (!H || !y || !sym || !metric) return fail(MIMO_ERR_INVALID_ARG, "%s: null pointer", who);
+    hipLaunchKernelGGL(metric_kernel, dim3((B + 3) / 4), dim3(256), 0, (hipStream_t)stream,
+                       reinterpret_cast<const float2*>(H), reinterpret_cast<const float2*>(y), sym, B, n_rx, n_tx,
+                       pam, flags, mask, value, metric);
+    return check_launch(who);
+}
+
+}  // namespace mimo
+
 extern "C" int32_t mimo_metric(const float* H, const float* y, const int32_t* sym, int32_t B, int32_t n_rx,
                                int32_t n_tx, int32_t pam, double* metric, void* stream)
 {
-    using namespace mimo;
-    if (B < 0 || n_tx < 1 || n_rx < n_tx) return fail(MIMO_ERR_INVALID_ARG, "mimo_metric: bad sizes");
-    if (pam != 2 && pam != 4 && pam != 8) return fail(MIMO_ERR_INVALID_ARG, "mimo_metric: pam must be 2, 4 or 8");
-    if (n_rx > MIMO_MAX_RX || n_tx > MIMO_MAX_TX) return fail(MIMO_ERR_UNSUPPORTED, "mimo_metric: size limit");
-    if (B == 0) return MIMO_OK;
-    if (!H || !y || !sym || !metric) return fail(MIMO_ERR_INVALID_ARG, "mimo_metric: null pointer");
-    hipLaunchKernelGGL(metric_kernel, dim3((B + 3) / 4), dim3(256), 0, (hipStream_t)stream,
-                       reinterpret_cast<const float2*>(H), reinterpret_cast<const float2*>(y), sym, B, n_rx, n_tx,
-                       pam, metric);
-    return check_launch("mimo_metric");
+    return mimo::launch_metric("mimo_metric", H, y, sym, B, n_rx, n_tx, pam, nullptr, 0u, 0u, metric, stream);
+}
+
+extern "C" int32_t mimo_metric_select(const float* H, const float* y, const int32_t* sym, const uint32_t* flags,
+                                      uint32_t mask, uint32_t value, int32_t B, int32_t n_rx, int32_t n_tx,
+                                      int32_t pam, double* metric, void* stream)
+{
+    if (B > 0 && !flags) return mimo::fail(MIMO_ERR_INVALID_ARG, "mimo_metric_select: null flags");
+    return mimo::launch_metric("mimo_metric_select", H, y, sym, B, n_rx, n_tx, pam, flags, mask, value, metric,
+                               stream);
 }
 
 extern "C" int32_t mimo_error_count(const int32_t* sym, const int32_t* ref, int32_t B, int32_t n_tx, int32_t pam,

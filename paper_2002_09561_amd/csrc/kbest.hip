@@ -41,16 +41,32 @@ struct KbestArgs {
     float fb_beta;
 };
 
+// does a first detection stand?  Not when flagged for the fallback or not
+// found, nor when its search metric exceeds (sigma2 / 2) (n + beta sqrt(2 n))
+__device__ inline bool kb_first_stands(uint32_t fl, float pd, float sigma2, float beta, int n)
+{
+    if (fl & MIMO_FLAG_LEARNED_FALLBACK) return false;
+    if (!(fl & MIMO_FLAG_FOUND)) return false;
+    const float nf = (float)n;
+    const float bound = 0.5f * sigma2 * (nf + beta * sqrtf(2.f * nf));
+    return pd <= bound;
+}
+
 // fallback mode: does frame `frame` keep its first detection?
 __device__ inline bool kb_keep_first(const KbestArgs& a, int frame)
 {
     if (!a.fb_sigma2) return false;
-    const uint32_t fl = a.flags[frame];
-    if (fl & MIMO_FLAG_LEARNED_FALLBACK) return false;
-    if (!(fl & MIMO_FLAG_FOUND)) return false;
-    const float n = (float)a.n;
-    const float bound = 0.5f * a.fb_sigma2[frame] * (n + a.fb_beta * sqrtf(2.f * n));
-    return a.pd[frame] <= bound;
+    return kb_first_stands(a.flags[frame], a.pd[frame], a.fb_sigma2[frame], a.fb_beta, a.n);
+}
+
+// marks (MIMO_FLAG_LEARNED_FALLBACK) the frames the fallback will detect again
+__global__ void fallback_mark_kernel(const float* __restrict__ pd, uint32_t* __restrict__ flags,
+                                     const float* __restrict__ sigma2, float beta, int n, int B)
+{
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= B) return;
+    const uint32_t fl = flags[f];
+    if (!kb_first_stands(fl, pd[f], sigma2[f], beta, n)) flags[f] = fl | MIMO_FLAG_LEARNED_FALLBACK;
 }
 
 template <int P, int E>
@@ -1235,6 +1251,19 @@ extern "C" int32_t kbest_rank_labels(const float* R, const float* z, int32_t B, 
     if (!R || !z || !force_sym || !rank) return fail(MIMO_ERR_INVALID_ARG, "kbest_rank_labels: null pointer");
     KbestArgs a{R, z, 2 * n_tx, K, nullptr, 0, nullptr, force_sym, rank, nullptr, nullptr, nullptr, nullptr, nullptr, 0.f};
     return dispatch_kbest(a, pam, B, (hipStream_t)stream);
+}
+
+extern "C" int32_t kbest_fallback_mark(const float* pd, uint32_t* flags, const float* sigma2, int32_t B,
+                                       int32_t n_tx, float beta, void* stream)
+{
+    using namespace mimo;
+    if (B < 0 || n_tx < 1) return fail(MIMO_ERR_INVALID_ARG, "kbest_fallback_mark: bad sizes");
+    if (!(beta >= 0.f)) return fail(MIMO_ERR_INVALID_ARG, "kbest_fallback_mark: beta must be >= 0");
+    if (B == 0) return MIMO_OK;
+    if (!pd || !flags || !sigma2) return fail(MIMO_ERR_INVALID_ARG, "kbest_fallback_mark: null pointer");
+    hipLaunchKernelGGL(fallback_mark_kernel, dim3((B + 255) / 256), dim3(256), 0, (hipStream_t)stream, pd, flags,
+                       sigma2, beta, 2 * n_tx, B);
+    return check_launch("kbest_fallback_mark");
 }
 
 extern "C" int32_t kbest_fallback(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam, int32_t K,

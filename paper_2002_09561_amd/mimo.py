@@ -33,6 +33,8 @@ SIGNATURES = {
     "mrc_detect": ([_P, _P, _I32, _I32, _I32, _I32, _P, _P, _P], _I32),
     "kbest_detect": ([_P, _P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P, _P], _I32),
     "kbest_detect_complex": ([_P, _P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P, _P], _I32),
+    "kbest_fallback_mark": ([_P, _P, _P, _I32, _I32, _F, _P], _I32),
+    "mimo_metric_select": ([_P, _P, _P, _P, ctypes.c_uint32, ctypes.c_uint32, _I32, _I32, _I32, _I32, _P, _P], _I32),
     "kbest_rank_labels": ([_P, _P, _I32, _I32, _I32, _I32, _P, _P, _P], _I32),
     "kbest_fallback": ([_P, _P, _I32, _I32, _I32, _I32, _P, _F, _P, _P, _P, _P, _P], _I32),
     "sd_hybrid_detect": ([_P, _P, _I32, _I32, _I32, _P, _I32, _I32, _P, _I32, _I32, _I64, _P, _P, _P, _P,
@@ -221,6 +223,16 @@ def kbest_fallback(R, z, n_tx: int, pam: int, K: int, sigma2, beta: float, out, 
     return sym, pd, flags
 
 
+def kbest_fallback_mark(n_tx: int, sigma2, beta: float, out, stream=None):
+    """Flag (FLAG_LEARNED_FALLBACK) the frames of `out` = (sym, pd, flags) that
+    kbest_fallback would detect again."""
+    pd, flags = out[1], out[2]
+    B = pd.shape[0]
+    _check(load().kbest_fallback_mark(_ptr(pd, torch.float32, "pd"), _ptr(flags, torch.int32, "flags"),
+                                      _ptr(sigma2, torch.float32, "sigma2"), B, n_tx, float(beta), _stream(stream)))
+    return flags
+
+
 def kbest_rank_labels(R, z, n_tx: int, pam: int, K: int, force_sym, stream=None):
     B = z.shape[0]
     rank = torch.empty(B, 2 * n_tx, device=z.device, dtype=torch.int32)
@@ -250,6 +262,15 @@ def metric(H, y, sym, pam: int, out=None, stream=None):
     _check(load().mimo_metric(_ptr(H, torch.complex64, "H"), _ptr(y, torch.complex64, "y"),
                               _ptr(sym, torch.int32, "sym"), B, N, M, pam, _ptr(m, torch.float64), _stream(stream)))
     return m
+
+
+def metric_select(H, y, sym, pam: int, flags, mask: int, value: int, out, stream=None):
+    """FP64 metric of the frames with (flags & mask) == value, into `out`."""
+    B, N, M = H.shape
+    _check(load().mimo_metric_select(_ptr(H, torch.complex64, "H"), _ptr(y, torch.complex64, "y"),
+                                     _ptr(sym, torch.int32, "sym"), _ptr(flags, torch.int32, "flags"), int(mask),
+                                     int(value), B, N, M, pam, _ptr(out, torch.float64), _stream(stream)))
+    return out
 
 
 def error_count(sym, ref, pam: int, counts=None, stream=None):

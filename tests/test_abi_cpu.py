@@ -76,6 +76,11 @@ def test_host_validation_without_gpu(lib):
     assert lib.linear_detect(P, P, 2, 4, 4, P, P, P) == -1
     assert lib.mrc_detect(P, P, 2, 300, 200, 4, P, P, P) == -2
     assert lib.mrc_detect(P, P, 2, 8, 4, 4, P, P, P) == -1
+    # fallback marking and selective metric
+    assert lib.kbest_fallback_mark(P, P, P, 2, 4, ctypes.c_float(-1.0), P) == -1
+    assert lib.kbest_fallback_mark(P, P, P, 2, 4, ctypes.c_float(3.0), P) == -1
+    assert lib.mimo_metric_select(P, P, P, P, 16, 0, 2, 4, 4, 4, P, P) == -1
+    assert "flags" in _err(lib)
     # MLP
     assert lib.prune_mlp_schedule(P, P, 10, 0.0, 0, 4, 8, P, P, P) == -1
     assert lib.prune_mlp_loss_grad(P, P, P, 10, 1.5, P, P, P, 0, P) == -1

@@ -259,3 +259,35 @@ def test_kbest_fallback(gpu, orc):
     Ro, zo, _ = orc.qr(f.H, f.y)
     kb = orc.kbest(Ro[redo], zo[redo], P, 32)
     compare_symbols(_np(sym)[redo], orc.x_to_sym(kb["x"], P), kb["margin"], near_tie_tol(n), "fallback")
+
+
+def test_fallback_mark_and_metric_select(gpu):
+    """kbest_fallback_mark flags exactly the frames kbest_fallback detects
+    again (and changes nothing else); mimo_metric_select writes the metric of
+    the selected frames only, equal to the full metric there."""
+    import torch
+
+    M, q, B, P = 16, 16, 400, 4
+    f = gen_frames(M, M, q, 8.0, B, seed=2700)
+    H, y, _ = _dev(f)
+    R, z = gpu.qr_preprocess(H, y)
+    s2 = torch.full((B,), f.sigma2, device="cuda", dtype=torch.float32)
+    sym, pd, flags = gpu.kbest_detect(R, z, M, P, 1)
+    beta = 2.0
+    fl_mark = flags.clone()
+    gpu.kbest_fallback_mark(M, s2, beta, (sym, pd, fl_mark))
+    s_fb, pd_fb, fl_fb = sym.clone(), pd.clone(), flags.clone()
+    gpu.kbest_fallback(R, z, M, P, 16, s2, beta, (s_fb, pd_fb, fl_fb))
+    FB = gpu.FLAG_LEARNED_FALLBACK
+    marked = (_np(fl_mark) & FB) != 0
+    assert 0 < marked.sum() < B
+    assert np.array_equal(marked, (_np(fl_fb) & FB) != 0)
+    assert np.array_equal(_np(fl_mark)[~marked], _np(flags)[~marked])
+    assert np.array_equal(_np(s_fb)[~marked], _np(sym)[~marked])
+    full = gpu.metric(H, y, s_fb, P)
+    out = torch.full((B,), float("nan"), device="cuda", dtype=torch.float64)
+    gpu.metric_select(H, y, s_fb, P, fl_mark, FB, 0, out)
+    o = _np(out)
+    assert np.array_equal(o[~marked], _np(full)[~marked]) and np.all(np.isnan(o[marked]))
+    gpu.metric_select(H, y, s_fb, P, fl_mark, FB, FB, out)
+    assert np.array_equal(_np(out), _np(full))
