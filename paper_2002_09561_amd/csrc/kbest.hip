@@ -245,9 +245,10 @@ __device__ __forceinline__ void bitonic_sort_lim(uint64_t& key, int lane)
 
 // Selection by sorting, for at most 128 candidates (ES = 1 or 2 blocks of
 // 64): all candidate keys (pd bits, candidate index; invalid = ~0) are put
-// in order by one in-wave bitonic sort and the first `keep` survive.  Same
-// contract and result as kb_select; no ballot counting.
-template <int E, int ES>
+// in order by one in-wave bitonic sort and the first `keep` survive; with one
+// block whose candidates sit in lanes 0 .. LIM-1, only those lanes are sorted.
+// Same contract and result as kb_select; no ballot counting.
+template <int E, int ES, int LIM = WAVE>
 __device__ __forceinline__ int kb_select_sort(const uint32_t (&kh)[E], int nvalid, int Kt, int fm, int lane,
                                               float* sn, int32_t* sel, int* fpos_out)
 {
@@ -266,7 +267,8 @@ __device__ __forceinline__ int kb_select_sort(const uint32_t (&kh)[E], int nvali
             if (e == fe) fh = __shfl(kh[e], fl, WAVE);
         if (fh != ~0u) fkey = ((uint64_t)fh << 32) | (uint32_t)fm;
     }
-    bitonic_sort<ES>(key, lane);
+    if constexpr (ES == 1) bitonic_sort_lim<LIM>(key[0], lane);
+    else bitonic_sort<ES>(key, lane);
     int fpos = -1;
     if (fkey != ~0ull) {  // the forced candidate's rank = its sorted position
 #pragma unroll
@@ -780,7 +782,10 @@ __device__ __forceinline__ void kbest_frame_reg(const KbestArgs& a, int frame, u
         int fpos = -1;
         int keep;
         if constexpr (E <= 2) {
-            if (cnt * P <= WAVE)
+            // the candidates sit in lanes 0 .. cnt P - 1: sort only as many lanes
+            if (cnt * P <= 32)
+                keep = kb_select_sort<E, 1, 32>(kh, nvalid, Kt, fm, lane, sn, sel, &fpos);
+            else if (cnt * P <= WAVE)
                 keep = kb_select_sort<E, 1>(kh, nvalid, Kt, fm, lane, sn, sel, &fpos);
             else
                 keep = kb_select_sort<E, E>(kh, nvalid, Kt, fm, lane, sn, sel, &fpos);
