@@ -1347,8 +1347,8 @@ extern "C" int32_t kbest_detect_uneven(const mimo_frame_desc* desc, int32_t B, c
     hipStream_t st = (hipStream_t)stream;
     if (grid == 0) {
         int dev = 0, cus = 0;
-        hipGetDevice(&dev);
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         grid = 8 * (cus > 0 ? cus : 256);
     }
     if (grid > B) grid = B;
