@@ -14,10 +14,13 @@
 // (the tile stays in registers for the whole frame); frames of 4 to 6 waves
 // run two per workgroup.
 //   1. Gram: [H | y] streams through LDS in chunks of up to 16 rows (as many
-//      as let each thread stage at most 4 elements), converted to FP64 once
-//      when staged; the next chunk is prefetched into registers while the
-//      current one is consumed; each thread accumulates conj(a_i)^T a_j over
-//      the rows for its tile.
+//      as let each thread stage at most 4 elements), kept in FP32 there and
+//      converted to FP64 when read (the Gram loop is bound by LDS reads, so
+//      half the bytes per read outweighs the conversions); the next chunk is
+//      prefetched into registers while the current one is consumed; each
+//      thread accumulates conj(a_i)^T a_j over the rows for its tile.  The
+//      products of FP32 inputs are exact in FP64, so this is the same
+//      arithmetic as staging FP64 copies.
 //   2. Right-looking Cholesky: at step k the owners of row k of the current
 //      Schur complement publish it in LDS (double-buffered, so one barrier per
 //      step) and every thread applies G_ij -= conj(g_ki) g_kj / g_kk to its
@@ -69,11 +72,11 @@ __host__ __device__ inline int cq_rows(int M, int nthr)
 }
 
 // LDS bytes: row buffers [2][CP] complex double, pivots [CP] and a 4-entry
-// spare [4] double, chunk buffers [2][rch][CP] complex double
+// spare [4] double, chunk buffers [2][rch][CP] complex float
 __host__ __device__ inline size_t cq_lds_bytes(int M, int rch)
 {
     const int CP = cq_shape(M).CP;
-    return (size_t)CP * (2 * 16 + 8) + CQ_T * 8 + (size_t)2 * rch * CP * 16;
+    return (size_t)CP * (2 * 16 + 8) + CQ_T * 8 + (size_t)2 * rch * CP * 8;
 }
 
 struct cd {
@@ -98,8 +101,8 @@ __device__ __forceinline__ float2 cq_elem(const float2* __restrict__ Hf, const f
 }
 
 // LDS slot of chunk element e (row, col = 4J + q) in the chunk layout
-// [row][q][J] of complex doubles, so that the lanes of a wave (consecutive J)
-// read 16-byte neighbours.
+// [row][q][J] of complex floats, so that the lanes of a wave (consecutive J)
+// read 8-byte neighbours.
 __device__ __forceinline__ int cq_lds_slot(int e, int CP, int nb, float rcp_cp)
 {
     const int row = (int)(((float)e + 0.5f) * rcp_cp);
@@ -132,12 +135,16 @@ __device__ __forceinline__ void cq_store_row(cd* row, double* rinv, int nb, int 
 }
 
 // one step k of the right-looking Cholesky; S = k mod 4 (row k+1 sits in
-// register row (S + 1) mod 4 of the tiles that publish it)
-template <int S>
-__device__ __forceinline__ void cq_step(int k, int M, int CP, int nb, int tid, bool has_tile, int I, int J, int i0,
+// register row (S + 1) mod 4 of the tiles that publish it).  NBC > 0 fixes
+// the tile-row count at compile time (else nb_ is used): the plane offsets
+// q nb of the LDS rows then fold into the instructions' offset fields.
+template <int S, int NBC>
+__device__ __forceinline__ void cq_step(int k, int M, int nb_, int tid, bool has_tile, int I, int J, int i0,
                                         cd* rowbuf, double* rinv, double* diag, double (&gr)[CQ_T][CQ_T],
                                         double (&gi)[CQ_T][CQ_T])
 {
+    const int nb = NBC > 0 ? NBC : nb_;
+    const int CP = CQ_T * nb;
     __syncthreads();  // row k published; the other buffer is free
     const cd* rk = rowbuf + (k & 1) * CP;
     if (tid == 0) diag[k] = rk[(k & (CQ_T - 1)) * nb + k / CQ_T].x;
@@ -169,18 +176,19 @@ __device__ __forceinline__ void cq_step(int k, int M, int CP, int nb, int tid, b
     }
 }
 
+template <int NBC>
 __device__ __forceinline__ void cholqr_frame(const float2* __restrict__ Hf, const float2* __restrict__ yf, int N,
                                              int M, float* __restrict__ Rf, float* __restrict__ zf,
                                              float* __restrict__ resid_out, const float* __restrict__ load,
                                              unsigned char* smem, int tid, int nthr, bool live)
 {
     const CqShape sh = cq_shape(M);
-    const int CP = sh.CP;
+    const int nb = NBC > 0 ? NBC : sh.nb;
+    const int CP = CQ_T * nb;
     const int n = 2 * M;
-    const int nb = sh.nb;
     cd* rowbuf = reinterpret_cast<cd*>(smem);                   // [2][4][nb]
     double* diag = reinterpret_cast<double*>(rowbuf + 2 * CP);  // [CP] pivots, then [4] spare
-    cd* ach = reinterpret_cast<cd*>(diag + CP + CQ_T);           // [2][16][4][nb] complex
+    float2* ach = reinterpret_cast<float2*>(diag + CP + CQ_T);   // [2][rch][4][nb] complex float
 
     // tile (I, J), I <= J, enumerated row by row
     const bool has_tile = tid < sh.ntiles;
@@ -210,11 +218,11 @@ __device__ __forceinline__ void cholqr_frame(const float2* __restrict__ Hf, cons
 #pragma unroll
     for (int q = 0; q < CQ_PF; ++q) pf[q] = cq_elem(Hf, yf, N, M, CP, rcp_cp, tot, rch, 0, tid + q * nthr);
     for (int c = 0; c < nchunk; ++c) {
-        cd* buf = ach + (c & 1) * tot;
+        float2* buf = ach + (c & 1) * tot;
 #pragma unroll
         for (int q = 0; q < CQ_PF; ++q) {
             const int e = tid + q * nthr;
-            if (e < tot) buf[cq_lds_slot(e, CP, nb, rcp_cp)] = {(double)pf[q].x, (double)pf[q].y};
+            if (e < tot) buf[cq_lds_slot(e, CP, nb, rcp_cp)] = pf[q];
         }
         __syncthreads();  // chunk c visible; chunk c-1's buffer no longer read
         if (c + 1 < nchunk) {
@@ -225,15 +233,15 @@ __device__ __forceinline__ void cholqr_frame(const float2* __restrict__ Hf, cons
         if (has_tile) {
             const int nr = min(rch, N - c * rch);
             for (int rr = 0; rr < nr; ++rr) {
-                const cd* rowp = buf + rr * CP;
+                const float2* rowp = buf + rr * CP;
                 double ar[CQ_T], ai[CQ_T], br[CQ_T], bi[CQ_T];
 #pragma unroll
                 for (int q = 0; q < CQ_T; ++q) {
-                    const cd a = rowp[q * nb + I], b = rowp[q * nb + J];
-                    ar[q] = a.x;
-                    ai[q] = a.y;
-                    br[q] = b.x;
-                    bi[q] = b.y;
+                    const float2 a = rowp[q * nb + I], b = rowp[q * nb + J];
+                    ar[q] = (double)a.x;
+                    ai[q] = (double)a.y;
+                    br[q] = (double)b.x;
+                    bi[q] = (double)b.y;
                 }
                 // G_ij += conj(a_i) a_j
 #pragma unroll
@@ -263,10 +271,10 @@ __device__ __forceinline__ void cholqr_frame(const float2* __restrict__ Hf, cons
     double* rinv = diag + CP;  // [2] reciprocal pivots of the published rows (the spare entries)
     if (has_tile && I == 0) cq_store_row<0>(rowbuf, rinv, nb, I, J, gr, gi);
     for (int kb = 0; kb < M; kb += CQ_T) {
-        cq_step<0>(kb, M, CP, nb, tid, has_tile, I, J, i0, rowbuf, rinv, diag, gr, gi);
-        if (kb + 1 < M) cq_step<1>(kb + 1, M, CP, nb, tid, has_tile, I, J, i0, rowbuf, rinv, diag, gr, gi);
-        if (kb + 2 < M) cq_step<2>(kb + 2, M, CP, nb, tid, has_tile, I, J, i0, rowbuf, rinv, diag, gr, gi);
-        if (kb + 3 < M) cq_step<3>(kb + 3, M, CP, nb, tid, has_tile, I, J, i0, rowbuf, rinv, diag, gr, gi);
+        cq_step<0, NBC>(kb, M, nb, tid, has_tile, I, J, i0, rowbuf, rinv, diag, gr, gi);
+        if (kb + 1 < M) cq_step<1, NBC>(kb + 1, M, nb, tid, has_tile, I, J, i0, rowbuf, rinv, diag, gr, gi);
+        if (kb + 2 < M) cq_step<2, NBC>(kb + 2, M, nb, tid, has_tile, I, J, i0, rowbuf, rinv, diag, gr, gi);
+        if (kb + 3 < M) cq_step<3, NBC>(kb + 3, M, nb, tid, has_tile, I, J, i0, rowbuf, rinv, diag, gr, gi);
     }
     __syncthreads();  // diag complete
 
@@ -317,7 +325,8 @@ __device__ __forceinline__ void cholqr_frame(const float2* __restrict__ Hf, cons
 // SIMD): a workgroup of 6 waves at 3 waves per SIMD leaves the second
 // workgroup of a CU no room on the SIMDs that hold two of its waves.  tpf
 // threads per frame; a second half beyond the batch computes the last frame
-// again and stores nothing.
+// again and stores nothing.  NBC: compile-time tile-row count, or 0.
+template <int NBC>
 __global__ void __launch_bounds__(CQ_MAX_WG) qr_kernel(const float2* __restrict__ H, const float2* __restrict__ y,
                                                        int N, int M, float* __restrict__ R, float* __restrict__ z,
                                                        float* __restrict__ resid, const float* __restrict__ load,
@@ -330,7 +339,7 @@ __global__ void __launch_bounds__(CQ_MAX_WG) qr_kernel(const float2* __restrict_
     const int frame = live ? f : B - 1;
     const int n = 2 * M;
     const size_t lds = (cq_lds_bytes(M, cq_rows(M, tpf)) + 15) & ~(size_t)15;
-    cholqr_frame(H + (size_t)frame * N * M, y + (size_t)frame * N, N, M, R + (size_t)frame * r_packed_size(n),
+    cholqr_frame<NBC>(H + (size_t)frame * N * M, y + (size_t)frame * N, N, M, R + (size_t)frame * r_packed_size(n),
                      z + (size_t)frame * n, resid ? resid + frame : nullptr, load ? load + frame : nullptr,
                      smem_qr + half * lds,
                      (int)threadIdx.x - half * tpf, tpf, live);
@@ -355,7 +364,7 @@ __global__ void __launch_bounds__(CQ_MAX_THREADS) qr_uneven_kernel(const mimo_fr
         const mimo_frame_desc d = desc[f];
         // the workgroup and its LDS are sized for n_tx <= n_rx <= max_rx
         if (d.n_tx < 1 || d.n_tx > d.n_rx || d.n_rx > max_rx) continue;
-        cholqr_frame(H + d.h_off, y + d.y_off, d.n_rx, d.n_tx, R + d.r_off, z + d.z_off, nullptr, nullptr, smem_qr,
+        cholqr_frame<0>(H + d.h_off, y + d.y_off, d.n_rx, d.n_tx, R + d.r_off, z + d.z_off, nullptr, nullptr, smem_qr,
                          (int)threadIdx.x, (int)blockDim.x, true);
     }
 }
@@ -395,8 +404,15 @@ static int32_t launch_qr(const char* who, const float* H, const float* y, const 
     const size_t lds = fpw * ((cq_lds_bytes(n_tx, cq_rows(n_tx, threads)) + 15) & ~(size_t)15);
     const int grid = (B + fpw - 1) / fpw;
     hipStream_t st = (hipStream_t)stream;
-    if (int32_t rc = cq_allow_lds((const void*)qr_kernel, lds)) return rc;
-    hipLaunchKernelGGL(qr_kernel, dim3(grid), dim3(fpw * threads), lds, st, H2, y2, n_rx, n_tx, R, z, resid, load, B,
+    // compile-time tile rows for 32, 64, 100 and 128 transmit antennas
+    const int nb = cq_shape(n_tx).nb;
+    auto kern = nb == 9    ? qr_kernel<9>
+                : nb == 17 ? qr_kernel<17>
+                : nb == 26 ? qr_kernel<26>
+                : nb == 33 ? qr_kernel<33>
+                           : qr_kernel<0>;
+    if (int32_t rc = cq_allow_lds((const void*)kern, lds)) return rc;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(fpw * threads), lds, st, H2, y2, n_rx, n_tx, R, z, resid, load, B,
                        fpw, threads);
     return check_launch(who);
 }
