@@ -14,13 +14,15 @@
 // (the tile stays in registers for the whole frame); frames of 4 to 6 waves
 // run two per workgroup.
 //   1. Gram: [H | y] streams through LDS in chunks of up to 16 rows (as many
-//      as let each thread stage at most 4 elements), kept in FP32 there and
-//      converted to FP64 when read (the Gram loop is bound by LDS reads, so
-//      half the bytes per read outweighs the conversions); the next chunk is
-//      prefetched into registers while the current one is consumed; each
-//      thread accumulates conj(a_i)^T a_j over the rows for its tile.  The
-//      products of FP32 inputs are exact in FP64, so this is the same
-//      arithmetic as staging FP64 copies.
+//      as let each thread stage at most 4 elements), staged twice: an FP64
+//      copy for the tile-row operand and an FP32 copy for the tile-column
+//      operand, converted when read.  With two FP64 operands the loop is
+//      bound by LDS reads, with two FP32 ones by the conversions' VALU
+//      issue; one of each balances the two.  The next chunk is prefetched
+//      into registers while the current one is consumed; each thread
+//      accumulates conj(a_i)^T a_j over the rows for its tile.  The products
+//      of FP32 inputs are exact in FP64, so the arithmetic is that of FP64
+//      copies.
 //   2. Right-looking Cholesky: at step k the owners of row k of the current
 //      Schur complement publish it in LDS (double-buffered, so one barrier per
 //      step) and every thread applies G_ij -= conj(g_ki) g_kj / g_kk to its
@@ -72,11 +74,12 @@ __host__ __device__ inline int cq_rows(int M, int nthr)
 }
 
 // LDS bytes: row buffers [2][CP] complex double, pivots [CP] and a 4-entry
-// spare [4] double, chunk buffers [2][rch][CP] complex float
+// spare [4] double, chunk buffers [2][rch][CP] complex double, then the same
+// as complex float (at most 154 KB for two frames of up to 6 waves)
 __host__ __device__ inline size_t cq_lds_bytes(int M, int rch)
 {
     const int CP = cq_shape(M).CP;
-    return (size_t)CP * (2 * 16 + 8) + CQ_T * 8 + (size_t)2 * rch * CP * 8;
+    return (size_t)CP * (2 * 16 + 8) + CQ_T * 8 + (size_t)2 * rch * CP * (16 + 8);
 }
 
 struct cd {
@@ -101,8 +104,7 @@ __device__ __forceinline__ float2 cq_elem(const float2* __restrict__ Hf, const f
 }
 
 // LDS slot of chunk element e (row, col = 4J + q) in the chunk layout
-// [row][q][J] of complex floats, so that the lanes of a wave (consecutive J)
-// read 8-byte neighbours.
+// [row][q][J], so that the lanes of a wave (consecutive J) read neighbours.
 __device__ __forceinline__ int cq_lds_slot(int e, int CP, int nb, float rcp_cp)
 {
     const int row = (int)(((float)e + 0.5f) * rcp_cp);
@@ -188,7 +190,9 @@ __device__ __forceinline__ void cholqr_frame(const float2* __restrict__ Hf, cons
     const int n = 2 * M;
     cd* rowbuf = reinterpret_cast<cd*>(smem);                   // [2][4][nb]
     double* diag = reinterpret_cast<double*>(rowbuf + 2 * CP);  // [CP] pivots, then [4] spare
-    float2* ach = reinterpret_cast<float2*>(diag + CP + CQ_T);   // [2][rch][4][nb] complex float
+    const int rch = cq_rows(M, nthr);
+    cd* ach64 = reinterpret_cast<cd*>(diag + CP + CQ_T);          // [2][rch][4][nb] complex double
+    float2* ach32 = reinterpret_cast<float2*>(ach64 + 2 * rch * CP);  // [2][rch][4][nb] complex float
 
     // tile (I, J), I <= J, enumerated row by row
     const bool has_tile = tid < sh.ntiles;
@@ -210,7 +214,6 @@ __device__ __forceinline__ void cholqr_frame(const float2* __restrict__ Hf, cons
         for (int c = 0; c < CQ_T; ++c) gr[r][c] = gi[r][c] = 0.0;
 
     // ---- 1. Gram matrix over chunks of 16 rows
-    const int rch = cq_rows(M, nthr);
     const int nchunk = (N + rch - 1) / rch;
     const int tot = rch * CP;
     const float rcp_cp = 1.0f / (float)CP;
@@ -218,11 +221,16 @@ __device__ __forceinline__ void cholqr_frame(const float2* __restrict__ Hf, cons
 #pragma unroll
     for (int q = 0; q < CQ_PF; ++q) pf[q] = cq_elem(Hf, yf, N, M, CP, rcp_cp, tot, rch, 0, tid + q * nthr);
     for (int c = 0; c < nchunk; ++c) {
-        float2* buf = ach + (c & 1) * tot;
+        cd* buf64 = ach64 + (c & 1) * tot;
+        float2* buf32 = ach32 + (c & 1) * tot;
 #pragma unroll
         for (int q = 0; q < CQ_PF; ++q) {
             const int e = tid + q * nthr;
-            if (e < tot) buf[cq_lds_slot(e, CP, nb, rcp_cp)] = pf[q];
+            if (e < tot) {
+                const int slot = cq_lds_slot(e, CP, nb, rcp_cp);
+                buf64[slot] = {(double)pf[q].x, (double)pf[q].y};
+                buf32[slot] = pf[q];
+            }
         }
         __syncthreads();  // chunk c visible; chunk c-1's buffer no longer read
         if (c + 1 < nchunk) {
@@ -233,13 +241,15 @@ __device__ __forceinline__ void cholqr_frame(const float2* __restrict__ Hf, cons
         if (has_tile) {
             const int nr = min(rch, N - c * rch);
             for (int rr = 0; rr < nr; ++rr) {
-                const float2* rowp = buf + rr * CP;
+                const cd* row64 = buf64 + rr * CP;
+                const float2* row32 = buf32 + rr * CP;
                 double ar[CQ_T], ai[CQ_T], br[CQ_T], bi[CQ_T];
 #pragma unroll
                 for (int q = 0; q < CQ_T; ++q) {
-                    const float2 a = rowp[q * nb + I], b = rowp[q * nb + J];
-                    ar[q] = (double)a.x;
-                    ai[q] = (double)a.y;
+                    const cd a = row64[q * nb + I];
+                    const float2 b = row32[q * nb + J];
+                    ar[q] = a.x;
+                    ai[q] = a.y;
                     br[q] = (double)b.x;
                     bi[q] = (double)b.y;
                 }
