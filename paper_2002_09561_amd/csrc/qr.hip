@@ -126,30 +126,49 @@ __device__ __forceinline__ double cq_inv(double d)
 // in registers).  A published row is stored in planes: column j = 4J + q at
 // [q][J], so the lanes of a wave, which hold consecutive J, read 16-byte
 // neighbours (no LDS bank conflicts).  The owner of the diagonal entry also
-// publishes its reciprocal, which every thread of the next step needs.
+// publishes its reciprocal, which every thread of the next step needs, and
+// records the pivot for the output.
 template <int LR>
-__device__ __forceinline__ void cq_store_row(cd* row, double* rinv, int nb, int I, int J,
+__device__ __forceinline__ void cq_store_row(cd* row, double* rinv, double* pivot, int nb, int I, int J,
                                              const double (&gr)[CQ_T][CQ_T], const double (&gi)[CQ_T][CQ_T])
 {
 #pragma unroll
     for (int c = 0; c < CQ_T; ++c) row[c * nb + J] = {gr[LR][c], gi[LR][c]};
-    if (J == I) *rinv = cq_inv(gr[LR][LR]);
+    if (J == I) {
+        *rinv = cq_inv(gr[LR][LR]);
+        *pivot = gr[LR][LR];
+    }
+}
+
+// orders one wave's LDS writes before its later LDS reads (a wave's LDS
+// operations complete in order; this keeps the compiler from reordering them
+// and waits for the writes)
+__device__ __forceinline__ void cq_wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // one step k of the right-looking Cholesky; S = k mod 4 (row k+1 sits in
 // register row (S + 1) mod 4 of the tiles that publish it).  NBC > 0 fixes
 // the tile-row count at compile time (else nb_ is used): the plane offsets
-// q nb of the LDS rows then fold into the instructions' offset fields.
+// q nb of the LDS rows then fold into the instructions' offset fields.  wg:
+// the step's tiles span several waves (workgroup barrier), else one wave
+// runs the step alone.
 template <int S, int NBC>
-__device__ __forceinline__ void cq_step(int k, int M, int nb_, int tid, bool has_tile, int I, int J, int i0,
+__device__ __forceinline__ void cq_step(int k, int M, int nb_, bool wg, bool has_tile, int I, int J, int i0,
                                         cd* rowbuf, double* rinv, double* diag, double (&gr)[CQ_T][CQ_T],
                                         double (&gi)[CQ_T][CQ_T])
 {
     const int nb = NBC > 0 ? NBC : nb_;
     const int CP = CQ_T * nb;
-    __syncthreads();  // row k published; the other buffer is free
+    if (wg)
+        __syncthreads();  // row k published; the other buffer is free
+    else
+        cq_wave_sync();
     const cd* rk = rowbuf + (k & 1) * CP;
-    if (tid == 0) diag[k] = rk[(k & (CQ_T - 1)) * nb + k / CQ_T].x;
     if (has_tile && i0 + CQ_T - 1 > k) {
         const double inv = rinv[k & 1];  // 1 / g_kk
         double ur[CQ_T], ui[CQ_T], vr[CQ_T], vi[CQ_T];
@@ -174,7 +193,8 @@ __device__ __forceinline__ void cq_step(int k, int M, int nb_, int tid, bool has
                 gi[r][q] = fma(-ui[r], vr[q], gi[r][q]);
             }
         if (k + 1 < M && (k + 1) / CQ_T == I)
-            cq_store_row<(S + 1) & (CQ_T - 1)>(rowbuf + ((k + 1) & 1) * CP, rinv + ((k + 1) & 1), nb, I, J, gr, gi);
+            cq_store_row<(S + 1) & (CQ_T - 1)>(rowbuf + ((k + 1) & 1) * CP, rinv + ((k + 1) & 1), diag + k + 1, nb,
+                                               I, J, gr, gi);
     }
 }
 
@@ -277,16 +297,27 @@ __device__ __forceinline__ void cholqr_frame(const float2* __restrict__ Hf, cons
     }
 
     // ---- 2. right-looking Cholesky, one barrier per step (unrolled by the
-    //         tile edge so the published register row is a constant)
-    double* rinv = diag + CP;  // [2] reciprocal pivots of the published rows (the spare entries)
-    if (has_tile && I == 0) cq_store_row<0>(rowbuf, rinv, nb, I, J, gr, gi);
+    //         tile edge so the published register row is a constant).  Step
+    //         k updates the tiles of tile rows >= k / 4 only; from the first
+    //         tile row whose tiles all sit in the frame's last wave (tiles
+    //         are numbered row by row), that wave runs the remaining steps
+    //         alone, without workgroup barriers, and the other waves go on
+    //         to the output: their rows and pivots are final by then.
+    const int last0 = (sh.ntiles - 1) / WAVE * WAVE;  // first tile of the last wave
+    int Iw = 0;  // first tile row starting at or after last0 (tile (I, I) is number I nb - I (I - 1) / 2)
+    while (Iw * nb - Iw * (Iw - 1) / 2 < last0) ++Iw;
+    const int k1 = min(M, CQ_T * Iw);
+    const bool tail = tid >= last0;  // this thread's wave runs the steps k >= k1
+    double* rinv = diag + CP;        // [2] reciprocal pivots of the published rows
+    if (has_tile && I == 0) cq_store_row<0>(rowbuf, rinv, diag, nb, I, J, gr, gi);
     for (int kb = 0; kb < M; kb += CQ_T) {
-        cq_step<0, NBC>(kb, M, nb, tid, has_tile, I, J, i0, rowbuf, rinv, diag, gr, gi);
-        if (kb + 1 < M) cq_step<1, NBC>(kb + 1, M, nb, tid, has_tile, I, J, i0, rowbuf, rinv, diag, gr, gi);
-        if (kb + 2 < M) cq_step<2, NBC>(kb + 2, M, nb, tid, has_tile, I, J, i0, rowbuf, rinv, diag, gr, gi);
-        if (kb + 3 < M) cq_step<3, NBC>(kb + 3, M, nb, tid, has_tile, I, J, i0, rowbuf, rinv, diag, gr, gi);
+        if (kb >= k1 && !tail) break;
+        cq_step<0, NBC>(kb, M, nb, kb < k1, has_tile, I, J, i0, rowbuf, rinv, diag, gr, gi);
+        if (kb + 1 < M) cq_step<1, NBC>(kb + 1, M, nb, kb + 1 < k1, has_tile, I, J, i0, rowbuf, rinv, diag, gr, gi);
+        if (kb + 2 < M) cq_step<2, NBC>(kb + 2, M, nb, kb + 2 < k1, has_tile, I, J, i0, rowbuf, rinv, diag, gr, gi);
+        if (kb + 3 < M) cq_step<3, NBC>(kb + 3, M, nb, kb + 3 < k1, has_tile, I, J, i0, rowbuf, rinv, diag, gr, gi);
     }
-    __syncthreads();  // diag complete
+    if (tail) cq_wave_sync();  // the tail's own last pivot writes
 
     // ---- 3. output: R_ij = g_ij / sqrt(g_ii), real blocks in packed level order
     if (has_tile && live) {
@@ -319,12 +350,10 @@ __device__ __forceinline__ void cholqr_frame(const float2* __restrict__ Hf, cons
                 }
             }
         }
-        // rho^2 = ||y||^2 - ||z||^2 is the Schur complement left at (M, M):
-        // its tile publishes the diagonal, the thread of (M, M) reads it back
+        // rho^2 = ||y||^2 - ||z||^2 is the Schur complement left at (M, M)
         if (resid_out && I == J && I == M / CQ_T) {
-#pragma unroll
-            for (int r = 0; r < CQ_T; ++r) diag[CP + r] = gr[r][r];
-            const double v = diag[CP + (M & (CQ_T - 1))];
+            const int r = M & (CQ_T - 1);
+            const double v = r == 0 ? gr[0][0] : r == 1 ? gr[1][1] : r == 2 ? gr[2][2] : gr[3][3];
             *resid_out = (float)(v > 0.0 ? v : 0.0);
         }
     }
