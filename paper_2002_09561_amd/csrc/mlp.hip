@@ -7,7 +7,9 @@
 //     accumulator's initial value;
 //   * layer 2: FP16 MFMA 16x16x32 with FP32 accumulation: ReLU(h1) and W2 are
 //     rounded to binary16 (their products are exact in FP32); the W2
-//     fragments stay in registers for the whole kernel;
+//     fragments are staged once per workgroup in LDS (32 KB, each lane's
+//     fragment a 16-byte neighbour of the next lane's), which keeps the
+//     kernel at a few waves per SIMD instead of one;
 //   * layer 3, biases and ReLU in FP32 on the vector ALUs.
 // The hidden units of layer 1 are computed in a permuted order so that its
 // result registers are already laid out as layer 2's B operand.
@@ -72,17 +74,17 @@ __global__ void __launch_bounds__(256) mlp_infer_kernel(const float* __restrict_
     float a1[8];
 #pragma unroll
     for (int hb = 0; hb < 8; ++hb) a1[hb] = w[OW1 + mlp_perm(hb, s16) * NIN + g];
-    // layer-2 A operand of output block nb, step t: W2[16nb + s16][32t + 8g + e]
-    half8 a2[8][4];
-#pragma unroll
-    for (int nb = 0; nb < 8; ++nb)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const float* row = w + OW2 + (16 * nb + s16) * HID + 32 * t + 8 * g;
-            const float4 lo = *reinterpret_cast<const float4*>(row), hi = *reinterpret_cast<const float4*>(row + 4);
-            a2[nb][t] = half8{(_Float16)lo.x, (_Float16)lo.y, (_Float16)lo.z, (_Float16)lo.w,
-                              (_Float16)hi.x, (_Float16)hi.y, (_Float16)hi.z, (_Float16)hi.w};
-        }
+    // layer-2 A operand of output block nb, step t, for lane (g, s16):
+    // W2[16nb + s16][32t + 8g + e], e = 0..7, at w2f[(4nb + t) 64 + lane]
+    __shared__ half8 w2f[8 * 4 * WAVE];
+    for (int idx = tid; idx < 8 * 4 * WAVE; idx += blockDim.x) {
+        const int f = idx / WAVE, ln = idx % WAVE;
+        const int nb = f >> 2, t = f & 3;
+        const float* row = w + OW2 + (16 * nb + (ln & 15)) * HID + 32 * t + 8 * (ln >> 4);
+        const float4 lo = *reinterpret_cast<const float4*>(row), hi = *reinterpret_cast<const float4*>(row + 4);
+        w2f[idx] = half8{(_Float16)lo.x, (_Float16)lo.y, (_Float16)lo.z, (_Float16)lo.w,
+                         (_Float16)hi.x, (_Float16)hi.y, (_Float16)hi.z, (_Float16)hi.w};
+    }
     const float b3 = w[OB3];
     __syncthreads();
 
@@ -91,6 +93,7 @@ __global__ void __launch_bounds__(256) mlp_infer_kernel(const float* __restrict_
     for (int64_t grp = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (tid >> 6); grp < ngrp; grp += nwaves) {
         const int64_t s = grp * 16 + s16;
         const float xb = s < S ? X[s * NIN + g] : 0.f;  // layer-1 B operand: feature g of state s16
+        asm volatile("" ::: "memory");  // W2 fragments are read from LDS each step, not hoisted into registers
         f32x4 d2[8];
 #pragma unroll
         for (int nb = 0; nb < 8; ++nb) d2[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -102,7 +105,8 @@ __global__ void __launch_bounds__(256) mlp_infer_kernel(const float* __restrict_
                               (_Float16)fmaxf(h0[3], 0.f), (_Float16)fmaxf(h1[0], 0.f), (_Float16)fmaxf(h1[1], 0.f),
                               (_Float16)fmaxf(h1[2], 0.f), (_Float16)fmaxf(h1[3], 0.f)};
 #pragma unroll
-            for (int nb = 0; nb < 8; ++nb) d2[nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a2[nb][t], bk, d2[nb], 0, 0, 0);
+            for (int nb = 0; nb < 8; ++nb)
+                d2[nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w2f[(4 * nb + t) * WAVE + lane], bk, d2[nb], 0, 0, 0);
         }
         // lane (g, s16) holds units 16nb + 4g + r of state s16
         float part = 0.f;
@@ -140,7 +144,7 @@ static int mlp_infer_grid(int64_t S)
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int64_t want = ((S + 15) / 16 + 3) / 4;
-    const int64_t cap = 2 * (int64_t)(cus > 0 ? cus : 256);
+    const int64_t cap = 4 * (int64_t)(cus > 0 ? cus : 256);
     return (int)(want < cap ? want : cap);
 }
 
