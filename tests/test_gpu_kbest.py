@@ -50,6 +50,30 @@ def test_qr_parity(gpu, orc, N, M, q, B):
         assert np.all(Rg[:, off + 1] == 0.0)
 
 
+@pytest.mark.parametrize("M", [2, 3, 7, 15, 31, 47, 64, 72, 73, 96, 97, 104, 107, 111, 127])
+def test_qr_parity_sizes(gpu, orc, M):
+    """Sizes across the kernel's launch shapes: one frame per workgroup (up to
+    3 and from 7 waves), two per workgroup (4 to 6 waves, an odd batch leaves
+    the second half of the last workgroup idle), the compile-time tile-row
+    counts (M = 64) and the generic ones, and the step from which the last
+    wave runs the Cholesky alone; N > M on every other size."""
+    N = min(128, M + (M % 2) * 3)
+    B = 3
+    f = gen_frames(N, M, 16, 15.0, B, seed=1500 + M)
+    H, y, _ = _dev(f)
+    R, z, resid = gpu.qr_preprocess(H, y, want_resid=True)
+    Ro, zo, reso = orc.qr(f.H, f.y)
+    n = 2 * M
+    u = 2.0 ** -24
+    hn = np.sqrt((np.abs(f.H.astype(np.complex128)) ** 2).sum(axis=(1, 2)) * 2)
+    yn = np.sqrt((np.abs(f.y.astype(np.complex128)) ** 2).sum(axis=1))
+    err_R = np.sqrt(((_np(R) - pack_level_order(Ro)) ** 2).sum(axis=1))
+    err_z = np.sqrt(((_np(z) - zo) ** 2).sum(axis=1))
+    assert np.all(err_R <= 8 * n * u * hn), f"{N}x{M}"
+    assert np.all(err_z <= 8 * n * u * (yn + hn)), f"{N}x{M}"
+    assert np.all(np.abs(_np(resid) - reso) <= 8 * n * u * yn ** 2 + 1e-6), f"{N}x{M}"
+
+
 # ----------------------------------------------------------------- K-best
 def _kbest_case(gpu, orc, N, M, q, snr, B, K, seed, radius=None, sched=None):
     import torch
