@@ -285,6 +285,43 @@ def test_kbest_fallback(gpu, orc):
     compare_symbols(_np(sym)[redo], orc.x_to_sym(kb["x"], P), kb["margin"], near_tie_tol(n), "fallback")
 
 
+@pytest.mark.parametrize("M,snr,B,K", [(16, 14.0, 200, 64), (16, 10.0, 120, 40), (40, 18.0, 60, 64),
+                                       (100, 22.0, 8, 64)])
+def test_kbest_fallback_64qam(gpu, orc, M, snr, B, K):
+    """64-QAM fallback with 33..64 survivors (the learned detector's case):
+    the re-detected frames equal the oracle's K-best (up to near ties) and
+    plain K-best's result on the same frames, with the same expanded-node
+    counts; the other frames keep their first detection."""
+    import torch
+
+    q, P, n = 64, 8, 2 * M
+    f = gen_frames(M, M, q, snr, B, seed=2800 + M + K)
+    H, y, _ = _dev(f)
+    R, z = gpu.qr_preprocess(H, y)
+    sym, pd, flags = gpu.kbest_detect(R, z, M, P, 1)
+    flags[::2] |= gpu.FLAG_LEARNED_FALLBACK  # half the frames forced
+    first_flags = _np(flags).copy()
+    first_sym = _np(sym).copy()
+    s2 = torch.full((B,), f.sigma2, device="cuda", dtype=torch.float32)
+    ctr = torch.zeros(B, 4, device="cuda", dtype=torch.int64)
+    print(f"fallback {M}x{M} 64-QAM K={K} B={B}", flush=True)
+    gpu.kbest_fallback(R, z, M, P, K, s2, 3.0, (sym, pd, flags), counters=ctr)
+    redo = (_np(flags) & gpu.FLAG_LEARNED_FALLBACK) != 0
+    assert np.all(redo[::2])
+    assert np.array_equal(_np(sym)[~redo], first_sym[~redo])
+    # the one-wave K-best on the same frames
+    s1, p1, f1, c1 = gpu.kbest_detect(R, z, M, P, K, want_counters=True)
+    Ro, zo, _ = orc.qr(f.H, f.y)
+    kb = orc.kbest(Ro[redo], zo[redo], P, K)
+    tol = near_tie_tol(n)
+    compare_symbols(_np(sym)[redo], orc.x_to_sym(kb["x"], P), kb["margin"], tol, "multiwave fallback")
+    clean = kb["margin"][:, 0] > tol
+    assert np.array_equal(_np(ctr)[redo][clean, :2], kb["counters"][clean, :2])
+    assert np.array_equal(_np(sym)[redo][clean], _np(s1)[redo][clean])
+    assert np.allclose(_np(pd)[redo][clean], _np(p1)[redo][clean], rtol=5e-5)
+    assert np.all((_np(flags)[redo] & gpu.FLAG_FOUND) != 0)
+
+
 def test_fallback_mark_and_metric_select(gpu):
     """kbest_fallback_mark flags exactly the frames kbest_fallback detects
     again (and changes nothing else); mimo_metric_select writes the metric of
