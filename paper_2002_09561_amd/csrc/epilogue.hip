@@ -16,7 +16,9 @@ __device__ __forceinline__ double xor_lanes_f64(double v, int m, int lane)
 }
 
 // One wave per frame, four rows of H at a time: the 16 lanes of a row group
-// run along the row (coalesced 128-byte segments, up to 8 columns per lane),
+// run along the row, two adjacent columns per 16-byte load (coalesced
+// 256-byte segments; with an odd n_tx the rows are not 16-byte aligned and
+// the columns are loaded one by one), up to 8 columns per lane,
 // the row's residual y_i - sum_j h_ij s_j is reduced over those 16 lanes in
 // FP64 in a fixed order (DPP exchanges only), and each group accumulates
 // |residual|^2 over its rows; the four group sums are added at the end.
@@ -30,11 +32,13 @@ __global__ void __launch_bounds__(256) metric_kernel(const float2* __restrict__ 
     const int f = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x >> 6);
     if (f >= B) return;
     if (flags && (flags[f] & mask) != value) return;  // frame not selected (uniform per wave)
-    constexpr int CPL = (MIMO_MAX_TX + 15) / 16;  // columns per lane
-    double sr[CPL], si[CPL];
+    // lane l holds columns 2l + 32c and 2l + 1 + 32c; a row of an even-M frame is 16-byte aligned
+    constexpr int CPL = (MIMO_MAX_TX + 31) / 32;
+    const bool v4 = (M & 1) == 0;
+    double sr[2 * CPL], si[2 * CPL];
 #pragma unroll
-    for (int c = 0; c < CPL; ++c) {
-        const int j = l + 16 * c;
+    for (int c = 0; c < 2 * CPL; ++c) {
+        const int j = 2 * l + 32 * (c >> 1) + (c & 1);
         sr[c] = si[c] = 0.0;
         if (j < M) {
             const int q = sym[(size_t)f * M + j];
@@ -52,11 +56,21 @@ __global__ void __launch_bounds__(256) metric_kernel(const float2* __restrict__ 
             const int i = i0 + 4 * u + g;
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
-                const int j = l + 16 * c;
-                if (j < M && i < N) {
-                    const float2 h = Hf[(size_t)i * M + j];
-                    pr[u] += (double)h.x * sr[c] - (double)h.y * si[c];
-                    pi[u] += (double)h.x * si[c] + (double)h.y * sr[c];
+                const int j = 2 * l + 32 * c;
+                if (i < N && j < M) {
+                    float2 h0, h1;
+                    if (v4) {
+                        const float4 hh = *reinterpret_cast<const float4*>(Hf + (size_t)i * M + j);
+                        h0 = make_float2(hh.x, hh.y);
+                        h1 = make_float2(hh.z, hh.w);
+                    } else {
+                        h0 = Hf[(size_t)i * M + j];
+                        h1 = j + 1 < M ? Hf[(size_t)i * M + j + 1] : make_float2(0.f, 0.f);
+                    }
+                    pr[u] += (double)h0.x * sr[2 * c] - (double)h0.y * si[2 * c];
+                    pi[u] += (double)h0.x * si[2 * c] + (double)h0.y * sr[2 * c];
+                    pr[u] += (double)h1.x * sr[2 * c + 1] - (double)h1.y * si[2 * c + 1];
+                    pi[u] += (double)h1.x * si[2 * c + 1] + (double)h1.y * sr[2 * c + 1];
                 }
             }
         }

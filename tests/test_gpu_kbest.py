@@ -74,6 +74,25 @@ def test_qr_parity_sizes(gpu, orc, M):
     assert np.all(np.abs(_np(resid) - reso) <= 8 * n * u * yn ** 2 + 1e-6), f"{N}x{M}"
 
 
+@pytest.mark.parametrize("N,M,q", [(1, 1, 4), (3, 3, 16), (6, 5, 64), (7, 7, 4), (13, 12, 16), (33, 33, 64),
+                                   (100, 100, 64), (128, 127, 16), (40, 8, 64)])
+def test_metric_parity_sizes(gpu, orc, N, M, q):
+    """FP64 metric ||y - H s||^2 of random symbols: even n_tx takes the
+    16-byte loads (two columns), odd n_tx the single-column path; n_rx > n_tx
+    and rows not a multiple of the row groups."""
+    import torch
+
+    B = 7
+    f = gen_frames(N, M, q, 12.0, B, seed=1600 + N + M)
+    H, y, _ = _dev(f)
+    rng = np.random.default_rng(N * 1000 + M)
+    s = rng.integers(0, q, (B, M)).astype(np.int32)
+    P = math.isqrt(q)
+    m_gpu = _np(gpu.metric(H, y, torch.from_numpy(s).cuda(), P))
+    m_orc = orc.metric(f.H, f.y, s, q)
+    assert np.allclose(m_gpu, m_orc, rtol=1e-10, atol=1e-12), f"{N}x{M}"
+
+
 # ----------------------------------------------------------------- K-best
 def _kbest_case(gpu, orc, N, M, q, snr, B, K, seed, radius=None, sched=None):
     import torch
