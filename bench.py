@@ -392,6 +392,8 @@ def main():
         from paper_2002_09561_amd.graph import CapturedStep
 
         g = CapturedStep(lambda: (o["counts"].zero_(), step(det, False)))
+        for _ in range(args.warmup):  # untimed replays, as the eager steps' warmup
+            g.replay()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
