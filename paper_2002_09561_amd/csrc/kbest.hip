@@ -657,6 +657,7 @@ __device__ __forceinline__ void kbest_frame_reg(const KbestArgs& a, int frame, u
     using S = KbestShape<P, E>;
     constexpr int KCAP = S::KCAP, L = S::L;
     static_assert(KCAP <= 64, "register variant holds at most one survivor per lane");
+    static_assert(NWMAX % L == 0, "a survivor's lanes share its path capacity evenly");
     constexpr int NWL = NWMAX / L;  // path words per lane
     constexpr int CHW = NWL < 8 ? NWL : 8;  // words per guarded chunk
     const int lane = threadIdx.x & 63;
@@ -731,7 +732,7 @@ __device__ __forceinline__ void kbest_frame_reg(const KbestArgs& a, int frame, u
         for (int c0 = 0; c0 < NWL; c0 += CHW) {
             if (c0 + CHW > i_lo && c0 < i_hi) {
 #pragma unroll
-                for (int i = c0; i < c0 + CHW; ++i) {
+                for (int i = c0; i < c0 + CHW && i < NWL; ++i) {
                     const float2 rr = *reinterpret_cast<const float2*>(rrow + 2 * (q + L * i));
                     if (i & 1) {
                         a2 = fmaf(rr.x, half_lo(pw[i]), a2);
@@ -810,7 +811,7 @@ __device__ __forceinline__ void kbest_frame_reg(const KbestArgs& a, int frame, u
         for (int c0 = 0; c0 < NWL; c0 += CHW) {
             if (c0 + CHW > ik && c0 < i_hi) {
 #pragma unroll
-                for (int i = c0; i < c0 + CHW; ++i) pw[i] = (uint32_t)__shfl((int)pw[i], src, WAVE);
+                for (int i = c0; i < c0 + CHW && i < NWL; ++i) pw[i] = (uint32_t)__shfl((int)pw[i], src, WAVE);
             }
         }
         if (s_own < keep && q == wk % L) {
@@ -820,7 +821,7 @@ __device__ __forceinline__ void kbest_frame_reg(const KbestArgs& a, int frame, u
             for (int c0 = 0; c0 < NWL; c0 += CHW) {
                 if (ik >= c0 && ik < c0 + CHW) {
 #pragma unroll
-                    for (int i = c0; i < c0 + CHW; ++i)
+                    for (int i = c0; i < c0 + CHW && i < NWL; ++i)
                         if (i == ik)
                             pw[i] = (k & 1) ? ((pw[i] & 0x0000ffffu) | (hb << 16)) : ((pw[i] & 0xffff0000u) | hb);
                 }
@@ -1134,8 +1135,13 @@ template <int P, int E>
 static int32_t launch_kbest_reg(const KbestArgs& a, int B, hipStream_t st)
 {
     using S = KbestShape<P, E>;
+    // path capacity (words) by frame size: the lanes of a survivor sum and move
+    // whole chunks of words, so a capacity close to n / 2 wastes the least
     if (a.n <= 64) {
         hipLaunchKernelGGL((kbest_reg_kernel<P, E, 32>), dim3(B), dim3(WAVE), kbest_reg_lds_bytes<32>(S::KCAP), st, a);
+    } else if (a.n <= 208) {
+        hipLaunchKernelGGL((kbest_reg_kernel<P, E, 104>), dim3(B), dim3(WAVE), kbest_reg_lds_bytes<104>(S::KCAP), st,
+                           a);
     } else {
         hipLaunchKernelGGL((kbest_reg_kernel<P, E, 128>), dim3(B), dim3(WAVE), kbest_reg_lds_bytes<128>(S::KCAP), st,
                            a);
