@@ -134,17 +134,17 @@ __global__ void __launch_bounds__(256) errors_kernel(const int32_t* __restrict__
 // Four frames per wave, 16 lanes per frame: lane l of a frame holds the
 // decided amplitudes x_j of the levels j = l + 16 i in registers and loads
 // the matching entries R_kj of each row (coalesced 64-byte segments), so the
-// centre is 16 register FMAs and a 16-lane reduction (DPP); the R rows of the
-// next two levels are loaded while the current one is used.
-constexpr int FEAT_SLOTS = 16;  // levels per lane: n <= 256
-
+// centre is SL register FMAs and a 16-lane reduction (DPP); the R rows of the
+// next two levels are loaded while the current one is used.  SL levels per
+// lane (16 SL >= n): 13 for up to 208 levels, else 16.
+template <int SL>
 __device__ __forceinline__ void feat_load(const float* __restrict__ Rf, const float* __restrict__ zf, int n, int k,
-                                          int l, float (&r)[FEAT_SLOTS], float& rkk, float& zk)
+                                          int l, float (&r)[SL], float& rkk, float& zk)
 {
     if (k < 0) return;
     const float* rk = Rf + r_row_off(n, k);  // rk[j - k] = R_kj
 #pragma unroll
-    for (int i = 0; i < FEAT_SLOTS; ++i) {
+    for (int i = 0; i < SL; ++i) {
         const int jj = l + 16 * i;
         r[i] = (jj > k && jj < n) ? rk[jj - k] : 0.f;
     }
@@ -152,13 +152,14 @@ __device__ __forceinline__ void feat_load(const float* __restrict__ Rf, const fl
     zk = zf[k];
 }
 
+template <int SL>
 __device__ __forceinline__ void feat_level(int k, int n, int P, float c, float rc, float lc, float rs2, int lane,
-                                           const float (&r)[FEAT_SLOTS], float rkk, float zk,
-                                           float (&xr)[FEAT_SLOTS], float& pd, float* __restrict__ featf, bool live)
+                                           const float (&r)[SL], float rkk, float zk,
+                                           float (&xr)[SL], float& pd, float* __restrict__ featf, bool live)
 {
     float acc = 0.f;
 #pragma unroll
-    for (int i = 0; i < FEAT_SLOTS; ++i) acc = fmaf(r[i], xr[i], acc);
+    for (int i = 0; i < SL; ++i) acc = fmaf(r[i], xr[i], acc);
 #pragma unroll
     for (int m = 8; m >= 1; m >>= 1) acc += shfl_xor_f(acc, m);
     const float b = zk - acc;
@@ -178,10 +179,11 @@ __device__ __forceinline__ void feat_level(int k, int n, int P, float c, float r
     // level k's decision goes to lane k mod 16, slot k / 16 (uniform index)
     const int slot = k >> 4;
 #pragma unroll
-    for (int q = 0; q < FEAT_SLOTS; ++q)
+    for (int q = 0; q < SL; ++q)
         if (q == slot && l == (k & 15)) xr[q] = a;
 }
 
+template <int SL>
 __global__ void __launch_bounds__(256) features_kernel(const float* __restrict__ R, const float* __restrict__ z,
                                                        const float* __restrict__ sigma2, int B, int n, int P,
                                                        float* __restrict__ feat)
@@ -199,27 +201,27 @@ __global__ void __launch_bounds__(256) features_kernel(const float* __restrict__
     const float lc = log2f(2.f * c / sqrtf(s2r));
     const float rs2 = 1.f / s2r;
     const float rc = 1.f / c;
-    float xr[FEAT_SLOTS];
+    float xr[SL];
 #pragma unroll
-    for (int i = 0; i < FEAT_SLOTS; ++i) xr[i] = 0.f;
+    for (int i = 0; i < SL; ++i) xr[i] = 0.f;
     float pd = 0.f;
-    float ra[FEAT_SLOTS], rb[FEAT_SLOTS], rka = 0.f, rkb = 0.f, za = 0.f, zb = 0.f;
-    feat_load(Rf, zf, n, n - 1, l, ra, rka, za);
-    feat_load(Rf, zf, n, n - 2, l, rb, rkb, zb);
+    float ra[SL], rb[SL], rka = 0.f, rkb = 0.f, za = 0.f, zb = 0.f;
+    feat_load<SL>(Rf, zf, n, n - 1, l, ra, rka, za);
+    feat_load<SL>(Rf, zf, n, n - 2, l, rb, rkb, zb);
     // n = 2 n_tx is even: levels go in pairs (k, k-1) from buffers a and b
     for (int k = n - 1; k >= 1; k -= 2) {
-        float rcur[FEAT_SLOTS];
+        float rcur[SL];
 #pragma unroll
-        for (int i = 0; i < FEAT_SLOTS; ++i) rcur[i] = ra[i];
+        for (int i = 0; i < SL; ++i) rcur[i] = ra[i];
         float rk = rka, zk = za;
-        feat_load(Rf, zf, n, k - 2, l, ra, rka, za);
-        feat_level(k, n, P, c, rc, lc, rs2, lane, rcur, rk, zk, xr, pd, featf, live);
+        feat_load<SL>(Rf, zf, n, k - 2, l, ra, rka, za);
+        feat_level<SL>(k, n, P, c, rc, lc, rs2, lane, rcur, rk, zk, xr, pd, featf, live);
 #pragma unroll
-        for (int i = 0; i < FEAT_SLOTS; ++i) rcur[i] = rb[i];
+        for (int i = 0; i < SL; ++i) rcur[i] = rb[i];
         rk = rkb;
         zk = zb;
-        feat_load(Rf, zf, n, k - 3, l, rb, rkb, zb);
-        feat_level(k - 1, n, P, c, rc, lc, rs2, lane, rcur, rk, zk, xr, pd, featf, live);
+        feat_load<SL>(Rf, zf, n, k - 3, l, rb, rkb, zb);
+        feat_level<SL>(k - 1, n, P, c, rc, lc, rs2, lane, rcur, rk, zk, xr, pd, featf, live);
     }
 }
 
@@ -281,7 +283,11 @@ extern "C" int32_t prune_features(const float* R, const float* z, const float* s
     if (n_tx > MIMO_MAX_TX) return fail(MIMO_ERR_UNSUPPORTED, "prune_features: n_tx > %d", MIMO_MAX_TX);
     if (B == 0) return MIMO_OK;
     if (!R || !z || !sigma2 || !feat) return fail(MIMO_ERR_INVALID_ARG, "prune_features: null pointer");
-    hipLaunchKernelGGL(features_kernel, dim3((B + 15) / 16), dim3(256), 0, (hipStream_t)stream, R, z, sigma2, B,
-                       2 * n_tx, pam, feat);
+    if (2 * n_tx <= 208)
+        hipLaunchKernelGGL(features_kernel<13>, dim3((B + 15) / 16), dim3(256), 0, (hipStream_t)stream, R, z, sigma2,
+                           B, 2 * n_tx, pam, feat);
+    else
+        hipLaunchKernelGGL(features_kernel<16>, dim3((B + 15) / 16), dim3(256), 0, (hipStream_t)stream, R, z, sigma2,
+                           B, 2 * n_tx, pam, feat);
     return check_launch("prune_features");
 }
