@@ -1131,6 +1131,252 @@ __global__ void __launch_bounds__(64) kbest_reg_kernel(KbestArgs a)
     kbest_frame_reg<P, E, NWMAX>(a, blockIdx.x, smem_kbr);
 }
 
+// K-best with at most 8 survivors and P = 8 (at most 64 candidates per
+// level), two frames per wavefront: the learned detector's case, where most
+// levels have at most four survivors, so that one frame's candidates fill
+// half a wave and a 32-lane sort.  Lanes 32h .. 32h+31 hold frame 2b+h:
+// four lanes per survivor (path words q + 4i in registers), one or two
+// candidates per lane (two while some frame of the pair has more than four
+// survivors), sorted within the half.  Keys and the tie rule are those of
+// the one-frame kernels; a centre is summed over four lanes instead of
+// eight, which can move a pd by an FP32 rounding.
+constexpr int PR_P = 8;
+constexpr int PR_KCAP = 8;                 // survivors per frame
+constexpr int PR_HALF = WAVE / 2;          // lanes per frame
+constexpr int PR_L = PR_HALF / PR_KCAP;    // lanes per survivor
+
+// bitonic sort within each half of the wave, ascending in lane & 31
+__device__ __forceinline__ void pr_sort32(uint64_t& key, int lane)
+{
+    const int h = lane & (PR_HALF - 1);
+#pragma unroll
+    for (int size = 2; size <= PR_HALF; size <<= 1) {
+#pragma unroll
+        for (int j = size >> 1; j > 0; j >>= 1) {
+            const uint64_t o = xor_lanes_u64(key, j, lane);
+            const bool take_max = ((h & size) != 0) != ((h & j) != 0);
+            key = ((o < key) != take_max) ? o : key;
+        }
+    }
+}
+
+// bitonic sort of 64 keys per half, element 32 r + (lane & 31) in key[r]:
+// ascending, so key[0] ends with the 32 smallest
+__device__ __forceinline__ void pr_sort64(uint64_t (&key)[2], int lane)
+{
+    const int h = lane & (PR_HALF - 1);
+#pragma unroll
+    for (int size = 2; size <= 2 * PR_HALF; size <<= 1) {
+#pragma unroll
+        for (int j = size >> 1; j > 0; j >>= 1) {
+            if (j == PR_HALF) {  // elements h and 32 + h sit in one lane (size = 64: ascending)
+                const uint64_t lo = key[1] < key[0] ? key[1] : key[0];
+                const uint64_t hi = key[1] < key[0] ? key[0] : key[1];
+                key[0] = lo;
+                key[1] = hi;
+            } else {
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const int x = PR_HALF * r + h;
+                    const uint64_t o = xor_lanes_u64(key[r], j, lane);
+                    const bool take_max = ((x & size) != 0) != ((x & j) != 0);
+                    key[r] = ((o < key[r]) != take_max) ? o : key[r];
+                }
+            }
+        }
+    }
+}
+
+template <int NWMAX>
+__host__ __device__ inline size_t kbest_pair_lds_bytes()
+{
+    return 2 * sizeof(float) * (3 * PR_KCAP + 2 * NWMAX + 16);  // per frame: pd [2][8], sel [8], R row
+}
+
+template <int NWMAX>
+__global__ void __launch_bounds__(WAVE) kbest_pair_kernel(KbestArgs a, int B)
+{
+    constexpr int P = PR_P, KCAP = PR_KCAP, L = PR_L;
+    constexpr int NWL = NWMAX / L;                     // path words per lane
+    constexpr int CHW = NWL < 8 ? NWL : 8;             // words per guarded chunk
+    constexpr int RPL = (2 * NWMAX + PR_HALF - 1) / PR_HALF;  // row entries per lane (n <= 2 NWMAX)
+    constexpr int HW = 3 * KCAP + 2 * NWMAX + 16;      // LDS words per frame
+    static_assert(NWMAX % L == 0, "a survivor's lanes share its path capacity evenly");
+    extern __shared__ __align__(16) unsigned char smem_kp[];
+    const int lane = threadIdx.x & 63, half = lane / PR_HALF, hl = lane % PR_HALF;
+    const int fr = 2 * (int)blockIdx.x + half;
+    const bool live = fr < B;
+    const int frame = live ? fr : B - 1;  // a half beyond the batch repeats the last frame, storing nothing
+    const int s_own = hl / L, q = hl % L;
+    const int n = a.n, nw = n / 2;
+    float* spd = reinterpret_cast<float*>(smem_kp) + half * HW;  // [2][KCAP] survivor pd by level parity
+    int32_t* sel = reinterpret_cast<int32_t*>(spd + 2 * KCAP);   // [KCAP]
+    float* rrow = spd + 3 * KCAP;                                // [2 NWMAX + 16] staged R row
+
+    const float* Rf = a.R + (size_t)frame * r_packed_size(n);
+    const float* zf = a.z + (size_t)frame * n;
+    const float r2 = a.radius2 ? a.radius2[frame] : INFINITY;
+    const float cs = pam_scale(P);
+    const int32_t* ks = a.k_sched ? a.k_sched + (size_t)frame * a.k_sched_stride : nullptr;
+    const uint64_t hmask = half ? 0xffffffff00000000ull : 0x00000000ffffffffull;
+
+    uint32_t pw[NWL];
+#pragma unroll
+    for (int i = 0; i < NWL; ++i) pw[i] = 0u;  // unassigned levels are amplitude 0
+    for (int t = hl; t < 2 * NWMAX + 16; t += PR_HALF) rrow[t] = 0.f;
+    if (hl == 0) spd[0] = 0.f;
+    int cnt = 1;
+    int64_t expanded = 0;
+    uint32_t flags = 0;
+    const int i_hi = (nw + L - 1) / L;  // words beyond nw read zero row entries
+
+    float rnext[RPL];
+    float rkk_next, zk_next;
+    {
+        const float* rk = Rf + r_row_off(n, n - 1);
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) rnext[i] = (hl + PR_HALF * i < 1) ? rk[hl + PR_HALF * i] : 0.f;
+        rkk_next = rk[0];
+        zk_next = zf[n - 1];
+    }
+    kb_wave_sync();
+
+    for (int k = n - 1; k >= 0; --k) {
+        const int cur = (n - 1 - k) & 1;
+        const float* sc = spd + cur * KCAP;
+        float* sn = spd + (cur ^ 1) * KCAP;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int t = hl + PR_HALF * i;
+            if (t < n - k) rrow[k + t] = t == 0 ? 0.f : cs * rnext[i];
+        }
+        const float rkk = cs * rkk_next;
+        const float zk = zk_next;
+        if (k > 0) {
+            const float* rk = Rf + r_row_off(n, k - 1);
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int t = hl + PR_HALF * i;
+                rnext[i] = t < n - k + 1 ? rk[t] : 0.f;
+            }
+            rkk_next = rk[0];
+            zk_next = zf[k - 1];
+        }
+        kb_wave_sync();
+        // centre of this lane's survivor (levels <= k hold amplitude 0 and rrow[k] = 0)
+        const int i_lo = ((k + 1) >> 1) / L;
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+#pragma unroll
+        for (int c0 = 0; c0 < NWL; c0 += CHW) {
+            if (c0 + CHW > i_lo && c0 < i_hi) {
+#pragma unroll
+                for (int i = c0; i < c0 + CHW && i < NWL; ++i) {
+                    const float2 rr = *reinterpret_cast<const float2*>(rrow + 2 * (q + L * i));
+                    if (i & 1) {
+                        a2 = fmaf(rr.x, half_lo(pw[i]), a2);
+                        a3 = fmaf(rr.y, half_hi(pw[i]), a3);
+                    } else {
+                        a0 = fmaf(rr.x, half_lo(pw[i]), a0);
+                        a1 = fmaf(rr.y, half_hi(pw[i]), a1);
+                    }
+                }
+            }
+        }
+        float acc = (a0 + a1) + (a2 + a3);
+        acc += shfl_xor_f(acc, 1);
+        acc += shfl_xor_f(acc, 2);
+        const float bown = zk - acc;
+        // candidates m = hl (and 32 + hl): child m % P of survivor m / P
+        const int cmax = max(cnt, (int)xor_lanes((uint32_t)cnt, PR_HALF, lane));
+        const bool two = cmax * P > PR_HALF;  // the same in both halves
+        uint64_t key[2] = {~0ull, ~0ull};
+        int nvalid = 0;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            if (e == 1 && !two) break;
+            const int m = PR_HALF * e + hl;
+            const int s = m / P, c = m % P;
+            const float b = shfl_f(bown, PR_HALF * half + s * L);
+            uint32_t kh = ~0u;
+            if (s < cnt) {
+                const float ee = fmaf(-rkk, (float)(2 * c - (P - 1)), b);
+                const float pdc = fmaf(ee, ee, sc[s]);
+                if (pdc < r2) kh = __float_as_uint(pdc);
+            }
+            nvalid += __popcll(__ballot(kh != ~0u) & hmask);
+            key[e] = kh == ~0u ? ~0ull : (((uint64_t)kh << 32) | (uint32_t)m);
+        }
+        expanded += cnt;
+        if (cnt > 0 && nvalid == 0) flags |= MIMO_FLAG_EMPTY_SPHERE;  // this frame ends here
+        int Kt = ks ? ks[k] : a.K;
+        Kt = Kt > a.K ? a.K : (Kt < 1 ? 1 : Kt);
+        const int keep = Kt < nvalid ? Kt : nvalid;
+        if (two) pr_sort64(key, lane);
+        else pr_sort32(key[0], lane);
+        if (hl < keep) {
+            sn[hl] = __uint_as_float((uint32_t)(key[0] >> 32));
+            sel[hl] = (int32_t)(uint32_t)key[0];
+        }
+        kb_wave_sync();
+        // new survivor s_own takes its parent's words (those holding levels >= k)
+        int src = lane, cnew = 0;
+        if (s_own < keep) {
+            const int m = sel[s_own];
+            src = PR_HALF * half + (m / P) * L + q;
+            cnew = m % P;
+        }
+        const int wk = k >> 1, ik = wk / L;
+#pragma unroll
+        for (int c0 = 0; c0 < NWL; c0 += CHW) {
+            if (c0 + CHW > ik && c0 < i_hi) {
+#pragma unroll
+                for (int i = c0; i < c0 + CHW && i < NWL; ++i) pw[i] = (uint32_t)__shfl((int)pw[i], src, WAVE);
+            }
+        }
+        if (s_own < keep && q == wk % L) {
+            const uint32_t hb = half_bits((float)(2 * cnew - (P - 1)));
+#pragma unroll
+            for (int c0 = 0; c0 < NWL; c0 += CHW) {
+                if (ik >= c0 && ik < c0 + CHW) {
+#pragma unroll
+                    for (int i = c0; i < c0 + CHW && i < NWL; ++i)
+                        if (i == ik)
+                            pw[i] = (k & 1) ? ((pw[i] & 0x0000ffffu) | (hb << 16)) : ((pw[i] & 0xffff0000u) | hb);
+                }
+            }
+        }
+        cnt = keep;
+    }
+
+    if (live && hl == 0) {
+        if (cnt > 0) flags |= MIMO_FLAG_FOUND;
+        if (a.flags) a.flags[frame] = flags;
+        if (a.pd) a.pd[frame] = cnt > 0 ? spd[(n & 1) * KCAP] : INFINITY;
+        if (a.counters) {
+            int64_t* c = a.counters + (size_t)frame * 4;
+            c[0] = expanded;
+            c[1] = expanded * P;
+            c[2] = 0;
+            c[3] = 0;
+        }
+    }
+    // survivor 0 (lanes 32h .. 32h+3) is the best leaf; word w holds symbol w
+    if (!live || !a.sym || s_own != 0) return;
+#pragma unroll
+    for (int i = 0; i < NWL; ++i) {
+        const int w = q + L * i;
+        if (w < nw) {
+            int v = 0;
+            if (cnt > 0) {
+                const int ire = ((int)half_lo(pw[i]) + (P - 1)) / 2;
+                const int iim = ((int)half_hi(pw[i]) + (P - 1)) / 2;
+                v = ire * P + iim;
+            }
+            a.sym[(size_t)frame * nw + w] = v;
+        }
+    }
+}
+
 template <int P, int E>
 static int32_t launch_kbest_reg(const KbestArgs& a, int B, hipStream_t st)
 {
@@ -1181,6 +1427,14 @@ template <int P>
 static int32_t dispatch_kbest_p(const KbestArgs& a, int B, hipStream_t st)
 {
     const int need = a.K * P;  // candidates per level
+    if constexpr (P == PR_P) {
+        // at most 8 survivors of 64-QAM, 64 < n <= 208, detection mode: two frames per wavefront
+        if (need <= 64 && a.n > 64 && a.n <= 208 && !a.fb_sigma2 && !a.force_sym) {
+            hipLaunchKernelGGL(kbest_pair_kernel<104>, dim3((B + 1) / 2), dim3(WAVE), kbest_pair_lds_bytes<104>(), st,
+                               a, B);
+            return check_launch("kbest_detect");
+        }
+    }
     if (need <= 64) return launch_kbest_any<P, 1>(a, B, st);
     if (need <= 128) return launch_kbest_any<P, 2>(a, B, st);
     if (need <= 256) return launch_kbest_any<P, 4>(a, B, st);

@@ -200,6 +200,45 @@ def test_kbest_per_frame_schedule(gpu, orc):
     assert np.array_equal(_np(ctr)[:, 0], exp)
 
 
+@pytest.mark.parametrize("M,snr,B,K", [(40, 16.0, 101, 8), (100, 24.0, 13, 6), (33, 14.0, 64, 3), (104, 26.0, 5, 8)])
+def test_kbest_two_frames_per_wave(gpu, orc, M, snr, B, K):
+    """64-QAM with at most 8 survivors and 64 < n <= 208 runs two frames per
+    wavefront (the learned detector's case): parity with the oracle under a
+    per-frame schedule, expanded-node counts, and an odd batch whose last
+    wavefront has an idle half."""
+    rng = np.random.default_rng(M + K)
+    n = 2 * M
+    sched = rng.integers(1, K + 1, size=(B, n)).astype(np.int32)
+    f, P, n, out, (sym, pd, flags, ctr), _ = _kbest_case(gpu, orc, M, M, 64, snr, B, K, seed=2350 + M, sched=sched)
+    tol = near_tie_tol(n)
+    compare_symbols(_np(sym), orc.x_to_sym(out["x"], P), out["margin"], tol, f"two frames per wave {M}x{M}")
+    clean = out["margin"][:, 0] > tol
+    assert np.array_equal(_np(ctr)[clean, :2], out["counters"][clean, :2])
+    assert np.allclose(_np(pd)[clean], out["pd"][clean], rtol=5e-5)
+    assert np.all((_np(flags) & gpu.FLAG_FOUND) != 0)
+
+
+def test_kbest_two_frames_per_wave_radius(gpu, orc):
+    """Per-frame radius on the two-frames-per-wave kernel: a frame whose
+    sphere empties ends there (EMPTY_SPHERE) while its partner goes on."""
+    M, B, K = 40, 61, 4
+    f = gen_frames(M, M, 64, 16.0, B, seed=2400)
+    Ro, zo, _ = orc.qr(f.H, f.y)
+    ref = orc.kbest(Ro, zo, 8, K)
+    rng = np.random.default_rng(7)
+    radius = ref["pd"] * rng.uniform(0.3, 1.6, size=B)  # some spheres hold no K-best leaf
+    f2, P, n, out, (sym, pd, flags, ctr), _ = _kbest_case(gpu, orc, M, M, 64, 16.0, B, K, seed=2400, radius=radius)
+    fl = _np(flags)
+    empty_o = (out["flags"] & 2) != 0
+    empty_g = (fl & 2) != 0
+    near = out["margin"][:, 0] <= near_tie_tol(n)
+    assert np.all((empty_o == empty_g) | near)
+    assert empty_o.any() and (~empty_o).any()
+    ok = ~empty_o & ~empty_g
+    compare_symbols(_np(sym)[ok], orc.x_to_sym(out["x"], P)[ok], out["margin"][ok], near_tie_tol(n), "pair radius")
+    assert np.all(np.isinf(_np(pd)[empty_g]))
+
+
 @pytest.mark.parametrize("K", [16, 64, 3])
 def test_rank_labels_parity(gpu, orc, K):
     import torch
