@@ -214,11 +214,15 @@ __device__ __forceinline__ void cholqr_frame(const float2* __restrict__ Hf, cons
     cd* ach64 = reinterpret_cast<cd*>(diag + CP + CQ_T);          // [2][rch][4][nb] complex double
     float2* ach32 = reinterpret_cast<float2*>(ach64 + 2 * rch * CP);  // [2][rch][4][nb] complex float
 
-    // tile (I, J), I <= J, enumerated row by row
-    const bool has_tile = tid < sh.ntiles;
+    // tile (I, J), I <= J, enumerated row by row from thread `toff` on: the
+    // idle lanes of the frame's last wave move to its first, so that the
+    // last wave holds as many of the trailing tile rows as fit (see step 2)
+    const int tpf = cq_threads(M);       // the frame's threads, whole waves
+    const int toff = tpf - sh.ntiles;    // threads before the first tile
+    const bool has_tile = tid >= toff && tid < tpf;
     int I = 0, J = 0;
     if (has_tile) {
-        int rem = tid;
+        int rem = tid - toff;
         while (rem >= sh.nb - I) {
             rem -= sh.nb - I;
             ++I;
@@ -303,11 +307,11 @@ __device__ __forceinline__ void cholqr_frame(const float2* __restrict__ Hf, cons
     //         are numbered row by row), that wave runs the remaining steps
     //         alone, without workgroup barriers, and the other waves go on
     //         to the output: their rows and pivots are final by then.
-    const int last0 = (sh.ntiles - 1) / WAVE * WAVE;  // first tile of the last wave
+    const int last0 = tpf - WAVE - toff > 0 ? tpf - WAVE - toff : 0;  // first tile of the last wave
     int Iw = 0;  // first tile row starting at or after last0 (tile (I, I) is number I nb - I (I - 1) / 2)
     while (Iw * nb - Iw * (Iw - 1) / 2 < last0) ++Iw;
     const int k1 = min(M, CQ_T * Iw);
-    const bool tail = tid >= last0;  // this thread's wave runs the steps k >= k1
+    const bool tail = tid >= tpf - WAVE;  // this thread's wave runs the steps k >= k1
     double* rinv = diag + CP;        // [2] reciprocal pivots of the published rows
     if (has_tile && I == 0) cq_store_row<0>(rowbuf, rinv, diag, nb, I, J, gr, gi);
     for (int kb = 0; kb < M; kb += CQ_T) {
