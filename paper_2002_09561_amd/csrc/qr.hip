@@ -113,27 +113,35 @@ __device__ __forceinline__ int cq_lds_slot(int e, int CP, int nb, float rcp_cp)
     return row * CP + q * nb + J;
 }
 
-// 1 / d for d > 0 (else 0): hardware reciprocal refined by two Newton steps
+// 1 / d for d of at least the smallest normal double (else 0, so the result
+// is always finite): hardware reciprocal refined by two Newton steps
 __device__ __forceinline__ double cq_inv(double d)
 {
     double inv = __builtin_amdgcn_rcp(d);
     inv = fma(inv, fma(-d, inv, 1.0), inv);
     inv = fma(inv, fma(-d, inv, 1.0), inv);
-    return d > 0.0 ? inv : 0.0;
+    return d >= 2.2250738585072014e-308 ? inv : 0.0;
 }
 
 // publish register row LR of the tile (a compile-time index keeps the tile
 // in registers).  A published row is stored in planes: column j = 4J + q at
 // [q][J], so the lanes of a wave, which hold consecutive J, read 16-byte
-// neighbours (no LDS bank conflicts).  The owner of the diagonal entry also
-// publishes its reciprocal, which every thread of the next step needs, and
-// records the pivot for the output.
+// neighbours (no LDS bank conflicts).  In the diagonal tile the entries up to
+// and including the pivot are published as zeros: a reader scales the entry
+// in its own row's column, so the rows that are already final (up to the
+// pivot row) get a zero update without a per-row mask, and the entries left
+// of the diagonal, which no output reads, are not updated.  The owner of the
+// diagonal entry also publishes its reciprocal, which every thread of the next
+// step needs, and records the pivot for the output.
 template <int LR>
 __device__ __forceinline__ void cq_store_row(cd* row, double* rinv, double* pivot, int nb, int I, int J,
                                              const double (&gr)[CQ_T][CQ_T], const double (&gi)[CQ_T][CQ_T])
 {
 #pragma unroll
-    for (int c = 0; c < CQ_T; ++c) row[c * nb + J] = {gr[LR][c], gi[LR][c]};
+    for (int c = 0; c < CQ_T; ++c) {
+        const bool z = J == I && c <= LR;
+        row[c * nb + J] = {z ? 0.0 : gr[LR][c], z ? 0.0 : gi[LR][c]};
+    }
     if (J == I) {
         *rinv = cq_inv(gr[LR][LR]);
         *pivot = gr[LR][LR];
@@ -174,10 +182,9 @@ __device__ __forceinline__ void cq_step(int k, int M, int nb_, bool wg, bool has
         double ur[CQ_T], ui[CQ_T], vr[CQ_T], vi[CQ_T];
 #pragma unroll
         for (int r = 0; r < CQ_T; ++r) {
-            const cd a = rk[r * nb + I];
-            const bool below = i0 + r > k;  // rows <= k are final
-            ur[r] = below ? a.x * inv : 0.0;
-            ui[r] = below ? -a.y * inv : 0.0;
+            const cd a = rk[r * nb + I];  // 0 for the final rows <= k
+            ur[r] = a.x * inv;
+            ui[r] = -a.y * inv;
             const cd b = rk[r * nb + J];
             vr[r] = b.x;
             vi[r] = b.y;
