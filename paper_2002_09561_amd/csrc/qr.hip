@@ -40,6 +40,9 @@ constexpr int CQ_RCH_MAX = 16;  // rows of [H | y] per LDS chunk, at most
 constexpr int CQ_PF = 4;        // chunk elements a thread stages, at most
 constexpr int CQ_MAX_THREADS = 576;  // 33 x 34 / 2 = 561 tiles at n_tx = 128
 constexpr int CQ_MAX_WG = 768;       // two frames of up to 6 waves per workgroup
+// pivots below the smallest normal double count as zero: their row of R is 0
+// and the Cholesky update skips them, so R stays finite for singular H
+constexpr double CQ_PIVOT_MIN = 2.2250738585072014e-308;
 
 struct CqShape {
     int C;       // M + 1 columns of [H | y]
@@ -113,14 +116,14 @@ __device__ __forceinline__ int cq_lds_slot(int e, int CP, int nb, float rcp_cp)
     return row * CP + q * nb + J;
 }
 
-// 1 / d for d of at least the smallest normal double (else 0, so the result
+// 1 / d for d >= CQ_PIVOT_MIN (else 0, so the result
 // is always finite): hardware reciprocal refined by two Newton steps
 __device__ __forceinline__ double cq_inv(double d)
 {
     double inv = __builtin_amdgcn_rcp(d);
     inv = fma(inv, fma(-d, inv, 1.0), inv);
     inv = fma(inv, fma(-d, inv, 1.0), inv);
-    return d >= 2.2250738585072014e-308 ? inv : 0.0;
+    return d >= CQ_PIVOT_MIN ? inv : 0.0;
 }
 
 // publish register row LR of the tile (a compile-time index keeps the tile
@@ -337,8 +340,9 @@ __device__ __forceinline__ void cholqr_frame(const float2* __restrict__ Hf, cons
             const int i = i0 + r;
             if (i >= M) continue;
             const double d = diag[i];
-            const double s = d > 0.0 ? sqrt(d) : 0.0;
-            const double is = d > 0.0 ? 1.0 / s : 0.0;
+            const bool pos = d >= CQ_PIVOT_MIN;
+            const double s = pos ? sqrt(d) : 0.0;
+            const double is = pos ? 1.0 / s : 0.0;
             float* row_re = Rf + r_row_off(n, 2 * i);
             float* row_im = Rf + r_row_off(n, 2 * i + 1);
 #pragma unroll

@@ -74,6 +74,75 @@ def test_qr_parity_sizes(gpu, orc, M):
     assert np.all(np.abs(_np(resid) - reso) <= 8 * n * u * yn ** 2 + 1e-6), f"{N}x{M}"
 
 
+def _unpack_level_order(Rp, n):
+    """Packed level order [B, n(n+1)/2] -> full upper-triangular [B, n, n]."""
+    R = np.zeros((Rp.shape[0], n, n))
+    off = 0
+    for k in range(n - 1, -1, -1):
+        R[:, k, k:] = Rp[:, off: off + n - k]
+        off += n - k
+    return R
+
+
+def _real_embedding(H):
+    """Complex [B, N, M] -> real [B, 2N, 2M] with 2x2 blocks [[a, -b], [b, a]]
+    (entry j of s at real indices 2j, 2j + 1, as in the level order)."""
+    B, N, M = H.shape
+    Hr = np.zeros((B, 2 * N, 2 * M))
+    Hr[:, 0::2, 0::2] = H.real
+    Hr[:, 0::2, 1::2] = -H.imag
+    Hr[:, 1::2, 0::2] = H.imag
+    Hr[:, 1::2, 1::2] = H.real
+    return Hr
+
+
+@pytest.mark.parametrize("N,M", [(16, 16), (100, 100)])
+def test_qr_rank_deficient(gpu, orc, N, M):
+    """Channels with a zero column (at a tile edge, inside a tile, the last
+    one) or two equal columns.  The factor is then not unique, so what is
+    checked is what every valid one satisfies: R^T R = H^T H and R^T z = H^T y
+    for the real model, rho^2 = ||y||^2 - ||z||^2 >= 0, all finite, and a zero
+    column gives an exactly zero row and column of R.  The healthy first frame
+    pins the real embedding against the oracle's factor."""
+    B = 5
+    f = gen_frames(N, M, 64, 20.0, B, seed=1700 + M)
+    H = f.H.copy()
+    zero_cols = {1: 4, 2: 6, 3: M - 1}  # frame -> zeroed column
+    for b, j in zero_cols.items():
+        H[b, :, j] = 0
+    H[4, :, M // 2] = H[4, :, 1]
+    import torch
+
+    R, z, resid = gpu.qr_preprocess(torch.from_numpy(H).cuda(), torch.from_numpy(f.y).cuda(), want_resid=True)
+    n = 2 * M
+    Rf = _unpack_level_order(_np(R).astype(np.float64), n)
+    zf = _np(z).astype(np.float64)
+    rs = _np(resid).astype(np.float64)
+    assert np.all(np.isfinite(Rf)) and np.all(np.isfinite(zf)) and np.all(np.isfinite(rs))
+    Hr = _real_embedding(H.astype(np.complex128))
+    yr = np.zeros((B, 2 * N))
+    yr[:, 0::2] = f.y.real
+    yr[:, 1::2] = f.y.imag
+    u = 2.0 ** -24
+    y2 = (yr ** 2).sum(axis=1)
+    G = np.einsum("bki,bkj->bij", Hr, Hr)
+    Gq = np.einsum("bki,bkj->bij", Rf, Rf)
+    hy = np.einsum("bki,bk->bi", Hr, yr)
+    rz = np.einsum("bki,bk->bi", Rf, zf)
+    d = np.sqrt(np.einsum("bii->bi", G))  # column norms of the real H
+    # per entry: the FP32 rounding of R and z, c n u |h_i| |h_j| (0 for a zero column)
+    for b in range(B):
+        assert np.all(np.abs(Gq[b] - G[b]) <= 4 * n * u * np.outer(d[b], d[b])), b
+        assert np.all(np.abs(rz[b] - hy[b]) <= 4 * n * u * d[b] * np.sqrt(y2[b])), b
+        assert rs[b] >= 0.0 and abs(rs[b] - (y2[b] - (zf[b] ** 2).sum())) <= 16 * n * u * y2[b], b
+    for b, j in zero_cols.items():
+        assert np.all(Rf[b, 2 * j: 2 * j + 2, :] == 0.0) and np.all(Rf[b, :, 2 * j: 2 * j + 2] == 0.0), b
+        assert np.all(zf[b, 2 * j: 2 * j + 2] == 0.0), b
+    # the healthy frame against the oracle's factor (unique there)
+    Ro, zo, _ = orc.qr(f.H[:1], f.y[:1])
+    assert np.max(np.abs(Rf[0] - Ro[0])) <= 8 * n * u * np.sqrt((d[0] ** 2).sum())
+
+
 @pytest.mark.parametrize("N,M,q", [(1, 1, 4), (3, 3, 16), (6, 5, 64), (7, 7, 4), (13, 12, 16), (33, 33, 64),
                                    (100, 100, 64), (128, 127, 16), (40, 8, 64)])
 def test_metric_parity_sizes(gpu, orc, N, M, q):
