@@ -134,21 +134,32 @@ __global__ void __launch_bounds__(256) errors_kernel(const int32_t* __restrict__
 // Four frames per wave, 16 lanes per frame: lane l of a frame holds the
 // decided amplitudes x_j of the levels j = l + 16 i in registers and loads
 // the matching entries R_kj of each row (coalesced 64-byte segments), so the
-// centre is SL register FMAs and a 16-lane reduction (DPP); the R rows of the
-// next two levels are loaded while the current one is used.  SL levels per
-// lane (16 SL >= n): 13 for up to 208 levels, else 16.
+// centre is SL register FMAs and a 16-lane reduction (DPP).  Four row
+// buffers keep the loads of the next three or four levels in flight while
+// the current one is used (the kernel waits on memory latency, not on issue).
+// SL levels per lane (16 SL >= n): 13 for up to 208 levels, else 16.
+//
+// Row k of the frame through a buffer resource that spans the wave's four
+// frames: lane l's slot i holds R_k,l+16i, read at byte offset
+// 4 (fbase + row_off(k) - k + l) + 64 i (the slot's part is the load's
+// immediate offset).  Slots whose levels all lie at or left of the diagonal
+// are not loaded (a uniform branch).  A loaded lane whose level is not in
+// row k (j <= k or j >= n) reads another row or frame of the same buffer, or
+// nothing (an offset outside the buffer reads 0), and a slot not loaded keeps
+// an earlier row's values: either way it meets a zero amplitude in the centre
+// (a level not yet decided, or beyond n), so its product adds nothing.
 template <int SL>
-__device__ __forceinline__ void feat_load(const float* __restrict__ Rf, const float* __restrict__ zf, int n, int k,
-                                          int l, float (&r)[SL], float& rkk, float& zk)
+__device__ __forceinline__ void feat_load(__amdgpu_buffer_rsrc_t rs, int fbase, const float* __restrict__ zf, int n,
+                                          int k, int l, float (&r)[SL], float& rkk, float& zk)
 {
     if (k < 0) return;
-    const float* rk = Rf + r_row_off(n, k);  // rk[j - k] = R_kj
+    const int row = fbase + (int)r_row_off(n, k);  // float index of R_kk in the buffer
+    const int v = 4 * (row - k + l);               // may be negative: then out of range
 #pragma unroll
-    for (int i = 0; i < SL; ++i) {
-        const int jj = l + 16 * i;
-        r[i] = (jj > k && jj < n) ? rk[jj - k] : 0.f;
-    }
-    rkk = rk[0];
+    for (int i = 0; i < SL; ++i)
+        if (16 * i + 15 > k && 16 * i < n)
+            r[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, v + 64 * i, 0, 0));
+    rkk = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, 4 * row, 0, 0));
     zk = zf[k];
 }
 
@@ -178,9 +189,8 @@ __device__ __forceinline__ void feat_level(int k, int n, int P, float c, float r
             make_float4((float)k / (float)n, fabsf(v - nb) * 0.5f, log2f(rkk) + lc, pd * rs2 / (float)(n - k));
     // level k's decision goes to lane k mod 16, slot k / 16 (uniform index)
     const int slot = k >> 4;
-#pragma unroll
-    for (int q = 0; q < SL; ++q)
-        if (q == slot && l == (k & 15)) xr[q] = a;
+    const float cur = xr[slot];
+    xr[slot] = l == (k & 15) ? a : cur;
 }
 
 template <int SL>
@@ -189,11 +199,17 @@ __global__ void __launch_bounds__(256) features_kernel(const float* __restrict__
                                                        float* __restrict__ feat)
 {
     const int lane = threadIdx.x & 63, l = lane & 15;
-    const int fr = (blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x >> 6)) * 4 + (lane >> 4);
-    if ((fr & ~3) >= B) return;  // whole wave beyond the batch
+    const int f0 = __builtin_amdgcn_readfirstlane((blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x >> 6)) * 4);
+    const int fr = f0 + (lane >> 4);
+    if (f0 >= B) return;  // whole wave beyond the batch
     const bool live = fr < B;
     const int f = live ? fr : B - 1;  // a slot beyond the batch repeats the last frame, storing nothing
-    const float* Rf = R + (size_t)f * r_packed_size(n);
+    // the wave's frames f0 .. f0 + 3 (fewer at the end of the batch) as one buffer
+    const int size = (int)r_packed_size(n);
+    const int nf = B - f0 < 4 ? B - f0 : 4;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(R + (size_t)f0 * size), 0, nf * size * (int)sizeof(float), 0x00020000);
+    const int fbase = (f - f0) * size;
     const float* zf = z + (size_t)f * n;
     float* featf = feat + (size_t)f * n * 4;
     const float c = pam_scale(P);
@@ -205,23 +221,30 @@ __global__ void __launch_bounds__(256) features_kernel(const float* __restrict__
 #pragma unroll
     for (int i = 0; i < SL; ++i) xr[i] = 0.f;
     float pd = 0.f;
-    float ra[SL], rb[SL], rka = 0.f, rkb = 0.f, za = 0.f, zb = 0.f;
-    feat_load<SL>(Rf, zf, n, n - 1, l, ra, rka, za);
-    feat_load<SL>(Rf, zf, n, n - 2, l, rb, rkb, zb);
-    // n = 2 n_tx is even: levels go in pairs (k, k-1) from buffers a and b
-    for (int k = n - 1; k >= 1; k -= 2) {
-        float rcur[SL];
+    float ra[SL], rb[SL], rc4[SL], rd[SL];
+    float rka = 0.f, rkb = 0.f, rkc = 0.f, rkd = 0.f, za = 0.f, zb = 0.f, zc = 0.f, zd = 0.f;
 #pragma unroll
-        for (int i = 0; i < SL; ++i) rcur[i] = ra[i];
-        float rk = rka, zk = za;
-        feat_load<SL>(Rf, zf, n, k - 2, l, ra, rka, za);
-        feat_level<SL>(k, n, P, c, rc, lc, rs2, lane, rcur, rk, zk, xr, pd, featf, live);
-#pragma unroll
-        for (int i = 0; i < SL; ++i) rcur[i] = rb[i];
-        rk = rkb;
-        zk = zb;
-        feat_load<SL>(Rf, zf, n, k - 3, l, rb, rkb, zb);
-        feat_level<SL>(k - 1, n, P, c, rc, lc, rs2, lane, rcur, rk, zk, xr, pd, featf, live);
+    for (int i = 0; i < SL; ++i) ra[i] = rb[i] = rc4[i] = rd[i] = 0.f;
+    feat_load<SL>(rs, fbase, zf, n, n - 1, l, ra, rka, za);
+    feat_load<SL>(rs, fbase, zf, n, n - 2, l, rb, rkb, zb);
+    feat_load<SL>(rs, fbase, zf, n, n - 3, l, rc4, rkc, zc);
+    feat_load<SL>(rs, fbase, zf, n, n - 4, l, rd, rkd, zd);
+    // four row buffers: a buffer is refilled four levels ahead as soon as its
+    // level is done; n = 2 n_tx is even, so two levels may remain (in a and b)
+    int k = n - 1;
+    for (; k >= 3; k -= 4) {
+        feat_level<SL>(k, n, P, c, rc, lc, rs2, lane, ra, rka, za, xr, pd, featf, live);
+        feat_load<SL>(rs, fbase, zf, n, k - 4, l, ra, rka, za);
+        feat_level<SL>(k - 1, n, P, c, rc, lc, rs2, lane, rb, rkb, zb, xr, pd, featf, live);
+        feat_load<SL>(rs, fbase, zf, n, k - 5, l, rb, rkb, zb);
+        feat_level<SL>(k - 2, n, P, c, rc, lc, rs2, lane, rc4, rkc, zc, xr, pd, featf, live);
+        feat_load<SL>(rs, fbase, zf, n, k - 6, l, rc4, rkc, zc);
+        feat_level<SL>(k - 3, n, P, c, rc, lc, rs2, lane, rd, rkd, zd, xr, pd, featf, live);
+        feat_load<SL>(rs, fbase, zf, n, k - 7, l, rd, rkd, zd);
+    }
+    if (k == 1) {
+        feat_level<SL>(1, n, P, c, rc, lc, rs2, lane, ra, rka, za, xr, pd, featf, live);
+        feat_level<SL>(0, n, P, c, rc, lc, rs2, lane, rb, rkb, zb, xr, pd, featf, live);
     }
 }
 

@@ -343,22 +343,28 @@ def test_error_count_parity(gpu, orc):
         assert c[0] == bits and c[1] == syms and c[2] == int(np.any(hat != ref, axis=1).sum())
 
 
-def test_prune_features_parity(gpu, orc):
+@pytest.mark.parametrize("M,q,B", [(16, 16, 64), (7, 64, 37), (33, 4, 21), (100, 64, 30), (128, 16, 6)])
+def test_prune_features_parity(gpu, orc, M, q, B):
+    """Sizes with n = 2 n_tx a multiple of 4 and not (the kernel's four row
+    buffers then leave two levels), both slot counts (13 up to 208 levels,
+    16 above), and batches that leave the last wave's four frames partly
+    empty."""
     import torch
 
-    B, M, q = 64, 16, 16
-    f = gen_frames(M, M, q, 14.0, B, seed=2500)
+    P = math.isqrt(q)
+    f = gen_frames(M, M, q, 14.0, B, seed=2500 + M)
     Ro, zo, _ = orc.qr(f.H, f.y)
-    fo = orc.prune_features(Ro, zo, 4, f.sigma2)
+    fo = orc.prune_features(Ro, zo, P, f.sigma2)
     H, y, _ = _dev(f)
     R, z = gpu.qr_preprocess(H, y)
     s2 = torch.full((B,), f.sigma2, device="cuda", dtype=torch.float32)
-    fg = _np(gpu.prune_features(R, z, s2, M, 4))
+    fg = _np(gpu.prune_features(R, z, s2, M, P))
+    assert fg.shape == fo.shape
     # the cancellation path is the K = 1 path: compare where it agrees
-    xs, _ = orc.zf_sic(Ro, zo, 4)
-    sym1, _, _ = gpu.kbest_detect(R, z, M, 4, 1)
-    same = np.all(_np(sym1) == orc.x_to_sym(xs, 4), axis=1)
-    assert same.mean() > 0.9
+    xs, _ = orc.zf_sic(Ro, zo, P)
+    sym1, _, _ = gpu.kbest_detect(R, z, M, P, 1)
+    same = np.all(_np(sym1) == orc.x_to_sym(xs, P), axis=1)
+    assert same.mean() > 0.8, same.mean()
     d = np.abs(fg[same] - fo[same])
     assert np.all(d[..., 0] < 1e-6)
     assert np.all(d[..., 1] < 1e-3)
