@@ -2,7 +2,7 @@
 
 Every .hip file under csrc/ is compiled for gfx950 and linked into one shared
 library next to this file.  Packed FP32 instructions are disabled for all
-device code (-packed-fp32-ops).
+device code (-packed-fp32-ops); FILE_FLAGS adds per-file options.
 """
 from __future__ import annotations
 
@@ -25,10 +25,17 @@ CFLAGS = [
     "-Wno-unused-command-line-argument",
 ]
 
+# Per-file additions.  mlp.hip: matrix-core results go to ordinary VGPRs, not
+# to accumulation registers (whose values the ReLU and the next layer would
+# first have to copy out: 64 v_accvgpr_read per 16 states); same arithmetic.
+FILE_FLAGS = {
+    "mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *CFLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
