@@ -25,7 +25,15 @@ def k_for(table: dict, n_tx: int, qam: int, default: int = 16) -> int:
 
 
 class UnevenBatch:
-    """Device-resident uneven batch with its descriptors and output buffers."""
+    """Device-resident uneven batch with its descriptors and output buffers.
+
+    `desc_np` holds the descriptors in frame order.  The device copy `desc` is
+    in launch order: most expensive frames first (levels x K x PAM points,
+    the K-best's work per frame), so that the persistent launches, which pull
+    frames in descriptor order, end on cheap frames instead of waiting on a
+    late expensive one.  R, z and sym sit at each frame's own offsets; pd and
+    flags are indexed by launch position: entry j belongs to frame order[j]
+    (`by_frame` reorders them)."""
 
     def __init__(self, frames, k_table: dict, device="cuda"):
         B = len(frames)
@@ -43,8 +51,10 @@ class UnevenBatch:
         desc["z_off"] = np.concatenate([[0], np.cumsum(n)[:-1]])
         desc["s_off"] = frames.s_off
         self.desc_np = desc
+        cost = n * desc["K"].astype(np.int64) * desc["pam"].astype(np.int64)
+        self.order = np.argsort(-cost, kind="stable")
         self.max_rx = int(frames.n_rx.max())
-        self.desc = torch.from_numpy(desc.view(np.uint8)).to(device)
+        self.desc = torch.from_numpy(np.ascontiguousarray(desc[self.order]).view(np.uint8)).to(device)
         self.H = torch.from_numpy(frames.H_flat).to(device)
         self.y = torch.from_numpy(frames.y_flat).to(device)
         self.s_true = torch.from_numpy(frames.s_flat).to(device)
@@ -61,6 +71,12 @@ class UnevenBatch:
                                   self.counter[0:1], grid=qr_grid, stream=stream)
         mimo.kbest_detect_uneven(self.desc, self.B, self.R, self.z, self.sym, self.pd, self.flags,
                                  self.counter[1:2], grid=kb_grid, stream=stream)
+
+    def by_frame(self, t: torch.Tensor) -> np.ndarray:
+        """A per-launch-position output (pd, flags) in frame order."""
+        out = np.empty(self.B, t.cpu().numpy().dtype)
+        out[self.order] = t.cpu().numpy()
+        return out
 
     def symbol_errors(self) -> int:
         return int((self.sym != self.s_true).sum())

@@ -23,18 +23,23 @@ def test_uneven_matches_batched_path_and_oracle(gpu, orc):
     torch.cuda.synchronize()
     d = ub.desc_np
     R, z, sym = ub.R.cpu().numpy(), ub.z.cpu().numpy(), ub.sym.cpu().numpy()
+    pd_frame = ub.by_frame(ub.pd)
+    cost = 2 * d["n_tx"].astype(np.int64) * d["K"] * d["pam"]
+    assert np.all(np.diff(cost[ub.order]) <= 0) and sorted(ub.order.tolist()) == list(range(ub.B))
     # the same frames through the batched launches, one shape class at a time
     for (m, q) in {(int(a), int(b)) for a, b in zip(fr.n_tx, fr.qam)}:
         idx = np.nonzero((fr.n_tx == m) & (fr.qam == q))[0]
         H = torch.from_numpy(np.stack([fr.frame(i)[0] for i in idx])).cuda()
         y = torch.from_numpy(np.stack([fr.frame(i)[1] for i in idx])).cuda()
         Rb, zb = gpu.qr_preprocess(H, y)
-        sb, _, _ = gpu.kbest_detect(Rb, zb, m, math.isqrt(q), K_TABLE[f"{m}x{q}"])
+        sb, pb, _ = gpu.kbest_detect(Rb, zb, m, math.isqrt(q), K_TABLE[f"{m}x{q}"])
         n = 2 * m
         for j, i in enumerate(idx):
             assert np.array_equal(R[d["r_off"][i]: d["r_off"][i] + n * (n + 1) // 2], Rb[j].cpu().numpy())
             assert np.array_equal(z[d["z_off"][i]: d["z_off"][i] + n], zb[j].cpu().numpy())
             assert np.array_equal(sym[d["s_off"][i]: d["s_off"][i] + m], sb[j].cpu().numpy())
+        # pd comes back in launch order (most expensive frames first)
+        assert np.array_equal(pd_frame[idx], pb.cpu().numpy())
     # oracle parity on a sample of frames
     for i in range(0, 700, 37):
         H, y, s = fr.frame(i)
