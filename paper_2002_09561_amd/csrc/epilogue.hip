@@ -146,8 +146,10 @@ __global__ void __launch_bounds__(256) errors_kernel(const int32_t* __restrict__
 // are not loaded (a uniform branch).  A loaded lane whose level is not in
 // row k (j <= k or j >= n) reads another row or frame of the same buffer, or
 // nothing (an offset outside the buffer reads 0), and a slot not loaded keeps
-// an earlier row's values: either way it meets a zero amplitude in the centre
-// (a level not yet decided, or beyond n), so its product adds nothing.
+// an earlier row's values: either way its level has amplitude 0 (not yet
+// decided, or beyond n), and the centre drops such entries outright (a
+// select, not a product with 0), so a non-finite R in a neighbouring frame
+// cannot reach this frame.
 template <int SL>
 __device__ __forceinline__ void feat_load(__amdgpu_buffer_rsrc_t rs, int fbase, const float* __restrict__ zf, int n,
                                           int k, int l, float (&r)[SL], float& rkk, float& zk)
@@ -170,7 +172,7 @@ __device__ __forceinline__ void feat_level(int k, int n, int P, float c, float r
 {
     float acc = 0.f;
 #pragma unroll
-    for (int i = 0; i < SL; ++i) acc = fmaf(r[i], xr[i], acc);
+    for (int i = 0; i < SL; ++i) acc = fmaf(xr[i] != 0.f ? r[i] : 0.f, xr[i], acc);
 #pragma unroll
     for (int m = 8; m >= 1; m >>= 1) acc += shfl_xor_f(acc, m);
     const float b = zk - acc;

@@ -372,6 +372,29 @@ def test_prune_features_parity(gpu, orc, M, q, B):
     assert np.all(d[..., 3] < 1e-3 * np.maximum(1.0, np.abs(fo[same][..., 3])))
 
 
+@pytest.mark.parametrize("M", [100, 128])
+def test_prune_features_frames_isolated(gpu, M):
+    """A wave computes the features of four frames and its lanes may read
+    entries of a neighbouring frame's R (which meet a zero amplitude): a
+    non-finite frame must leave every other frame's features unchanged."""
+    import torch
+
+    B = 8
+    f = gen_frames(M, M, 64, 20.0, B, seed=2550 + M)
+    H, y, _ = _dev(f)
+    s2 = torch.full((B,), f.sigma2, device="cuda", dtype=torch.float32)
+    R, z = gpu.qr_preprocess(H, y)
+    clean = _np(gpu.prune_features(R, z, s2, M, 8))
+    for bad in (0, 2, 3, 7):  # first, inside and last of a wave of four, last frame
+        Hb = H.clone()
+        Hb[bad, 1, 2] = float("nan")
+        Rb, zb = gpu.qr_preprocess(Hb, y)
+        fb = _np(gpu.prune_features(Rb, zb, s2, M, 8))
+        for i in range(B):
+            if i != bad:
+                assert np.array_equal(fb[i], clean[i]), (bad, i)
+
+
 # ----------------------------------------------------------------- full size, sampled
 def test_kbest_100x100_64qam_sampled(gpu, orc):
     """The benchmark's shape (100x100 64-QAM, K = 16) in its launch
