@@ -675,6 +675,11 @@ __device__ __forceinline__ void kbest_frame_reg(const KbestArgs& a, int frame, u
     const float cs = pam_scale(P);
     const int32_t* ks = a.k_sched ? a.k_sched + (size_t)frame * a.k_sched_stride : nullptr;
     const int32_t* fsym = a.force_sym ? a.force_sym + (size_t)frame * (n / 2) : nullptr;
+    // the frame's R as one buffer: a row is loaded with one address and the
+    // entry in the immediate offset; a lane past the end of the row reads the
+    // next rows (or, past the frame, 0), which the staging never stores
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(Rf), 0, (int)r_packed_size(n) * (int)sizeof(float), 0x00020000);
 
     uint32_t pw[NWL];
 #pragma unroll
@@ -711,11 +716,10 @@ __device__ __forceinline__ void kbest_frame_reg(const KbestArgs& a, int frame, u
         const float zk = zk_next;
         if (k > 0) {
             const float* rk = Rf + r_row_off(n, k - 1);
+            const int v = 4 * ((int)r_row_off(n, k - 1) + lane);
 #pragma unroll
-            for (int i = 0; i < RPL; ++i) {
-                const int t = lane + WAVE * i;
-                rnext[i] = t < n - k + 1 ? rk[t] : 0.f;
-            }
+            for (int i = 0; i < RPL; ++i)
+                rnext[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, v + 4 * WAVE * i, 0, 0));
             rkk_next = rk[0];
             zk_next = zf[k - 1];
         }
@@ -1219,6 +1223,16 @@ __global__ void __launch_bounds__(WAVE) kbest_pair_kernel(KbestArgs a, int B)
     const float cs = pam_scale(P);
     const int32_t* ks = a.k_sched ? a.k_sched + (size_t)frame * a.k_sched_stride : nullptr;
     const uint64_t hmask = half ? 0xffffffff00000000ull : 0x00000000ffffffffull;
+    // the R rows of the wave's two frames as one buffer: a row is loaded with
+    // one address and the entry in the immediate offset; a lane past the end
+    // of the row reads the next rows (or, past the buffer, 0), which the
+    // staging below never stores
+    const int f0 = 2 * (int)blockIdx.x;
+    const int rsz = (int)r_packed_size(n);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(a.R + (size_t)f0 * rsz), 0, (B - f0 < 2 ? B - f0 : 2) * rsz * (int)sizeof(float),
+        0x00020000);
+    const int fb = (frame - f0) * rsz;
 
     uint32_t pw[NWL];
 #pragma unroll
@@ -1254,11 +1268,10 @@ __global__ void __launch_bounds__(WAVE) kbest_pair_kernel(KbestArgs a, int B)
         const float zk = zk_next;
         if (k > 0) {
             const float* rk = Rf + r_row_off(n, k - 1);
+            const int v = 4 * (fb + (int)r_row_off(n, k - 1) + hl);
 #pragma unroll
-            for (int i = 0; i < RPL; ++i) {
-                const int t = hl + PR_HALF * i;
-                rnext[i] = t < n - k + 1 ? rk[t] : 0.f;
-            }
+            for (int i = 0; i < RPL; ++i)
+                rnext[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, v + 4 * PR_HALF * i, 0, 0));
             rkk_next = rk[0];
             zk_next = zf[k - 1];
         }
