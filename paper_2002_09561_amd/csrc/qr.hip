@@ -326,12 +326,16 @@ __device__ __forceinline__ void cholqr_frame(const float2* __restrict__ Hf, cons
     if (has_tile && I == 0) cq_store_row<0>(rowbuf, rinv, diag, nb, I, J, gr, gi);
     for (int kb = 0; kb < M; kb += CQ_T) {
         if (kb >= k1 && !tail) break;
+        // the tail wave is the workgroup's critical path: its instructions go
+        // ahead of the other waves' output on the same SIMD
+        if (kb == k1) __builtin_amdgcn_s_setprio(2);
         cq_step<0, NBC>(kb, M, nb, kb < k1, has_tile, I, J, i0, rowbuf, rinv, diag, gr, gi);
         if (kb + 1 < M) cq_step<1, NBC>(kb + 1, M, nb, kb + 1 < k1, has_tile, I, J, i0, rowbuf, rinv, diag, gr, gi);
         if (kb + 2 < M) cq_step<2, NBC>(kb + 2, M, nb, kb + 2 < k1, has_tile, I, J, i0, rowbuf, rinv, diag, gr, gi);
         if (kb + 3 < M) cq_step<3, NBC>(kb + 3, M, nb, kb + 3 < k1, has_tile, I, J, i0, rowbuf, rinv, diag, gr, gi);
     }
     if (tail) cq_wave_sync();  // the tail's own last pivot writes
+    __builtin_amdgcn_s_setprio(0);
 
     // ---- 3. output: R_ij = g_ij / sqrt(g_ii), real blocks in packed level order
     if (has_tile && live) {
