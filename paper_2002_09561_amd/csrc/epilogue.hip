@@ -22,6 +22,10 @@ __device__ __forceinline__ double xor_lanes_f64(double v, int m, int lane)
 // the row's residual y_i - sum_j h_ij s_j is reduced over those 16 lanes in
 // FP64 in a fixed order (DPP exchanges only), and each group accumulates
 // |residual|^2 over its rows; the four group sums are added at the end.
+// row groups (of four rows) per loop step: one keeps the kernel at 56
+// registers, so that six of its waves still fit on a SIMD beside one wave of
+// the K = 64 fallback (176 registers) that runs at the same time
+constexpr int MU = 1;
 __global__ void __launch_bounds__(256) metric_kernel(const float2* __restrict__ H, const float2* __restrict__ y,
                                                      const int32_t* __restrict__ sym, int B, int N, int M, int P,
                                                      const uint32_t* __restrict__ flags, uint32_t mask,
@@ -49,10 +53,12 @@ __global__ void __launch_bounds__(256) metric_kernel(const float2* __restrict__ 
     const float2* Hf = H + (size_t)f * N * M;
     const float2* yf = y + (size_t)f * N;
     double acc = 0.0;
-    for (int i0 = 0; i0 < N; i0 += 8) {
-        double pr[2] = {0.0, 0.0}, pi[2] = {0.0, 0.0};
+    for (int i0 = 0; i0 < N; i0 += 4 * MU) {
+        double pr[MU], pi[MU];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
+        for (int u = 0; u < MU; ++u) pr[u] = pi[u] = 0.0;
+#pragma unroll
+        for (int u = 0; u < MU; ++u) {
             const int i = i0 + 4 * u + g;
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
@@ -77,13 +83,13 @@ __global__ void __launch_bounds__(256) metric_kernel(const float2* __restrict__ 
 #pragma unroll
         for (int m = 8; m >= 1; m >>= 1) {
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
+            for (int u = 0; u < MU; ++u) {
                 pr[u] += xor_lanes_f64(pr[u], m, lane);
                 pi[u] += xor_lanes_f64(pi[u], m, lane);
             }
         }
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
+        for (int u = 0; u < MU; ++u) {
             const int i = i0 + 4 * u + g;
             if (i < N) {
                 const float2 yy = yf[i];
