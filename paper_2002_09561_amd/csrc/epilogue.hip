@@ -140,9 +140,9 @@ __global__ void __launch_bounds__(256) errors_kernel(const int32_t* __restrict__
 // Four frames per wave, 16 lanes per frame: lane l of a frame holds the
 // decided amplitudes x_j of the levels j = l + 16 i in registers and loads
 // the matching entries R_kj of each row (coalesced 64-byte segments), so the
-// centre is SL register FMAs and a 16-lane reduction (DPP).  Four row
-// buffers keep the loads of the next three or four levels in flight while
-// the current one is used (the kernel waits on memory latency, not on issue).
+// centre is SL register FMAs and a 16-lane reduction (DPP).  Six row
+// buffers keep the loads of the next five or six levels in flight while the
+// current one is used (the kernel waits on memory latency, not on issue).
 // SL levels per lane (16 SL >= n): 13 for up to 208 levels, else 16.
 //
 // Row k of the frame through a buffer resource that spans the wave's four
@@ -229,31 +229,37 @@ __global__ void __launch_bounds__(256) features_kernel(const float* __restrict__
 #pragma unroll
     for (int i = 0; i < SL; ++i) xr[i] = 0.f;
     float pd = 0.f;
-    float ra[SL], rb[SL], rc4[SL], rd[SL];
-    float rka = 0.f, rkb = 0.f, rkc = 0.f, rkd = 0.f, za = 0.f, zb = 0.f, zc = 0.f, zd = 0.f;
+    float ra[SL], rb[SL], rc4[SL], rd[SL], re[SL], rf[SL];
+    float rka = 0.f, rkb = 0.f, rkc = 0.f, rkd = 0.f, rke = 0.f, rkf = 0.f;
+    float za = 0.f, zb = 0.f, zc = 0.f, zd = 0.f, ze = 0.f, zf6 = 0.f;
 #pragma unroll
-    for (int i = 0; i < SL; ++i) ra[i] = rb[i] = rc4[i] = rd[i] = 0.f;
+    for (int i = 0; i < SL; ++i) ra[i] = rb[i] = rc4[i] = rd[i] = re[i] = rf[i] = 0.f;
     feat_load<SL>(rs, fbase, zf, n, n - 1, l, ra, rka, za);
     feat_load<SL>(rs, fbase, zf, n, n - 2, l, rb, rkb, zb);
     feat_load<SL>(rs, fbase, zf, n, n - 3, l, rc4, rkc, zc);
     feat_load<SL>(rs, fbase, zf, n, n - 4, l, rd, rkd, zd);
-    // four row buffers: a buffer is refilled four levels ahead as soon as its
-    // level is done; n = 2 n_tx is even, so two levels may remain (in a and b)
+    feat_load<SL>(rs, fbase, zf, n, n - 5, l, re, rke, ze);
+    feat_load<SL>(rs, fbase, zf, n, n - 6, l, rf, rkf, zf6);
     int k = n - 1;
-    for (; k >= 3; k -= 4) {
+    for (; k >= 5; k -= 6) {
         feat_level<SL>(k, n, P, c, rc, lc, rs2, lane, ra, rka, za, xr, pd, featf, live);
-        feat_load<SL>(rs, fbase, zf, n, k - 4, l, ra, rka, za);
+        feat_load<SL>(rs, fbase, zf, n, k - 6, l, ra, rka, za);
         feat_level<SL>(k - 1, n, P, c, rc, lc, rs2, lane, rb, rkb, zb, xr, pd, featf, live);
-        feat_load<SL>(rs, fbase, zf, n, k - 5, l, rb, rkb, zb);
+        feat_load<SL>(rs, fbase, zf, n, k - 7, l, rb, rkb, zb);
         feat_level<SL>(k - 2, n, P, c, rc, lc, rs2, lane, rc4, rkc, zc, xr, pd, featf, live);
-        feat_load<SL>(rs, fbase, zf, n, k - 6, l, rc4, rkc, zc);
+        feat_load<SL>(rs, fbase, zf, n, k - 8, l, rc4, rkc, zc);
         feat_level<SL>(k - 3, n, P, c, rc, lc, rs2, lane, rd, rkd, zd, xr, pd, featf, live);
-        feat_load<SL>(rs, fbase, zf, n, k - 7, l, rd, rkd, zd);
+        feat_load<SL>(rs, fbase, zf, n, k - 9, l, rd, rkd, zd);
+        feat_level<SL>(k - 4, n, P, c, rc, lc, rs2, lane, re, rke, ze, xr, pd, featf, live);
+        feat_load<SL>(rs, fbase, zf, n, k - 10, l, re, rke, ze);
+        feat_level<SL>(k - 5, n, P, c, rc, lc, rs2, lane, rf, rkf, zf6, xr, pd, featf, live);
+        feat_load<SL>(rs, fbase, zf, n, k - 11, l, rf, rkf, zf6);
     }
-    if (k == 1) {
-        feat_level<SL>(1, n, P, c, rc, lc, rs2, lane, ra, rka, za, xr, pd, featf, live);
-        feat_level<SL>(0, n, P, c, rc, lc, rs2, lane, rb, rkb, zb, xr, pd, featf, live);
-    }
+    // n is even: 0, 2 or 4 levels remain, in buffers a, b, c, d
+    if (k >= 0) feat_level<SL>(k, n, P, c, rc, lc, rs2, lane, ra, rka, za, xr, pd, featf, live);
+    if (k >= 1) feat_level<SL>(k - 1, n, P, c, rc, lc, rs2, lane, rb, rkb, zb, xr, pd, featf, live);
+    if (k >= 2) feat_level<SL>(k - 2, n, P, c, rc, lc, rs2, lane, rc4, rkc, zc, xr, pd, featf, live);
+    if (k >= 3) feat_level<SL>(k - 3, n, P, c, rc, lc, rs2, lane, rd, rkd, zd, xr, pd, featf, live);
 }
 
 }  // namespace mimo
