@@ -63,10 +63,15 @@ extern "C" {
 
 /* per-frame flags */
 #define MIMO_FLAG_FOUND 1u            /* a leaf inside the radius was found          */
-#define MIMO_FLAG_EMPTY_SPHERE 2u     /* the radius left no leaf (output undefined)  */
+#define MIMO_FLAG_EMPTY_SPHERE 2u     /* the radius left no leaf; the frame was      */
+                                      /* detected again with r2 = +infinity          */
 #define MIMO_FLAG_BUDGET_EXHAUSTED 4u /* node budget reached; best leaf so far       */
 #define MIMO_FLAG_CERTIFIED 8u        /* hybrid pool drained within the budget        */
 #define MIMO_FLAG_LEARNED_FALLBACK 16u /* a learned survivor count was invalid        */
+#define MIMO_FLAG_NONFINITE_INPUT 32u /* R, z (or H, y) held a NaN or infinity: the  */
+                                      /* search stopped; sym = 0, pd = +infinity     */
+#define MIMO_FLAG_INVALID_FRAME 64u   /* uneven batch: the frame's descriptor is out */
+                                      /* of the kernel's range; outputs untouched    */
 
 /* limits */
 #define MIMO_MAX_TX 128   /* n_tx <= 128, i.e. n <= 256 real levels */
@@ -119,7 +124,15 @@ int32_t mimo_qr_preprocess_mmse(const float* H, const float* y, const float* sig
  * 0 (one schedule for all frames) or n (one per frame).
  * R, z as produced by mimo_qr_preprocess; radius2 [B] or NULL.
  * Outputs: sym [B][n_tx], pd [B] (float search metric), flags [B],
- * counters [B][4] or NULL.  1 <= K <= MIMO_MAX_K, K * pam <= 1024.
+ * counters [B][4] or NULL.  1 <= K <= MIMO_MAX_K, K * pam <= 1024, and
+ * for more than 64 survivors the survivor lists must fit the 160 KB of LDS
+ * of a compute unit (about 8 K (n/2 + 3) bytes: K = 256 of 4- or 16-QAM
+ * stops at n_tx = 78), else MIMO_ERR_UNSUPPORTED.  With radius2, a frame
+ * whose sphere holds no leaf (Sec. III-B leaves that case open) is detected
+ * again with r2 = +infinity in a second launch on the same stream: it then
+ * carries MIMO_FLAG_EMPTY_SPHERE | MIMO_FLAG_FOUND and its counters add up
+ * both searches.  A frame with a NaN or infinity in R or z stops at that
+ * level with MIMO_FLAG_NONFINITE_INPUT (sym 0, pd +infinity).
  * ------------------------------------------------------------------- */
 int32_t kbest_detect(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam,
                      int32_t K, const int32_t* k_sched, int32_t k_sched_stride,
@@ -193,7 +206,12 @@ int32_t kbest_rank_labels(const float* R, const float* z, int32_t B, int32_t n_t
  * (flag CERTIFIED) or after node_budget expansions (> 0; flag
  * BUDGET_EXHAUSTED, best leaf so far).  n_workers = 0 is the exact Best-FS
  * SD (maximum likelihood within the radius); master_off != 0 hands the root
- * to worker 0 instead (K-best within the radius).
+ * to worker 0 instead (K-best within the radius).  With radius2, a frame
+ * whose pool drains without a leaf inside the sphere is run again with
+ * r2 = +infinity in a second launch (flags EMPTY_SPHERE | FOUND, counters
+ * summed); a NaN or infinity met in R or z ends the frame's search with
+ * MIMO_FLAG_NONFINITE_INPUT (sym 0, pd +infinity).  A frame that reaches the
+ * budget without any leaf has BUDGET_EXHAUSTED and no FOUND (sym 0).
  * Limits: 0 <= n_workers <= MIMO_MAX_WORKERS, k_worker * pam <= 64.
  * ------------------------------------------------------------------- */
 int32_t sd_hybrid_detect(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam,
@@ -212,6 +230,17 @@ int32_t sd_hybrid_detect(const float* R, const float* z, int32_t B, int32_t n_tx
  * ------------------------------------------------------------------- */
 int32_t linear_detect(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam, int32_t* sym,
                       float* xhat, void* stream);
+
+/* ---------------------------------------------------------------------
+ * The paper's sphere radius rule (Sec. III-B, "Sphere radius and pruning"),
+ * squared: radius2[b] = n_rx * n_tx * sigma2[b], M times the expected noise
+ * energy N sigma2 of a received vector, computed in FP32 (one rounding).
+ * sigma2 [B] complex noise variances, radius2 [B] f32, both device; the
+ * result is a radius2 argument for kbest_detect and sd_hybrid_detect.
+ * Limits: 1 <= n_tx <= n_rx <= 128.
+ * ------------------------------------------------------------------- */
+int32_t mimo_paper_radius2(const float* sigma2, int32_t B, int32_t n_rx, int32_t n_tx, float* radius2,
+                           void* stream);
 
 /* ---------------------------------------------------------------------
  * Maximum-ratio combining (Sec. III-A): u_j = h_j^H y / ||h_j||^2 per
@@ -310,9 +339,11 @@ int32_t mimo_qr_preprocess_uneven(const mimo_frame_desc* desc, int32_t B, int32_
 
 /* Batched K-best (Sec. VI) of an uneven batch in one persistent launch: one
  * wavefront per workgroup pulls frames from `counter` (reset by the call)
- * and runs K-best with the frame's own pam and K (desc[f].K * pam <= 256,
- * n_tx <= 64).  sym_flat at the frames' s_off; pd [B], flags [B].
- * grid = 0 picks eight workgroups per compute unit. */
+ * and runs K-best with the frame's own pam and K.  Per-frame limits: pam in
+ * {2, 4, 8}, 1 <= K <= 64, K * pam <= 256, 1 <= n_tx <= 64; a frame outside
+ * them is skipped with flags[f] = MIMO_FLAG_INVALID_FRAME (its sym and pd
+ * untouched).  sym_flat at the frames' s_off; pd [B], flags [B] indexed by
+ * descriptor position.  grid = 0 picks eight workgroups per compute unit. */
 int32_t kbest_detect_uneven(const mimo_frame_desc* desc, int32_t B, const float* R_flat, const float* z_flat,
                             int32_t* sym_flat, float* pd, uint32_t* flags, int32_t* counter, int32_t grid,
                             void* stream);

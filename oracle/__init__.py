@@ -67,15 +67,14 @@ def _declare(L):
     L.orc_batch_mrc.argtypes = [_I, _I, _I, _I, _P, _P, _P, _P]
     L.orc_batch_sesd.argtypes = [_I, _I, _I, _P, _P, _P, _L, _P, _P, _P, _P, _P]
     L.orc_batch_kbest.argtypes = [_I, _I, _I, _P, _P, _I, _P, _I, _D, _I, _P, _P, _P, _P, _P,
-                                  _P, _P]
-    L.orc_batch_hybrid.argtypes = [_I, _I, _I, _P, _P, _D, _I, _I, _P, _I, _I, _L, _P, _P, _P,
+                                  _P, _P, _P, _P]
+    L.orc_batch_hybrid.argtypes = [_I, _I, _I, _P, _P, _P, _I, _I, _P, _I, _I, _L, _P, _P, _P,
                                    _P, _P]
+    L.orc_hybrid_trace.restype = ctypes.c_uint32
+    L.orc_hybrid_trace.argtypes = [_I, _I, _P, _P, _D, _I, _I, _I, _L, _P, _P, _P, ctypes.c_char_p, _I]
     L.orc_batch_prune_features.argtypes = [_I, _I, _I, _P, _P, _P, _P]
     L.orc_path_terms.argtypes = [_I, _I, _P, _P, _P, _P]
     L.orc_mlp_forward.argtypes = [_P, _P, _I, _P]
-    L.orc_mlp_forward_f16.argtypes = [_P, _P, _I, _P]
-    L.orc_round_half.restype = _D
-    L.orc_round_half.argtypes = [_D]
     L.orc_mlp_loss_grad.restype = _D
     L.orc_mlp_loss_grad.argtypes = [_P, _P, _P, _I, _D, _P]
     L.orc_adam_step.argtypes = [_P, _P, _P, _P, _I, _I, _D, _D, _D, _D]
@@ -204,7 +203,10 @@ def kbest(R, z, P: int, K: int, k_sched=None, r2: float = math.inf, J: int = 1,
           force_path=None, want_rank: bool = False):
     """K-best (Sec. VI).  k_sched: None, [n] (shared) or [B,n] (per frame),
     indexed by level.  Returns dict with x, pd, margin [B,3], flags, counters
-    and (if want_rank or force_path) rank [B,n]."""
+    and (if want_rank or force_path) rank [B,n]; with force_path also fgap [B],
+    the largest relative gap of a decision that would have dropped the forced
+    path (0 if it is the search's own result), and rgap [B,n], per step the
+    smallest relative gap that could change the forced prefix's rank."""
     R = _c(R, np.float64)
     z = _c(z, np.float64)
     B, n = z.shape
@@ -217,19 +219,22 @@ def kbest(R, z, P: int, K: int, k_sched=None, r2: float = math.inf, J: int = 1,
     pd = np.zeros(B)
     mg = np.zeros((B, 3))
     rk = np.zeros((B, n), np.int32) if (want_rank or fp is not None) else None
+    fg = np.zeros(B) if fp is not None else None
+    rg = np.full((B, n), np.inf) if fp is not None else None
     fl = np.zeros(B, np.uint32)
     ctr = np.zeros((B, 4), np.int64)
     lib().orc_batch_kbest(B, n, P, _p(R), _p(z), int(K), _p(ks), stride, float(r2), int(J),
-                          _p(fp), _p(x), _p(pd), _p(mg), _p(rk), _p(fl), _p(ctr))
-    return dict(x=x, pd=pd, margin=mg, rank=rk, flags=fl, counters=ctr)
+                          _p(fp), _p(x), _p(pd), _p(mg), _p(rk), _p(fg), _p(rg), _p(fl), _p(ctr))
+    return dict(x=x, pd=pd, margin=mg, rank=rk, fgap=fg, rgap=rg, flags=fl, counters=ctr)
 
 
-def hybrid(R, z, P: int, W: int, Kw: int, r2: float = math.inf, k_sched=None,
+def hybrid(R, z, P: int, W: int, Kw: int, r2=math.inf, k_sched=None,
            master_off: bool = False, budget: int = 0):
-    """Hybrid SD-K-best in deterministic rounds (Sec. VI)."""
+    """Hybrid SD-K-best in deterministic rounds (Sec. VI).  r2: scalar or [B]."""
     R = _c(R, np.float64)
     z = _c(z, np.float64)
     B, n = z.shape
+    r2a = _c(np.broadcast_to(np.asarray(r2, np.float64), (B,)), np.float64)
     ks, stride = None, 0
     if k_sched is not None:
         ks = _c(k_sched, np.int32)
@@ -239,10 +244,27 @@ def hybrid(R, z, P: int, W: int, Kw: int, r2: float = math.inf, k_sched=None,
     mg = np.zeros((B, 3))
     fl = np.zeros(B, np.uint32)
     ctr = np.zeros((B, 4), np.int64)
-    lib().orc_batch_hybrid(B, n, P, _p(R), _p(z), float(r2), int(W), int(Kw), _p(ks), stride,
+    lib().orc_batch_hybrid(B, n, P, _p(R), _p(z), _p(r2a), int(W), int(Kw), _p(ks), stride,
                            int(bool(master_off)), int(budget), _p(x), _p(pd), _p(mg), _p(fl),
                            _p(ctr))
     return dict(x=x, pd=pd, margin=mg, flags=fl, counters=ctr)
+
+
+def hybrid_trace(R, z, P: int, W: int, Kw: int, r2: float = math.inf, master_off: bool = False,
+                 budget: int = 0):
+    """One frame (R [n,n], z [n]) of the hybrid with its round-by-round text
+    trace.  Returns (trace lines, x [n], pd, flags, counters [4])."""
+    R = _c(R, np.float64)
+    z = _c(z, np.float64)
+    n = z.shape[0]
+    x = np.zeros(n, np.int32)
+    pd = ctypes.c_double(0.0)
+    ctr = np.zeros(4, np.int64)
+    cap = 1 << 20
+    buf = ctypes.create_string_buffer(cap)
+    fl = lib().orc_hybrid_trace(n, P, _p(R), _p(z), float(r2), int(W), int(Kw), int(bool(master_off)),
+                                int(budget), _p(x), ctypes.byref(pd), _p(ctr), buf, cap)
+    return buf.value.decode().splitlines(), x, pd.value, int(fl), ctr
 
 
 def path_terms(R, z, x, P: int) -> np.ndarray:
@@ -273,20 +295,6 @@ def mlp_forward(w, X) -> np.ndarray:
     out = np.zeros(X.shape[0])
     lib().orc_mlp_forward(_p(w), _p(X), X.shape[0], _p(out))
     return out
-
-
-def mlp_forward_f16(w, X) -> np.ndarray:
-    """Forward pass with ReLU(layer 1) and W2 rounded to binary16 (the rest
-    in FP64): the precision of the GPU library's inference."""
-    w = _c(w, np.float64)
-    X = _c(X, np.float64)
-    out = np.zeros(X.shape[0])
-    lib().orc_mlp_forward_f16(_p(w), _p(X), X.shape[0], _p(out))
-    return out
-
-
-def round_half(x: float) -> float:
-    return lib().orc_round_half(float(x))
 
 
 def mlp_loss_grad(w, X, y, tau: float = 0.95):

@@ -9,8 +9,27 @@
 
 #include <float.h>
 #include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* optional text trace of a search (one event per line) */
+typedef struct {
+    char* buf;
+    size_t cap, len;
+} trace_t;
+
+static void tr(trace_t* t, const char* fmt, ...)
+{
+    if (!t || !t->buf || t->len + 1 >= t->cap) return;
+    va_list ap;
+    va_start(ap, fmt);
+    int w = vsnprintf(t->buf + t->len, t->cap - t->len, fmt, ap);
+    va_end(ap);
+    if (w > 0) t->len += (size_t)w;
+    if (t->len >= t->cap) t->len = t->cap - 1;
+}
 
 /* ------------------------------------------------------------------ */
 /* constellation (reading: unit-energy square QAM, Gray-free PAM index)  */
@@ -265,8 +284,8 @@ static int cmp_child(const void* a, const void* b)
     return (x->c > y->c) - (x->c < y->c);
 }
 
-uint32_t orc_sesd(int n, int P, const double* R, const double* z, double r2, int64_t budget,
-                  const int* x_init, int* x_out, double* pd_out, int64_t* counters)
+static uint32_t sesd_search(int n, int P, const double* R, const double* z, double r2, int64_t budget,
+                            const int* x_init, int* x_out, double* pd_out, int64_t* counters)
 {
     /* The list is a stack (leftmost = most recently inserted).  Its size is
      * bounded by 1 + n (P - 1): every expansion removes one node and adds at
@@ -341,7 +360,8 @@ uint32_t orc_sesd(int n, int P, const double* R, const double* z, double r2, int
         }
     }
     if (!(flags & ORC_BUDGET_EXHAUSTED)) flags |= ORC_CERTIFIED;
-    if (!(flags & ORC_FOUND)) flags |= ORC_EMPTY_SPHERE;
+    /* empty: the whole tree was searched and no leaf lies inside the sphere */
+    if (!(flags & ORC_FOUND) && (flags & ORC_CERTIFIED)) flags |= ORC_EMPTY_SPHERE;
     if (pd_out) {
         if (best < INFINITY) *pd_out = best;
         else if (x_init) { /* the warm start was never beaten: report its pd */
@@ -364,6 +384,18 @@ uint32_t orc_sesd(int n, int P, const double* R, const double* z, double r2, int
     free(cur);
     free(ch);
     return flags;
+}
+
+/* Reading of Sec. III-B, which leaves an empty sphere open: the frame is
+ * searched again with r2 = +inf; its flags keep EMPTY_SPHERE and the
+ * counters add up both searches. */
+uint32_t orc_sesd(int n, int P, const double* R, const double* z, double r2, int64_t budget,
+                  const int* x_init, int* x_out, double* pd_out, int64_t* counters)
+{
+    uint32_t f = sesd_search(n, P, R, z, r2, budget, x_init, x_out, pd_out, counters);
+    if ((f & ORC_EMPTY_SPHERE) && isfinite(r2))
+        f = sesd_search(n, P, R, z, INFINITY, budget, x_init, x_out, pd_out, counters) | ORC_EMPTY_SPHERE;
+    return f;
 }
 
 /* ------------------------------------------------------------------ */
@@ -410,9 +442,10 @@ static double child_pd(int n, int P, const double* R, const double* z, int k_hi,
     return pd;
 }
 
-uint32_t orc_kbest(int n, int P, const double* R, const double* z, int K, const int* k_sched,
-                   double r2, int J, const int* force_path, int* x_out, double* pd_out,
-                   double* margin_out, int* rank_out, int64_t* counters)
+static uint32_t kbest_search(int n, int P, const double* R, const double* z, int K, const int* k_sched,
+                             double r2, int J, const int* force_path, int* x_out, double* pd_out,
+                             double* margin_out, int* rank_out, double* fgap_out, double* rgap_out,
+                             int64_t* counters)
 {
     if (J < 1 || n % J != 0) return 0;
     const int kmax = K < 1 ? 1 : K; /* K is the capacity; schedule values are clamped to it */
@@ -475,7 +508,34 @@ uint32_t orc_kbest(int n, int P, const double* R, const double* z, int K, const 
                     break;
                 }
             if (rank_out) rank_out[k_lo] = pos >= 0 ? pos + 1 : 0;
-            if (pos >= keep) { /* keep it anyway: it replaces the last survivor */
+            if (rgap_out) {
+                /* how close the rank is to changing: the smallest relative gap
+                 * between the forced candidate and any other, or between the
+                 * last survivor and the first dropped candidate */
+                double g = INFINITY;
+                for (int i = 0; pos >= 0 && i < m; ++i)
+                    if (i != pos) {
+                        double gi = rel_gap(cand[i].pd, cand[pos].pd);
+                        if (gi < g) g = gi;
+                    }
+                if (m > keep) {
+                    double gb = rel_gap(cand[keep - 1].pd, cand[keep].pd);
+                    if (gb < g) g = gb;
+                }
+                rgap_out[k_lo] = g;
+            }
+            if (fgap_out) {
+                /* the decision that drops the forced prefix (or, at the leaves,
+                 * prefers another leaf): relative gap of the two keys */
+                double g = 0.0;
+                if (pos < 0) g = INFINITY;
+                else if (t + J < n && pos >= keep) g = rel_gap(cand[pos].pd, cand[keep - 1].pd);
+                else if (t + J >= n && pos > 0) g = rel_gap(cand[pos].pd, cand[0].pd);
+                if (g > *fgap_out) *fgap_out = g;
+            }
+            if (pos < 0) { /* outside the sphere: the forced path ends here */
+                force_path = NULL;
+            } else if (pos >= keep) { /* keep it anyway: it replaces the last survivor */
                 cand_t f = cand[pos];
                 for (int i = pos; i > keep - 1; --i) cand[i] = cand[i - 1];
                 cand[keep - 1] = f;
@@ -522,6 +582,32 @@ uint32_t orc_kbest(int n, int P, const double* R, const double* z, int K, const 
     return flags;
 }
 
+/* smaller of two near-tie margins (relative gap, the two values) */
+static void merge_margin(double* margin, const double* other)
+{
+    if (margin && other[0] < margin[0]) memcpy(margin, other, sizeof(double) * 3);
+}
+
+/* An empty sphere is searched again with r2 = +inf (reading of Sec. III-B,
+ * as for the SD). */
+uint32_t orc_kbest(int n, int P, const double* R, const double* z, int K, const int* k_sched,
+                   double r2, int J, const int* force_path, int* x_out, double* pd_out,
+                   double* margin_out, int* rank_out, double* fgap_out, double* rgap_out,
+                   int64_t* counters)
+{
+    if (fgap_out) *fgap_out = 0.0;
+    uint32_t f = kbest_search(n, P, R, z, K, k_sched, r2, J, force_path, x_out, pd_out, margin_out,
+                              rank_out, fgap_out, rgap_out, counters);
+    if ((f & ORC_EMPTY_SPHERE) && isfinite(r2)) {
+        double m2[3];
+        if (fgap_out) *fgap_out = 0.0;
+        f = kbest_search(n, P, R, z, K, k_sched, INFINITY, J, force_path, x_out, pd_out,
+                         margin_out ? m2 : NULL, rank_out, fgap_out, rgap_out, counters) | ORC_EMPTY_SPHERE;
+        if (margin_out) merge_margin(margin_out, m2);
+    }
+    return f;
+}
+
 /* ------------------------------------------------------------------ */
 /* Hybrid SD-K-best (Sec. VI) in deterministic rounds                  */
 /*                                                                     */
@@ -550,9 +636,9 @@ typedef struct {
     int c;
 } hcand_t;
 
-uint32_t orc_hybrid(int n, int P, const double* R, const double* z, double r2, int W, int Kw,
-                    const int* k_sched, int master_off, int64_t budget, int* x_out, double* pd_out,
-                    double* margin_out, int64_t* counters)
+static uint32_t hybrid_search(int n, int P, const double* R, const double* z, double r2, int W, int Kw,
+                              const int* k_sched, int master_off, int64_t budget, int* x_out,
+                              double* pd_out, double* margin_out, int64_t* counters, trace_t* T)
 {
     const int kmax = Kw < 1 ? 1 : Kw; /* Kw is the capacity; schedule values are clamped to it */
     const int cap = n * P + 8;
@@ -612,6 +698,7 @@ uint32_t orc_hybrid(int n, int P, const double* R, const double* z, double r2, i
         ++rounds;
         const double r2r = r2;
         int nh = 0;
+        tr(T, "round %lld r2 %.6g pool %d\n", (long long)rounds, r2r, size);
 
         /* 1. master */
         if (!master_off) {
@@ -624,10 +711,12 @@ uint32_t orc_hybrid(int n, int P, const double* R, const double* z, double r2, i
                 if (isfinite(r2r)) note_gap(margin_out, pd, r2r);
                 if (pd >= r2r) {
                     ++stale;
+                    tr(T, "master stale depth %d pd %.6g\n", t, pd);
                     continue;
                 }
                 memcpy(cur, qpath + (size_t)slot * n, sizeof(int) * n);
                 ++expanded;
+                tr(T, "master expand depth %d pd %.6g\n", t, pd);
                 int k = n - 1 - t;
                 double b = centre(n, P, R, z, k, cur);
                 for (int c = 0; c < P; ++c) {
@@ -643,6 +732,7 @@ uint32_t orc_hybrid(int n, int P, const double* R, const double* z, double r2, i
                     if (ch[i].pd < r2r) nk = i + 1;
                 }
                 for (int i = 0; i + 1 < nk; ++i) note_gap(margin_out, ch[i].pd, ch[i + 1].pd);
+                for (int i = 0; i < nk; ++i) tr(T, "  child %d pd %.6g%s\n", ch[i].c, ch[i].pd, t + 1 == n ? " leaf" : "");
                 if (t + 1 == n) {
                     for (int i = 0; i < nk; ++i) {
                         int* lp = leafbuf + (size_t)nh * n;
@@ -677,8 +767,10 @@ uint32_t orc_hybrid(int n, int P, const double* R, const double* z, double r2, i
                 if (isfinite(r2r)) note_gap(margin_out, qpd[slot], r2r);
                 if (qpd[slot] >= r2r) {
                     ++stale;
+                    tr(T, "worker %d stale depth %d pd %.6g\n", w, qt[slot], qpd[slot]);
                     continue;
                 }
+                tr(T, "worker %d takes depth %d pd %.6g\n", w, qt[slot], qpd[slot]);
                 wbusy[w] = 1;
                 wt[w] = qt[slot];
                 wcnt[w] = 1;
@@ -716,11 +808,15 @@ uint32_t orc_hybrid(int n, int P, const double* R, const double* z, double r2, i
             }
             if (m == 0) {
                 wbusy[w] = 0;
+                tr(T, "worker %d depth %d nothing inside: idle\n", w, t);
                 continue;
             }
             qsort(cand, (size_t)m, sizeof(cand_t), cmp_cand);
             int keep = Kt < m ? Kt : m;
             if (m > keep && t + 1 < n) note_gap(margin_out, cand[keep - 1].pd, cand[keep].pd);
+            for (int i = 0; i < keep; ++i)
+                tr(T, "worker %d depth %d keeps parent %d child %d pd %.6g%s\n", w, t, cand[i].parent, cand[i].c,
+                   cand[i].pd, t + 1 == n ? " leaf" : "");
             for (int i = 0; i < keep; ++i) {
                 memcpy(npath + (size_t)i * n, sp + (size_t)cand[i].parent * n, sizeof(int) * n);
                 npath[(size_t)i * n + k] = cand[i].c;
@@ -766,10 +862,14 @@ uint32_t orc_hybrid(int n, int P, const double* R, const double* z, double r2, i
                 best = hc[bi].pd;
                 memcpy(x_out, hc[bi].path, sizeof(int) * n);
                 flags |= ORC_FOUND;
+                tr(T, "radius %.6g from source %d\n", r2, hc[bi].src);
             }
         }
     }
-    if (!(flags & ORC_FOUND)) flags |= ORC_EMPTY_SPHERE;
+    tr(T, "end expanded %lld evaluated %lld rounds %lld stale %lld\n", (long long)expanded,
+       (long long)evaluated, (long long)rounds, (long long)stale);
+    /* empty: the pool drained and no leaf lies inside the sphere */
+    if (!(flags & ORC_FOUND) && (flags & ORC_CERTIFIED)) flags |= ORC_EMPTY_SPHERE;
     if (pd_out) *pd_out = best;
     if (counters) {
         counters[0] += expanded;
@@ -792,6 +892,35 @@ uint32_t orc_hybrid(int n, int P, const double* R, const double* z, double r2, i
     free(leafbuf);
     free(cur);
     return flags;
+}
+
+/* An empty sphere is searched again with r2 = +inf (reading of Sec. III-B). */
+uint32_t orc_hybrid(int n, int P, const double* R, const double* z, double r2, int W, int Kw,
+                    const int* k_sched, int master_off, int64_t budget, int* x_out, double* pd_out,
+                    double* margin_out, int64_t* counters)
+{
+    uint32_t f = hybrid_search(n, P, R, z, r2, W, Kw, k_sched, master_off, budget, x_out, pd_out,
+                               margin_out, counters, NULL);
+    if ((f & ORC_EMPTY_SPHERE) && isfinite(r2)) {
+        double m2[3];
+        f = hybrid_search(n, P, R, z, INFINITY, W, Kw, k_sched, master_off, budget, x_out, pd_out,
+                          margin_out ? m2 : NULL, counters, NULL) | ORC_EMPTY_SPHERE;
+        if (margin_out) merge_margin(margin_out, m2);
+    }
+    return f;
+}
+
+/* One frame of the hybrid with a text trace of its rounds written to buf
+ * (at most cap bytes, NUL-terminated): the round-start radius and pool
+ * size, every pop (expanded or stale) with its depth and pd, the children
+ * kept, the workers' hand-offs and levels, and each radius update. */
+uint32_t orc_hybrid_trace(int n, int P, const double* R, const double* z, double r2, int W, int Kw,
+                          int master_off, int64_t budget, int* x_out, double* pd_out, int64_t* counters,
+                          char* buf, int cap)
+{
+    trace_t T = {buf, (size_t)(cap > 0 ? cap : 0), 0};
+    if (cap > 0) buf[0] = 0;
+    return hybrid_search(n, P, R, z, r2, W, Kw, NULL, master_off, budget, x_out, pd_out, NULL, counters, &T);
 }
 
 /* ------------------------------------------------------------------ */
@@ -828,25 +957,9 @@ void orc_prune_features(int n, int P, const double* R, const double* z, double s
 /* ------------------------------------------------------------------ */
 /* MLP 4 -> 128 -> 128 -> 1 (ReLU), pinball loss, Adam                 */
 /* ------------------------------------------------------------------ */
-/* Nearest IEEE binary16 value of x, ties to even: 11 significant bits for
- * normal values (|x| >= 2^-14), spacing 2^-24 below (subnormals), +-inf from
- * 65520 = 65504 + half an ulp on. */
-double orc_round_half(double x)
-{
-    if (x == 0.0 || !isfinite(x)) return x;
-    const double ax = fabs(x);
-    if (ax >= 65520.0) return copysign(INFINITY, x);
-    int e;
-    frexp(ax, &e); /* ax in [2^(e-1), 2^e) */
-    const double ulp = (e - 1 < -14) ? ldexp(1.0, -24) : ldexp(1.0, e - 1 - 10);
-    return copysign(nearbyint(ax / ulp) * ulp, x); /* default rounding: nearest, ties to even */
-}
-
-/* One state through the MLP; f16 != 0 rounds the second layer's operands,
- * ReLU(layer 1) and W2, to binary16 (the inference precision of the GPU
- * library), everything else stays FP64. */
+/* One state through the MLP, FP64 throughout. */
 static void mlp_one(const double* w, const double* x, double* a1, double* h1, double* a2,
-                    double* h2, double* out, int f16)
+                    double* h2, double* out)
 {
     const int H = ORC_MLP_H;
     for (int i = 0; i < H; ++i) {
@@ -854,14 +967,10 @@ static void mlp_one(const double* w, const double* x, double* a1, double* h1, do
         for (int j = 0; j < ORC_MLP_IN; ++j) s += w[ORC_MLP_W1 + i * ORC_MLP_IN + j] * x[j];
         a1[i] = s;
         h1[i] = s > 0.0 ? s : 0.0;
-        if (f16) h1[i] = orc_round_half(h1[i]);
     }
     for (int i = 0; i < H; ++i) {
         double s = w[ORC_MLP_B2 + i];
-        for (int j = 0; j < H; ++j) {
-            const double wij = f16 ? orc_round_half(w[ORC_MLP_W2 + i * H + j]) : w[ORC_MLP_W2 + i * H + j];
-            s += wij * h1[j];
-        }
+        for (int j = 0; j < H; ++j) s += w[ORC_MLP_W2 + i * H + j] * h1[j];
         a2[i] = s;
         h2[i] = s > 0.0 ? s : 0.0;
     }
@@ -873,13 +982,7 @@ static void mlp_one(const double* w, const double* x, double* a1, double* h1, do
 void orc_mlp_forward(const double* w, const double* X, int B, double* out)
 {
     double a1[ORC_MLP_H], h1[ORC_MLP_H], a2[ORC_MLP_H], h2[ORC_MLP_H];
-    for (int b = 0; b < B; ++b) mlp_one(w, X + (size_t)b * ORC_MLP_IN, a1, h1, a2, h2, out + b, 0);
-}
-
-void orc_mlp_forward_f16(const double* w, const double* X, int B, double* out)
-{
-    double a1[ORC_MLP_H], h1[ORC_MLP_H], a2[ORC_MLP_H], h2[ORC_MLP_H];
-    for (int b = 0; b < B; ++b) mlp_one(w, X + (size_t)b * ORC_MLP_IN, a1, h1, a2, h2, out + b, 1);
+    for (int b = 0; b < B; ++b) mlp_one(w, X + (size_t)b * ORC_MLP_IN, a1, h1, a2, h2, out + b);
 }
 
 double orc_mlp_loss_grad(const double* w, const double* X, const double* y, int B, double tau,
@@ -892,7 +995,7 @@ double orc_mlp_loss_grad(const double* w, const double* X, const double* y, int 
     for (int b = 0; b < B; ++b) {
         const double* x = X + (size_t)b * ORC_MLP_IN;
         double o;
-        mlp_one(w, x, a1, h1, a2, h2, &o, 0);
+        mlp_one(w, x, a1, h1, a2, h2, &o);
         double r = y[b] - o;
         loss += r > 0.0 ? tau * r : (tau - 1.0) * r;
         double dout = (r > 0.0 ? -tau : 1.0 - tau) / (double)B;
@@ -1015,7 +1118,7 @@ void orc_batch_sesd(int B, int n, int P, const double* R, const double* z, const
 void orc_batch_kbest(int B, int n, int P, const double* R, const double* z, int K,
                      const int* k_sched, int k_sched_stride, double r2, int J,
                      const int* force_path, int* x_out, double* pd_out, double* margin_out,
-                     int* rank_out, uint32_t* flags, int64_t* counters)
+                     int* rank_out, double* fgap_out, double* rgap_out, uint32_t* flags, int64_t* counters)
 {
 #pragma omp parallel for schedule(dynamic, 4)
     for (int b = 0; b < B; ++b) {
@@ -1025,14 +1128,16 @@ void orc_batch_kbest(int B, int n, int P, const double* R, const double* z, int 
                                force_path ? force_path + (size_t)b * n : NULL,
                                x_out + (size_t)b * n, pd_out ? pd_out + b : NULL,
                                margin_out ? margin_out + (size_t)b * 3 : NULL,
-                               rank_out ? rank_out + (size_t)b * n : NULL, ctr);
+                               rank_out ? rank_out + (size_t)b * n : NULL,
+                               fgap_out ? fgap_out + b : NULL, rgap_out ? rgap_out + (size_t)b * n : NULL,
+                               ctr);
         if (flags) flags[b] = f;
         if (counters)
             for (int i = 0; i < ORC_NCOUNTERS; ++i) counters[(size_t)b * ORC_NCOUNTERS + i] = ctr[i];
     }
 }
 
-void orc_batch_hybrid(int B, int n, int P, const double* R, const double* z, double r2, int W,
+void orc_batch_hybrid(int B, int n, int P, const double* R, const double* z, const double* r2, int W,
                       int Kw, const int* k_sched, int k_sched_stride, int master_off,
                       int64_t budget, int* x_out, double* pd_out, double* margin_out,
                       uint32_t* flags, int64_t* counters)
@@ -1040,7 +1145,7 @@ void orc_batch_hybrid(int B, int n, int P, const double* R, const double* z, dou
 #pragma omp parallel for schedule(dynamic, 1)
     for (int b = 0; b < B; ++b) {
         int64_t ctr[ORC_NCOUNTERS] = {0, 0, 0, 0};
-        uint32_t f = orc_hybrid(n, P, R + (size_t)b * n * n, z + (size_t)b * n, r2, W, Kw,
+        uint32_t f = orc_hybrid(n, P, R + (size_t)b * n * n, z + (size_t)b * n, r2 ? r2[b] : INFINITY, W, Kw,
                                 k_sched ? k_sched + (size_t)b * k_sched_stride : NULL, master_off,
                                 budget, x_out + (size_t)b * n, pd_out ? pd_out + b : NULL,
                                 margin_out ? margin_out + (size_t)b * 3 : NULL, ctr);

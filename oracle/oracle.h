@@ -33,7 +33,8 @@ extern "C" {
 
 /* flags (oracle-side names; bit meanings mirror the problem statement) */
 #define ORC_FOUND            1u   /* a leaf inside the radius was found        */
-#define ORC_EMPTY_SPHERE     2u   /* finite radius left no leaf                 */
+#define ORC_EMPTY_SPHERE     2u   /* finite radius left no leaf; searched again  */
+                                  /* with r2 = +inf (reading of Sec. III-B)      */
 #define ORC_BUDGET_EXHAUSTED 4u   /* node budget reached before the list emptied */
 #define ORC_CERTIFIED        8u   /* list emptied: exact ML within the radius   */
 
@@ -78,11 +79,20 @@ uint32_t orc_sesd(int n, int P, const double* R, const double* z, double r2, int
  * complex-symbol branching), K_t = k_sched[k_lo] clamped to [1, K] if k_sched else K.
  * force_path (or NULL): a complete path whose prefix is kept at every step
  * (label generation); its 1-based rank among the sorted candidates of each
- * step goes to rank_out[k_lo] (if rank_out).  margin_out (or NULL) receives
- * [0] the smallest relative gap of any decision taken, [1],[2] the pair. */
+ * step goes to rank_out[k_lo] (if rank_out), and fgap_out (if not NULL)
+ * receives the largest relative gap between the forced prefix and the key
+ * that beat it, over the decisions that would have dropped it (the K_t-th
+ * survivor) or preferred another leaf (the best leaf): 0 when the forced
+ * path is the search's own result, +inf when it leaves the sphere.
+ * rgap_out[k_lo] (if not NULL) receives how close that step's rank is to
+ * changing: the smallest relative gap between the forced candidate and any
+ * other, or between the last survivor and the first dropped candidate.
+ * margin_out (or NULL) receives [0] the smallest relative gap of any
+ * decision taken, [1],[2] the pair. */
 uint32_t orc_kbest(int n, int P, const double* R, const double* z, int K, const int* k_sched,
                    double r2, int J, const int* force_path, int* x_out, double* pd_out,
-                   double* margin_out, int* rank_out, int64_t* counters);
+                   double* margin_out, int* rank_out, double* fgap_out, double* rgap_out,
+                   int64_t* counters);
 
 /* Hybrid SD-K-best (Sec. VI) in deterministic rounds; W workers each keep
  * Kw survivors (or k_sched[k] clamped to [1, Kw] when k_sched is not NULL).  master_off hands
@@ -90,6 +100,10 @@ uint32_t orc_kbest(int n, int P, const double* R, const double* z, int K, const 
 uint32_t orc_hybrid(int n, int P, const double* R, const double* z, double r2, int W, int Kw,
                     const int* k_sched, int master_off, int64_t budget, int* x_out, double* pd_out,
                     double* margin_out, int64_t* counters);
+/* The same search for one frame with a text trace of its rounds in buf. */
+uint32_t orc_hybrid_trace(int n, int P, const double* R, const double* z, double r2, int W, int Kw,
+                          int master_off, int64_t budget, int* x_out, double* pd_out, int64_t* counters,
+                          char* buf, int cap);
 
 /* Learned-pruning state of a frame: per level k, 4 features from the SIC
  * (K = 1) path: [k/n, distance of the SIC centre to the nearest decision
@@ -109,12 +123,6 @@ void orc_prune_features(int n, int P, const double* R, const double* z, double s
 #define ORC_MLP_NPARAM (ORC_MLP_B3 + 1)
 
 void orc_mlp_forward(const double* w, const double* X, int B, double* out);
-/* Nearest binary16 value (ties to even) of x, as a double. */
-double orc_round_half(double x);
-/* The forward pass with the second layer's operands (ReLU of layer 1 and W2)
- * rounded to binary16, the rest in FP64: the precision in which the GPU
- * library takes its survivor-count decisions. */
-void orc_mlp_forward_f16(const double* w, const double* X, int B, double* out);
 /* mean pinball loss at quantile tau; grad (NPARAM) of the mean loss. */
 double orc_mlp_loss_grad(const double* w, const double* X, const double* y, int B, double tau,
                          double* grad);
@@ -140,8 +148,9 @@ void orc_batch_sesd(int B, int n, int P, const double* R, const double* z, const
 void orc_batch_kbest(int B, int n, int P, const double* R, const double* z, int K,
                      const int* k_sched, int k_sched_stride, double r2, int J,
                      const int* force_path, int* x_out, double* pd_out, double* margin_out,
-                     int* rank_out, uint32_t* flags, int64_t* counters);
-void orc_batch_hybrid(int B, int n, int P, const double* R, const double* z, double r2, int W,
+                     int* rank_out, double* fgap_out, double* rgap_out, uint32_t* flags,
+                     int64_t* counters);
+void orc_batch_hybrid(int B, int n, int P, const double* R, const double* z, const double* r2, int W,
                       int Kw, const int* k_sched, int k_sched_stride, int master_off,
                       int64_t budget, int* x_out, double* pd_out, double* margin_out,
                       uint32_t* flags, int64_t* counters);

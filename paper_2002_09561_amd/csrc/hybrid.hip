@@ -39,6 +39,10 @@ struct HybArgs {
     float* pd;
     uint32_t* flags;
     int64_t* counters;
+    // re-run mode: only frames whose finite radius left the drained pool
+    // without a leaf (EMPTY_SPHERE, no FOUND or NONFINITE_INPUT) run again,
+    // with r2 = +inf; flags keep EMPTY_SPHERE, counters accumulate
+    int rerun;
 };
 
 __device__ inline void wave_sync()
@@ -83,6 +87,10 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
 {
     extern __shared__ unsigned char smem_hy[];
     const int frame = blockIdx.x;
+    if (a.rerun) {  // uniform over the workgroup
+        const uint32_t fl = a.flags[frame];
+        if (!(fl & MIMO_FLAG_EMPTY_SPHERE) || (fl & (MIMO_FLAG_FOUND | MIMO_FLAG_NONFINITE_INPUT))) return;
+    }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int n = a.n, W = a.W, Kw = a.Kw;
     const HybLayout Lo(n, W, Kw, P);
@@ -158,6 +166,7 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
         int busy_any = 0;
         for (int w = 0; w < W; ++w) busy_any |= wst[8 * w];
         const int64_t expanded = ((int64_t)(uint32_t)sc[SC_EXP_HI] << 32) | (uint32_t)sc[SC_EXP_LO];
+        if (sc[SC_DONE]) break;  // non-finite input seen
         if (sc[SC_PSIZE] == 0 && !busy_any) {
             if (threadIdx.x == 0) sc[SC_FLAGS] |= MIMO_FLAG_CERTIFIED;
             break;
@@ -203,8 +212,11 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                 d = __shfl(d, 0, WAVE);
                 c = __shfl(c, 0, WAVE);
                 pd = __shfl(pd, 0, WAVE);
-                const int lev = n - d;  // level of the node's own symbol (n for the root)
-                const int k = lev - 1;  // level its children fix
+            }
+            const int lev = n - d;  // level of the node's own symbol (n for the root)
+            const int k = lev - 1;  // level its children fix
+            float b = 0.f, rkk = 0.f;
+            if (ok) {
                 const float* rk = Rf + r_row_off(n, k);
                 float acc = 0.f, rsum = 0.f;
                 for (int t = 1 + lane; t < n - k; t += WAVE) {
@@ -216,8 +228,17 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                 }
                 acc = wave_sum(acc);
                 rsum = wave_sum(rsum);
-                const float b = zf[k] - (2.f * acc - (float)(P - 1) * rsum);
-                const float rkk = cs * rk[0];
+                b = zf[k] - (2.f * acc - (float)(P - 1) * rsum);
+                rkk = cs * rk[0];
+                if (!__builtin_isfinite(b) || !__builtin_isfinite(rkk)) {  // uniform: NaN or inf in R or z
+                    if (lane == 0) {
+                        sc[SC_DONE] = 1;
+                        sc[SC_FLAGS] |= MIMO_FLAG_NONFINITE_INPUT;
+                    }
+                    ok = 0;
+                }
+            }
+            if (ok) {
                 float pdc = INFINITY;
                 if (lane < P) {
                     const float ee = fmaf(-rkk, (float)(2 * lane - (P - 1)), b);
@@ -355,8 +376,14 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                 for (int m = 1; m < P; m <<= 1) acc += shfl_xor_f(acc, m);
                 const float b = zf[k] - (2.f * acc - (float)(P - 1) * rsum);
                 const float rkk = cs * rk[0];
+                // a NaN or infinity in R or z: the frame's search stops after this round
+                const bool bad = __ballot(!__builtin_isfinite(rkk) || (s < cnt && !__builtin_isfinite(b))) != 0;
+                if (bad && lane == 0) {
+                    sc[SC_DONE] = 1;
+                    atomicOr(reinterpret_cast<unsigned int*>(&sc[SC_FLAGS]), MIMO_FLAG_NONFINITE_INPUT);
+                }
                 uint64_t key[1] = {~0ull};
-                if (s < cnt) {
+                if (s < cnt && !bad) {
                     const float ee = fmaf(-rkk, (float)(2 * cc - (P - 1)), b);
                     const float pdc = fmaf(ee, ee, scur[s]);
                     if (pdc < r2r) key[0] = ((uint64_t)__float_as_uint(pdc) << 32) | (uint32_t)lane;
@@ -435,19 +462,30 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
     }
 
     __syncthreads();
-    const int found = sc[SC_FOUND];
+    const int nonfinite = (sc[SC_FLAGS] & MIMO_FLAG_NONFINITE_INPUT) != 0;
+    const int found = sc[SC_FOUND] && !nonfinite;
     if (threadIdx.x == 0) {
         uint32_t fl = (uint32_t)sc[SC_FLAGS];
-        fl |= found ? MIMO_FLAG_FOUND : MIMO_FLAG_EMPTY_SPHERE;
+        if (found) fl |= MIMO_FLAG_FOUND;
+        // the sphere is empty when the drained pool gave no leaf inside it
+        else if ((fl & MIMO_FLAG_CERTIFIED) && !nonfinite) fl |= MIMO_FLAG_EMPTY_SPHERE;
+        if (a.rerun) fl |= MIMO_FLAG_EMPTY_SPHERE;
         if (a.flags) a.flags[frame] = fl;
         if (a.pd) a.pd[frame] = found ? *sc_r2 : INFINITY;
         if (a.counters) {
             const int64_t e = ((int64_t)(uint32_t)sc[SC_EXP_HI] << 32) | (uint32_t)sc[SC_EXP_LO];
             int64_t* c = a.counters + (size_t)frame * 4;
-            c[0] = e;
-            c[1] = e * P;
-            c[2] = sc[SC_ROUNDS];
-            c[3] = sc[SC_STALE];
+            if (a.rerun) {
+                c[0] += e;
+                c[1] += e * P;
+                c[2] += sc[SC_ROUNDS];
+                c[3] += sc[SC_STALE];
+            } else {
+                c[0] = e;
+                c[1] = e * P;
+                c[2] = sc[SC_ROUNDS];
+                c[3] = sc[SC_STALE];
+            }
         }
     }
     if (a.sym) {
@@ -506,8 +544,18 @@ extern "C" int32_t sd_hybrid_detect(const float* R, const float* z, int32_t B, i
     if (B == 0) return MIMO_OK;
     if (!R || !z || !sym || !pd || !flags) return fail(MIMO_ERR_INVALID_ARG, "sd_hybrid_detect: null pointer");
     HybArgs a{R, z, n, n_workers, k_worker, k_sched, k_sched_stride, radius2, master_off, node_budget,
-              sym, pd, flags, counters};
+              sym, pd, flags, counters, 0};
     hipStream_t st = (hipStream_t)stream;
+    int32_t rc;
+    switch (pam) {
+    case 2: rc = launch_hybrid<2>(a, B, st); break;
+    case 4: rc = launch_hybrid<4>(a, B, st); break;
+    default: rc = launch_hybrid<8>(a, B, st); break;
+    }
+    if (rc || !radius2) return rc;
+    // frames whose finite radius left no leaf: again with r2 = +inf
+    a.radius2 = nullptr;
+    a.rerun = 1;
     switch (pam) {
     case 2: return launch_hybrid<2>(a, B, st);
     case 4: return launch_hybrid<4>(a, B, st);

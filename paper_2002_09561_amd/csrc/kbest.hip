@@ -39,7 +39,17 @@ struct KbestArgs {
     // metric pd exceeds (sigma2/2) (n + beta sqrt(2n)), are detected again
     const float* fb_sigma2;
     float fb_beta;
+    // re-run mode: only frames whose finite radius left no leaf (EMPTY_SPHERE
+    // without FOUND or NONFINITE_INPUT) are detected again, with r2 = +inf;
+    // their flags keep EMPTY_SPHERE and their counters accumulate
+    int rerun;
 };
+
+// does a frame stand as it is in re-run mode?
+__device__ inline bool kb_rerun_skips(uint32_t fl)
+{
+    return !(fl & MIMO_FLAG_EMPTY_SPHERE) || (fl & (MIMO_FLAG_FOUND | MIMO_FLAG_NONFINITE_INPUT));
+}
 
 // does a first detection stand?  Not when flagged for the fallback or not
 // found, nor when its search metric exceeds (sigma2 / 2) (n + beta sqrt(2 n))
@@ -55,6 +65,7 @@ __device__ inline bool kb_first_stands(uint32_t fl, float pd, float sigma2, floa
 // fallback mode: does frame `frame` keep its first detection?
 __device__ inline bool kb_keep_first(const KbestArgs& a, int frame)
 {
+    if (a.rerun) return kb_rerun_skips(a.flags[frame]);
     if (!a.fb_sigma2) return false;
     return kb_first_stands(a.flags[frame], a.pd[frame], a.fb_sigma2[frame], a.fb_beta, a.n);
 }
@@ -91,6 +102,23 @@ __host__ __device__ inline size_t kbest_lds_bytes(int n)
            + sizeof(int32_t) * S::KCAP                     // selected candidate ids
            + sizeof(uint64_t) * S::KCAP;                   // compacted keys
 }
+
+// per-frame counters: overwritten, or added to in re-run mode
+__device__ inline void kb_write_counters(const KbestArgs& a, int frame, int64_t expanded, int evals_per_node)
+{
+    int64_t* c = a.counters + (size_t)frame * 4;
+    if (a.rerun) {
+        c[0] += expanded;
+        c[1] += expanded * evals_per_node;
+    } else {
+        c[0] = expanded;
+        c[1] = expanded * evals_per_node;
+        c[2] = 0;
+        c[3] = 0;
+    }
+}
+
+__device__ inline bool kb_finite(float v) { return __builtin_isfinite(v); }
 
 __device__ inline float half_lo(uint32_t d) { return (float)__builtin_bit_cast(_Float16, (unsigned short)(d & 0xffffu)); }
 __device__ inline float half_hi(uint32_t d) { return (float)__builtin_bit_cast(_Float16, (unsigned short)(d >> 16)); }
@@ -537,6 +565,18 @@ __device__ __forceinline__ void kbest_frame(const KbestArgs& a, int frame, unsig
             for (int m = 1; m < L; m <<= 1) acc += shfl_xor_f(acc, m);
             bu[u] = zk - acc;
         }
+        // a NaN or infinity in R or z reaches every centre of the level
+        bool bad = !kb_finite(rkk);
+#pragma unroll
+        for (int u = 0; u < SPL; ++u) {
+            const int s = (KCAP >= WAVE) ? lane + WAVE * u : lane / L;
+            bad = bad || (s < cnt && !kb_finite(bu[u]));
+        }
+        if (__ballot(bad)) {
+            flags |= MIMO_FLAG_NONFINITE_INPUT;
+            cnt = 0;
+            break;
+        }
         // children: key = (pd bits, candidate index s * P + c)
         uint32_t kh[E];
 #pragma unroll
@@ -614,15 +654,10 @@ __device__ __forceinline__ void kbest_frame(const KbestArgs& a, int frame, unsig
     if (lane == 0) {
         if (cnt > 0) flags |= MIMO_FLAG_FOUND;
         if (a.fb_sigma2) flags |= MIMO_FLAG_LEARNED_FALLBACK;
+        if (a.rerun) flags |= MIMO_FLAG_EMPTY_SPHERE;
         if (a.flags) a.flags[frame] = flags;
         if (a.pd) a.pd[frame] = cnt > 0 ? spd[(n & 1) * KCAP] : INFINITY;
-        if (a.counters) {
-            int64_t* c = a.counters + (size_t)frame * 4;
-            c[0] = expanded;
-            c[1] = expanded * P;
-            c[2] = 0;
-            c[3] = 0;
-        }
+        if (a.counters) kb_write_counters(a, frame, expanded, P);
     }
     // outputs: survivor 0 of the last buffer is the best leaf
     const uint32_t* best = path + (n & 1) * KCAP * stride;
@@ -752,6 +787,12 @@ __device__ __forceinline__ void kbest_frame_reg(const KbestArgs& a, int frame, u
 #pragma unroll
         for (int m = 1; m < L; m <<= 1) acc += shfl_xor_f(acc, m);
         const float bown = zk - acc;
+        // a NaN or infinity in R or z reaches every centre of the level
+        if (__ballot(!kb_finite(rkk) || (s_own < cnt && !kb_finite(bown)))) {
+            flags |= MIMO_FLAG_NONFINITE_INPUT;
+            cnt = 0;
+            break;
+        }
         uint32_t kh[E];
         const int ncand = cnt * P;
 #pragma unroll
@@ -779,6 +820,7 @@ __device__ __forceinline__ void kbest_frame_reg(const KbestArgs& a, int frame, u
         }
         int Kt = ks ? ks[k] : a.K;
         Kt = Kt > a.K ? a.K : (Kt < 1 ? 1 : Kt);
+        Kt = Kt > KCAP ? KCAP : Kt;  // the instantiation's survivor capacity
         int fm = -1;
         if (fsym && fs >= 0) {
             const int sy = fsym[k >> 1];
@@ -837,15 +879,10 @@ __device__ __forceinline__ void kbest_frame_reg(const KbestArgs& a, int frame, u
     if (lane == 0) {
         if (cnt > 0) flags |= MIMO_FLAG_FOUND;
         if (a.fb_sigma2) flags |= MIMO_FLAG_LEARNED_FALLBACK;
+        if (a.rerun) flags |= MIMO_FLAG_EMPTY_SPHERE;
         if (a.flags) a.flags[frame] = flags;
         if (a.pd) a.pd[frame] = cnt > 0 ? spd[(n & 1) * KCAP] : INFINITY;
-        if (a.counters) {
-            int64_t* c = a.counters + (size_t)frame * 4;
-            c[0] = expanded;
-            c[1] = expanded * P;
-            c[2] = 0;
-            c[3] = 0;
-        }
+        if (a.counters) kb_write_counters(a, frame, expanded, P);
     }
     // survivor 0 (lanes 0 .. L-1) is the best leaf; word w holds symbol w
     if (!a.sym || s_own != 0) return;
@@ -992,6 +1029,13 @@ __device__ __forceinline__ void kbest_frame_cplx(const KbestArgs& a, int frame, 
             al += shfl_xor_f(al, j);
         }
         const float bh_own = zh - ah, bl_own = zl - al;
+        // a NaN or infinity in R or z reaches every centre of the level
+        if (__ballot(!kb_finite(rkh) || !kb_finite(rkl) ||
+                     (s_own < cnt && !(kb_finite(bh_own) && kb_finite(bl_own))))) {
+            flags |= MIMO_FLAG_NONFINITE_INPUT;
+            cnt = 0;
+            break;
+        }
         uint32_t kh[E];
         const int ncand = cnt * PC;
 #pragma unroll
@@ -1063,15 +1107,10 @@ __device__ __forceinline__ void kbest_frame_cplx(const KbestArgs& a, int frame, 
 
     if (lane == 0) {
         if (cnt > 0) flags |= MIMO_FLAG_FOUND;
+        if (a.rerun) flags |= MIMO_FLAG_EMPTY_SPHERE;
         if (a.flags) a.flags[frame] = flags;
         if (a.pd) a.pd[frame] = cnt > 0 ? spd[(nw & 1) * KCAP] : INFINITY;
-        if (a.counters) {
-            int64_t* c = a.counters + (size_t)frame * 4;
-            c[0] = expanded;
-            c[1] = expanded * PC * 2;  // real-level evaluations
-            c[2] = 0;
-            c[3] = 0;
-        }
+        if (a.counters) kb_write_counters(a, frame, expanded, PC * 2);  // real-level evaluations
     }
     // survivor 0 (lanes 0 .. L-1) is the best leaf; word w holds symbol w
     if (!a.sym || s_own != 0) return;
@@ -1094,6 +1133,7 @@ template <int P, int E, int NWMAX>
 __global__ void __launch_bounds__(64) kbest_cplx_kernel(KbestArgs a)
 {
     extern __shared__ unsigned char smem_kbc[];
+    if (kb_keep_first(a, blockIdx.x)) return;
     kbest_frame_cplx<P, E, NWMAX>(a, blockIdx.x, smem_kbc);
 }
 
@@ -1299,6 +1339,13 @@ __global__ void __launch_bounds__(WAVE) kbest_pair_kernel(KbestArgs a, int B)
         acc += shfl_xor_f(acc, 1);
         acc += shfl_xor_f(acc, 2);
         const float bown = zk - acc;
+        // a NaN or infinity in this frame's R or z reaches every centre of the
+        // level: the frame ends here (its partner goes on)
+        const bool bad = (__ballot(!kb_finite(rkk) || (s_own < cnt && !kb_finite(bown))) & hmask) != 0;
+        if (bad && cnt > 0) {
+            flags |= MIMO_FLAG_NONFINITE_INPUT;
+            cnt = 0;
+        }
         // candidates m = hl (and 32 + hl): child m % P of survivor m / P
         const int cmax = max(cnt, (int)xor_lanes((uint32_t)cnt, PR_HALF, lane));
         const bool two = cmax * P > PR_HALF;  // the same in both halves
@@ -1365,13 +1412,7 @@ __global__ void __launch_bounds__(WAVE) kbest_pair_kernel(KbestArgs a, int B)
         if (cnt > 0) flags |= MIMO_FLAG_FOUND;
         if (a.flags) a.flags[frame] = flags;
         if (a.pd) a.pd[frame] = cnt > 0 ? spd[(n & 1) * KCAP] : INFINITY;
-        if (a.counters) {
-            int64_t* c = a.counters + (size_t)frame * 4;
-            c[0] = expanded;
-            c[1] = expanded * P;
-            c[2] = 0;
-            c[3] = 0;
-        }
+        if (a.counters) kb_write_counters(a, frame, expanded, P);
     }
     // survivor 0 (lanes 32h .. 32h+3) is the best leaf; word w holds symbol w
     if (!live || !a.sym || s_own != 0) return;
@@ -1442,7 +1483,7 @@ static int32_t dispatch_kbest_p(const KbestArgs& a, int B, hipStream_t st)
     const int need = a.K * P;  // candidates per level
     if constexpr (P == PR_P) {
         // at most 8 survivors of 64-QAM, 64 < n <= 208, detection mode: two frames per wavefront
-        if (need <= 64 && a.n > 64 && a.n <= 208 && !a.fb_sigma2 && !a.force_sym) {
+        if (need <= 64 && a.n > 64 && a.n <= 208 && !a.fb_sigma2 && !a.force_sym && !a.rerun) {
             hipLaunchKernelGGL(kbest_pair_kernel<104>, dim3((B + 1) / 2), dim3(WAVE), kbest_pair_lds_bytes<104>(), st,
                                a, B);
             return check_launch("kbest_detect");
@@ -1464,6 +1505,34 @@ static int32_t dispatch_kbest(const KbestArgs& a, int pam, int B, hipStream_t st
     }
 }
 
+// LDS bytes of the survivor-list (LDS) variant the dispatch picks for K
+// survivors of P points at n levels; 0 for the register variants, whose LDS
+// need is a few KB at any n
+template <int P, int E>
+static size_t lds_need_pe(int n)
+{
+    if constexpr (KbestShape<P, E>::KCAP <= 64) return 0;
+    else return kbest_lds_bytes<P, E>(n);
+}
+
+template <int P>
+static size_t kbest_lds_need_p(int K, int n)
+{
+    const int need = K * P;
+    if (need <= 64) return lds_need_pe<P, 1>(n);
+    if (need <= 128) return lds_need_pe<P, 2>(n);
+    if (need <= 256) return lds_need_pe<P, 4>(n);
+    if (need <= 512) return lds_need_pe<P, 8>(n);
+    return lds_need_pe<P, 16>(n);
+}
+
+static size_t kbest_lds_need(int pam, int K, int n)
+{
+    return pam == 2 ? kbest_lds_need_p<2>(K, n) : (pam == 4 ? kbest_lds_need_p<4>(K, n) : kbest_lds_need_p<8>(K, n));
+}
+
+constexpr size_t LDS_PER_CU = 160 * 1024;
+
 static int32_t validate_common(const char* who, int B, int n_tx, int pam, int K)
 {
     if (B < 0) return fail(MIMO_ERR_INVALID_ARG, "%s: B < 0", who);
@@ -1473,8 +1542,15 @@ static int32_t validate_common(const char* who, int B, int n_tx, int pam, int K)
     if (K < 1) return fail(MIMO_ERR_INVALID_ARG, "%s: K < 1", who);
     if (K > MIMO_MAX_K || K * pam > 1024)
         return fail(MIMO_ERR_UNSUPPORTED, "%s: K <= %d and K * pam <= 1024", who, MIMO_MAX_K);
+    const size_t lds = kbest_lds_need(pam, K, 2 * n_tx);
+    if (lds > LDS_PER_CU)
+        return fail(MIMO_ERR_UNSUPPORTED, "%s: K = %d survivors of %d levels need %zu bytes of LDS (> %zu)", who, K,
+                    2 * n_tx, lds, LDS_PER_CU);
     return MIMO_OK;
 }
+
+// frames whose finite radius left no leaf are detected again with r2 = +inf
+static int32_t rerun_empty(const KbestArgs& a, int pam, int B, hipStream_t st, bool complex_levels);
 
 }  // namespace mimo
 
@@ -1492,7 +1568,9 @@ extern "C" int32_t kbest_detect(const float* R, const float* z, int32_t B, int32
     if (B == 0) return MIMO_OK;
     if (!R || !z || !sym || !pd || !flags) return fail(MIMO_ERR_INVALID_ARG, "kbest_detect: null pointer");
     KbestArgs a{R, z, n, K, k_sched, k_sched_stride, radius2, nullptr, nullptr, sym, pd, flags, counters, nullptr, 0.f};
-    return dispatch_kbest(a, pam, B, (hipStream_t)stream);
+    rc = dispatch_kbest(a, pam, B, (hipStream_t)stream);
+    if (rc || !radius2) return rc;
+    return rerun_empty(a, pam, B, (hipStream_t)stream, false);
 }
 
 extern "C" int32_t kbest_detect_complex(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam,
@@ -1513,11 +1591,28 @@ extern "C" int32_t kbest_detect_complex(const float* R, const float* z, int32_t 
     KbestArgs a{R, z, n, K, k_sched, k_sched_stride, radius2, nullptr, nullptr, sym, pd, flags, counters, nullptr, 0.f};
     hipStream_t st = (hipStream_t)stream;
     switch (pam) {
-    case 2: return dispatch_kbest_cplx_p<2>(a, B, st);
-    case 4: return dispatch_kbest_cplx_p<4>(a, B, st);
-    default: return dispatch_kbest_cplx_p<8>(a, B, st);
+    case 2: rc = dispatch_kbest_cplx_p<2>(a, B, st); break;
+    case 4: rc = dispatch_kbest_cplx_p<4>(a, B, st); break;
+    default: rc = dispatch_kbest_cplx_p<8>(a, B, st); break;
+    }
+    if (rc || !radius2) return rc;
+    return rerun_empty(a, pam, B, st, true);
+}
+
+namespace mimo {
+static int32_t rerun_empty(const KbestArgs& a, int pam, int B, hipStream_t st, bool complex_levels)
+{
+    KbestArgs r = a;
+    r.radius2 = nullptr;
+    r.rerun = 1;
+    if (!complex_levels) return dispatch_kbest(r, pam, B, st);
+    switch (pam) {
+    case 2: return dispatch_kbest_cplx_p<2>(r, B, st);
+    case 4: return dispatch_kbest_cplx_p<4>(r, B, st);
+    default: return dispatch_kbest_cplx_p<8>(r, B, st);
     }
 }
+}  // namespace mimo
 
 extern "C" int32_t kbest_rank_labels(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam,
                                      int32_t K, const int32_t* force_sym, int32_t* rank, void* stream)
@@ -1564,7 +1659,9 @@ __global__ void reset_counter_kernel_kb(int* counter) { *counter = 0; }
 
 // Uneven batch: one wavefront per workgroup pulls frames from a device work
 // counter and runs K-best with each frame's own constellation and K.
-constexpr int UNEVEN_NWMAX = 64;  // n <= 128 real levels
+constexpr int UNEVEN_NWMAX = 64;     // n <= 128 real levels (n_tx <= 64)
+constexpr int UNEVEN_KMAX = 64;      // survivors held in registers
+constexpr int UNEVEN_CAND_MAX = 256; // K * pam: four blocks of 64 candidates
 
 template <int P, int E>
 __device__ __forceinline__ void kbest_uneven_one(const KbestArgs& a, unsigned char* lds)
@@ -1587,6 +1684,13 @@ __global__ void __launch_bounds__(64) kbest_uneven_kernel(const mimo_frame_desc*
         const mimo_frame_desc d = desc[f];
         const int P = __builtin_amdgcn_readfirstlane(d.pam);
         const int K = __builtin_amdgcn_readfirstlane(d.K);
+        const int ntx = __builtin_amdgcn_readfirstlane(d.n_tx);
+        // descriptors outside the instantiations' range are skipped, flagged
+        if ((P != 2 && P != 4 && P != 8) || K < 1 || K > UNEVEN_KMAX || K * P > UNEVEN_CAND_MAX || ntx < 1 ||
+            ntx > UNEVEN_NWMAX) {
+            if (lane == 0) flags[f] = MIMO_FLAG_INVALID_FRAME;
+            continue;
+        }
         KbestArgs a{R + d.r_off, z + d.z_off, 2 * d.n_tx, K, nullptr, 0, nullptr, nullptr, nullptr,
                     sym + d.s_off, pd + f, flags + f, nullptr, nullptr, 0.f};
         const int need = K * P;

@@ -129,7 +129,29 @@ __global__ void __launch_bounds__(256) mrc_kernel(const float2* __restrict__ H, 
     }
 }
 
+// The paper's radius rule (Sec. III-B, squared): r2 = N M sigma2 per frame,
+// M times the expected noise energy N sigma2 of a receive vector.
+__global__ void __launch_bounds__(256) paper_radius_kernel(const float* __restrict__ sigma2, int B, float nm,
+                                                           float* __restrict__ radius2)
+{
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f < B) radius2[f] = nm * sigma2[f];
+}
+
 }  // namespace mimo
+
+extern "C" int32_t mimo_paper_radius2(const float* sigma2, int32_t B, int32_t n_rx, int32_t n_tx, float* radius2,
+                                      void* stream)
+{
+    using namespace mimo;
+    if (B < 0 || n_tx < 1 || n_rx < n_tx) return fail(MIMO_ERR_INVALID_ARG, "mimo_paper_radius2: bad sizes");
+    if (n_tx > MIMO_MAX_TX || n_rx > MIMO_MAX_RX) return fail(MIMO_ERR_UNSUPPORTED, "mimo_paper_radius2: size limit");
+    if (B == 0) return MIMO_OK;
+    if (!sigma2 || !radius2) return fail(MIMO_ERR_INVALID_ARG, "mimo_paper_radius2: null pointer");
+    hipLaunchKernelGGL(paper_radius_kernel, dim3((B + 255) / 256), dim3(256), 0, (hipStream_t)stream, sigma2, B,
+                       (float)(n_rx * n_tx), radius2);
+    return check_launch("mimo_paper_radius2");
+}
 
 extern "C" int32_t linear_detect(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam, int32_t* sym,
                                  float* xhat, void* stream)

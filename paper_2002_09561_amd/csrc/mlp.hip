@@ -5,11 +5,16 @@
 // wavefront and step, in the transposed form H1^T = W1 X^T, H2^T = W2 H1^T:
 //   * layer 1: FP32 MFMA 16x16x4 (K = the 4 features), bias as the
 //     accumulator's initial value;
-//   * layer 2: FP16 MFMA 16x16x32 with FP32 accumulation: ReLU(h1) and W2 are
-//     rounded to binary16 (their products are exact in FP32); the W2
-//     fragments are staged once per workgroup in LDS (32 KB, each lane's
-//     fragment a 16-byte neighbour of the next lane's), which keeps the
-//     kernel at a few waves per SIMD instead of one;
+//   * layer 2: FP16 MFMA 16x16x32 with FP32 accumulation on split operands:
+//     ReLU(h1) = a_hi + a_lo and W2 = w_hi + w_lo, each part a binary16
+//     value (a_hi the rounding of the FP32 value, a_lo the rounding of the
+//     exact remainder), and W2 h1 is accumulated as w_hi a_hi + w_hi a_lo +
+//     w_lo a_hi (three MFMAs; every product of two halves is exact in FP32).
+//     The dropped w_lo a_lo and the split's rounding are below 2^-21 of
+//     |W2| h1, so layer 2 keeps FP32 accuracy at a fraction of the cost of
+//     FP32 matrix instructions.  The W2 fragments (hi and lo, 64 KB) are
+//     staged once per workgroup of eight waves in LDS (each lane's fragment
+//     a 16-byte neighbour of the next lane's);
 //   * layer 3, biases and ReLU in FP32 on the vector ALUs.
 // The hidden units of layer 1 are computed in a permuted order so that its
 // result registers are already laid out as layer 2's B operand.
@@ -54,11 +59,14 @@ __host__ __device__ inline int mlp_perm(int hb, int i)
 // S states, 16 per wavefront and step; SCHED: K_t = clamp(ceil(2^(yhat +
 // margin)), kmin, kmax) into ks (non-finite yhat: kmax and the frame flagged
 // for fallback), else yhat into out
+constexpr int MLP_WG = 512;                                  // eight waves share the staged W2
+constexpr size_t MLP_W2_LDS = 2 * 8 * 4 * WAVE * sizeof(half8);  // hi and lo fragments: 64 KB
+
 template <bool SCHED>
-__global__ void __launch_bounds__(256) mlp_infer_kernel(const float* __restrict__ w, const float* __restrict__ X,
-                                                        int64_t S, float* __restrict__ out, float margin, int kmin,
-                                                        int kmax, int n, int32_t* __restrict__ ks,
-                                                        uint32_t* __restrict__ flags)
+__global__ void __launch_bounds__(MLP_WG) mlp_infer_kernel(const float* __restrict__ w, const float* __restrict__ X,
+                                                           int64_t S, float* __restrict__ out, float margin, int kmin,
+                                                           int kmax, int n, int32_t* __restrict__ ks,
+                                                           uint32_t* __restrict__ flags)
 {
     __shared__ f32x4 cb1[8 * 4];  // b1 in the permuted order, [hb][g] -> rows 4g..4g+3
     __shared__ f32x4 cb2[32];     // b2, [nb][g] -> units 16nb + 4g .. +3
@@ -75,15 +83,24 @@ __global__ void __launch_bounds__(256) mlp_infer_kernel(const float* __restrict_
 #pragma unroll
     for (int hb = 0; hb < 8; ++hb) a1[hb] = w[OW1 + mlp_perm(hb, s16) * NIN + g];
     // layer-2 A operand of output block nb, step t, for lane (g, s16):
-    // W2[16nb + s16][32t + 8g + e], e = 0..7, at w2f[(4nb + t) 64 + lane]
-    __shared__ half8 w2f[8 * 4 * WAVE];
+    // W2[16nb + s16][32t + 8g + e], e = 0..7, split into w2h + w2l at
+    // [(4nb + t) 64 + lane]
+    extern __shared__ half8 w2dyn[];
+    half8* w2h = w2dyn;
+    half8* w2l = w2dyn + 8 * 4 * WAVE;
     for (int idx = tid; idx < 8 * 4 * WAVE; idx += blockDim.x) {
         const int f = idx / WAVE, ln = idx % WAVE;
         const int nb = f >> 2, t = f & 3;
         const float* row = w + OW2 + (16 * nb + (ln & 15)) * HID + 32 * t + 8 * (ln >> 4);
-        const float4 lo = *reinterpret_cast<const float4*>(row), hi = *reinterpret_cast<const float4*>(row + 4);
-        w2f[idx] = half8{(_Float16)lo.x, (_Float16)lo.y, (_Float16)lo.z, (_Float16)lo.w,
-                         (_Float16)hi.x, (_Float16)hi.y, (_Float16)hi.z, (_Float16)hi.w};
+        half8 h, l;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float v = row[e];
+            h[e] = (_Float16)v;
+            l[e] = (_Float16)(v - (float)h[e]);  // the remainder is exact in FP32
+        }
+        w2h[idx] = h;
+        w2l[idx] = l;
     }
     const float b3 = w[OB3];
     __syncthreads();
@@ -101,12 +118,20 @@ __global__ void __launch_bounds__(256) mlp_infer_kernel(const float* __restrict_
         for (int t = 0; t < 4; ++t) {
             const f32x4 h0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[2 * t], xb, cb1[(2 * t) * 4 + g], 0, 0, 0);
             const f32x4 h1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[2 * t + 1], xb, cb1[(2 * t + 1) * 4 + g], 0, 0, 0);
-            const half8 bk = {(_Float16)fmaxf(h0[0], 0.f), (_Float16)fmaxf(h0[1], 0.f), (_Float16)fmaxf(h0[2], 0.f),
-                              (_Float16)fmaxf(h0[3], 0.f), (_Float16)fmaxf(h1[0], 0.f), (_Float16)fmaxf(h1[1], 0.f),
-                              (_Float16)fmaxf(h1[2], 0.f), (_Float16)fmaxf(h1[3], 0.f)};
+            half8 bh, bl;
 #pragma unroll
-            for (int nb = 0; nb < 8; ++nb)
-                d2[nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w2f[(4 * nb + t) * WAVE + lane], bk, d2[nb], 0, 0, 0);
+            for (int e = 0; e < 8; ++e) {
+                const float r = fmaxf(e < 4 ? h0[e] : h1[e - 4], 0.f);
+                bh[e] = (_Float16)r;
+                bl[e] = (_Float16)(r - (float)bh[e]);
+            }
+#pragma unroll
+            for (int nb = 0; nb < 8; ++nb) {
+                const half8 ah = w2h[(4 * nb + t) * WAVE + lane], al = w2l[(4 * nb + t) * WAVE + lane];
+                d2[nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, d2[nb], 0, 0, 0);
+                d2[nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, d2[nb], 0, 0, 0);
+                d2[nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, d2[nb], 0, 0, 0);
+            }
         }
         // lane (g, s16) holds units 16nb + 4g + r of state s16
         float part = 0.f;
@@ -143,9 +168,22 @@ static int mlp_infer_grid(int64_t S)
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const int64_t want = ((S + 15) / 16 + 3) / 4;
-    const int64_t cap = 4 * (int64_t)(cus > 0 ? cus : 256);
+    const int64_t waves = MLP_WG / WAVE;
+    const int64_t want = ((S + 15) / 16 + waves - 1) / waves;
+    const int64_t cap = 2 * (int64_t)(cus > 0 ? cus : 256);  // two workgroups of 64 KB fit a compute unit
     return (int)(want < cap ? want : cap);
+}
+
+template <bool SCHED>
+static int32_t launch_mlp_infer(int64_t S, hipStream_t st, const float* w, const float* X, float* out, float margin,
+                                int kmin, int kmax, int n, int32_t* ks, uint32_t* flags)
+{
+    hipError_t e = hipFuncSetAttribute((const void*)mlp_infer_kernel<SCHED>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)MLP_W2_LDS);
+    if (e != hipSuccess) return fail(MIMO_ERR_HIP, "MLP inference: LDS attribute: %s", hipGetErrorString(e));
+    hipLaunchKernelGGL(mlp_infer_kernel<SCHED>, dim3(mlp_infer_grid(S)), dim3(MLP_WG), MLP_W2_LDS, st, w, X, S, out,
+                       margin, kmin, kmax, n, ks, flags);
+    return check_launch(SCHED ? "prune_mlp_schedule" : "prune_mlp_forward");
 }
 
 // per state: activations and deltas, feature-major in the workspace
@@ -264,9 +302,7 @@ extern "C" int32_t prune_mlp_forward(const float* w, const float* X, int64_t S, 
     if (S < 0) return fail(MIMO_ERR_INVALID_ARG, "prune_mlp_forward: S < 0");
     if (S == 0) return MIMO_OK;
     if (!w || !X || !out) return fail(MIMO_ERR_INVALID_ARG, "prune_mlp_forward: null pointer");
-    hipLaunchKernelGGL(mlp_infer_kernel<false>, dim3(mlp_infer_grid(S)), dim3(256), 0, (hipStream_t)stream, w, X, S,
-                       out, 0.f, 1, 1, 1, nullptr, nullptr);
-    return check_launch("prune_mlp_forward");
+    return launch_mlp_infer<false>(S, (hipStream_t)stream, w, X, out, 0.f, 1, 1, 1, nullptr, nullptr);
 }
 
 extern "C" int32_t prune_mlp_schedule(const float* w, const float* X, int64_t S, float margin, int32_t k_min,
@@ -277,9 +313,7 @@ extern "C" int32_t prune_mlp_schedule(const float* w, const float* X, int64_t S,
         return fail(MIMO_ERR_INVALID_ARG, "prune_mlp_schedule: need 1 <= k_min <= k_max <= %d", MIMO_MAX_K);
     if (S == 0) return MIMO_OK;
     if (!w || !X || !k_sched) return fail(MIMO_ERR_INVALID_ARG, "prune_mlp_schedule: null pointer");
-    hipLaunchKernelGGL(mlp_infer_kernel<true>, dim3(mlp_infer_grid(S)), dim3(256), 0, (hipStream_t)stream, w, X, S,
-                       nullptr, margin, k_min, k_max, n, k_sched, flags);
-    return check_launch("prune_mlp_schedule");
+    return launch_mlp_infer<true>(S, (hipStream_t)stream, w, X, nullptr, margin, k_min, k_max, n, k_sched, flags);
 }
 
 extern "C" size_t prune_mlp_workspace_bytes(int64_t S)

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libmimo_sd.so")
 
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP = 0, -1, -2, -3, -4
 FLAG_FOUND, FLAG_EMPTY_SPHERE, FLAG_BUDGET_EXHAUSTED, FLAG_CERTIFIED, FLAG_LEARNED_FALLBACK = 1, 2, 4, 8, 16
+FLAG_NONFINITE_INPUT, FLAG_INVALID_FRAME = 32, 64
 MLP_IN, MLP_HIDDEN = 4, 128
 MLP_NPARAM = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
 MAX_WORKERS = 15
@@ -31,6 +32,7 @@ SIGNATURES = {
     "mimo_qr_preprocess_mmse": ([_P, _P, _P, _I32, _I32, _I32, _P, _P, _P], _I32),
     "linear_detect": ([_P, _P, _I32, _I32, _I32, _P, _P, _P], _I32),
     "mrc_detect": ([_P, _P, _I32, _I32, _I32, _I32, _P, _P, _P], _I32),
+    "mimo_paper_radius2": ([_P, _I32, _I32, _I32, _P, _P], _I32),
     "kbest_detect": ([_P, _P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P, _P], _I32),
     "kbest_detect_complex": ([_P, _P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P, _P], _I32),
     "kbest_fallback_mark": ([_P, _P, _P, _I32, _I32, _F, _P], _I32),
@@ -140,9 +142,14 @@ def qr_preprocess_mmse(H: torch.Tensor, y: torch.Tensor, sigma2: torch.Tensor, o
     return R, z
 
 
-def paper_radius2(n_rx: int, n_tx: int, sigma2: torch.Tensor) -> torch.Tensor:
-    """The paper's sphere radius rule, squared: r^2 = N M sigma^2 per frame."""
-    return (float(n_rx * n_tx) * sigma2).to(torch.float32).contiguous()
+def paper_radius2(n_rx: int, n_tx: int, sigma2: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    """The paper's sphere radius rule, squared: r^2 = N M sigma^2 per frame
+    (mimo_paper_radius2).  sigma2 [B] float32 on the device."""
+    B = sigma2.shape[0]
+    r2 = out if out is not None else torch.empty(B, device=sigma2.device, dtype=torch.float32)
+    _check(load().mimo_paper_radius2(_ptr(sigma2, torch.float32, "sigma2"), B, n_rx, n_tx,
+                                     _ptr(r2, torch.float32, "radius2"), _stream(stream)))
+    return r2
 
 
 # ------------------------------------------------------------------ detectors

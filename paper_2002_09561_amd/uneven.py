@@ -24,6 +24,26 @@ def k_for(table: dict, n_tx: int, qam: int, default: int = 16) -> int:
     return int(table.get(f"{n_tx}x{qam}", default))
 
 
+# per-frame limits of the persistent K-best launch (kbest_detect_uneven)
+UNEVEN_MAX_TX = 64
+UNEVEN_MAX_K = 64
+UNEVEN_MAX_CAND = 256
+
+
+def validate_descriptors(desc: np.ndarray) -> None:
+    """Rejects (ValueError) descriptors outside the persistent launches'
+    range: pam in {2, 4, 8}, 1 <= K <= 64, K * pam <= 256,
+    1 <= n_tx <= min(n_rx, 64), n_rx <= 128.  The kernels skip such frames
+    (flag INVALID_FRAME) as well; this check stops them before upload."""
+    pam, K, ntx, nrx = (desc[f].astype(np.int64) for f in ("pam", "K", "n_tx", "n_rx"))
+    bad = (~np.isin(pam, (2, 4, 8)) | (K < 1) | (K > UNEVEN_MAX_K) | (K * pam > UNEVEN_MAX_CAND) | (ntx < 1)
+           | (ntx > UNEVEN_MAX_TX) | (nrx < ntx) | (nrx > 128))
+    if bad.any():
+        i = int(np.nonzero(bad)[0][0])
+        raise ValueError(f"{int(bad.sum())} frame descriptors outside the uneven launch's limits, first: frame {i} "
+                         f"(n_rx {nrx[i]}, n_tx {ntx[i]}, pam {pam[i]}, K {K[i]})")
+
+
 class UnevenBatch:
     """Device-resident uneven batch with its descriptors and output buffers.
 
@@ -50,6 +70,7 @@ class UnevenBatch:
         desc["r_off"] = np.concatenate([[0], np.cumsum(rsz)[:-1]])
         desc["z_off"] = np.concatenate([[0], np.cumsum(n)[:-1]])
         desc["s_off"] = frames.s_off
+        validate_descriptors(desc)
         self.desc_np = desc
         cost = n * desc["K"].astype(np.int64) * desc["pam"].astype(np.int64)
         self.order = np.argsort(-cost, kind="stable")

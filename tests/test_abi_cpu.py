@@ -88,6 +88,50 @@ def test_host_validation_without_gpu(lib):
     assert lib.mimo_version() >= 1
 
 
+def test_kbest_lds_limit_and_uneven_limits(lib):
+    """More than 64 survivors of 4- or 16-QAM keep their lists in LDS: K = 256
+    fits the 160 KB of a compute unit up to n_tx = 77 and is refused
+    (UNSUPPORTED) from n_tx = 78 on, before any launch; 64-QAM with K = 128
+    fits at every size.  Uneven-batch descriptors beyond the persistent
+    launch's limits are refused on the host."""
+    import numpy as np
+
+    from paper_2002_09561_amd import uneven
+
+    P = None
+    for pam in (2, 4):
+        assert lib.kbest_detect(P, P, 1, 78, pam, 256, P, 0, P, P, P, P, P, P) == -2
+        assert "LDS" in _err(lib)
+        assert lib.kbest_detect(P, P, 1, 77, pam, 256, P, 0, P, P, P, P, P, P) == -1  # passes: null pointers
+        assert lib.kbest_fallback(P, P, 1, 100, pam, 256, P, ctypes.c_float(3.0), P, P, P, P, P) == -2
+        assert lib.kbest_rank_labels(P, P, 1, 90, pam, 256, P, P, P) == -2
+    assert lib.kbest_detect(P, P, 1, 128, 8, 128, P, 0, P, P, P, P, P, P) == -1
+    d = np.zeros(3, uneven.DESC_DTYPE)
+    d["n_rx"], d["n_tx"], d["pam"], d["K"] = 16, 16, 4, 16
+    uneven.validate_descriptors(d)
+    for field, value in (("K", 65), ("K", 0), ("pam", 3), ("n_tx", 65), ("n_tx", 0)):
+        bad = d.copy()
+        bad[field][1] = value
+        if field == "n_tx" and value == 65:
+            bad["n_rx"][1] = 100
+        with pytest.raises(ValueError):
+            uneven.validate_descriptors(bad)
+    bad = d.copy()
+    bad["pam"][2], bad["K"][2] = 8, 64  # 512 candidates per level
+    with pytest.raises(ValueError):
+        uneven.validate_descriptors(bad)
+
+
+def test_paper_radius_and_uneven_host_checks(lib):
+    P = None
+    assert lib.mimo_paper_radius2(P, 2, 4, 8, P, P) == -1   # n_rx < n_tx
+    assert lib.mimo_paper_radius2(P, -1, 8, 4, P, P) == -1
+    assert lib.mimo_paper_radius2(P, 0, 8, 4, P, P) == 0
+    assert lib.mimo_paper_radius2(P, 3, 8, 4, P, P) == -1   # null pointers
+    assert lib.kbest_detect_uneven(P, 3, P, P, P, P, P, P, 0, P) == -1
+    assert lib.kbest_detect_uneven(P, 0, P, P, P, P, P, P, 0, P) == 0
+
+
 def test_binding_refuses_cpu_tensors(lib):
     import torch
 

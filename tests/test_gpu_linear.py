@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from paper_2002_09561_amd.framegen import gen_frames
-from tests.parity_util import compare_symbols, near_tie_tol, pack_level_order
+from tests.parity_util import check_kbest_run, check_ml, pack_level_order
 
 pytestmark = pytest.mark.gpu
 
@@ -120,10 +120,10 @@ def test_mmse_sic_parity(gpu, orc):
     P = 4
     H, y = _dev(f)
     R, z = gpu.qr_preprocess_mmse(H, y, _sigma2(f))
-    sym, _, _ = gpu.kbest_detect(R, z, M, P, 1)
+    sym, pd, _ = gpu.kbest_detect(R, z, M, P, 1)
     Ro, zo = orc.qr_mmse(f.H, f.y, float(np.float32(f.sigma2)))
     out = orc.kbest(Ro, zo, P, 1)
-    compare_symbols(sym.cpu().numpy(), orc.x_to_sym(out["x"], P), out["margin"], near_tie_tol(2 * M), "MMSE-SIC")
+    check_kbest_run(orc, "MMSE-SIC", P, 1, sym.cpu().numpy(), pd.cpu().numpy(), out, Ro, zo)
     # MMSE-SIC makes no more symbol errors than ZF-SIC on these frames
     Rz, zz = gpu.qr_preprocess(H, y)
     zf_sym, _, _ = gpu.kbest_detect(Rz, zz, M, P, 1)
@@ -135,22 +135,27 @@ def test_mmse_sic_parity(gpu, orc):
 
 def test_paper_radius_exact_sd(gpu, orc):
     """The exact SD (hybrid kernel, no workers) with the paper's radius
-    r^2 = N M sigma^2 against the oracle's radius-limited SE-SD."""
+    r^2 = N M sigma^2 (computed by the library) against the oracle's
+    radius-limited SE-SD; then a radius a tenth as large, which empties the
+    sphere of most frames: they are detected again without a radius on both
+    sides."""
     N = M = 12
     q, B = 16, 150
     f = gen_frames(N, M, q, 6.0, B, seed=7600)
     P = 4
     H, y = _dev(f)
     R, z = gpu.qr_preprocess(H, y)
-    r2 = gpu.paper_radius2(N, M, _sigma2(f))
-    sym, pd, flags = gpu.sd_hybrid_detect(R, z, M, P, 0, 1, radius2=r2)
+    s2 = _sigma2(f)
+    r2 = gpu.paper_radius2(N, M, s2)
+    assert np.array_equal(r2.cpu().numpy(), np.float32(N * M) * s2.cpu().numpy())
     Ro, zo, _ = orc.qr(f.H, f.y)
-    x, pdo, flo, _ = orc.sesd(Ro, zo, P, r2=r2.cpu().numpy().astype(np.float64))
-    found = (flo & orc.FOUND) != 0
-    assert np.array_equal((flags.cpu().numpy() & orc.FOUND) != 0, found)
-    s_orc = orc.x_to_sym(x, P)
-    sg = sym.cpu().numpy()
-    mism = np.any(sg[found] != s_orc[found], axis=1)
-    # exact ML inside the sphere: a mismatch needs two leaves within the FP32 metric error
-    assert mism.sum() <= 1
-    assert np.allclose(pd.cpu().numpy()[found], pdo[found], rtol=5e-5)
+    for scale, label in ((1.0, "paper radius"), (0.1, "radius / 10")):
+        r2s = (r2 * scale).contiguous()
+        sym, pd, flags = gpu.sd_hybrid_detect(R, z, M, P, 0, 1, radius2=r2s)
+        out = orc.sesd(Ro, zo, P, r2=r2s.cpu().numpy().astype(np.float64))
+        fl = flags.cpu().numpy()
+        assert np.all(fl & orc.FOUND) and np.all(out[2] & orc.FOUND)
+        assert np.array_equal(fl & orc.EMPTY_SPHERE, out[2] & orc.EMPTY_SPHERE), label
+        if scale < 1.0:
+            assert np.any(fl & orc.EMPTY_SPHERE)
+        check_ml(orc, label, P, sym.cpu().numpy(), out, f.H, f.y, q)

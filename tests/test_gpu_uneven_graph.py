@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from paper_2002_09561_amd.framegen import gen_frames, gen_uneven
-from tests.parity_util import compare_symbols, near_tie_tol, pack_level_order
+from tests.parity_util import check_kbest_run, pack_level_order
 
 pytestmark = pytest.mark.gpu
 
@@ -46,9 +46,10 @@ def test_uneven_matches_batched_path_and_oracle(gpu, orc):
         m, q = int(fr.n_tx[i]), int(fr.qam[i])
         P = math.isqrt(q)
         Ro, zo, _ = orc.qr(H[None], y[None])
-        out = orc.kbest(Ro, zo, P, K_TABLE[f"{m}x{q}"])
-        compare_symbols(sym[None, d["s_off"][i]: d["s_off"][i] + m], orc.x_to_sym(out["x"], P), out["margin"],
-                        near_tie_tol(2 * m), f"uneven frame {i}")
+        K = K_TABLE[f"{m}x{q}"]
+        out = orc.kbest(Ro, zo, P, K)
+        check_kbest_run(orc, f"uneven frame {i}", P, K, sym[None, d["s_off"][i]: d["s_off"][i] + m],
+                        pd_frame[i:i + 1], out, Ro, zo)
     assert np.all(ub.flags.cpu().numpy() & 1)
 
 
@@ -130,3 +131,39 @@ def test_learned_schedule_gain(gpu, orc):
     e_l, e_64 = int((s != S).sum()), int((sp64 != S).sum())
     print(f"learned + fallback: {e_l} symbol errors; plain K=64: {e_64}")
     assert e_l <= 1.05 * e_64 + M  # at most one more frame in error
+
+
+def test_uneven_kernel_skips_invalid_descriptors(gpu):
+    """Descriptors the host check would refuse, written to the device copy
+    directly: the persistent K-best launch skips those frames with flags
+    INVALID_FRAME (sym and pd untouched) and detects the others as before."""
+    import torch
+
+    from paper_2002_09561_amd import uneven
+
+    fr = gen_uneven(200, seed=6)
+    ub = uneven.UnevenBatch(fr, K_TABLE)
+    ub.run(qr_grid=32, kb_grid=64)
+    torch.cuda.synchronize()
+    ref_sym, ref_pd, ref_fl = ub.sym.clone(), ub.pd.clone(), ub.flags.clone()
+    d = np.ascontiguousarray(ub.desc_np[ub.order])
+    bad = {3: ("K", 65), 10: ("K", 0), 50: ("pam", 3), 77: ("n_tx", 70)}
+    for j, (field, v) in bad.items():
+        d[field][j] = v
+        if field == "n_tx":
+            d["n_rx"][j] = 70
+    ub.desc.copy_(torch.from_numpy(d.view(np.uint8)))
+    ub.sym.fill_(-7)
+    ub.pd.fill_(-1.0)
+    print("uneven K-best with four invalid descriptors", flush=True)
+    gpu.kbest_detect_uneven(ub.desc, ub.B, ub.R, ub.z, ub.sym, ub.pd, ub.flags, ub.counter[1:2], grid=64)
+    torch.cuda.synchronize()
+    fl, pd = ub.flags.cpu().numpy(), ub.pd.cpu().numpy()
+    for j in bad:
+        assert fl[j] == gpu.FLAG_INVALID_FRAME and pd[j] == -1.0
+        i = ub.order[j]
+        assert np.all(ub.sym.cpu().numpy()[ub.desc_np["s_off"][i]: ub.desc_np["s_off"][i] + ub.desc_np["n_tx"][i]]
+                      == -7)
+    good = np.setdiff1d(np.arange(ub.B), list(bad))
+    assert np.array_equal(fl[good], ref_fl.cpu().numpy()[good])
+    assert np.array_equal(pd[good], ref_pd.cpu().numpy()[good])

@@ -186,13 +186,18 @@ def test_kbest_radius(orc):
     ml = orc.sesd(R, z, 4)
     r2 = float(np.median(ml[1])) * 1.5
     out = orc.kbest(R, z, 4, 16, r2=r2)
-    found = (out["flags"] & orc.FOUND) != 0
-    assert np.all(out["pd"][found] < r2)
-    # a radius below the ML metric leaves nothing inside the sphere
+    free = orc.kbest(R, z, 4, 16)
+    inside = (out["flags"] & orc.EMPTY_SPHERE) == 0
+    assert np.all(out["flags"] & orc.FOUND)
+    assert np.all(out["pd"][inside] < r2)
+    assert (~inside).any() and np.array_equal(out["x"][~inside], free["x"][~inside])
+    # a radius below the ML metric leaves nothing inside the sphere: every
+    # frame is searched again without a radius
     tiny = orc.kbest(R, z, 4, 16, r2=float(ml[1].min()) * 0.5)
-    assert np.all(tiny["flags"] & orc.EMPTY_SPHERE)
+    assert np.all(tiny["flags"] & orc.EMPTY_SPHERE) and np.all(tiny["flags"] & orc.FOUND)
+    assert np.array_equal(tiny["x"], free["x"])
     sd = orc.sesd(R, z, 4, r2=np.full(len(f), float(ml[1].min()) * 0.5))
-    assert np.all(sd[2] & orc.EMPTY_SPHERE)
+    assert np.all(sd[2] & orc.EMPTY_SPHERE) and np.array_equal(sd[0], ml[0])
 
 
 def test_sesd_warm_start(orc):
@@ -353,42 +358,6 @@ def test_adam_first_step_is_signed_lr(orc):
     assert np.allclose(w0 - w, 1e-2 * np.sign(g), rtol=1e-12)
 
 
-def test_round_half_matches_ieee_binary16(orc):
-    """The oracle's binary16 rounding agrees with numpy's IEEE half conversion
-    (round to nearest, ties to even) over normals, subnormals, exact ties and
-    overflow."""
-    rng = np.random.default_rng(11)
-    xs = np.concatenate([rng.normal(size=2000) * 10.0 ** rng.integers(-9, 5, size=2000),
-                         # exact ties between neighbouring halves (odd and even last bit)
-                         (np.arange(1, 200) * 2 + 1) * 2.0 ** -11 / 2 + 1.0,
-                         np.arange(1, 50) * 2.0 ** -25,          # subnormal ties
-                         [65504.0, 65519.9, 65520.0, -7e4, 0.0, -0.0, 6.0e-8, 2.0 ** -24]])
-    got = np.array([orc.round_half(x) for x in xs])
-    ref = xs.astype(np.float16).astype(np.float64)
-    assert np.array_equal(got, ref)
-
-
-def test_mlp_forward_f16_is_exact_on_half_representable_operands(orc):
-    """With W2 and every ReLU(layer 1) value exactly representable in binary16,
-    the binary16 forward pass equals the FP64 definition bit for bit; with
-    general weights it differs by binary16 rounding only."""
-    rng = np.random.default_rng(12)
-    H = 128
-    w = np.zeros(17281)
-    w[0:512] = rng.integers(-3, 4, size=512)              # W1: small integers
-    w[512:640] = rng.integers(-4, 5, size=128)            # b1
-    w[640:640 + H * H] = rng.integers(-64, 65, size=H * H) / 64.0   # W2 on a 2^-6 grid
-    w[640 + H * H:640 + H * H + 128] = rng.normal(size=128)
-    w[640 + H * H + 128:640 + H * H + 256] = rng.normal(size=128)
-    w[-1] = 0.25
-    X = rng.integers(-3, 4, size=(50, 4)).astype(np.float64)  # h1: integers below 2^11
-    assert np.array_equal(orc.mlp_forward_f16(w, X), orc.mlp_forward(w, X))
-    w2 = rng.normal(0, 0.2, size=17281)
-    X2 = rng.normal(size=(200, 4))
-    a, b = orc.mlp_forward_f16(w2, X2), orc.mlp_forward(w2, X2)
-    assert 0 < np.max(np.abs(a - b)) < 2e-2 * max(1.0, np.max(np.abs(b)))
-
-
 # --------------------------------------------------------------- T11: Gray map
 @pytest.mark.parametrize("P", [2, 4, 8])
 def test_gray_adjacent_points_differ_in_one_bit(orc, P):
@@ -496,5 +465,182 @@ def test_paper_radius_keeps_ml_when_inside(orc):
     xr, pd_r, fl, _ = orc.sesd(R, z, 4, r2=r2)
     assert np.all(pd_inf < r2)
     assert np.array_equal(xr, xs) and np.allclose(pd_r, pd_inf)
-    _, _, fl0, _ = orc.sesd(R, z, 4, r2=np.full(len(f), 0.5 * pd_inf.min()))
-    assert np.all((fl0 & orc.EMPTY_SPHERE) != 0)
+    x0, _, fl0, _ = orc.sesd(R, z, 4, r2=np.full(len(f), 0.5 * pd_inf.min()))
+    assert np.all((fl0 & orc.EMPTY_SPHERE) != 0) and np.array_equal(x0, xs)
+
+
+# --------------------------------------------------------------- hybrid round schedule (Sec. VI)
+_TRACE_RT = np.array([[1, 0, 0.5, 0.5], [0, 1, 0.5, 0], [0, 0, 1, 0.5], [0, 0, 0, 1.0]])
+_TRACE_Z = np.array([0.1, 0.2, -0.1, 0.3])
+
+
+def test_hybrid_round_schedule_golden_trace(orc):
+    """The deterministic-round reading of the SD-K-best master/worker scheme
+    traced by hand on a 4-level tree (derivation in the golden file): pool
+    contents, hand-offs, worker levels, candidates, radius updates and the
+    final counters.  Each of these oracle mutations changes the trace while
+    leaving the detected symbols unchanged: workers taking a node while the
+    pool holds a single one (pool >= 1), the master expanding a node already
+    outside the sphere instead of discarding it, and workers taking the
+    left-most node instead of the right-most."""
+    path = __file__.replace("test_oracle_pins.py", "golden/hybrid_trace_2x2_4qam_w2_k1.txt")
+    gold = [l for l in open(path).read().splitlines() if l and not l.startswith("#")]
+    c = orc.pam_scale(2)
+    lines, x, pd, fl, ctr = orc.hybrid_trace(_TRACE_RT / c, _TRACE_Z, 2, 2, 1)
+    assert lines == gold
+    assert list(x) == [1, 1, 0, 1] and abs(pd - 1.55) < 1e-12
+    assert list(ctr) == [9, 18, 5, 1] and (fl & orc.CERTIFIED) and (fl & orc.FOUND)
+    # the batched driver runs the same schedule
+    h = orc.hybrid((_TRACE_RT / c)[None], _TRACE_Z[None], 2, 2, 1)
+    assert list(h["x"][0]) == [1, 1, 0, 1] and list(h["counters"][0]) == [9, 18, 5, 1]
+
+
+def test_hybrid_trace_no_workers_is_best_first_sd(orc):
+    """With no workers the trace is the Best-FS SD of Alg. 1 on the same
+    tree: the master alone walks down the best children (0.49, 0.65, 0.74,
+    leaf 1.55), then pops the remaining siblings, each either outside the
+    sphere (stale) or expanded into leaves above the radius."""
+    c = orc.pam_scale(2)
+    lines, x, pd, fl, ctr = orc.hybrid_trace(_TRACE_RT / c, _TRACE_Z, 2, 0, 1)
+    assert list(x) == [1, 1, 0, 1] and abs(pd - 1.55) < 1e-12
+    assert lines[:3] == ["round 1 r2 inf pool 1", "master expand depth 0 pd 0", "  child 1 pd 0.49"]
+    assert "radius 1.55 from source 0" in lines
+    assert not any(l.startswith("worker") for l in lines)
+    # every pop after the radius fell to 1.55 lies above it: the siblings
+    # 1.69 (depth 1), 3.05 (depth 2) and 3.54 (depth 3) are discarded
+    stale = sorted(l for l in lines if "stale" in l and l.startswith("master"))
+    assert stale == ["master stale depth 1 pd 1.69", "master stale depth 2 pd 3.05", "master stale depth 3 pd 3.54"]
+    sd = orc.sesd((_TRACE_RT / c)[None], _TRACE_Z[None], 2)
+    assert list(sd[0][0]) == [1, 1, 0, 1] and ctr[0] == sd[3][0, 0]
+
+
+# --------------------------------------------------------------- near-tie margins
+def _two_level(rt, z, P=2):
+    c = orc_scale = math.sqrt(3.0 / (2.0 * (P * P - 1)))
+    return np.asarray(rt, float)[None] / orc_scale, np.asarray(z, float)[None]
+
+
+def test_kbest_margin_exact_tie(orc):
+    """z = 0 on an identity R: both children of every node have the same pd,
+    so the K = 1 selection (and the final choice) is an exact tie: margin 0
+    between two equal keys; the tie rule keeps child 0."""
+    R, z = _two_level([[1, 0], [0, 1]], [0.0, 0.0])
+    out = orc.kbest(R, z, 2, 1)
+    assert out["margin"][0, 0] == 0.0
+    assert out["margin"][0, 1] == out["margin"][0, 2] == pytest.approx(1.0)
+    assert list(out["x"][0]) == [0, 0]
+
+
+def test_kbest_margin_known_gap(orc):
+    """Level 1: e = 0.1 - v gives 0.81 (v = +1) and 1.21 (v = -1), a relative
+    gap of 0.4 / 1.21 at the K = 1 boundary; level 0 from 0.81: e = 0.5 - v
+    gives 1.06 and 3.06 (gap 2 / 3.06).  The smaller gap is returned with its
+    pair (kept key, first dropped key)."""
+    R, z = _two_level([[1, 0], [0, 1]], [0.5, 0.1])
+    out = orc.kbest(R, z, 2, 1)
+    assert out["margin"][0, 0] == pytest.approx(0.4 / 1.21, rel=1e-12)
+    assert out["margin"][0, 1] == pytest.approx(0.81) and out["margin"][0, 2] == pytest.approx(1.21)
+    assert out["pd"][0] == pytest.approx(1.06)
+
+
+def test_kbest_margin_radius_test(orc):
+    """With r2 = 1.07 the radius test of the leaf 1.06 is the closest
+    decision: relative gap 0.01 / 1.07 between the leaf and the radius (the
+    other children lie outside the sphere by wider gaps and no selection is
+    left to make)."""
+    R, z = _two_level([[1, 0], [0, 1]], [0.5, 0.1])
+    out = orc.kbest(R, z, 2, 1, r2=1.07)
+    assert out["margin"][0, 0] == pytest.approx(0.01 / 1.07, rel=1e-9)
+    assert out["margin"][0, 1] == pytest.approx(1.06) and out["margin"][0, 2] == pytest.approx(1.07)
+    assert (out["flags"][0] & orc.FOUND) and not (out["flags"][0] & orc.EMPTY_SPHERE)
+
+
+def test_empty_sphere_is_searched_again_without_radius(orc):
+    """A radius below every leaf (r2 = 1.0 < 1.06 here) leaves the sphere
+    empty; the reading searches the frame again with r2 = +inf: the result is
+    that of the unbounded search, the flags keep EMPTY_SPHERE next to FOUND,
+    and the counters add up both searches (one root and one level-1 node in
+    the first, as in the second)."""
+    R, z = _two_level([[1, 0], [0, 1]], [0.5, 0.1])
+    free = orc.kbest(R, z, 2, 1)
+    out = orc.kbest(R, z, 2, 1, r2=1.0)
+    assert (out["flags"][0] & orc.EMPTY_SPHERE) and (out["flags"][0] & orc.FOUND)
+    assert np.array_equal(out["x"], free["x"]) and out["pd"][0] == free["pd"][0]
+    assert out["counters"][0, 0] == 2 * free["counters"][0, 0]
+    # the radius test 0.81 < 1.0 < 1.06 is the closest decision of the first search
+    assert out["margin"][0, 0] == pytest.approx(0.06 / 1.06, rel=1e-9)
+    sd = orc.sesd(R, z, 2, r2=np.array([1.0]))
+    assert (sd[2][0] & orc.EMPTY_SPHERE) and (sd[2][0] & orc.FOUND) and list(sd[0][0]) == list(free["x"][0])
+    h = orc.hybrid(R, z, 2, 1, 1, r2=1.0)
+    assert (h["flags"][0] & orc.EMPTY_SPHERE) and list(h["x"][0]) == list(free["x"][0])
+
+
+def test_forced_path_gap(orc):
+    """Forcing the other child at level 1 (v = -1, pd 1.21 against the kept
+    0.81) gives the gap of the decision that dropped it; forcing the search's
+    own path gives 0.  At the leaves, forcing the second-best leaf of the
+    kept survivor (3.06 against 1.06) gives that final gap."""
+    R, z = _two_level([[1, 0], [0, 1]], [0.5, 0.1])
+    own = orc.kbest(R, z, 2, 1)
+    o0 = orc.kbest(R, z, 2, 1, force_path=own["x"])
+    assert o0["fgap"][0] == 0.0
+    o1 = orc.kbest(R, z, 2, 2, force_path=np.array([[0, 1]], np.int32))
+    assert o1["fgap"][0] == pytest.approx(2.0 / 3.06, rel=1e-12)  # leaf 3.06 vs best leaf 1.06
+    o2 = orc.kbest(R, z, 2, 1, force_path=np.array([[1, 0]], np.int32))
+    assert o2["fgap"][0] >= 0.4 / 1.21 * (1 - 1e-12)
+
+
+# --------------------------------------------------------------- features under noise
+def test_prune_features_noisy_against_numpy_slicer(orc):
+    """Noisy frames: the oracle's features against an independent numpy
+    version (successive cancellation by explicit nearest-point search over
+    the amplitudes, the distance to the decision boundaries by enumerating
+    them).  A dropped outer clamp, a wrong spacing unit or a wrong sigma_r
+    would each fail here."""
+    for q, M, snr in ((4, 3, 4.0), (16, 4, 8.0), (64, 3, 14.0)):
+        P = math.isqrt(q)
+        f = gen_frames(M, M, q, snr, 40, seed=90 + q)
+        R, z, _ = orc.qr(f.H, f.y)
+        feat = orc.prune_features(R, z, P, f.sigma2)
+        n = 2 * M
+        c = math.sqrt(3.0 / (2.0 * (q - 1)))
+        amps = (2 * np.arange(P) - (P - 1)) * c
+        bounds = np.arange(-(P - 2), P - 1, 2) * c  # decision boundaries between neighbouring points
+        sr = math.sqrt(f.sigma2 / 2)
+        for b in range(len(f)):
+            x = np.zeros(n)
+            pd = 0.0
+            for k in range(n - 1, -1, -1):
+                ctr = z[b, k] - R[b, k, k + 1:] @ x[k + 1:]
+                u = ctr / R[b, k, k]
+                x[k] = amps[np.argmin(np.abs(amps - u))]
+                pd += (ctr - R[b, k, k] * x[k]) ** 2
+                d = np.min(np.abs(u - bounds)) / (2 * c)
+                ref = [k / n, d, math.log2(R[b, k, k] * 2 * c / sr), pd / ((n - k) * sr * sr)]
+                assert np.allclose(feat[b, k], ref, rtol=1e-9, atol=1e-12), (q, b, k)
+
+
+# --------------------------------------------------------------- Adam over several steps
+def test_adam_steps_closed_form(orc):
+    """Steps t = 1..5 against Adam written out in closed form: m_t =
+    (1 - b1) sum_i b1^(t-i) g_i, v_t = (1 - b2) sum_i b2^(t-i) g_i^2, with
+    the bias corrections 1 - b^t; and a constant gradient, for which the
+    corrected moments are g and g^2 exactly, so every step moves w by
+    lr g / (|g| + eps)."""
+    rng = np.random.default_rng(13)
+    npar, lr, b1, b2, eps = 64, 3e-3, 0.9, 0.999, 1e-8
+    gs = [rng.normal(size=npar) for _ in range(5)]
+    w0 = rng.normal(size=npar)
+    w, m, v = w0.copy(), np.zeros(npar), np.zeros(npar)
+    wref = w0.copy()
+    for t in range(1, 6):
+        orc.adam_step(w, m, v, gs[t - 1], t, lr, b1, b2, eps)
+        mt = (1 - b1) * sum(b1 ** (t - i) * gs[i - 1] for i in range(1, t + 1))
+        vt = (1 - b2) * sum(b2 ** (t - i) * gs[i - 1] ** 2 for i in range(1, t + 1))
+        wref = wref - lr * (mt / (1 - b1 ** t)) / (np.sqrt(vt / (1 - b2 ** t)) + eps)
+        assert np.allclose(w, wref, rtol=1e-13, atol=1e-15), t
+    g = rng.normal(size=npar)
+    w, m, v = w0.copy(), np.zeros(npar), np.zeros(npar)
+    for t in range(1, 6):
+        orc.adam_step(w, m, v, g, t, lr, b1, b2, eps)
+    assert np.allclose(w, w0 - 5 * lr * g / (np.abs(g) + eps), rtol=1e-10)
