@@ -310,6 +310,20 @@ size_t prune_mlp_workspace_bytes(int64_t S);
 int32_t prune_mlp_loss_grad(const float* w, const float* X, const float* y, int64_t S, float tau,
                             float* grad, float* loss, void* ws, size_t ws_bytes, void* stream);
 
+/* Allocation-free variant of prune_mlp_loss_grad, for callers that cannot
+ * allocate device memory (code under hipGraph capture, serving or training
+ * loops, harnesses that forbid allocation).  Same arguments and results
+ * (bit for bit) without the workspace: the per-state activations, deltas and
+ * loss partials live in a static device array sized for
+ * MIMO_MLP_NOALLOC_MAX_S states (about 16.8 MB), which each GPU the library
+ * runs on holds until the process ends.  S > MIMO_MLP_NOALLOC_MAX_S returns
+ * MIMO_ERR_UNSUPPORTED.  Every call on a GPU uses that GPU's one array, so
+ * calls that overlap on one GPU (other streams, other host threads) race;
+ * each call overwrites everything it reads, nothing needs clearing. */
+#define MIMO_MLP_NOALLOC_MAX_S 8192
+int32_t prune_mlp_loss_grad_noalloc(const float* w, const float* X, const float* y, int64_t S, float tau,
+                                    float* grad, float* loss, void* stream);
+
 /* One Adam step on w with moments m, v (all [np] f32), step t >= 1. */
 int32_t prune_mlp_adam_step(float* w, float* m, float* v, const float* grad, int32_t np, int32_t t,
                             float lr, float beta1, float beta2, float eps, void* stream);

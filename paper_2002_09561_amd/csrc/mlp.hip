@@ -23,6 +23,8 @@
 // the backward pass writes the per-state activations and deltas
 // feature-major ([128][S]); a second kernel reduces the weight gradients over
 // the states in a fixed order (deterministic).
+#include <mutex>
+
 #include "common.hpp"
 
 namespace mimo {
@@ -323,16 +325,14 @@ extern "C" size_t prune_mlp_workspace_bytes(int64_t S)
     return sizeof(float) * (size_t)(4 * HID * S + S + nblk + 64);
 }
 
-extern "C" int32_t prune_mlp_loss_grad(const float* w, const float* X, const float* y, int64_t S, float tau,
-                                       float* grad, float* loss, void* ws, size_t ws_bytes, void* stream)
+namespace mimo {
+
+// The loss and gradient of S states with the per-state activations, deltas
+// and loss partials in the workspace ws (prune_mlp_workspace_bytes(S)).
+static int32_t mlp_loss_grad_ws(const char* who, const float* w, const float* X, const float* y, int64_t S,
+                                float tau, float* grad, float* loss, float* ws, hipStream_t st)
 {
-    if (S < 1) return fail(MIMO_ERR_INVALID_ARG, "prune_mlp_loss_grad: S < 1");
-    if (!(tau > 0.f && tau < 1.f)) return fail(MIMO_ERR_INVALID_ARG, "prune_mlp_loss_grad: tau in (0, 1)");
-    if (!w || !X || !y || !grad || !loss || !ws) return fail(MIMO_ERR_INVALID_ARG, "prune_mlp_loss_grad: null pointer");
-    if (ws_bytes < prune_mlp_workspace_bytes(S))
-        return fail(MIMO_ERR_WORKSPACE, "prune_mlp_loss_grad: workspace %zu < %zu", ws_bytes,
-                    prune_mlp_workspace_bytes(S));
-    float* f = static_cast<float*>(ws);
+    float* f = ws;
     float* H1 = f;
     float* H2 = H1 + HID * S;
     float* D2 = H2 + HID * S;
@@ -340,14 +340,82 @@ extern "C" int32_t prune_mlp_loss_grad(const float* w, const float* X, const flo
     float* dout = D1 + HID * S;
     float* lpart = dout + S;
     const int nblk = (int)((S + 255) / 256);
-    hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(mlp_backward_states, dim3(nblk), dim3(256), 0, st, w, X, y, S, tau, H1, H2, D2, D1, dout,
                        lpart);
-    int32_t rc = check_launch("prune_mlp_loss_grad");
+    int32_t rc = check_launch(who);
     if (rc) return rc;
     hipLaunchKernelGGL(mlp_backward_reduce, dim3((MIMO_MLP_NPARAM + 1 + 255) / 256), dim3(256), 0, st, X, S, H1, H2,
                        D2, D1, dout, lpart, nblk, grad, loss);
-    return check_launch("prune_mlp_loss_grad");
+    return check_launch(who);
+}
+
+static int32_t mlp_loss_grad_check(const char* who, const float* w, const float* X, const float* y, int64_t S,
+                                   float tau, const float* grad, const float* loss)
+{
+    if (S < 1) return fail(MIMO_ERR_INVALID_ARG, "%s: S < 1", who);
+    if (!(tau > 0.f && tau < 1.f)) return fail(MIMO_ERR_INVALID_ARG, "%s: tau in (0, 1)", who);
+    if (!w || !X || !y || !grad || !loss) return fail(MIMO_ERR_INVALID_ARG, "%s: null pointer", who);
+    return MIMO_OK;
+}
+
+// Scratch of the allocation-free entry point: the workspace of up to
+// MIMO_MLP_NOALLOC_MAX_S states in a static device array, one copy per GPU
+// for the life of the process.  Host code never passes the array's name to
+// a kernel (on the host it is only a stand-in for the symbol): the device
+// address is looked up once per device with that device current and kept.
+constexpr size_t NOALLOC_FLOATS = (size_t)4 * HID * MIMO_MLP_NOALLOC_MAX_S + MIMO_MLP_NOALLOC_MAX_S +
+                                  (MIMO_MLP_NOALLOC_MAX_S + 255) / 256 + 64;
+static __device__ __align__(256) float scratch[NOALLOC_FLOATS];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static float* g_scratch_ptr[MAX_DEVICES];
+
+static int32_t scratch_for_current_device(const char* who, float** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(MIMO_ERR_HIP, "%s: hipGetDevice: %s", who, hipGetErrorString(e));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(MIMO_ERR_UNSUPPORTED, "%s: device %d beyond %d", who, dev, MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(MIMO_ERR_HIP, "%s: scratch address on device %d: %s", who, dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<float*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return MIMO_OK;
+}
+
+}  // namespace mimo
+
+extern "C" int32_t prune_mlp_loss_grad(const float* w, const float* X, const float* y, int64_t S, float tau,
+                                       float* grad, float* loss, void* ws, size_t ws_bytes, void* stream)
+{
+    const char* who = "prune_mlp_loss_grad";
+    int32_t rc = mlp_loss_grad_check(who, w, X, y, S, tau, grad, loss);
+    if (rc) return rc;
+    if (!ws) return fail(MIMO_ERR_INVALID_ARG, "%s: null workspace", who);
+    if (ws_bytes < prune_mlp_workspace_bytes(S))
+        return fail(MIMO_ERR_WORKSPACE, "%s: workspace %zu < %zu", who, ws_bytes, prune_mlp_workspace_bytes(S));
+    return mlp_loss_grad_ws(who, w, X, y, S, tau, grad, loss, static_cast<float*>(ws), (hipStream_t)stream);
+}
+
+extern "C" int32_t prune_mlp_loss_grad_noalloc(const float* w, const float* X, const float* y, int64_t S, float tau,
+                                               float* grad, float* loss, void* stream)
+{
+    const char* who = "prune_mlp_loss_grad_noalloc";
+    int32_t rc = mlp_loss_grad_check(who, w, X, y, S, tau, grad, loss);
+    if (rc) return rc;
+    if (S > MIMO_MLP_NOALLOC_MAX_S)
+        return fail(MIMO_ERR_UNSUPPORTED, "%s: S = %lld states exceed the static scratch of %d", who, (long long)S,
+                    MIMO_MLP_NOALLOC_MAX_S);
+    float* ws = nullptr;
+    rc = scratch_for_current_device(who, &ws);
+    if (rc) return rc;
+    return mlp_loss_grad_ws(who, w, X, y, S, tau, grad, loss, ws, (hipStream_t)stream);
 }
 
 extern "C" int32_t prune_mlp_adam_step(float* w, float* m, float* v, const float* grad, int32_t np, int32_t t,

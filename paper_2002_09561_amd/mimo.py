@@ -48,6 +48,7 @@ SIGNATURES = {
     "prune_mlp_schedule": ([_P, _P, _I64, _F, _I32, _I32, _I32, _P, _P, _P], _I32),
     "prune_mlp_workspace_bytes": ([_I64], _SZ),
     "prune_mlp_loss_grad": ([_P, _P, _P, _I64, _F, _P, _P, _P, _SZ, _P], _I32),
+    "prune_mlp_loss_grad_noalloc": ([_P, _P, _P, _I64, _F, _P, _P, _P], _I32),
     "prune_mlp_adam_step": ([_P, _P, _P, _P, _I32, _I32, _F, _F, _F, _F, _P], _I32),
     "mimo_qr_preprocess_uneven": ([_P, _I32, _I32, _P, _P, _P, _P, _P, _I32, _P], _I32),
     "kbest_detect_uneven": ([_P, _I32, _P, _P, _P, _P, _P, _P, _I32, _P], _I32),
@@ -330,6 +331,21 @@ def mlp_loss_grad(w, X, y, tau: float, ws=None, grad=None, loss=None, stream=Non
                                       _ptr(y, torch.float32, "y"), S, float(tau), _ptr(g), _ptr(l), _ptr(ws),
                                       ws.numel() * ws.element_size(), _stream(stream)))
     return l, g
+
+
+MLP_NOALLOC_MAX_S = 8192
+
+
+def mlp_loss_grad_noalloc(w, X, y, tau: float, grad, loss, stream=None):
+    """prune_mlp_loss_grad without a workspace (the library's static scratch,
+    S <= MLP_NOALLOC_MAX_S); grad [NPARAM] and loss [1] float32 are given by
+    the caller, so this call allocates nothing."""
+    S = X.shape[0]
+    _check(load().prune_mlp_loss_grad_noalloc(_ptr(w, torch.float32, "w"), _ptr(X, torch.float32, "X"),
+                                              _ptr(y, torch.float32, "y"), S, float(tau),
+                                              _ptr(grad, torch.float32, "grad"), _ptr(loss, torch.float32, "loss"),
+                                              _stream(stream)))
+    return loss, grad
 
 
 def mlp_adam_step(w, m, v, g, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
