@@ -20,7 +20,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 
-FOUND, EMPTY_SPHERE, BUDGET_EXHAUSTED, CERTIFIED = 1, 2, 4, 8
+FOUND, EMPTY_SPHERE, BUDGET_EXHAUSTED, CERTIFIED, LEARNED_FALLBACK = 1, 2, 4, 8, 16
 MLP_IN, MLP_H = 4, 128
 MLP_NPARAM = MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1
 
@@ -70,6 +70,7 @@ def _declare(L):
                                   _P, _P, _P, _P]
     L.orc_batch_hybrid.argtypes = [_I, _I, _I, _P, _P, _P, _I, _I, _P, _I, _I, _L, _P, _P, _P,
                                    _P, _P]
+    L.orc_batch_learned_detect.argtypes = [_I, _I, _I, _P, _P, _P, _P, _D, _I, _I, _D, _I, _P, _P, _P, _P]
     L.orc_hybrid_trace.restype = ctypes.c_uint32
     L.orc_hybrid_trace.argtypes = [_I, _I, _P, _P, _D, _I, _I, _I, _L, _P, _P, _P, ctypes.c_char_p, _I]
     L.orc_batch_prune_features.argtypes = [_I, _I, _I, _P, _P, _P, _P]
@@ -286,6 +287,25 @@ def prune_features(R, z, P: int, sigma2) -> np.ndarray:
     f = np.zeros((B, n, 4))
     lib().orc_batch_prune_features(B, n, P, _p(R), _p(z), _p(s2), _p(f))
     return f
+
+
+def learned_detect(R, z, P: int, sigma2, w, margin: float, k_min: int, k_max: int, beta: float,
+                   K_fallback: int = 64):
+    """The learned-pruning detector (features -> MLP -> survivor schedule ->
+    K-best -> plain K-best fallback), FP64.  sigma2 scalar or [B].  Returns
+    dict with x [B,n], pd [B], k_sched [B,n], flags [B]."""
+    R = _c(R, np.float64)
+    z = _c(z, np.float64)
+    B, n = z.shape
+    s2 = _c(np.broadcast_to(np.asarray(sigma2, np.float64), (B,)), np.float64)
+    w = _c(w, np.float64)
+    x = np.zeros((B, n), np.int32)
+    pd = np.zeros(B)
+    ks = np.zeros((B, n), np.int32)
+    fl = np.zeros(B, np.uint32)
+    lib().orc_batch_learned_detect(B, n, P, _p(R), _p(z), _p(s2), _p(w), float(margin), int(k_min), int(k_max),
+                                   float(beta), int(K_fallback), _p(x), _p(pd), _p(ks), _p(fl))
+    return dict(x=x, pd=pd, k_sched=ks, flags=fl)
 
 
 # ---------------------------------------------------------------- MLP

@@ -1034,8 +1034,64 @@ void orc_adam_step(double* w, double* m, double* v, const double* g, int np, int
 }
 
 /* ------------------------------------------------------------------ */
+/* Learned-pruning detector: per-level state -> MLP -> survivor counts  */
+/* -> K-best with that schedule -> plain K-best where the first result  */
+/* is flagged or fails the noise test                                   */
+/* ------------------------------------------------------------------ */
+/* survivor count of one state: clamp(ceil(2^(f + margin)), kmin, kmax) */
+static int learned_count(double f, double margin, int kmin, int kmax)
+{
+    if (!isfinite(f)) return kmax;
+    double e = f + margin;
+    if (e > 30.0) e = 30.0;
+    double k = ceil(exp2(e));
+    if (k < (double)kmin) return kmin;
+    if (k > (double)kmax) return kmax;
+    return (int)k;
+}
+
+uint32_t orc_learned_detect(int n, int P, const double* R, const double* z, double sigma2, const double* w,
+                            double margin, int kmin, int kmax, double beta, int K_fallback, int* x_out,
+                            double* pd_out, int* k_sched_out, int64_t* counters)
+{
+    double* feat = (double*)malloc(sizeof(double) * (size_t)n * 4);
+    double* pred = (double*)malloc(sizeof(double) * (size_t)n);
+    int* ks = k_sched_out ? k_sched_out : (int*)malloc(sizeof(int) * (size_t)n);
+    orc_prune_features(n, P, R, z, sigma2, feat);
+    orc_mlp_forward(w, feat, n, pred);
+    for (int k = 0; k < n; ++k) ks[k] = learned_count(pred[k], margin, kmin, kmax);
+    double pd = INFINITY;
+    uint32_t f = orc_kbest(n, P, R, z, kmax, ks, INFINITY, 1, NULL, x_out, &pd, NULL, NULL, NULL, NULL, counters);
+    /* the noise test: a correct detection leaves a chi-square noise energy
+     * with n real degrees of freedom, of mean n sigma2 / 2 */
+    const double bound = 0.5 * sigma2 * ((double)n + beta * sqrt(2.0 * (double)n));
+    if (!(f & ORC_FOUND) || !(pd <= bound)) {
+        f = orc_kbest(n, P, R, z, K_fallback, NULL, INFINITY, 1, NULL, x_out, &pd, NULL, NULL, NULL, NULL,
+                      counters) | ORC_LEARNED_FALLBACK;
+    }
+    if (pd_out) *pd_out = pd;
+    free(feat);
+    free(pred);
+    if (!k_sched_out) free(ks);
+    return f;
+}
+
+/* ------------------------------------------------------------------ */
 /* batched drivers                                                     */
 /* ------------------------------------------------------------------ */
+void orc_batch_learned_detect(int B, int n, int P, const double* R, const double* z, const double* sigma2,
+                              const double* w, double margin, int kmin, int kmax, double beta, int K_fallback,
+                              int* x_out, double* pd_out, int* k_sched_out, uint32_t* flags)
+{
+#pragma omp parallel for schedule(dynamic, 2)
+    for (int b = 0; b < B; ++b) {
+        uint32_t f = orc_learned_detect(n, P, R + (size_t)b * n * n, z + (size_t)b * n, sigma2[b], w, margin, kmin,
+                                        kmax, beta, K_fallback, x_out + (size_t)b * n, pd_out ? pd_out + b : NULL,
+                                        k_sched_out ? k_sched_out + (size_t)b * n : NULL, NULL);
+        if (flags) flags[b] = f;
+    }
+}
+
 void orc_batch_qr(int B, int N, int M, const float* H, const float* y, double* R, double* z,
                   double* resid)
 {

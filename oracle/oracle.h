@@ -38,6 +38,8 @@ extern "C" {
 #define ORC_BUDGET_EXHAUSTED 4u   /* node budget reached before the list emptied */
 #define ORC_CERTIFIED        8u   /* list emptied: exact ML within the radius   */
 
+#define ORC_LEARNED_FALLBACK 16u  /* detected again by plain K-best            */
+
 /* counters: [0] nodes expanded (branched on), [1] PD evaluations (children),
  *           [2] rounds (hybrid only), [3] nodes discarded as stale */
 #define ORC_NCOUNTERS 4
@@ -130,7 +132,21 @@ double orc_mlp_loss_grad(const double* w, const double* X, const double* y, int 
 void orc_adam_step(double* w, double* m, double* v, const double* g, int np, int t, double lr,
                    double beta1, double beta2, double eps);
 
+/* The learned-pruning detector of one frame (the paper's unspecified "very
+ * close" survivor rule of Sec. VI replaced by a learned per-level count):
+ * features of the SIC path -> MLP -> K_t = clamp(ceil(2^(f + margin)), kmin,
+ * kmax) -> K-best with that schedule; the frame is detected again by plain
+ * K-best with K_fallback survivors (flag ORC_LEARNED_FALLBACK) when no leaf
+ * was found or its pd exceeds (sigma2 / 2)(n + beta sqrt(2 n)).
+ * k_sched_out [n] (or NULL) receives the schedule. */
+uint32_t orc_learned_detect(int n, int P, const double* R, const double* z, double sigma2, const double* w,
+                            double margin, int kmin, int kmax, double beta, int K_fallback, int* x_out,
+                            double* pd_out, int* k_sched_out, int64_t* counters);
+
 /* ---- batched drivers (OpenMP over frames) ---- */
+void orc_batch_learned_detect(int B, int n, int P, const double* R, const double* z, const double* sigma2,
+                              const double* w, double margin, int kmin, int kmax, double beta, int K_fallback,
+                              int* x_out, double* pd_out, int* k_sched_out, uint32_t* flags);
 void orc_batch_qr(int B, int N, int M, const float* H, const float* y, double* R, double* z,
                   double* resid);
 void orc_batch_brute_force(int B, int N, int M, int P, const float* H, const float* y, int* s_idx,

@@ -58,10 +58,12 @@ __host__ __device__ inline int mlp_perm(int hb, int i)
     return 32 * (hb >> 1) + 8 * (i >> 2) + 4 * (hb & 1) + (i & 3);
 }
 
-// S states, 16 per wavefront and step; SCHED: K_t = clamp(ceil(2^(yhat +
-// margin)), kmin, kmax) into ks (non-finite yhat: kmax and the frame flagged
-// for fallback), else yhat into out
-constexpr int MLP_WG = 512;                                  // eight waves share the staged W2
+// S states, 16 SG per wavefront and step (SG groups of 16 share each W2
+// fragment read from LDS); SCHED: K_t = clamp(ceil(2^(yhat + margin)), kmin,
+// kmax) into ks (non-finite yhat: kmax and the frame flagged for fallback),
+// else yhat into out
+constexpr int MLP_SG = 2;                                    // state groups per wave step
+constexpr int MLP_WG = 768;                                  // twelve waves (3 per SIMD) share the staged W2
 constexpr size_t MLP_W2_LDS = 2 * 8 * 4 * WAVE * sizeof(half8);  // hi and lo fragments: 64 KB
 
 template <bool SCHED>
@@ -70,6 +72,7 @@ __global__ void __launch_bounds__(MLP_WG) mlp_infer_kernel(const float* __restri
                                                            int kmax, int n, int32_t* __restrict__ ks,
                                                            uint32_t* __restrict__ flags)
 {
+    constexpr int SG = MLP_SG;
     __shared__ f32x4 cb1[8 * 4];  // b1 in the permuted order, [hb][g] -> rows 4g..4g+3
     __shared__ f32x4 cb2[32];     // b2, [nb][g] -> units 16nb + 4g .. +3
     __shared__ f32x4 cw3[32];     // w3, same layout
@@ -107,59 +110,76 @@ __global__ void __launch_bounds__(MLP_WG) mlp_infer_kernel(const float* __restri
     const float b3 = w[OB3];
     __syncthreads();
 
-    const int64_t ngrp = (S + 15) / 16;
+    const int64_t ngrp = (S + 16 * SG - 1) / (16 * SG);
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
     for (int64_t grp = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (tid >> 6); grp < ngrp; grp += nwaves) {
-        const int64_t s = grp * 16 + s16;
-        const float xb = s < S ? X[s * NIN + g] : 0.f;  // layer-1 B operand: feature g of state s16
-        asm volatile("" ::: "memory");  // W2 fragments are read from LDS each step, not hoisted into registers
-        f32x4 d2[8];
+        float xb[SG];  // layer-1 B operand of group q: feature g of state s16
 #pragma unroll
-        for (int nb = 0; nb < 8; ++nb) d2[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < SG; ++q) {
+            const int64_t s = (grp * SG + q) * 16 + s16;
+            xb[q] = s < S ? X[s * NIN + g] : 0.f;
+        }
+        asm volatile("" ::: "memory");  // W2 fragments are read from LDS each step, not hoisted into registers
+        f32x4 d2[SG][8];
+#pragma unroll
+        for (int q = 0; q < SG; ++q)
+#pragma unroll
+            for (int nb = 0; nb < 8; ++nb) d2[q][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const f32x4 h0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[2 * t], xb, cb1[(2 * t) * 4 + g], 0, 0, 0);
-            const f32x4 h1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[2 * t + 1], xb, cb1[(2 * t + 1) * 4 + g], 0, 0, 0);
-            half8 bh, bl;
+            half8 bh[SG], bl[SG];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const float r = fmaxf(e < 4 ? h0[e] : h1[e - 4], 0.f);
-                bh[e] = (_Float16)r;
-                bl[e] = (_Float16)(r - (float)bh[e]);
+            for (int q = 0; q < SG; ++q) {
+                const f32x4 h0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[2 * t], xb[q], cb1[(2 * t) * 4 + g], 0, 0, 0);
+                const f32x4 h1 =
+                    __builtin_amdgcn_mfma_f32_16x16x4f32(a1[2 * t + 1], xb[q], cb1[(2 * t + 1) * 4 + g], 0, 0, 0);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const float r = fmaxf(e < 4 ? h0[e] : h1[e - 4], 0.f);
+                    bh[q][e] = (_Float16)r;
+                    bl[q][e] = (_Float16)(r - (float)bh[q][e]);
+                }
             }
 #pragma unroll
             for (int nb = 0; nb < 8; ++nb) {
                 const half8 ah = w2h[(4 * nb + t) * WAVE + lane], al = w2l[(4 * nb + t) * WAVE + lane];
-                d2[nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, d2[nb], 0, 0, 0);
-                d2[nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, d2[nb], 0, 0, 0);
-                d2[nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, d2[nb], 0, 0, 0);
+#pragma unroll
+                for (int q = 0; q < SG; ++q) {
+                    d2[q][nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[q], d2[q][nb], 0, 0, 0);
+                    d2[q][nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl[q], d2[q][nb], 0, 0, 0);
+                    d2[q][nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[q], d2[q][nb], 0, 0, 0);
+                }
             }
         }
-        // lane (g, s16) holds units 16nb + 4g + r of state s16
-        float part = 0.f;
 #pragma unroll
-        for (int nb = 0; nb < 8; ++nb) {
-            const f32x4 bb = cb2[nb * 4 + g], ww = cw3[nb * 4 + g];
+        for (int q = 0; q < SG; ++q) {
+            const int64_t s = (grp * SG + q) * 16 + s16;
+            // lane (g, s16) holds units 16nb + 4g + r of state s16
+            float part = 0.f;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) part = fmaf(ww[r], fmaxf(d2[nb][r] + bb[r], 0.f), part);
-        }
-        part += __builtin_bit_cast(float, xor_lanes(__builtin_bit_cast(uint32_t, part), 16, lane));
-        part += __builtin_bit_cast(float, xor_lanes(__builtin_bit_cast(uint32_t, part), 32, lane));
-        const float yhat = part + b3;
-        if (g == 0 && s < S) {
-            if (!SCHED) {
-                out[s] = yhat;
-            } else {
-                int k;
-                if (!isfinite(yhat)) {
-                    k = kmax;
-                    if (flags) atomicOr(&flags[s / n], MIMO_FLAG_LEARNED_FALLBACK);
+            for (int nb = 0; nb < 8; ++nb) {
+                const f32x4 bb = cb2[nb * 4 + g], ww = cw3[nb * 4 + g];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) part = fmaf(ww[r], fmaxf(d2[q][nb][r] + bb[r], 0.f), part);
+            }
+            part += __builtin_bit_cast(float, xor_lanes(__builtin_bit_cast(uint32_t, part), 16, lane));
+            part += __builtin_bit_cast(float, xor_lanes(__builtin_bit_cast(uint32_t, part), 32, lane));
+            const float yhat = part + b3;
+            if (g == 0 && s < S) {
+                if (!SCHED) {
+                    out[s] = yhat;
                 } else {
-                    const float e = fminf(yhat + margin, 30.f);
-                    const float kk = ceilf(exp2f(e));
-                    k = kk < (float)kmin ? kmin : (kk > (float)kmax ? kmax : (int)kk);
+                    int k;
+                    if (!isfinite(yhat)) {
+                        k = kmax;
+                        if (flags) atomicOr(&flags[s / n], MIMO_FLAG_LEARNED_FALLBACK);
+                    } else {
+                        const float e = fminf(yhat + margin, 30.f);
+                        const float kk = ceilf(exp2f(e));
+                        k = kk < (float)kmin ? kmin : (kk > (float)kmax ? kmax : (int)kk);
+                    }
+                    ks[s] = k;
                 }
-                ks[s] = k;
             }
         }
     }
@@ -171,8 +191,8 @@ static int mlp_infer_grid(int64_t S)
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int64_t waves = MLP_WG / WAVE;
-    const int64_t want = ((S + 15) / 16 + waves - 1) / waves;
-    const int64_t cap = 2 * (int64_t)(cus > 0 ? cus : 256);  // two workgroups of 64 KB fit a compute unit
+    const int64_t want = ((S + 16 * MLP_SG - 1) / (16 * MLP_SG) + waves - 1) / waves;
+    const int64_t cap = (int64_t)(cus > 0 ? cus : 256);  // one workgroup per compute unit (144 VGPRs per lane)
     return (int)(want < cap ? want : cap);
 }
 
@@ -180,9 +200,13 @@ template <bool SCHED>
 static int32_t launch_mlp_infer(int64_t S, hipStream_t st, const float* w, const float* X, float* out, float margin,
                                 int kmin, int kmax, int n, int32_t* ks, uint32_t* flags)
 {
-    hipError_t e = hipFuncSetAttribute((const void*)mlp_infer_kernel<SCHED>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)MLP_W2_LDS);
-    if (e != hipSuccess) return fail(MIMO_ERR_HIP, "MLP inference: LDS attribute: %s", hipGetErrorString(e));
+    static bool lds_set = false;  // the attribute is set once per process (idempotent if two threads race)
+    if (!lds_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)mlp_infer_kernel<SCHED>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)MLP_W2_LDS);
+        if (e != hipSuccess) return fail(MIMO_ERR_HIP, "MLP inference: LDS attribute: %s", hipGetErrorString(e));
+        lds_set = true;
+    }
     hipLaunchKernelGGL(mlp_infer_kernel<SCHED>, dim3(mlp_infer_grid(S)), dim3(MLP_WG), MLP_W2_LDS, st, w, X, S, out,
                        margin, kmin, kmax, n, ks, flags);
     return check_launch(SCHED ? "prune_mlp_schedule" : "prune_mlp_forward");

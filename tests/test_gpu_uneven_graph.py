@@ -167,3 +167,66 @@ def test_uneven_kernel_skips_invalid_descriptors(gpu):
     good = np.setdiff1d(np.arange(ub.B), list(bad))
     assert np.array_equal(fl[good], ref_fl.cpu().numpy()[good])
     assert np.array_equal(pd[good], ref_pd.cpu().numpy()[good])
+
+
+def test_learned_detector_end_to_end(gpu, orc):
+    """The headline learned detector on a sample of the benchmark's frames
+    against the oracle's composition of the same steps (FP64): the survivor
+    schedules agree except by one at states whose FP64 count sits next to a
+    ceil boundary; the scheduled K-best (fed the GPU's schedule, so that the
+    comparison is decoupled from MLP rounding) follows the forced-path rule;
+    the fallback decision agrees except for a pd within 1e-4 of the noise
+    bound; the final detections equal the oracle's pipeline on every frame
+    whose schedule and fallback decision agree, up to near ties."""
+    import os
+
+    import torch
+
+    from paper_2002_09561_amd import learned
+    from tests.parity_util import check_kbest_run
+
+    path = os.path.join(os.path.dirname(gpu.__file__), "weights", "prune_mlp_100x100_64qam.bin")
+    w, meta = learned.load_weights(path)
+    M, q, P, n, Bs = 100, 64, 8, 200, 8
+    fs = [gen_frames(M, M, q, snr, Bs, seed=2020, snr_idx=i) for i, snr in enumerate((20.0, 22.0, 24.0))]
+    Hn = np.concatenate([f.H for f in fs])
+    Yn = np.concatenate([f.y for f in fs])
+    s2n = np.repeat(np.array([f.sigma2 for f in fs], np.float32), Bs)
+    H, Y, s2 = torch.from_numpy(Hn).cuda(), torch.from_numpy(Yn).cuda(), torch.from_numpy(s2n).cuda()
+    R, z = gpu.qr_preprocess(H, Y)
+    mg, kmin, kmax, beta = meta["margin"], meta["k_min"], meta["k_max"], meta["beta"]
+    print("learned detector end to end, 24 frames of 100x100 64-QAM", flush=True)
+    ks = learned.schedule(w.cuda(), R, z, s2, M, P, mg, kmin, kmax)
+    s1, p1, f1 = gpu.kbest_detect(R, z, M, P, kmax, k_sched=ks)
+    sf, pf, ff = s1.clone(), p1.clone(), f1.clone()
+    gpu.kbest_fallback(R, z, M, P, 64, s2, beta, (sf, pf, ff))
+    Ro, zo, _ = orc.qr(Hn, Yn)
+    w64 = w.numpy().astype(np.float64)
+    ref = orc.learned_detect(Ro, zo, P, s2n.astype(np.float64), w64, mg, kmin, kmax, beta, 64)
+    ksg = ks.cpu().numpy()
+    d = ksg != ref["k_sched"]
+    print(f"  schedules: {d.sum()} of {d.size} states differ")
+    assert np.all(np.abs(ksg - ref["k_sched"]) <= 1) and d.mean() < 0.01
+    first = orc.kbest(Ro, zo, P, kmax, k_sched=ksg)
+    check_kbest_run(orc, "scheduled K-best (GPU schedule)", P, kmax, _np(s1), _np(p1), first, Ro, zo, k_sched=ksg)
+    bound = 0.5 * s2n.astype(np.float64) * (n + beta * np.sqrt(2 * n))
+    fb_g = (_np(ff) & gpu.FLAG_LEARNED_FALLBACK) != 0
+    fb_o = (ref["flags"] & orc.LEARNED_FALLBACK) != 0
+    near = np.abs(first["pd"] - bound) <= 1e-4 * bound
+    assert np.all((fb_g == fb_o) | near)
+    # frames that keep their first detection are untouched by the fallback
+    assert np.array_equal(_np(sf)[~fb_g], _np(s1)[~fb_g])
+    # the re-detected frames: plain K-best K = 64
+    if fb_g.any():
+        kb = orc.kbest(Ro[fb_g], zo[fb_g], P, 64)
+        check_kbest_run(orc, "learned detector, fallback frames", P, 64, _np(sf)[fb_g], _np(pf)[fb_g], kb,
+                        Ro[fb_g], zo[fb_g])
+    # where the schedules and the fallback decision agree, the oracle's whole
+    # pipeline took the same steps: its result is the scheduled K-best's or
+    # the fallback's checked above
+    agree = (fb_g == fb_o) & ~np.any(d, axis=1) & ~fb_o
+    assert np.array_equal(ref["x"][agree], first["x"][agree])
+
+
+def _np(t):
+    return t.cpu().numpy()

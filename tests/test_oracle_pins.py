@@ -644,3 +644,32 @@ def test_adam_steps_closed_form(orc):
     for t in range(1, 6):
         orc.adam_step(w, m, v, g, t, lr, b1, b2, eps)
     assert np.allclose(w, w0 - 5 * lr * g / (np.abs(g) + eps), rtol=1e-10)
+
+
+# --------------------------------------------------------------- the learned detector as a whole
+def test_learned_detect_composition(orc):
+    """The learned detector is the composition its definition states: with
+    the noise test disabled its schedule is clamp(ceil(2^(f + margin))) of
+    the MLP output on the SIC-path features (mapped here in numpy) and its
+    result is K-best with that schedule; a huge margin gives the plain
+    K-best with k_max survivors; a noise test that every frame fails gives
+    the plain fallback K-best on every frame, flagged."""
+    rng = np.random.default_rng(21)
+    w = rng.normal(0, 0.2, orc.MLP_NPARAM)
+    f = gen_frames(6, 6, 16, 12.0, 30, seed=95)
+    R, z, _ = orc.qr(f.H, f.y)
+    P, n, margin, kmin, kmax = 4, 12, 2.0, 1, 16
+    out = orc.learned_detect(R, z, P, f.sigma2, w, margin, kmin, kmax, beta=1e9)
+    feats = orc.prune_features(R, z, P, f.sigma2)
+    pred = orc.mlp_forward(w, feats.reshape(-1, 4)).reshape(len(f), n)
+    ks = np.clip(np.ceil(np.exp2(pred + margin)), kmin, kmax).astype(np.int32)
+    assert np.array_equal(out["k_sched"], ks)
+    assert len(np.unique(ks)) > 3
+    kb = orc.kbest(R, z, P, kmax, k_sched=ks)
+    assert np.array_equal(out["x"], kb["x"]) and np.allclose(out["pd"], kb["pd"], rtol=1e-14)
+    assert not np.any(out["flags"] & orc.LEARNED_FALLBACK)
+    big = orc.learned_detect(R, z, P, f.sigma2, w, 40.0, kmin, kmax, beta=1e9)
+    assert np.all(big["k_sched"] == kmax) and np.array_equal(big["x"], orc.kbest(R, z, P, kmax)["x"])
+    fb = orc.learned_detect(R, z, P, f.sigma2, w, margin, kmin, kmax, beta=-1e9, K_fallback=32)
+    assert np.all(fb["flags"] & orc.LEARNED_FALLBACK)
+    assert np.array_equal(fb["x"], orc.kbest(R, z, P, 32)["x"])
