@@ -158,6 +158,26 @@ int32_t kbest_detect_complex(const float* R, const float* z, int32_t B, int32_t 
                              int64_t* counters, void* stream);
 
 /* ---------------------------------------------------------------------
+ * Grouped K-best: the detection of kbest_detect (J = 1) or of
+ * kbest_detect_complex (J = 2: J real levels, one complex symbol, per step;
+ * Sec. IV-B grouping), with the successors' centres taken from one matrix
+ * product per group of 16 real levels (Sec. V-A evaluates all successors as
+ * B = Y* - R'V; here C = (c R)[group rows, levels above] X[levels above,
+ * survivors] on the matrix cores, c R split exactly into three bf16 parts,
+ * FP32 sums) and the levels inside the group added one by one (Eq. (inc)).
+ * The tree, the keys (pd, parent rank, child index), K_t = k_sched[level of
+ * the step's lowest real level], the radius, the empty-sphere re-run, the
+ * flags and the counters (counters[b][1] = J real-level evaluations per
+ * child) are those of kbest_detect / kbest_detect_complex; only the order of
+ * the FP32 sums in a centre differs.  Arguments and outputs as kbest_detect.
+ * Limits: J in {1, 2}, 1 <= K <= 64, K * pam^J <= 1024, n_tx <= 128.
+ * ------------------------------------------------------------------- */
+int32_t kbest_detect_grouped(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam,
+                             int32_t K, int32_t J, const int32_t* k_sched, int32_t k_sched_stride,
+                             const float* radius2, int32_t* sym, float* pd, uint32_t* flags,
+                             int64_t* counters, void* stream);
+
+/* ---------------------------------------------------------------------
  * Plain fallback of a learned detection (the plain K-best stays the
  * reference method): frame b is detected again by plain K-best with K
  * survivors, overwriting sym[b], pd[b], flags[b] (which then carry

@@ -1,0 +1,496 @@
+// Grouped K-best: the tree of kbest_detect (J = 1, real levels) or of
+// kbest_detect_complex (J = 2, one complex symbol per step), with the
+// successor evaluation of Sec. V-A done as one matrix product per group of
+// levels on the matrix cores.
+//
+// The paper evaluates all successors of a node at once as B = Y* - R'V, the
+// columns of V being the successors' fixed symbols (Sec. V-A), and branches
+// on J symbols per step (Sec. IV-B).  On a wavefront that holds K_t survivors
+// of one frame the heavy part of that product is the interference of the
+// levels already fixed:
+//
+//     C[k][s] = sum_{j > k} (c R)[k][j] x_s[j]
+//
+// for the rows k of the next levels and every survivor s.  The levels are
+// cut into groups of 16 (group h = levels 16h .. 16h + 15).  When a group
+// starts, the interference of every level above it is one product
+// C = (c R)[group rows, levels above] X[levels above, survivors], computed on
+// v_mfma_f32_16x16x32_bf16: c R is split exactly into three bf16 parts
+// (8 significant bits each, truncated: hi + mid + lo reproduces the FP32
+// value), the amplitudes 2i - (P-1) are exact in bf16, every product is exact
+// and the sums are FP32.  Inside the group, the centre of level k of
+// survivor s is
+//
+//     b = z_k - C[k][origin(s)] - sum_{k < j in group, fixed} (c R)[k][j] x_s[j]
+//
+// where origin(s) is the survivor, at the start of the group, that s descends
+// from (Eq. (inc): the part above the group is computed once per group, the
+// rest level by level).  Children, radius test and K_t selection are those of
+// the other K-best kernels, so the tree, the keys (pd, parent rank, child)
+// and the result are theirs; only the order of the FP32 sums in a centre
+// differs.
+//
+// Paths are never copied level by level.  A survivor carries its origin and
+// the 16 amplitude bytes of the current group (4 registers, a + 8 per level,
+// 8 = not yet fixed); when the group ends every survivor's bytes and origin
+// are written once to a per-group segment table in LDS.  The path of a
+// survivor is the chain segment(h, s) -> segment(h + 1, parent) -> ..., which
+// is what the matrix product's B operand reads.
+#include "common.hpp"
+#include "kbest_common.hpp"
+
+namespace mimo {
+
+typedef __bf16 gk_bf16x8 __attribute__((ext_vector_type(8)));
+typedef float gk_f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t gk_u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t gk_u32x2 __attribute__((ext_vector_type(2)));
+
+constexpr int GK_LEVELS = 16;       // levels per group = rows of one matrix-core tile
+constexpr int GK_CAND_MAX = 1024;   // K pam^J candidates per step
+constexpr uint32_t GK_UNFIXED = 0x08080808u;
+
+template <int P, int J, int E>
+struct GroupedShape {
+    static constexpr int PC = J == 1 ? P : P * P;                 // children per survivor
+    static constexpr int KCAP = WAVE * E / PC;                     // survivor capacity
+    static constexpr int L = WAVE / KCAP;                          // lanes per survivor
+    static constexpr int NT = KCAP >= 16 ? KCAP / 16 : 1;          // survivor tiles of 16 columns
+    static constexpr int CST = KCAP >= 16 ? KCAP : 16;             // row stride of C in LDS
+};
+
+// LDS of one frame: compaction keys, segment words [G][KCAP][4], C [16][CST],
+// in-group rows [16][16], diagonal [16], z [16], survivor pd [2][KCAP],
+// selected candidates [KCAP], segment parents [G][KCAP] (bytes)
+__host__ __device__ inline size_t gk_lds_bytes(int kcap, int G)
+{
+    const int cst = kcap >= 16 ? kcap : 16;
+    return sizeof(uint64_t) * 2 * WAVE + sizeof(uint32_t) * 4 * (size_t)G * kcap + sizeof(float) * 16 * cst +
+           sizeof(float) * (256 + 32) + sizeof(float) * 2 * kcap + sizeof(int32_t) * kcap + (size_t)G * kcap;
+}
+
+// exact three-way bf16 split of an FP32 value by truncation: hi keeps the
+// top 8 significant bits, mid the next 8 of the remainder, lo the rest (the
+// remainders are exact FP32 differences, and what is left for lo has at most
+// 8 significant bits)
+__device__ __forceinline__ void gk_split3(float v, __bf16& hi, __bf16& mid, __bf16& lo)
+{
+    const float h = __uint_as_float(__float_as_uint(v) & 0xffff0000u);
+    const float r1 = v - h;
+    const float m = __uint_as_float(__float_as_uint(r1) & 0xffff0000u);
+    const float r2 = r1 - m;
+    hi = (__bf16)h;
+    mid = (__bf16)m;
+    lo = (__bf16)r2;
+}
+
+// eight amplitude bytes (a + 8) -> bf16 amplitudes a
+__device__ __forceinline__ gk_bf16x8 gk_decode8(uint32_t w0, uint32_t w1)
+{
+    gk_bf16x8 b;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        b[e] = (__bf16)((float)((w0 >> (8 * e)) & 0xffu) - 8.f);
+        b[e + 4] = (__bf16)((float)((w1 >> (8 * e)) & 0xffu) - 8.f);
+    }
+    return b;
+}
+
+template <int P, int J, int E>
+__device__ __forceinline__ void kbest_frame_grouped(const KbestArgs& a, int frame, unsigned char* lds)
+{
+    using S = GroupedShape<P, J, E>;
+    constexpr int PC = S::PC, KCAP = S::KCAP, L = S::L, NT = S::NT, CST = S::CST;
+    static_assert(KCAP >= 1 && KCAP <= 64, "one survivor per lane at most, one at least");
+    static_assert(J == 1 || J == 2, "one or two real levels per step");
+    const int lane = threadIdx.x & 63;
+    const int s_own = lane / L, q = lane % L;
+    const int n = a.n;
+    const int G = (n + GK_LEVELS - 1) / GK_LEVELS;
+    uint64_t* skey = reinterpret_cast<uint64_t*>(lds);
+    uint32_t* segb = reinterpret_cast<uint32_t*>(skey + 2 * WAVE);
+    float* cg = reinterpret_cast<float*>(segb + 4 * G * KCAP);
+    float* rg = cg + 16 * CST;
+    float* rd = rg + 256;
+    float* zg = rd + 16;
+    float* spd = zg + 16;
+    int32_t* sel = reinterpret_cast<int32_t*>(spd + 2 * KCAP);
+    uint8_t* segp = reinterpret_cast<uint8_t*>(sel + KCAP);
+
+    const float* Rf = a.R + (size_t)frame * r_packed_size(n);
+    const float* zf = a.z + (size_t)frame * n;
+    const float r2 = a.radius2 ? a.radius2[frame] : INFINITY;
+    const float cs = pam_scale(P);
+    const int32_t* ks = a.k_sched ? a.k_sched + (size_t)frame * a.k_sched_stride : nullptr;
+    // the frame's R as one buffer: loads past its end return 0
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(Rf), 0, (int)r_packed_size(n) * (int)sizeof(float), 0x00020000);
+
+    uint32_t igw[4] = {GK_UNFIXED, GK_UNFIXED, GK_UNFIXED, GK_UNFIXED};
+    int orig = s_own;
+    if (lane == 0) spd[0] = 0.f;
+    int cnt = 1, step = 0;
+    int64_t expanded = 0;
+    uint32_t flags = 0;
+    bool stopped = false;
+
+    for (int h = G - 1; h >= 0 && !stopped; --h) {
+        const int k0 = GK_LEVELS * h;
+        const int ktop = min(k0 + GK_LEVELS - 1, n - 1);
+        // in-group rows: (c R)[k0 + r][k0 + c] for c > r (the complex-level
+        // tree drops the structural zero R[2m][2m+1]), the diagonal and z
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int idx = lane + WAVE * i;
+            const int r = idx >> 4, c = idx & 15;
+            const int k = k0 + r, j = k0 + c;
+            float v = 0.f;
+            if (c > r && j < n && !(J == 2 && !(r & 1) && c == r + 1)) v = cs * Rf[r_row_off(n, k) + (j - k)];
+            rg[idx] = v;
+        }
+        if (lane < 16) {
+            const int k = k0 + lane;
+            rd[lane] = k < n ? cs * Rf[r_row_off(n, k)] : 0.f;
+            zg[lane] = k < n ? zf[k] : 0.f;
+        }
+        // interference of the levels above the group, for every survivor, on the matrix cores
+        if (h < G - 1) {
+            gk_f32x4 acc[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[t] = gk_f32x4{0.f, 0.f, 0.f, 0.f};
+            const int row = k0 + (lane & 15);                  // A row of this lane (every row exists)
+            const int roff = (int)r_row_off(n, row) - row;     // (c R)[row][j] at roff + j
+            const int nch = (n - GK_LEVELS * (h + 1) + 31) / 32;
+            const int upper = lane >> 5;                       // B rows from group h+1+2ch (+1 for upper lanes)
+            const int bsub = 2 * ((lane >> 4) & 1);            // word offset in the segment: levels 0-7 or 8-15
+            int anc[NT];
+            bool live[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int s = 16 * t + (lane & 15);
+                live[t] = s < cnt;
+                anc[t] = live[t] ? s : 0;
+            }
+            int g = h + 1;
+            if (upper) {
+                if (g < G) {
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) anc[t] = segp[g * KCAP + anc[t]];
+                }
+                ++g;
+            }
+            for (int ch = 0; ch < nch; ++ch) {
+                const int j0 = GK_LEVELS * (h + 1) + 32 * ch + 8 * (lane >> 4);
+                const gk_u32x4 w0 = __builtin_amdgcn_raw_buffer_load_b128(rs, 4 * (roff + j0), 0, 0);
+                const gk_u32x4 w1 = __builtin_amdgcn_raw_buffer_load_b128(rs, 4 * (roff + j0 + 4), 0, 0);
+                gk_bf16x8 ahi, amid, alo;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const float rv = __uint_as_float(e < 4 ? w0[e] : w1[e - 4]);
+                    const float v = j0 + e < n ? cs * rv : 0.f;
+                    __bf16 hi, mid, lo;
+                    gk_split3(v, hi, mid, lo);
+                    ahi[e] = hi;
+                    amid[e] = mid;
+                    alo[e] = lo;
+                }
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    gk_bf16x8 b;
+                    if (g < G && live[t]) {
+                        const gk_u32x2 wb = *reinterpret_cast<const gk_u32x2*>(segb + 4 * (g * KCAP + anc[t]) + bsub);
+                        b = gk_decode8(wb[0], wb[1]);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) b[e] = (__bf16)0.f;
+                    }
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, b, acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(amid, b, acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, b, acc[t], 0, 0, 0);
+                }
+                // two groups up for the next chunk of 32 levels
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    if (g < G) {
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) anc[t] = segp[g * KCAP + anc[t]];
+                    }
+                    ++g;
+                }
+            }
+            // lane l holds C rows 4 (l / 16) + i of survivor column 16 t + l % 16
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int col = 16 * t + (lane & 15);
+                if (col < KCAP) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) cg[(4 * (lane >> 4) + i) * CST + col] = acc[t][i];
+                }
+            }
+        }
+        kb_wave_sync();
+
+        for (int k_hi = ktop; k_hi >= k0; k_hi -= J) {
+            const int r_hi = k_hi - k0, r_lo = r_hi - (J - 1);
+            const int cur = step & 1, nxt = cur ^ 1;
+            float* sc = spd + cur * KCAP;
+            float* sn = spd + nxt * KCAP;
+            // centres of this lane's survivor: the levels above the group
+            // (C at the survivor's origin), then the fixed levels of the group
+            float dh = 0.f, dl = 0.f;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                if (4 * d + 3 > r_hi) {  // a word with fixed levels above k_hi (uniform)
+                    const float4 rh = *reinterpret_cast<const float4*>(rg + 16 * r_hi + 4 * d);
+                    const float xs[4] = {(float)(igw[d] & 0xffu) - 8.f, (float)((igw[d] >> 8) & 0xffu) - 8.f,
+                                         (float)((igw[d] >> 16) & 0xffu) - 8.f, (float)(igw[d] >> 24) - 8.f};
+                    dh = fmaf(rh.x, xs[0], dh);
+                    dh = fmaf(rh.y, xs[1], dh);
+                    dh = fmaf(rh.z, xs[2], dh);
+                    dh = fmaf(rh.w, xs[3], dh);
+                    if constexpr (J == 2) {
+                        const float4 rl = *reinterpret_cast<const float4*>(rg + 16 * r_lo + 4 * d);
+                        dl = fmaf(rl.x, xs[0], dl);
+                        dl = fmaf(rl.y, xs[1], dl);
+                        dl = fmaf(rl.z, xs[2], dl);
+                        dl = fmaf(rl.w, xs[3], dl);
+                    }
+                }
+            }
+            const bool above = h < G - 1;
+            const float bh_own = zg[r_hi] - ((above ? cg[r_hi * CST + orig] : 0.f) + dh);
+            const float bl_own = J == 2 ? zg[r_lo] - ((above ? cg[r_lo * CST + orig] : 0.f) + dl) : 0.f;
+            const float rkh = rd[r_hi], rkl = rd[r_lo];
+            // a NaN or infinity in R or z reaches every centre of the level
+            if (__ballot(!kb_finite(rkh) || !kb_finite(rkl) ||
+                         (s_own < cnt && !(kb_finite(bh_own) && kb_finite(bl_own))))) {
+                flags |= MIMO_FLAG_NONFINITE_INPUT;
+                cnt = 0;
+                stopped = true;
+                break;
+            }
+            uint32_t kh[E];
+            const int ncand = cnt * PC;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                kh[e] = ~0u;
+                if (e * WAVE >= ncand) continue;  // block without candidates (uniform)
+                const int mm = e * WAVE + lane;
+                const int s = PC >= WAVE ? e * WAVE / PC : mm / PC;  // uniform when a block is one survivor
+                const int c = mm % PC;
+                float bh, bl = 0.f;
+                if constexpr (PC >= WAVE) {  // one survivor per block
+                    bh = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, bh_own), s * L));
+                    if constexpr (J == 2)
+                        bl = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, bl_own), s * L));
+                } else {
+                    bh = shfl_f(bh_own, s * L);
+                    if constexpr (J == 2) bl = shfl_f(bl_own, s * L);
+                }
+                if (s < cnt) {
+                    float pdc;
+                    if constexpr (J == 1) {
+                        const float ee = fmaf(-rkh, (float)(2 * c - (P - 1)), bh);
+                        pdc = fmaf(ee, ee, sc[s]);
+                    } else {
+                        const float eh = fmaf(-rkh, (float)(2 * (c / P) - (P - 1)), bh);
+                        const float el = fmaf(-rkl, (float)(2 * (c % P) - (P - 1)), bl);
+                        pdc = fmaf(el, el, fmaf(eh, eh, sc[s]));
+                    }
+                    if (pdc < r2) kh[e] = __float_as_uint(pdc);
+                }
+            }
+            expanded += cnt;
+            int nvalid = 0;
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                if (e * WAVE < ncand) nvalid += __popcll(__ballot(kh[e] != ~0u));
+            if (nvalid == 0) {
+                flags |= MIMO_FLAG_EMPTY_SPHERE;
+                cnt = 0;
+                stopped = true;
+                break;
+            }
+            int Kt = ks ? ks[k0 + r_lo] : a.K;
+            Kt = Kt > a.K ? a.K : (Kt < 1 ? 1 : Kt);
+            Kt = Kt > KCAP ? KCAP : Kt;
+            int fpos = -1;
+            int keep;
+            if constexpr (E <= 2) {
+                if (ncand <= 32)
+                    keep = kb_select_sort<E, 1, 32>(kh, nvalid, Kt, -1, lane, sn, sel, &fpos);
+                else if (ncand <= WAVE)
+                    keep = kb_select_sort<E, 1>(kh, nvalid, Kt, -1, lane, sn, sel, &fpos);
+                else
+                    keep = kb_select_sort<E, E>(kh, nvalid, Kt, -1, lane, sn, sel, &fpos);
+            } else {
+                keep = kb_select_merge<E, PC>(kh, ncand, nvalid, Kt, -1, lane, sn, sel, skey, &fpos);
+            }
+            kb_wave_sync();
+            // new survivor s_own: its parent's origin and group bytes, plus the new level(s)
+            int src = lane, cnew = 0;
+            if (s_own < keep) {
+                const int mm = sel[s_own];
+                src = (mm / PC) * L + q;
+                cnew = mm % PC;
+            }
+            orig = __shfl(orig, src, WAVE);
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+                if (4 * d + 3 > r_hi) igw[d] = (uint32_t)__shfl((int)igw[d], src, WAVE);
+            if (s_own < keep) {
+                const int d = r_hi >> 2;
+                uint32_t put, mask;
+                if constexpr (J == 1) {
+                    put = (uint32_t)(2 * cnew - (P - 1) + 8) << (8 * (r_hi & 3));
+                    mask = 0xffu << (8 * (r_hi & 3));
+                } else {  // levels r_lo (real part, even) and r_hi = r_lo + 1 (imaginary part)
+                    put = ((uint32_t)(2 * (cnew % P) - (P - 1) + 8) | ((uint32_t)(2 * (cnew / P) - (P - 1) + 8) << 8))
+                          << (8 * (r_lo & 3));
+                    mask = 0xffffu << (8 * (r_lo & 3));
+                }
+#pragma unroll
+                for (int dd = 0; dd < 4; ++dd)
+                    if (dd == d) igw[dd] = (igw[dd] & ~mask) | put;
+            }
+            cnt = keep;
+            ++step;
+        }
+        if (stopped) break;
+        // the group's segment of every survivor: its bytes and its origin
+        if (q == 0 && s_own < cnt) {
+            *reinterpret_cast<gk_u32x4*>(segb + 4 * (h * KCAP + s_own)) = gk_u32x4{igw[0], igw[1], igw[2], igw[3]};
+            segp[h * KCAP + s_own] = (uint8_t)orig;
+        }
+        kb_wave_sync();
+        orig = s_own;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) igw[d] = GK_UNFIXED;
+    }
+
+    if (lane == 0) {
+        if (cnt > 0) flags |= MIMO_FLAG_FOUND;
+        if (a.fb_sigma2) flags |= MIMO_FLAG_LEARNED_FALLBACK;
+        if (a.rerun) flags |= MIMO_FLAG_EMPTY_SPHERE;
+        if (a.flags) a.flags[frame] = flags;
+        if (a.pd) a.pd[frame] = cnt > 0 ? spd[(step & 1) * KCAP] : INFINITY;
+        if (a.counters) kb_write_counters(a, frame, expanded, PC * J);
+    }
+    if (!a.sym) return;
+    // survivor 0 is the best leaf: lane h rebuilds its segment of group h by
+    // following the parents from group 0 up
+    const int nw = n / 2;
+    if (lane < G) {
+        uint32_t w[4] = {GK_UNFIXED, GK_UNFIXED, GK_UNFIXED, GK_UNFIXED};
+        if (cnt > 0) {
+            int anc = 0;
+            for (int g = 0; g < lane; ++g) anc = segp[g * KCAP + anc];
+            const gk_u32x4 v = *reinterpret_cast<const gk_u32x4*>(segb + 4 * (lane * KCAP + anc));
+            w[0] = v[0];
+            w[1] = v[1];
+            w[2] = v[2];
+            w[3] = v[3];
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int sw = 8 * lane + i;  // complex symbol: real part at byte 2i, imaginary part at 2i + 1
+            if (sw < nw) {
+                int v = 0;
+                if (cnt > 0) {
+                    const int are = (int)((w[i >> 1] >> (16 * (i & 1))) & 0xffu) - 8;
+                    const int aim = (int)((w[i >> 1] >> (16 * (i & 1) + 8)) & 0xffu) - 8;
+                    v = ((are + (P - 1)) / 2) * P + (aim + (P - 1)) / 2;
+                }
+                a.sym[(size_t)frame * nw + sw] = v;
+            }
+        }
+    }
+}
+
+template <int P, int J, int E>
+__global__ void __launch_bounds__(64) kbest_grouped_kernel(KbestArgs a)
+{
+    extern __shared__ unsigned char smem_kbg[];
+    if (kb_keep_first(a, blockIdx.x)) return;
+    kbest_frame_grouped<P, J, E>(a, blockIdx.x, smem_kbg);
+}
+
+template <int P, int J, int E>
+static int32_t launch_grouped(const KbestArgs& a, int B, hipStream_t st)
+{
+    using S = GroupedShape<P, J, E>;
+    const int G = (a.n + GK_LEVELS - 1) / GK_LEVELS;
+    hipLaunchKernelGGL((kbest_grouped_kernel<P, J, E>), dim3(B), dim3(WAVE), gk_lds_bytes(S::KCAP, G), st, a);
+    return check_launch("kbest_detect_grouped");
+}
+
+// smallest block count E (a power of two) with 64 E >= K pam^J candidates
+template <int P, int J>
+static int32_t dispatch_grouped_pj(const KbestArgs& a, int B, hipStream_t st)
+{
+    constexpr int PC = J == 1 ? P : P * P;
+    const int need = a.K * PC;
+    if (need <= 64 && PC <= 64) return launch_grouped<P, J, 1>(a, B, st);
+    if constexpr (2 * WAVE / PC <= 64) {
+        if (need <= 128) return launch_grouped<P, J, 2>(a, B, st);
+    }
+    if constexpr (4 * WAVE / PC <= 64) {
+        if (need <= 256) return launch_grouped<P, J, 4>(a, B, st);
+    }
+    if constexpr (8 * WAVE / PC <= 64) {
+        if (need <= 512) return launch_grouped<P, J, 8>(a, B, st);
+    }
+    if constexpr (16 * WAVE / PC <= 64) {
+        if (need <= 1024) return launch_grouped<P, J, 16>(a, B, st);
+    }
+    return fail(MIMO_ERR_UNSUPPORTED, "kbest_detect_grouped: K * pam^J beyond the instantiations");
+}
+
+static int32_t dispatch_grouped(const KbestArgs& a, int pam, int J, int B, hipStream_t st)
+{
+    if (J == 1) {
+        switch (pam) {
+        case 2: return dispatch_grouped_pj<2, 1>(a, B, st);
+        case 4: return dispatch_grouped_pj<4, 1>(a, B, st);
+        default: return dispatch_grouped_pj<8, 1>(a, B, st);
+        }
+    }
+    switch (pam) {
+    case 2: return dispatch_grouped_pj<2, 2>(a, B, st);
+    case 4: return dispatch_grouped_pj<4, 2>(a, B, st);
+    default: return dispatch_grouped_pj<8, 2>(a, B, st);
+    }
+}
+
+}  // namespace mimo
+
+extern "C" int32_t kbest_detect_grouped(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam,
+                                        int32_t K, int32_t J, const int32_t* k_sched, int32_t k_sched_stride,
+                                        const float* radius2, int32_t* sym, float* pd, uint32_t* flags,
+                                        int64_t* counters, void* stream)
+{
+    using namespace mimo;
+    const char* who = "kbest_detect_grouped";
+    if (B < 0) return fail(MIMO_ERR_INVALID_ARG, "%s: B < 0", who);
+    if (pam != 2 && pam != 4 && pam != 8) return fail(MIMO_ERR_INVALID_ARG, "%s: pam must be 2, 4 or 8", who);
+    if (J != 1 && J != 2) return fail(MIMO_ERR_INVALID_ARG, "%s: J must be 1 or 2", who);
+    if (n_tx < 1) return fail(MIMO_ERR_INVALID_ARG, "%s: n_tx < 1", who);
+    if (n_tx > MIMO_MAX_TX) return fail(MIMO_ERR_UNSUPPORTED, "%s: n_tx > %d", who, MIMO_MAX_TX);
+    if (K < 1) return fail(MIMO_ERR_INVALID_ARG, "%s: K < 1", who);
+    const int pc = J == 1 ? pam : pam * pam;
+    if (K > 64 || K * pc > GK_CAND_MAX)
+        return fail(MIMO_ERR_UNSUPPORTED, "%s: K <= 64 and K * pam^J <= %d", who, GK_CAND_MAX);
+    const int n = 2 * n_tx;
+    if (k_sched && k_sched_stride != 0 && k_sched_stride != n)
+        return fail(MIMO_ERR_INVALID_ARG, "%s: k_sched_stride must be 0 or n = %d", who, n);
+    if (B == 0) return MIMO_OK;
+    if (!R || !z || !sym || !pd || !flags) return fail(MIMO_ERR_INVALID_ARG, "%s: null pointer", who);
+    KbestArgs a{R, z, n, K, k_sched, k_sched_stride, radius2, nullptr, nullptr, sym, pd, flags, counters, nullptr, 0.f};
+    hipStream_t st = (hipStream_t)stream;
+    int32_t rc = dispatch_grouped(a, pam, J, B, st);
+    if (rc || !radius2) return rc;
+    KbestArgs r = a;  // frames whose finite radius left no leaf: again with r2 = +inf
+    r.radius2 = nullptr;
+    r.rerun = 1;
+    return dispatch_grouped(r, pam, J, B, st);
+}

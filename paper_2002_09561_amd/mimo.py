@@ -35,6 +35,7 @@ SIGNATURES = {
     "mimo_paper_radius2": ([_P, _I32, _I32, _I32, _P, _P], _I32),
     "kbest_detect": ([_P, _P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P, _P], _I32),
     "kbest_detect_complex": ([_P, _P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P, _P], _I32),
+    "kbest_detect_grouped": ([_P, _P, _I32, _I32, _I32, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P, _P], _I32),
     "kbest_fallback_mark": ([_P, _P, _P, _I32, _I32, _F, _P], _I32),
     "mimo_metric_select": ([_P, _P, _P, _P, ctypes.c_uint32, ctypes.c_uint32, _I32, _I32, _I32, _I32, _P, _P], _I32),
     "kbest_rank_labels": ([_P, _P, _I32, _I32, _I32, _I32, _P, _P, _P], _I32),
@@ -213,6 +214,23 @@ def kbest_detect_complex(R, z, n_tx: int, pam: int, K: int, k_sched=None, radius
     sym, pd, flags, ctr = out if out is not None else _det_outputs(B, n_tx, z.device, want_counters)
     ks, stride = _sched(k_sched, n)
     _check(load().kbest_detect_complex(_ptr(R, torch.float32, "R"), _ptr(z, torch.float32, "z"), B, n_tx, pam, K,
+                                       _ptr(ks, torch.int32, "k_sched"), stride,
+                                       _ptr(radius2, torch.float32, "radius2"), _ptr(sym), _ptr(pd), _ptr(flags),
+                                       _ptr(ctr), _stream(stream)))
+    return (sym, pd, flags, ctr) if want_counters else (sym, pd, flags)
+
+
+def kbest_detect_grouped(R, z, n_tx: int, pam: int, K: int, J: int = 1, k_sched=None, radius2=None,
+                         want_counters=False, out=None, stream=None):
+    """Grouped K-best (J real levels per step; the interference of the levels
+    above each group of 16 from one matrix product).  Same tree and outputs
+    as kbest_detect (J = 1) or kbest_detect_complex (J = 2).
+    Returns (sym [B,n_tx] int32, pd [B] f32, flags [B] int32[, counters])."""
+    B = z.shape[0]
+    n = 2 * n_tx
+    sym, pd, flags, ctr = out if out is not None else _det_outputs(B, n_tx, z.device, want_counters)
+    ks, stride = _sched(k_sched, n)
+    _check(load().kbest_detect_grouped(_ptr(R, torch.float32, "R"), _ptr(z, torch.float32, "z"), B, n_tx, pam, K, J,
                                        _ptr(ks, torch.int32, "k_sched"), stride,
                                        _ptr(radius2, torch.float32, "radius2"), _ptr(sym), _ptr(pd), _ptr(flags),
                                        _ptr(ctr), _stream(stream)))

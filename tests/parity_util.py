@@ -44,14 +44,16 @@ def pack_level_order(R: np.ndarray) -> np.ndarray:
     return out
 
 
-def pd_error_bound(R, z, x, P):
+def pd_error_bound(R, z, x, P, terms=1):
     """Per-frame bound on |pd_FP32 - pd_FP64| of the path x [B, n] (PAM
     indices) for a search that holds R and z rounded to FP32 (relative 2^-24
     per entry), scales R by the PAM spacing in FP32 (one more rounding), sums
-    the centre b_k = z_k - sum_{j>k} R_kj a_j with FP32 FMAs in any order
-    (gamma_m, m terms), forms e_k = b_k - R_kk a_k and pd += e_k^2 with one
-    rounding each.  First order in u = 2^-24; second-order terms are covered
-    by the factor 1.5."""
+    the centre b_k = z_k - sum_{j>k} R_kj a_j with FP32 additions in any
+    order (gamma, terms * m roundings for m terms: terms = 3 when every
+    R_kj a_j enters as three exact partial products, as on the matrix cores
+    with c R split into three bf16 parts), forms e_k = b_k - R_kk a_k and
+    pd += e_k^2 with one rounding each.  First order in u = 2^-24;
+    second-order terms are covered by the factor 1.5."""
     R = np.asarray(R, np.float64)
     z = np.asarray(z, np.float64)
     B, n = z.shape
@@ -60,7 +62,7 @@ def pd_error_bound(R, z, x, P):
     S = np.abs(z) + T.sum(axis=2)                             # per level
     m = np.arange(n)[None, :]                                  # terms above level k ...
     m = (n - 1 - m).astype(np.float64)                         # ... n - 1 - k of them
-    db = (m + 4.0) * U32 * S
+    db = (terms * m + 4.0) * U32 * S
     diag = np.abs(np.einsum("bkk->bk", R) * amp)
     e = z - (np.triu(R) * amp[:, None, :]).sum(axis=2)
     de = db + 2.0 * U32 * diag + U32 * np.abs(e)
@@ -68,7 +70,7 @@ def pd_error_bound(R, z, x, P):
     return 1.5 * ((2.0 * np.abs(e) * de + de * de).sum(axis=1) + n * U32 * pd)
 
 
-def check_kbest(orc, label, P, x_gpu, pd_gpu, out, R, z, forced):
+def check_kbest(orc, label, P, x_gpu, pd_gpu, out, R, z, forced, terms=1):
     """Parity of a K-best detection with the oracle's `out` on the same
     frames.  x_gpu [B, n] PAM indices and pd_gpu [B] from the GPU; R, z the
     oracle's QR; forced(mask, x) runs the oracle on frames[mask] with x
@@ -78,7 +80,7 @@ def check_kbest(orc, label, P, x_gpu, pd_gpu, out, R, z, forced):
     same = np.all(x_gpu == out["x"], axis=1)
     eps = 0.0
     if same.any():
-        bnd = pd_error_bound(R[same], z[same], out["x"][same], P)
+        bnd = pd_error_bound(R[same], z[same], out["x"][same], P, terms)
         err = np.abs(pd_gpu[same] - out["pd"][same])
         bad = np.nonzero(err > bnd)[0]
         assert bad.size == 0, (f"{label}: FP32 search pd outside the derived bound on {bad.size} frames, "
@@ -98,7 +100,7 @@ def check_kbest(orc, label, P, x_gpu, pd_gpu, out, R, z, forced):
     return eps, tol, nm
 
 
-def check_kbest_run(orc, label, P, K, sym_gpu, pd_gpu, out, R, z, k_sched=None, r2=math.inf, J=1):
+def check_kbest_run(orc, label, P, K, sym_gpu, pd_gpu, out, R, z, k_sched=None, r2=math.inf, J=1, terms=1):
     """check_kbest for a batched oracle run with one radius for all frames
     (k_sched None, [n] or [B, n])."""
     def forced(mask, xf):
@@ -107,7 +109,7 @@ def check_kbest_run(orc, label, P, K, sym_gpu, pd_gpu, out, R, z, k_sched=None, 
             ks = ks[mask]
         return orc.kbest(R[mask], z[mask], P, K, k_sched=ks, r2=r2, J=J, force_path=xf)["fgap"]
 
-    return check_kbest(orc, label, P, orc.sym_to_x(np.asarray(sym_gpu), P), pd_gpu, out, R, z, forced)
+    return check_kbest(orc, label, P, orc.sym_to_x(np.asarray(sym_gpu), P), pd_gpu, out, R, z, forced, terms)
 
 
 def check_ml(orc, label, P, sym_gpu, out_sd, H, y, qam, metric_gpu=None):

@@ -132,6 +132,20 @@ def test_paper_radius_and_uneven_host_checks(lib):
     assert lib.kbest_detect_uneven(P, 0, P, P, P, P, P, P, 0, P) == 0
 
 
+def test_grouped_kbest_host_checks(lib):
+    P = None
+    g = lib.kbest_detect_grouped
+    assert g(P, P, 1, 8, 4, 16, 3, P, 0, P, P, P, P, P, P) == -1        # J not 1 or 2
+    assert "J" in _err(lib)
+    assert g(P, P, 1, 8, 4, 65, 1, P, 0, P, P, P, P, P, P) == -2        # K > 64
+    assert g(P, P, 1, 8, 8, 32, 2, P, 0, P, P, P, P, P, P) == -2        # 32 * 64 candidates
+    assert g(P, P, 1, 129, 4, 16, 1, P, 0, P, P, P, P, P, P) == -2      # n_tx > 128
+    assert g(P, P, 1, 8, 3, 16, 1, P, 0, P, P, P, P, P, P) == -1        # pam
+    assert g(P, P, 1, 8, 4, 16, 2, ctypes.c_void_p(1), 5, P, P, P, P, P, P) == -1  # schedule stride
+    assert g(P, P, 0, 8, 4, 16, 2, P, 0, P, P, P, P, P, P) == 0          # empty batch
+    assert g(P, P, 2, 8, 8, 16, 2, P, 0, P, P, P, P, P, P) == -1        # null pointers
+
+
 def test_binding_refuses_cpu_tensors(lib):
     import torch
 
