@@ -25,15 +25,21 @@
 //
 // where origin(s) is the survivor, at the start of the group, that s descends
 // from (Eq. (inc): the part above the group is computed once per group, the
-// rest level by level).  Children, radius test and K_t selection are those of
-// the other K-best kernels, so the tree, the keys (pd, parent rank, child)
-// and the result are theirs; only the order of the FP32 sums in a centre
-// differs.
+// rest level by level).  Children and radius test are those of the other
+// K-best kernels.
+//
+// Lane (s, q) evaluates children q, q + L, ... of its own survivor s (no
+// exchange; the candidate index s P^J + c is carried in the key), and the
+// K_t smallest keys (pd, parent rank, child) are selected as in the other
+// K-best kernels: a bound from the survivors' smallest children, compaction
+// of the candidates below it, and an in-wave sort.  The survivors stay in key
+// order, so the tree, the ties and the result are those of kbest_detect /
+// kbest_detect_complex; only the order of the FP32 sums in a centre differs.
 //
 // Paths are never copied level by level.  A survivor carries its origin and
 // the 16 amplitude bytes of the current group (4 registers, a + 8 per level,
-// 8 = not yet fixed); when the group ends every survivor's bytes and origin
-// are written once to a per-group segment table in LDS.  The path of a
+// 8 = not yet fixed); when the group ends every survivor's amplitudes (as 16
+// nibbles) and origin are written once to a per-group segment table in LDS.  The path of a
 // survivor is the chain segment(h, s) -> segment(h + 1, parent) -> ..., which
 // is what the matrix product's B operand reads.
 #include "common.hpp"
@@ -59,14 +65,15 @@ struct GroupedShape {
     static constexpr int CST = KCAP >= 16 ? KCAP : 16;             // row stride of C in LDS
 };
 
-// LDS of one frame: compaction keys, segment words [G][KCAP][4], C [16][CST],
-// in-group rows [16][16], diagonal [16], z [16], survivor pd [2][KCAP],
+// LDS of one frame: compaction keys, segment words [G][KCAP][2], C [16][CST],
+// in-group rows [16][16], diagonal [16], z [16], selected pds [KCAP],
 // selected candidates [KCAP], segment parents [G][KCAP] (bytes)
 __host__ __device__ inline size_t gk_lds_bytes(int kcap, int G)
 {
     const int cst = kcap >= 16 ? kcap : 16;
-    return sizeof(uint64_t) * 2 * WAVE + sizeof(uint32_t) * 4 * (size_t)G * kcap + sizeof(float) * 16 * cst +
-           sizeof(float) * (256 + 32) + sizeof(float) * 2 * kcap + sizeof(int32_t) * kcap + (size_t)G * kcap;
+    const size_t segw = ((size_t)2 * G * kcap + 3) & ~(size_t)3;  // whole 16-byte units
+    return sizeof(uint64_t) * 2 * WAVE + sizeof(uint32_t) * segw + sizeof(float) * 16 * cst +
+           sizeof(float) * (256 + 32) + sizeof(float) * kcap + sizeof(int32_t) * kcap + (size_t)G * kcap;
 }
 
 // exact three-way bf16 split of an FP32 value by truncation: hi keeps the
@@ -84,16 +91,140 @@ __device__ __forceinline__ void gk_split3(float v, __bf16& hi, __bf16& mid, __bf
     lo = (__bf16)r2;
 }
 
-// eight amplitude bytes (a + 8) -> bf16 amplitudes a
-__device__ __forceinline__ gk_bf16x8 gk_decode8(uint32_t w0, uint32_t w1)
+// eight amplitude nibbles (a + 8, level e at bits 4e) -> bf16 amplitudes a
+__device__ __forceinline__ gk_bf16x8 gk_decode8(uint32_t w)
 {
     gk_bf16x8 b;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        b[e] = (__bf16)((float)((w0 >> (8 * e)) & 0xffu) - 8.f);
-        b[e + 4] = (__bf16)((float)((w1 >> (8 * e)) & 0xffu) - 8.f);
-    }
+    for (int e = 0; e < 8; ++e) b[e] = (__bf16)((float)((w >> (4 * e)) & 0xfu) - 8.f);
     return b;
+}
+
+// four amplitude bytes (values below 16) -> four nibbles in the low 16 bits
+__device__ __forceinline__ uint32_t gk_nibbles4(uint32_t b)
+{
+    return (b & 0xfu) | ((b >> 4) & 0xf0u) | ((b >> 8) & 0xf00u) | ((b >> 12) & 0xf000u);
+}
+
+// sorts one register of keys ascending over lanes 0 .. LIM-1, LIM the
+// smallest of 16, 32, 64 that holds `count` keys (the rest of the lanes hold
+// ~0 and sort among themselves)
+__device__ __forceinline__ void gk_sort_upto(uint64_t& k, int count, int lane)
+{
+    if (count <= 16) bitonic_sort_lim<16>(k, lane);
+    else if (count <= 32) bitonic_sort_lim<32>(k, lane);
+    else bitonic_sort_lim<WAVE>(k, lane);
+}
+
+// the 64 smallest of 64 * E keys (distinct), ascending in key[0]: every
+// block sorted (even ones ascending, odd ones descending), then pairs merged
+// with truncation (the lane-wise minimum of an ascending and a descending
+// block is a bitonic sequence of the 64 smallest of the pair, put in order by
+// six half-cleaner stages)
+template <int E>
+__device__ __forceinline__ void gk_merge_select(uint64_t (&key)[E], int lane)
+{
+#pragma unroll
+    for (int size = 2; size <= WAVE; size <<= 1) {
+#pragma unroll
+        for (int j = size >> 1; j > 0; j >>= 1) {
+            const bool asc_min = ((lane & size) == 0) == ((lane & j) == 0);
+#pragma unroll
+            for (int e = 0; e < E; ++e) key[e] = kb_cx(key[e], j, asc_min != (bool)(e & 1), lane);
+        }
+    }
+#pragma unroll
+    for (int w = 1; w < E; w <<= 1) {
+#pragma unroll
+        for (int e = 0; e < E; e += 2 * w) {
+            const uint64_t b = key[e + w];
+            uint64_t c = b < key[e] ? b : key[e];
+            const bool desc = ((e / (2 * w)) & 1) != 0;
+#pragma unroll
+            for (int j = WAVE / 2; j > 0; j >>= 1) c = kb_cx(c, j, ((lane & j) == 0) != desc, lane);
+            key[e] = c;
+        }
+    }
+}
+
+// Selection of the keep = min(K_t, nvalid) smallest keys (pd bits, s PC + c)
+// -- i.e. (pd, parent rank, child), the survivors being kept in order --
+// written in order to sn (pd) and sel (candidate index).  Lane (s, q) holds
+// children c = e L + q of survivor s in block e.  With four blocks or more
+// and at least keep survivors expanded, the largest of their smallest
+// children, T, bounds the keep-th smallest key: the keys with pd bits <= T
+// (usually little more than keep) are compacted through LDS and sorted --
+// one register when at most 64, else the first 64 ascending and the rest
+// ascending then reversed, merged with truncation.  Otherwise all blocks
+// are sorted and merged.
+template <int E>
+__device__ __forceinline__ int gk_select(const uint32_t (&kh)[E], int nvalid, int Kt, int cnt, uint32_t idx0, int L,
+                                         int lane, float* sn, int32_t* sel, uint64_t* skey)
+{
+    const int keep = Kt < nvalid ? Kt : nvalid;  // <= 64
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint64_t res;  // the keep smallest keys, ascending in lanes 0 .. keep-1
+    bool done = false;
+    if (E >= 4 && cnt >= keep) {  // (one or two blocks are sorted directly)
+        uint32_t mn = kh[0];
+#pragma unroll
+        for (int e = 1; e < E; ++e) mn = min(mn, kh[e]);
+        for (int j = 1; j < L; j <<= 1) mn = min(mn, xor_lanes(mn, j, lane));
+        uint32_t t = lane / L < cnt ? mn : 0u;
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) t = max(t, xor_lanes(t, m, lane));
+        // t = ~0u when an expanded survivor has no child inside the radius: no bound
+        if (t != ~0u) {
+            int base = 0;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const bool take = kh[e] <= t;
+                const uint64_t bal = __ballot(take);
+                if (take) {
+                    const int slot = base + (int)__popcll(bal & below);
+                    if (slot < 2 * WAVE) skey[slot] = ((uint64_t)kh[e] << 32) | (idx0 + (uint32_t)(e * L));
+                }
+                base += (int)__popcll(bal);
+            }
+            if (base <= 2 * WAVE) {
+                kb_wave_sync();
+                uint64_t k0 = lane < base ? skey[lane] : ~0ull;
+                if (base <= WAVE) {
+                    gk_sort_upto(k0, base, lane);
+                } else {
+                    uint64_t k1 = WAVE + lane < base ? skey[WAVE + lane] : ~0ull;
+                    bitonic_sort_lim<WAVE>(k0, lane);
+                    gk_sort_upto(k1, base - WAVE, lane);
+                    const int rl = (WAVE - 1 - lane) << 2;  // reversed: descending, padding first
+                    const uint32_t rlo = (uint32_t)__builtin_amdgcn_ds_bpermute(rl, (int)(uint32_t)k1);
+                    const uint32_t rhi = (uint32_t)__builtin_amdgcn_ds_bpermute(rl, (int)(uint32_t)(k1 >> 32));
+                    const uint64_t k1r = ((uint64_t)rhi << 32) | rlo;
+                    k0 = k1r < k0 ? k1r : k0;
+#pragma unroll
+                    for (int j = WAVE / 2; j > 0; j >>= 1) k0 = kb_cx(k0, j, (lane & j) == 0, lane);
+                }
+                res = k0;
+                done = true;
+            }
+        }
+    }
+    if (!done) {
+        uint64_t key[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            key[e] = kh[e] == ~0u ? ~0ull : (((uint64_t)kh[e] << 32) | (idx0 + (uint32_t)(e * L)));
+        if constexpr (E == 1) {
+            gk_sort_upto(key[0], cnt * L, lane);  // candidates sit in lanes below cnt L
+        } else {
+            gk_merge_select<E>(key, lane);
+        }
+        res = key[0];
+    }
+    if (lane < keep) {
+        sn[lane] = __uint_as_float((uint32_t)(res >> 32));
+        sel[lane] = (int32_t)(uint32_t)res;
+    }
+    return keep;
 }
 
 template <int P, int J, int E>
@@ -103,18 +234,19 @@ __device__ __forceinline__ void kbest_frame_grouped(const KbestArgs& a, int fram
     constexpr int PC = S::PC, KCAP = S::KCAP, L = S::L, NT = S::NT, CST = S::CST;
     static_assert(KCAP >= 1 && KCAP <= 64, "one survivor per lane at most, one at least");
     static_assert(J == 1 || J == 2, "one or two real levels per step");
+    static_assert(E * L == PC, "a survivor's lanes hold its children over the E blocks");
     const int lane = threadIdx.x & 63;
     const int s_own = lane / L, q = lane % L;
     const int n = a.n;
     const int G = (n + GK_LEVELS - 1) / GK_LEVELS;
     uint64_t* skey = reinterpret_cast<uint64_t*>(lds);
-    uint32_t* segb = reinterpret_cast<uint32_t*>(skey + 2 * WAVE);
-    float* cg = reinterpret_cast<float*>(segb + 4 * G * KCAP);
+    uint32_t* segb = reinterpret_cast<uint32_t*>(skey + 2 * WAVE);  // [G][KCAP][2]: 16 nibbles
+    float* cg = reinterpret_cast<float*>(segb + ((2 * G * KCAP + 3) & ~3));  // 16-byte aligned
     float* rg = cg + 16 * CST;
     float* rd = rg + 256;
     float* zg = rd + 16;
-    float* spd = zg + 16;
-    int32_t* sel = reinterpret_cast<int32_t*>(spd + 2 * KCAP);
+    float* sn = zg + 16;
+    int32_t* sel = reinterpret_cast<int32_t*>(sn + KCAP);
     uint8_t* segp = reinterpret_cast<uint8_t*>(sel + KCAP);
 
     const float* Rf = a.R + (size_t)frame * r_packed_size(n);
@@ -128,8 +260,9 @@ __device__ __forceinline__ void kbest_frame_grouped(const KbestArgs& a, int fram
 
     uint32_t igw[4] = {GK_UNFIXED, GK_UNFIXED, GK_UNFIXED, GK_UNFIXED};
     int orig = s_own;
-    if (lane == 0) spd[0] = 0.f;
-    int cnt = 1, step = 0;
+    float pd_own = 0.f;                          // pd of this lane's survivor
+    const uint32_t idx0 = (uint32_t)(s_own * PC + q);  // candidate index of block 0: child q
+    int cnt = 1;
     int64_t expanded = 0;
     uint32_t flags = 0;
     bool stopped = false;
@@ -162,7 +295,7 @@ __device__ __forceinline__ void kbest_frame_grouped(const KbestArgs& a, int fram
             const int roff = (int)r_row_off(n, row) - row;     // (c R)[row][j] at roff + j
             const int nch = (n - GK_LEVELS * (h + 1) + 31) / 32;
             const int upper = lane >> 5;                       // B rows from group h+1+2ch (+1 for upper lanes)
-            const int bsub = 2 * ((lane >> 4) & 1);            // word offset in the segment: levels 0-7 or 8-15
+            const int bsub = (lane >> 4) & 1;                  // word of the segment: levels 0-7 or 8-15
             int anc[NT];
             bool live[NT];
 #pragma unroll
@@ -198,8 +331,7 @@ __device__ __forceinline__ void kbest_frame_grouped(const KbestArgs& a, int fram
                 for (int t = 0; t < NT; ++t) {
                     gk_bf16x8 b;
                     if (g < G && live[t]) {
-                        const gk_u32x2 wb = *reinterpret_cast<const gk_u32x2*>(segb + 4 * (g * KCAP + anc[t]) + bsub);
-                        b = gk_decode8(wb[0], wb[1]);
+                        b = gk_decode8(segb[2 * (g * KCAP + anc[t]) + bsub]);
                     } else {
 #pragma unroll
                         for (int e = 0; e < 8; ++e) b[e] = (__bf16)0.f;
@@ -232,9 +364,6 @@ __device__ __forceinline__ void kbest_frame_grouped(const KbestArgs& a, int fram
 
         for (int k_hi = ktop; k_hi >= k0; k_hi -= J) {
             const int r_hi = k_hi - k0, r_lo = r_hi - (J - 1);
-            const int cur = step & 1, nxt = cur ^ 1;
-            float* sc = spd + cur * KCAP;
-            float* sn = spd + nxt * KCAP;
             // centres of this lane's survivor: the levels above the group
             // (C at the survivor's origin), then the fixed levels of the group
             float dh = 0.f, dl = 0.f;
@@ -258,53 +387,37 @@ __device__ __forceinline__ void kbest_frame_grouped(const KbestArgs& a, int fram
                 }
             }
             const bool above = h < G - 1;
-            const float bh_own = zg[r_hi] - ((above ? cg[r_hi * CST + orig] : 0.f) + dh);
-            const float bl_own = J == 2 ? zg[r_lo] - ((above ? cg[r_lo * CST + orig] : 0.f) + dl) : 0.f;
+            const float bh = zg[r_hi] - ((above ? cg[r_hi * CST + orig] : 0.f) + dh);
+            const float bl = J == 2 ? zg[r_lo] - ((above ? cg[r_lo * CST + orig] : 0.f) + dl) : 0.f;
             const float rkh = rd[r_hi], rkl = rd[r_lo];
+            const bool live = s_own < cnt;
             // a NaN or infinity in R or z reaches every centre of the level
-            if (__ballot(!kb_finite(rkh) || !kb_finite(rkl) ||
-                         (s_own < cnt && !(kb_finite(bh_own) && kb_finite(bl_own))))) {
+            if (__ballot(!kb_finite(rkh) || !kb_finite(rkl) || (live && !(kb_finite(bh) && kb_finite(bl))))) {
                 flags |= MIMO_FLAG_NONFINITE_INPUT;
                 cnt = 0;
                 stopped = true;
                 break;
             }
+            // children: block e, lane (s, q) holds child c = e L + q of survivor s
             uint32_t kh[E];
-            const int ncand = cnt * PC;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                kh[e] = ~0u;
-                if (e * WAVE >= ncand) continue;  // block without candidates (uniform)
-                const int mm = e * WAVE + lane;
-                const int s = PC >= WAVE ? e * WAVE / PC : mm / PC;  // uniform when a block is one survivor
-                const int c = mm % PC;
-                float bh, bl = 0.f;
-                if constexpr (PC >= WAVE) {  // one survivor per block
-                    bh = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, bh_own), s * L));
-                    if constexpr (J == 2)
-                        bl = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, bl_own), s * L));
+                const int c = e * L + q;
+                float pdc;
+                if constexpr (J == 1) {
+                    const float ee = fmaf(-rkh, (float)(2 * c - (P - 1)), bh);
+                    pdc = fmaf(ee, ee, pd_own);
                 } else {
-                    bh = shfl_f(bh_own, s * L);
-                    if constexpr (J == 2) bl = shfl_f(bl_own, s * L);
+                    const float eh = fmaf(-rkh, (float)(2 * (c / P) - (P - 1)), bh);
+                    const float el = fmaf(-rkl, (float)(2 * (c % P) - (P - 1)), bl);
+                    pdc = fmaf(el, el, fmaf(eh, eh, pd_own));
                 }
-                if (s < cnt) {
-                    float pdc;
-                    if constexpr (J == 1) {
-                        const float ee = fmaf(-rkh, (float)(2 * c - (P - 1)), bh);
-                        pdc = fmaf(ee, ee, sc[s]);
-                    } else {
-                        const float eh = fmaf(-rkh, (float)(2 * (c / P) - (P - 1)), bh);
-                        const float el = fmaf(-rkl, (float)(2 * (c % P) - (P - 1)), bl);
-                        pdc = fmaf(el, el, fmaf(eh, eh, sc[s]));
-                    }
-                    if (pdc < r2) kh[e] = __float_as_uint(pdc);
-                }
+                kh[e] = (live && pdc < r2) ? __float_as_uint(pdc) : ~0u;
             }
             expanded += cnt;
             int nvalid = 0;
 #pragma unroll
-            for (int e = 0; e < E; ++e)
-                if (e * WAVE < ncand) nvalid += __popcll(__ballot(kh[e] != ~0u));
+            for (int e = 0; e < E; ++e) nvalid += __popcll(__ballot(kh[e] != ~0u));
             if (nvalid == 0) {
                 flags |= MIMO_FLAG_EMPTY_SPHERE;
                 cnt = 0;
@@ -314,25 +427,16 @@ __device__ __forceinline__ void kbest_frame_grouped(const KbestArgs& a, int fram
             int Kt = ks ? ks[k0 + r_lo] : a.K;
             Kt = Kt > a.K ? a.K : (Kt < 1 ? 1 : Kt);
             Kt = Kt > KCAP ? KCAP : Kt;
-            int fpos = -1;
-            int keep;
-            if constexpr (E <= 2) {
-                if (ncand <= 32)
-                    keep = kb_select_sort<E, 1, 32>(kh, nvalid, Kt, -1, lane, sn, sel, &fpos);
-                else if (ncand <= WAVE)
-                    keep = kb_select_sort<E, 1>(kh, nvalid, Kt, -1, lane, sn, sel, &fpos);
-                else
-                    keep = kb_select_sort<E, E>(kh, nvalid, Kt, -1, lane, sn, sel, &fpos);
-            } else {
-                keep = kb_select_merge<E, PC>(kh, ncand, nvalid, Kt, -1, lane, sn, sel, skey, &fpos);
-            }
+            const int keep = gk_select<E>(kh, nvalid, Kt, cnt, idx0, L, lane, sn, sel, skey);
             kb_wave_sync();
             // new survivor s_own: its parent's origin and group bytes, plus the new level(s)
             int src = lane, cnew = 0;
+            float pdn = pd_own;
             if (s_own < keep) {
                 const int mm = sel[s_own];
                 src = (mm / PC) * L + q;
                 cnew = mm % PC;
+                pdn = sn[s_own];
             }
             orig = __shfl(orig, src, WAVE);
 #pragma unroll
@@ -353,13 +457,15 @@ __device__ __forceinline__ void kbest_frame_grouped(const KbestArgs& a, int fram
                 for (int dd = 0; dd < 4; ++dd)
                     if (dd == d) igw[dd] = (igw[dd] & ~mask) | put;
             }
+            pd_own = pdn;
             cnt = keep;
-            ++step;
+            kb_wave_sync();  // sel and sn are read before the next level writes them
         }
         if (stopped) break;
         // the group's segment of every survivor: its bytes and its origin
         if (q == 0 && s_own < cnt) {
-            *reinterpret_cast<gk_u32x4*>(segb + 4 * (h * KCAP + s_own)) = gk_u32x4{igw[0], igw[1], igw[2], igw[3]};
+            *reinterpret_cast<gk_u32x2*>(segb + 2 * (h * KCAP + s_own)) =
+                gk_u32x2{gk_nibbles4(igw[0]) | (gk_nibbles4(igw[1]) << 16), gk_nibbles4(igw[2]) | (gk_nibbles4(igw[3]) << 16)};
             segp[h * KCAP + s_own] = (uint8_t)orig;
         }
         kb_wave_sync();
@@ -373,32 +479,28 @@ __device__ __forceinline__ void kbest_frame_grouped(const KbestArgs& a, int fram
         if (a.fb_sigma2) flags |= MIMO_FLAG_LEARNED_FALLBACK;
         if (a.rerun) flags |= MIMO_FLAG_EMPTY_SPHERE;
         if (a.flags) a.flags[frame] = flags;
-        if (a.pd) a.pd[frame] = cnt > 0 ? spd[(step & 1) * KCAP] : INFINITY;
+        if (a.pd) a.pd[frame] = cnt > 0 ? pd_own : INFINITY;  // survivor 0: the best leaf
         if (a.counters) kb_write_counters(a, frame, expanded, PC * J);
     }
     if (!a.sym) return;
-    // survivor 0 is the best leaf: lane h rebuilds its segment of group h by
-    // following the parents from group 0 up
+    // lane h rebuilds survivor 0's segment of group h by following the
+    // parents from group 0 up
     const int nw = n / 2;
     if (lane < G) {
-        uint32_t w[4] = {GK_UNFIXED, GK_UNFIXED, GK_UNFIXED, GK_UNFIXED};
+        gk_u32x2 w = {0x88888888u, 0x88888888u};
         if (cnt > 0) {
             int anc = 0;
             for (int g = 0; g < lane; ++g) anc = segp[g * KCAP + anc];
-            const gk_u32x4 v = *reinterpret_cast<const gk_u32x4*>(segb + 4 * (lane * KCAP + anc));
-            w[0] = v[0];
-            w[1] = v[1];
-            w[2] = v[2];
-            w[3] = v[3];
+            w = *reinterpret_cast<const gk_u32x2*>(segb + 2 * (lane * KCAP + anc));
         }
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            const int sw = 8 * lane + i;  // complex symbol: real part at byte 2i, imaginary part at 2i + 1
+            const int sw = 8 * lane + i;  // complex symbol: real part at level 2i of the group, imaginary part at 2i + 1
             if (sw < nw) {
                 int v = 0;
                 if (cnt > 0) {
-                    const int are = (int)((w[i >> 1] >> (16 * (i & 1))) & 0xffu) - 8;
-                    const int aim = (int)((w[i >> 1] >> (16 * (i & 1) + 8)) & 0xffu) - 8;
+                    const int are = (int)((w[i >> 2] >> (8 * (i & 3))) & 0xfu) - 8;
+                    const int aim = (int)((w[i >> 2] >> (8 * (i & 3) + 4)) & 0xfu) - 8;
                     v = ((are + (P - 1)) / 2) * P + (aim + (P - 1)) / 2;
                 }
                 a.sym[(size_t)frame * nw + sw] = v;
