@@ -132,7 +132,11 @@ int32_t mimo_qr_preprocess_mmse(const float* H, const float* y, const float* sig
  * again with r2 = +infinity in a second launch on the same stream: it then
  * carries MIMO_FLAG_EMPTY_SPHERE | MIMO_FLAG_FOUND and its counters add up
  * both searches.  A frame with a NaN or infinity in R or z stops at that
- * level with MIMO_FLAG_NONFINITE_INPUT (sym 0, pd +infinity).
+ * level with MIMO_FLAG_NONFINITE_INPUT (sym 0, pd +infinity).  For K <= 64
+ * the launch is the grouped kernel of kbest_detect_grouped (J = 1), except
+ * at most 8 survivors of 64-QAM at 64 < n <= 208 (two frames per wavefront)
+ * and K * pam > 64 at n <= 8; the detection is the same, only the order of
+ * the FP32 sums in a centre differs.
  * ------------------------------------------------------------------- */
 int32_t kbest_detect(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam,
                      int32_t K, const int32_t* k_sched, int32_t k_sched_stride,
@@ -149,7 +153,9 @@ int32_t kbest_detect(const float* R, const float* z, int32_t B, int32_t n_tx, in
  * (pd, parent rank, i_im pam + i_re) survive.  K_t = k_sched[... + 2m]
  * (the level of the real part), clamped to [1, K].  Arguments, outputs and
  * flags as kbest_detect; counters[b][0] = survivors expanded,
- * counters[b][1] = real-level evaluations (2 per child).
+ * counters[b][1] = real-level evaluations (2 per child).  From 512
+ * candidates per level (K pam^2) or 128 real levels on, the launch is the
+ * grouped kernel of kbest_detect_grouped (J = 2).
  * Limits: 1 <= K <= 64, K * pam^2 <= 1024.
  * ------------------------------------------------------------------- */
 int32_t kbest_detect_complex(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam,
@@ -373,7 +379,8 @@ int32_t mimo_qr_preprocess_uneven(const mimo_frame_desc* desc, int32_t B, int32_
 
 /* Batched K-best (Sec. VI) of an uneven batch in one persistent launch: one
  * wavefront per workgroup pulls frames from `counter` (reset by the call)
- * and runs K-best with the frame's own pam and K.  Per-frame limits: pam in
+ * and runs K-best with the frame's own pam and K -- per frame the detection
+ * kbest_detect_grouped (J = 1) returns.  Per-frame limits: pam in
  * {2, 4, 8}, 1 <= K <= 64, K * pam <= 256, 1 <= n_tx <= 64; a frame outside
  * them is skipped with flags[f] = MIMO_FLAG_INVALID_FRAME (its sym and pd
  * untouched).  sym_flat at the frames' s_off; pd [B], flags [B] indexed by

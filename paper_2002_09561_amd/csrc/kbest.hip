@@ -1053,8 +1053,23 @@ static int32_t dispatch_kbest_p(const KbestArgs& a, int B, hipStream_t st)
     return launch_kbest_any<P, 16>(a, B, st);
 }
 
+// Real-level K-best: the grouped kernel (interference above each group of 16
+// levels from one matrix product, paths as group segments) is faster on
+// gfx950 for K <= 64 at every measured shape but two, which keep the
+// row-recompute kernels: at most 8 survivors of 64-QAM at 64 < n <= 208
+// (two frames per wavefront), and K pam > 64 at n <= 8.  Label mode (forced
+// path and rank output) is served by the row-recompute kernels only.
+static bool grouped_real_preferred(const KbestArgs& a, int pam)
+{
+    if (a.force_sym || a.K > 64) return false;
+    if (pam == 8 && a.K <= 8 && a.n > 64 && a.n <= 208 && !a.fb_sigma2 && !a.rerun) return false;
+    if (a.n <= 8 && a.K * pam > 64) return false;
+    return true;
+}
+
 static int32_t dispatch_kbest(const KbestArgs& a, int pam, int B, hipStream_t st)
 {
+    if (grouped_real_preferred(a, pam)) return dispatch_grouped(a, pam, 1, B, st);
     switch (pam) {
     case 2: return dispatch_kbest_p<2>(a, B, st);
     case 4: return dispatch_kbest_p<4>(a, B, st);
@@ -1109,6 +1124,19 @@ static int32_t validate_common(const char* who, int B, int n_tx, int pam, int K)
 // frames whose finite radius left no leaf are detected again with r2 = +inf
 static int32_t rerun_empty(const KbestArgs& a, int pam, int B, hipStream_t st, bool complex_levels);
 
+// Complex-level K-best: the grouped kernel with J = 2 from 512 candidates
+// per level (K pam^2) or 128 real levels on, where it measured faster; the
+// row-recompute kernel below that.
+static int32_t dispatch_kbest_complex(const KbestArgs& a, int pam, int B, hipStream_t st)
+{
+    if (a.K * pam * pam >= 512 || a.n >= 128) return dispatch_grouped(a, pam, 2, B, st);
+    switch (pam) {
+    case 2: return dispatch_kbest_cplx_p<2>(a, B, st);
+    case 4: return dispatch_kbest_cplx_p<4>(a, B, st);
+    default: return dispatch_kbest_cplx_p<8>(a, B, st);
+    }
+}
+
 }  // namespace mimo
 
 extern "C" int32_t kbest_detect(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam,
@@ -1147,11 +1175,7 @@ extern "C" int32_t kbest_detect_complex(const float* R, const float* z, int32_t 
     if (!R || !z || !sym || !pd || !flags) return fail(MIMO_ERR_INVALID_ARG, "kbest_detect_complex: null pointer");
     KbestArgs a{R, z, n, K, k_sched, k_sched_stride, radius2, nullptr, nullptr, sym, pd, flags, counters, nullptr, 0.f};
     hipStream_t st = (hipStream_t)stream;
-    switch (pam) {
-    case 2: rc = dispatch_kbest_cplx_p<2>(a, B, st); break;
-    case 4: rc = dispatch_kbest_cplx_p<4>(a, B, st); break;
-    default: rc = dispatch_kbest_cplx_p<8>(a, B, st); break;
-    }
+    rc = dispatch_kbest_complex(a, pam, B, st);
     if (rc || !radius2) return rc;
     return rerun_empty(a, pam, B, st, true);
 }
@@ -1163,11 +1187,7 @@ static int32_t rerun_empty(const KbestArgs& a, int pam, int B, hipStream_t st, b
     r.radius2 = nullptr;
     r.rerun = 1;
     if (!complex_levels) return dispatch_kbest(r, pam, B, st);
-    switch (pam) {
-    case 2: return dispatch_kbest_cplx_p<2>(r, B, st);
-    case 4: return dispatch_kbest_cplx_p<4>(r, B, st);
-    default: return dispatch_kbest_cplx_p<8>(r, B, st);
-    }
+    return dispatch_kbest_complex(r, pam, B, st);
 }
 }  // namespace mimo
 
@@ -1208,88 +1228,4 @@ extern "C" int32_t kbest_fallback(const float* R, const float* z, int32_t B, int
     if (!R || !z || !sigma2 || !sym || !pd || !flags) return fail(MIMO_ERR_INVALID_ARG, "kbest_fallback: null pointer");
     KbestArgs a{R, z, 2 * n_tx, K, nullptr, 0, nullptr, nullptr, nullptr, sym, pd, flags, counters, sigma2, beta};
     return dispatch_kbest(a, pam, B, (hipStream_t)stream);
-}
-
-namespace mimo {
-
-__global__ void reset_counter_kernel_kb(int* counter) { *counter = 0; }
-
-// Uneven batch: one wavefront per workgroup pulls frames from a device work
-// counter and runs K-best with each frame's own constellation and K.
-constexpr int UNEVEN_NWMAX = 64;     // n <= 128 real levels (n_tx <= 64)
-constexpr int UNEVEN_KMAX = 64;      // survivors held in registers
-constexpr int UNEVEN_CAND_MAX = 256; // K * pam: four blocks of 64 candidates
-
-template <int P, int E>
-__device__ __forceinline__ void kbest_uneven_one(const KbestArgs& a, unsigned char* lds)
-{
-    kbest_frame_reg<P, E, UNEVEN_NWMAX>(a, 0, lds);
-}
-
-__global__ void __launch_bounds__(64) kbest_uneven_kernel(const mimo_frame_desc* __restrict__ desc, int B,
-                                                          const float* __restrict__ R, const float* __restrict__ z,
-                                                          int32_t* __restrict__ sym, float* __restrict__ pd,
-                                                          uint32_t* __restrict__ flags, int* __restrict__ counter)
-{
-    extern __shared__ unsigned char smem_kbu[];
-    const int lane = threadIdx.x & 63;
-    for (;;) {
-        int f = 0;
-        if (lane == 0) f = atomicAdd(counter, 1);
-        f = __builtin_amdgcn_readfirstlane(__shfl(f, 0, WAVE));
-        if (f >= B) break;
-        const mimo_frame_desc d = desc[f];
-        const int P = __builtin_amdgcn_readfirstlane(d.pam);
-        const int K = __builtin_amdgcn_readfirstlane(d.K);
-        const int ntx = __builtin_amdgcn_readfirstlane(d.n_tx);
-        // descriptors outside the instantiations' range are skipped, flagged
-        if ((P != 2 && P != 4 && P != 8) || K < 1 || K > UNEVEN_KMAX || K * P > UNEVEN_CAND_MAX || ntx < 1 ||
-            ntx > UNEVEN_NWMAX) {
-            if (lane == 0) flags[f] = MIMO_FLAG_INVALID_FRAME;
-            continue;
-        }
-        KbestArgs a{R + d.r_off, z + d.z_off, 2 * d.n_tx, K, nullptr, 0, nullptr, nullptr, nullptr,
-                    sym + d.s_off, pd + f, flags + f, nullptr, nullptr, 0.f};
-        const int need = K * P;
-        if (P == 2) {
-            if (need <= 64) kbest_uneven_one<2, 1>(a, smem_kbu);
-            else kbest_uneven_one<2, 2>(a, smem_kbu);
-        } else if (P == 4) {
-            if (need <= 64) kbest_uneven_one<4, 1>(a, smem_kbu);
-            else if (need <= 128) kbest_uneven_one<4, 2>(a, smem_kbu);
-            else kbest_uneven_one<4, 4>(a, smem_kbu);
-        } else {
-            if (need <= 64) kbest_uneven_one<8, 1>(a, smem_kbu);
-            else if (need <= 128) kbest_uneven_one<8, 2>(a, smem_kbu);
-            else kbest_uneven_one<8, 4>(a, smem_kbu);
-        }
-        kb_wave_sync();  // the next frame reuses the LDS
-    }
-}
-
-}  // namespace mimo
-
-extern "C" int32_t kbest_detect_uneven(const mimo_frame_desc* desc, int32_t B, const float* R_flat,
-                                       const float* z_flat, int32_t* sym_flat, float* pd, uint32_t* flags,
-                                       int32_t* counter, int32_t grid, void* stream)
-{
-    using namespace mimo;
-    if (B < 0 || grid < 0) return fail(MIMO_ERR_INVALID_ARG, "kbest_detect_uneven: B < 0 or grid < 0");
-    if (B == 0) return MIMO_OK;
-    if (!desc || !R_flat || !z_flat || !sym_flat || !pd || !flags || !counter)
-        return fail(MIMO_ERR_INVALID_ARG, "kbest_detect_uneven: null pointer");
-    hipStream_t st = (hipStream_t)stream;
-    if (grid == 0) {
-        int dev = 0, cus = 0;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        grid = 8 * (cus > 0 ? cus : 256);
-    }
-    if (grid > B) grid = B;
-    // largest LDS need over the instantiations (KCAP <= 64)
-    const size_t lds = kbest_reg_lds_bytes<UNEVEN_NWMAX>(64);
-    hipLaunchKernelGGL(reset_counter_kernel_kb, dim3(1), dim3(1), 0, st, counter);
-    hipLaunchKernelGGL(kbest_uneven_kernel, dim3(grid), dim3(WAVE), lds, st, desc, B, R_flat, z_flat, sym_flat, pd,
-                       flags, counter);
-    return check_launch("kbest_detect_uneven");
 }

@@ -452,4 +452,8 @@ __device__ __forceinline__ int kb_select_merge(const uint32_t (&kh)[E], int ncan
     return keep;
 }
 
+// the grouped K-best launch (J = 1 or 2 real levels per step) for K <= 64 and
+// K pam^J <= 1024; arguments validated by the caller
+int32_t dispatch_grouped(const KbestArgs& a, int pam, int J, int B, hipStream_t st);
+
 }  // namespace mimo

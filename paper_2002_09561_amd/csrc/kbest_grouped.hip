@@ -548,7 +548,7 @@ static int32_t dispatch_grouped_pj(const KbestArgs& a, int B, hipStream_t st)
     return fail(MIMO_ERR_UNSUPPORTED, "kbest_detect_grouped: K * pam^J beyond the instantiations");
 }
 
-static int32_t dispatch_grouped(const KbestArgs& a, int pam, int J, int B, hipStream_t st)
+int32_t dispatch_grouped(const KbestArgs& a, int pam, int J, int B, hipStream_t st)
 {
     if (J == 1) {
         switch (pam) {
@@ -595,4 +595,90 @@ extern "C" int32_t kbest_detect_grouped(const float* R, const float* z, int32_t 
     r.radius2 = nullptr;
     r.rerun = 1;
     return dispatch_grouped(r, pam, J, B, st);
+}
+
+namespace mimo {
+
+__global__ void reset_counter_kernel_kb(int* counter) { *counter = 0; }
+
+// Uneven batch: one wavefront per workgroup pulls frames from a device work
+// counter and runs the grouped K-best (real levels) with each frame's own
+// constellation and K -- per frame the detection of kbest_detect_grouped
+// with J = 1.
+constexpr int UNEVEN_NWMAX = 64;     // n <= 128 real levels (n_tx <= 64): at most 8 groups
+constexpr int UNEVEN_KMAX = 64;      // one survivor per lane at most
+constexpr int UNEVEN_CAND_MAX = 256; // K * pam: four blocks of 64 candidates
+
+template <int P, int E>
+__device__ __forceinline__ void kbest_uneven_one(const KbestArgs& a, unsigned char* lds)
+{
+    kbest_frame_grouped<P, 1, E>(a, 0, lds);
+}
+
+__global__ void __launch_bounds__(64) kbest_uneven_kernel(const mimo_frame_desc* __restrict__ desc, int B,
+                                                          const float* __restrict__ R, const float* __restrict__ z,
+                                                          int32_t* __restrict__ sym, float* __restrict__ pd,
+                                                          uint32_t* __restrict__ flags, int* __restrict__ counter)
+{
+    extern __shared__ unsigned char smem_kbu[];
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        int f = 0;
+        if (lane == 0) f = atomicAdd(counter, 1);
+        f = __builtin_amdgcn_readfirstlane(__shfl(f, 0, WAVE));
+        if (f >= B) break;
+        const mimo_frame_desc d = desc[f];
+        const int P = __builtin_amdgcn_readfirstlane(d.pam);
+        const int K = __builtin_amdgcn_readfirstlane(d.K);
+        const int ntx = __builtin_amdgcn_readfirstlane(d.n_tx);
+        // descriptors outside the instantiations' range are skipped, flagged
+        if ((P != 2 && P != 4 && P != 8) || K < 1 || K > UNEVEN_KMAX || K * P > UNEVEN_CAND_MAX || ntx < 1 ||
+            ntx > UNEVEN_NWMAX) {
+            if (lane == 0) flags[f] = MIMO_FLAG_INVALID_FRAME;
+            continue;
+        }
+        KbestArgs a{R + d.r_off, z + d.z_off, 2 * d.n_tx, K, nullptr, 0, nullptr, nullptr, nullptr,
+                    sym + d.s_off, pd + f, flags + f, nullptr, nullptr, 0.f};
+        const int need = K * P;
+        if (P == 2) {
+            if (need <= 64) kbest_uneven_one<2, 1>(a, smem_kbu);
+            else kbest_uneven_one<2, 2>(a, smem_kbu);
+        } else if (P == 4) {
+            if (need <= 64) kbest_uneven_one<4, 1>(a, smem_kbu);
+            else if (need <= 128) kbest_uneven_one<4, 2>(a, smem_kbu);
+            else kbest_uneven_one<4, 4>(a, smem_kbu);
+        } else {
+            if (need <= 64) kbest_uneven_one<8, 1>(a, smem_kbu);
+            else if (need <= 128) kbest_uneven_one<8, 2>(a, smem_kbu);
+            else kbest_uneven_one<8, 4>(a, smem_kbu);
+        }
+        kb_wave_sync();  // the next frame reuses the LDS
+    }
+}
+
+}  // namespace mimo
+
+extern "C" int32_t kbest_detect_uneven(const mimo_frame_desc* desc, int32_t B, const float* R_flat,
+                                       const float* z_flat, int32_t* sym_flat, float* pd, uint32_t* flags,
+                                       int32_t* counter, int32_t grid, void* stream)
+{
+    using namespace mimo;
+    if (B < 0 || grid < 0) return fail(MIMO_ERR_INVALID_ARG, "kbest_detect_uneven: B < 0 or grid < 0");
+    if (B == 0) return MIMO_OK;
+    if (!desc || !R_flat || !z_flat || !sym_flat || !pd || !flags || !counter)
+        return fail(MIMO_ERR_INVALID_ARG, "kbest_detect_uneven: null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    if (grid == 0) {
+        int dev = 0, cus = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        grid = 8 * (cus > 0 ? cus : 256);
+    }
+    if (grid > B) grid = B;
+    // largest LDS need over the instantiations (KCAP <= 64, 8 groups)
+    const size_t lds = gk_lds_bytes(64, (2 * UNEVEN_NWMAX + GK_LEVELS - 1) / GK_LEVELS);
+    hipLaunchKernelGGL(reset_counter_kernel_kb, dim3(1), dim3(1), 0, st, counter);
+    hipLaunchKernelGGL(kbest_uneven_kernel, dim3(grid), dim3(WAVE), lds, st, desc, B, R_flat, z_flat, sym_flat, pd,
+                       flags, counter);
+    return check_launch("kbest_detect_uneven");
 }

@@ -44,7 +44,7 @@ def pack_level_order(R: np.ndarray) -> np.ndarray:
     return out
 
 
-def pd_error_bound(R, z, x, P, terms=1):
+def pd_error_bound(R, z, x, P, terms=3):
     """Per-frame bound on |pd_FP32 - pd_FP64| of the path x [B, n] (PAM
     indices) for a search that holds R and z rounded to FP32 (relative 2^-24
     per entry), scales R by the PAM spacing in FP32 (one more rounding), sums
@@ -53,7 +53,9 @@ def pd_error_bound(R, z, x, P, terms=1):
     R_kj a_j enters as three exact partial products, as on the matrix cores
     with c R split into three bf16 parts), forms e_k = b_k - R_kk a_k and
     pd += e_k^2 with one rounding each.  First order in u = 2^-24;
-    second-order terms are covered by the factor 1.5."""
+    second-order terms are covered by the factor 1.5.  The default terms = 3
+    covers both centre forms the K-best entry points use (one FMA per term,
+    or three exact partial products per term on the matrix cores)."""
     R = np.asarray(R, np.float64)
     z = np.asarray(z, np.float64)
     B, n = z.shape
@@ -70,7 +72,7 @@ def pd_error_bound(R, z, x, P, terms=1):
     return 1.5 * ((2.0 * np.abs(e) * de + de * de).sum(axis=1) + n * U32 * pd)
 
 
-def check_kbest(orc, label, P, x_gpu, pd_gpu, out, R, z, forced, terms=1):
+def check_kbest(orc, label, P, x_gpu, pd_gpu, out, R, z, forced, terms=3):
     """Parity of a K-best detection with the oracle's `out` on the same
     frames.  x_gpu [B, n] PAM indices and pd_gpu [B] from the GPU; R, z the
     oracle's QR; forced(mask, x) runs the oracle on frames[mask] with x
@@ -100,7 +102,7 @@ def check_kbest(orc, label, P, x_gpu, pd_gpu, out, R, z, forced, terms=1):
     return eps, tol, nm
 
 
-def check_kbest_run(orc, label, P, K, sym_gpu, pd_gpu, out, R, z, k_sched=None, r2=math.inf, J=1, terms=1):
+def check_kbest_run(orc, label, P, K, sym_gpu, pd_gpu, out, R, z, k_sched=None, r2=math.inf, J=1, terms=3):
     """check_kbest for a batched oracle run with one radius for all frames
     (k_sched None, [n] or [B, n])."""
     def forced(mask, xf):

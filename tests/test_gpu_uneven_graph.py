@@ -32,7 +32,8 @@ def test_uneven_matches_batched_path_and_oracle(gpu, orc):
         H = torch.from_numpy(np.stack([fr.frame(i)[0] for i in idx])).cuda()
         y = torch.from_numpy(np.stack([fr.frame(i)[1] for i in idx])).cuda()
         Rb, zb = gpu.qr_preprocess(H, y)
-        sb, pb, _ = gpu.kbest_detect(Rb, zb, m, math.isqrt(q), K_TABLE[f"{m}x{q}"])
+        # the persistent launch runs the grouped K-best on each frame: bit-identical to the batched grouped launch
+        sb, pb, _ = gpu.kbest_detect_grouped(Rb, zb, m, math.isqrt(q), K_TABLE[f"{m}x{q}"], J=1)
         n = 2 * m
         for j, i in enumerate(idx):
             assert np.array_equal(R[d["r_off"][i]: d["r_off"][i] + n * (n + 1) // 2], Rb[j].cpu().numpy())
