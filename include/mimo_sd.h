@@ -133,10 +133,11 @@ int32_t mimo_qr_preprocess_mmse(const float* H, const float* y, const float* sig
  * carries MIMO_FLAG_EMPTY_SPHERE | MIMO_FLAG_FOUND and its counters add up
  * both searches.  A frame with a NaN or infinity in R or z stops at that
  * level with MIMO_FLAG_NONFINITE_INPUT (sym 0, pd +infinity).  For K <= 64
- * the launch is the grouped kernel of kbest_detect_grouped (J = 1), except
- * at most 8 survivors of 64-QAM at 64 < n <= 208 (two frames per wavefront)
- * and K * pam > 64 at n <= 8; the detection is the same, only the order of
- * the FP32 sums in a centre differs.
+ * without a schedule the launch is the grouped kernel of
+ * kbest_detect_grouped (J = 1), except at most 8 survivors of 64-QAM at
+ * 64 < n <= 208 (two frames per wavefront) and K * pam > 64 at n <= 8; the
+ * detection is the same, only the order of the FP32 sums in a centre
+ * differs.
  * ------------------------------------------------------------------- */
 int32_t kbest_detect(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam,
                      int32_t K, const int32_t* k_sched, int32_t k_sched_stride,
