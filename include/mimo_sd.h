@@ -248,6 +248,38 @@ int32_t sd_hybrid_detect(const float* R, const float* z, int32_t B, int32_t n_tx
                          int64_t* counters, void* stream);
 
 /* ---------------------------------------------------------------------
+ * Exact sphere decoding with the frame's tree spread over the wavefronts
+ * of one workgroup (Alg. 1 with the Schnorr-Euchner child order of
+ * Sec. IV-A; sub-problems go to whichever wavefront is free, under one
+ * shared radius, the GPU counterpart of the dynamically balanced parallel
+ * SD of Sec. V-C).  The prefixes of the top real levels (at most 512) that
+ * lie inside the radius are the sub-problems, taken in order of prefix pd;
+ * each is searched depth first, nearest child first, every leaf inside the
+ * radius shrinking it for all wavefronts of the frame.  The result is the
+ * maximum-likelihood point within the radius.
+ * radius2 [B] or NULL (no radius; with redo = 1 and radius2 NULL, each
+ * frame's current pd[b] x (1 + 1e-4), i.e. the earlier search's best leaf
+ * stays inside).  budget: node expansions per frame (0 = none); when it is
+ * spent the frame keeps its best leaf so far with BUDGET_EXHAUSTED and no
+ * CERTIFIED.  redo = 1: only frames whose flags hold BUDGET_EXHAUSTED and
+ * lack CERTIFIED (left unfinished by an earlier search such as
+ * sd_hybrid_detect with a budget) are searched, in place: sym, pd, flags
+ * overwritten, counters added to; other frames are untouched.
+ * Outputs: sym [B][n_tx], pd [B] (search metric), flags (FOUND; CERTIFIED
+ * when every sub-problem was searched), counters [B][4] or NULL: [0] node
+ * expansions, [1] child evaluations.  The counters depend on the order in
+ * which the wavefronts take the sub-problems and vary between runs; the
+ * result does not, apart from leaves whose FP32 pd ties.  A frame whose
+ * finite radius holds no leaf is searched again with r2 = +infinity
+ * (EMPTY_SPHERE | FOUND); a NaN or infinity in R or z stops it with
+ * NONFINITE_INPUT (sym 0, pd +infinity).  Limits: n_tx <= 128 (16
+ * wavefronts per frame up to 232 real levels, 8 beyond), budget >= 0.
+ * ------------------------------------------------------------------- */
+int32_t sd_parallel_detect(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam,
+                           const float* radius2, int64_t budget, int32_t redo, int32_t* sym, float* pd,
+                           uint32_t* flags, int64_t* counters, void* stream);
+
+/* ---------------------------------------------------------------------
  * Linear detection (the zero-forcing / MMSE baselines of Sec. III-A):
  * u = R^{-1} z by back-substitution in FP32 without decision feedback, then
  * every real level sliced to the nearest PAM amplitude on its own.  With R, z

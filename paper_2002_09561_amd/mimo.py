@@ -42,6 +42,7 @@ SIGNATURES = {
     "kbest_fallback": ([_P, _P, _I32, _I32, _I32, _I32, _P, _F, _P, _P, _P, _P, _P], _I32),
     "sd_hybrid_detect": ([_P, _P, _I32, _I32, _I32, _P, _I32, _I32, _P, _I32, _I32, _I64, _P, _P, _P, _P,
                           _P], _I32),
+    "sd_parallel_detect": ([_P, _P, _I32, _I32, _I32, _P, _I64, _I32, _P, _P, _P, _P, _P], _I32),
     "mimo_metric": ([_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P], _I32),
     "mimo_error_count": ([_P, _P, _I32, _I32, _I32, _P, _P], _I32),
     "prune_features": ([_P, _P, _P, _I32, _I32, _I32, _P, _P], _I32),
@@ -278,6 +279,26 @@ def sd_hybrid_detect(R, z, n_tx: int, pam: int, n_workers: int, k_worker: int, r
                                    _ptr(ks, torch.int32, "k_sched"), stride, int(bool(master_off)),
                                    int(node_budget), _ptr(sym), _ptr(pd), _ptr(flags), _ptr(ctr),
                                    _stream(stream)))
+    return (sym, pd, flags, ctr) if want_counters else (sym, pd, flags)
+
+
+def sd_parallel_detect(R, z, n_tx: int, pam: int, radius2=None, node_budget: int = 0, redo: bool = False,
+                       want_counters=False, out=None, stream=None):
+    """Exact SD with each frame's tree spread over the wavefronts of one
+    workgroup.  redo=True: only frames of `out` = (sym, pd, flags[, counters])
+    left unfinished (BUDGET_EXHAUSTED, no CERTIFIED) by an earlier search are
+    searched again, in place.  Returns (sym, pd, flags[, counters])."""
+    B = z.shape[0]
+    if redo and out is None:
+        raise ValueError("redo needs the earlier search's outputs in `out`")
+    if out is not None:
+        sym, pd, flags = out[:3]
+        ctr = out[3] if len(out) > 3 else None
+    else:
+        sym, pd, flags, ctr = _det_outputs(B, n_tx, z.device, want_counters)
+    _check(load().sd_parallel_detect(_ptr(R, torch.float32, "R"), _ptr(z, torch.float32, "z"), B, n_tx, pam,
+                                     _ptr(radius2, torch.float32, "radius2"), int(node_budget), int(bool(redo)),
+                                     _ptr(sym), _ptr(pd), _ptr(flags), _ptr(ctr), _stream(stream)))
     return (sym, pd, flags, ctr) if want_counters else (sym, pd, flags)
 
 

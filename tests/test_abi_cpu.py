@@ -146,6 +146,19 @@ def test_grouped_kbest_host_checks(lib):
     assert g(P, P, 2, 8, 8, 16, 2, P, 0, P, P, P, P, P, P) == -1        # null pointers
 
 
+def test_parallel_sd_host_checks(lib):
+    P = None
+    g = lib.sd_parallel_detect
+    assert g(P, P, -1, 8, 4, P, 0, 0, P, P, P, P, P) == -1
+    assert g(P, P, 2, 8, 5, P, 0, 0, P, P, P, P, P) == -1        # pam
+    assert g(P, P, 2, 129, 4, P, 0, 0, P, P, P, P, P) == -2      # n_tx > 128
+    assert g(P, P, 2, 8, 4, P, -1, 0, P, P, P, P, P) == -1       # budget < 0
+    assert "budget" in _err(lib)
+    assert g(P, P, 2, 8, 4, P, 0, 2, P, P, P, P, P) == -1        # redo not 0 or 1
+    assert g(P, P, 0, 8, 4, P, 0, 0, P, P, P, P, P) == 0         # empty batch
+    assert g(P, P, 2, 8, 4, P, 0, 0, P, P, P, P, P) == -1        # null pointers
+
+
 def test_binding_refuses_cpu_tensors(lib):
     import torch
 

@@ -1,0 +1,154 @@
+"""GPU parity of the exact sphere decoder whose tree is spread over the
+wavefronts of a workgroup (sd_parallel_detect) with the oracle's Best-FS
+sphere decoder: both return a maximum-likelihood point, so a mismatch is
+excused only where the FP64 metrics of the two points tie within 1e-5
+(tests/parity_util.check_ml).  Node counters depend on the order in which
+the wavefronts take the sub-problems and are not compared."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2002_09561_amd.framegen import gen_frames
+from tests.parity_util import check_ml, pd_error_bound
+
+pytestmark = pytest.mark.gpu
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def _orc_x(sym, P):
+    x = np.empty(sym.shape[:-1] + (2 * sym.shape[-1],), np.int32)
+    x[..., 0::2] = sym // P
+    x[..., 1::2] = sym % P
+    return x
+
+
+def _setup(gpu, M, q, snr, B, seed):
+    import torch
+
+    f = gen_frames(M, M, q, snr, B, seed=seed)
+    H, y = torch.from_numpy(f.H).cuda(), torch.from_numpy(f.y).cuda()
+    R, z = gpu.qr_preprocess(H, y)
+    return f, math.isqrt(q), R, z
+
+
+def _pd_within_bound(orc, f, P, sym, pd, x_orc, pd_orc, label):
+    Ro, zo, _ = orc.qr(f.H, f.y)
+    same = np.all(_orc_x(sym, P) == x_orc, axis=1)
+    bnd = pd_error_bound(Ro[same], zo[same], x_orc[same], P)
+    err = np.abs(pd[same] - pd_orc[same])
+    assert np.all(err <= bnd), f"{label}: search pd outside the FP32 bound"
+    eps = float(np.max(err / np.maximum(pd_orc[same], 1e-300))) if same.any() else 0.0
+    print(f"  {label}: eps_FP32 {eps:.2e} on {same.sum()} frames with the oracle's point")
+
+
+@pytest.mark.parametrize("M,q,snr,B", [(2, 16, 6.0, 200), (4, 16, 8.0, 200), (8, 4, 4.0, 150), (6, 64, 16.0, 100),
+                                       (12, 16, 8.0, 40), (16, 4, 3.0, 40), (5, 64, 10.0, 60)])
+def test_parallel_sd_is_ml(gpu, orc, M, q, snr, B):
+    f, P, R, z = _setup(gpu, M, q, snr, B, seed=11000 + 7 * M)
+    print(f"parallel SD {M}x{M} {q}-QAM {snr} dB B={B}", flush=True)
+    sym, pd, flags, ctr = gpu.sd_parallel_detect(R, z, M, P, want_counters=True)
+    sym, pd, flags, ctr = _np(sym), _np(pd), _np(flags), _np(ctr)
+    assert np.all(flags & gpu.FLAG_CERTIFIED) and np.all(flags & gpu.FLAG_FOUND)
+    assert not np.any(flags & gpu.FLAG_BUDGET_EXHAUSTED)
+    Ro, zo, _ = orc.qr(f.H, f.y)
+    x, pdo, flo, _ = orc.sesd(Ro, zo, P)
+    check_ml(orc, f"parallel SD {M}x{M} {q}-QAM", P, sym, (x,), f.H, f.y, q)
+    _pd_within_bound(orc, f, P, sym, pd, x, pdo, f"parallel SD {M}x{M}")
+    assert np.all(ctr[:, 0] > 0) and np.all(ctr[:, 1] >= ctr[:, 0])
+    if M <= 4:
+        sb, _ = orc.brute_force(f.H, f.y, q)
+        check_ml(orc, "parallel SD vs brute force", P, sym, {"x": _orc_x(sb, P)}, f.H, f.y, q)
+
+
+def test_parallel_sd_finishes_unfinished_frames(gpu, orc):
+    """The exact SD of sd_hybrid_detect with a tiny node budget leaves most
+    frames unfinished; sd_parallel_detect(redo=True) searches exactly those
+    again from their best leaf and certifies them, leaving the finished
+    frames untouched."""
+    import torch
+
+    M, q, B = 12, 16, 80
+    # half easy frames (20 dB: finished within the budget), half hard ones (4 dB)
+    fe, fh = gen_frames(M, M, q, 20.0, B // 2, seed=11500), gen_frames(M, M, q, 4.0, B // 2, seed=11501)
+    H, y = np.concatenate([fe.H, fh.H]), np.concatenate([fe.y, fh.y])
+    P = math.isqrt(q)
+    R, z = gpu.qr_preprocess(torch.from_numpy(H).cuda(), torch.from_numpy(y).cuda())
+    out = gpu.sd_hybrid_detect(R, z, M, P, 0, 1, node_budget=100, want_counters=True)
+    torch.cuda.synchronize()
+    before = [_np(t).copy() for t in out]
+    unfinished = (before[2] & gpu.FLAG_BUDGET_EXHAUSTED) != 0
+    assert unfinished.sum() >= B // 4 and (~unfinished).sum() >= B // 4
+    print(f"parallel SD redo: {unfinished.sum()} of {B} frames unfinished", flush=True)
+    gpu.sd_parallel_detect(R, z, M, P, redo=True, out=out)
+    sym, pd, flags, ctr = (_np(t) for t in out)
+    assert np.all(flags & gpu.FLAG_CERTIFIED) and np.all(flags & gpu.FLAG_FOUND)
+    for a, b in zip((sym, pd, flags, ctr), before):
+        assert np.array_equal(a[~unfinished], b[~unfinished])
+    assert np.all(ctr[unfinished, 0] > before[3][unfinished, 0])  # counters added to
+    assert np.all(pd[unfinished] <= before[1][unfinished] * (1 + 1e-4))
+    Ro, zo, _ = orc.qr(H, y)
+    x, _, _, _ = orc.sesd(Ro, zo, P)
+    check_ml(orc, "parallel SD redo", P, sym, (x,), H, y, q)
+
+
+def test_parallel_sd_radius_budget_nonfinite(gpu, orc):
+    """A radius below the ML metric: the frame is searched again without a
+    radius (EMPTY_SPHERE | FOUND) and still returns the ML point; a small
+    budget ends frames with BUDGET_EXHAUSTED (no CERTIFIED) and a leaf no
+    better than ML; a NaN in R stops its frame with NONFINITE_INPUT."""
+    import torch
+
+    M, q, snr, B = 10, 16, 8.0, 60
+    f, P, R, z = _setup(gpu, M, q, snr, B, seed=11700)
+    Ro, zo, _ = orc.qr(f.H, f.y)
+    x, ml, _, _ = orc.sesd(Ro, zo, P)
+    rng = np.random.default_rng(3)
+    radius = (ml * rng.uniform(0.5, 1.5, B)).astype(np.float32)
+    sym, pd, flags = gpu.sd_parallel_detect(R, z, M, P, radius2=torch.from_numpy(radius).cuda())
+    sym, pd, flags = _np(sym), _np(pd), _np(flags)
+    below = radius < ml * (1 - 1e-5)
+    above = radius > ml * (1 + 1e-5)
+    assert np.all(flags[below] & gpu.FLAG_EMPTY_SPHERE) and not np.any(flags[above] & gpu.FLAG_EMPTY_SPHERE)
+    assert np.all(flags & gpu.FLAG_FOUND) and np.all(flags & gpu.FLAG_CERTIFIED)
+    check_ml(orc, "parallel SD radius", P, sym, (x,), f.H, f.y, q)
+
+    sym, pd, flags = gpu.sd_parallel_detect(R, z, M, P, node_budget=20)
+    sym, pd, flags = _np(sym), _np(pd), _np(flags)
+    ex = (flags & gpu.FLAG_BUDGET_EXHAUSTED) != 0
+    assert ex.sum() >= B // 2 and not np.any(flags[ex] & gpu.FLAG_CERTIFIED)
+    got = ex & ((flags & gpu.FLAG_FOUND) != 0)
+    assert np.all(orc.metric(f.H[got], f.y[got], sym[got], q) >= orc.metric(f.H[got], f.y[got],
+                                                                               orc.x_to_sym(x[got], P), q) * (1 - 1e-6))
+
+    R2 = R.clone()
+    R2[3, 7] = float("nan")
+    sym, pd, flags = gpu.sd_parallel_detect(R2, z, M, P)
+    fl = _np(flags)
+    assert fl[3] & gpu.FLAG_NONFINITE_INPUT and not fl[3] & gpu.FLAG_FOUND and np.isinf(_np(pd)[3])
+    assert np.all(_np(sym)[3] == 0)
+    others = np.arange(B) != 3
+    assert np.all(fl[others] & gpu.FLAG_CERTIFIED)
+
+
+@pytest.mark.parametrize("M,q,snr,B,K", [(100, 64, 20.0, 8, 64), (128, 4, 12.0, 3, 16)])
+def test_parallel_sd_large_warm_start(gpu, orc, M, q, snr, B, K):
+    """100x100 64-QAM (16 wavefronts per frame) and 128x128 4-QAM (256
+    levels: 8 wavefronts per frame) warm-started by K-best as in the
+    benchmark's reference: the oracle's budgeted Best-FS SD with the same
+    FP32 radius certifies the same ML points."""
+    f, P, R, z = _setup(gpu, M, q, snr, B, seed=11900 + M)
+    _, pk, _ = gpu.kbest_detect(R, z, M, P, K)
+    r2 = (pk * (1.0 + 1e-4)).contiguous()
+    print(f"parallel SD {M}x{M} {q}-QAM warm start K={K}", flush=True)
+    sym, pd, flags = gpu.sd_parallel_detect(R, z, M, P, radius2=r2, node_budget=2_000_000)
+    sym, pd, flags = _np(sym), _np(pd), _np(flags)
+    assert np.all(flags & gpu.FLAG_CERTIFIED) and np.all(flags & gpu.FLAG_FOUND)
+    Ro, zo, _ = orc.qr(f.H, f.y)
+    x, pdo, flo, _ = orc.sesd(Ro, zo, P, r2=_np(r2).astype(np.float64), budget=2_000_000)
+    done = (flo & orc.CERTIFIED) != 0
+    assert done.sum() >= B - 1
+    check_ml(orc, f"parallel SD {M}x{M}", P, sym[done], (x[done],), f.H[done], f.y[done], q)
