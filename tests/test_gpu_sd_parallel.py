@@ -98,8 +98,9 @@ def test_parallel_sd_finishes_unfinished_frames(gpu, orc):
 def test_parallel_sd_radius_budget_nonfinite(gpu, orc):
     """A radius below the ML metric: the frame is searched again without a
     radius (EMPTY_SPHERE | FOUND) and still returns the ML point; a small
-    budget ends frames with BUDGET_EXHAUSTED (no CERTIFIED) and a leaf no
-    better than ML; a NaN in R stops its frame with NONFINITE_INPUT."""
+    budget ends the frames that reach it with BUDGET_EXHAUSTED (no CERTIFIED)
+    and a leaf no better than ML, the others finish certified; a NaN in R
+    stops its frame with NONFINITE_INPUT."""
     import torch
 
     M, q, snr, B = 10, 16, 8.0, 60
@@ -116,10 +117,12 @@ def test_parallel_sd_radius_budget_nonfinite(gpu, orc):
     assert np.all(flags & gpu.FLAG_FOUND) and np.all(flags & gpu.FLAG_CERTIFIED)
     check_ml(orc, "parallel SD radius", P, sym, (x,), f.H, f.y, q)
 
-    sym, pd, flags = gpu.sd_parallel_detect(R, z, M, P, node_budget=20)
-    sym, pd, flags = _np(sym), _np(pd), _np(flags)
+    budget = 20  # charged every 32 expansions of a wavefront
+    sym, pd, flags, ctr = gpu.sd_parallel_detect(R, z, M, P, node_budget=budget, want_counters=True)
+    sym, pd, flags, ctr = _np(sym), _np(pd), _np(flags), _np(ctr)
     ex = (flags & gpu.FLAG_BUDGET_EXHAUSTED) != 0
-    assert ex.sum() >= B // 2 and not np.any(flags[ex] & gpu.FLAG_CERTIFIED)
+    assert ex.sum() >= 5 and not np.any(flags[ex] & gpu.FLAG_CERTIFIED)
+    assert np.all(flags[~ex] & gpu.FLAG_CERTIFIED) and np.all(ctr[ex, 0] >= budget)
     got = ex & ((flags & gpu.FLAG_FOUND) != 0)
     assert np.all(orc.metric(f.H[got], f.y[got], sym[got], q) >= orc.metric(f.H[got], f.y[got],
                                                                                orc.x_to_sym(x[got], P), q) * (1 - 1e-6))
