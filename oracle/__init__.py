@@ -68,11 +68,11 @@ def _declare(L):
     L.orc_batch_sesd.argtypes = [_I, _I, _I, _P, _P, _P, _L, _P, _P, _P, _P, _P]
     L.orc_batch_kbest.argtypes = [_I, _I, _I, _P, _P, _I, _P, _I, _D, _I, _P, _P, _P, _P, _P,
                                   _P, _P, _P, _P]
-    L.orc_batch_hybrid.argtypes = [_I, _I, _I, _P, _P, _P, _I, _I, _P, _I, _I, _L, _P, _P, _P,
+    L.orc_batch_hybrid.argtypes = [_I, _I, _I, _I, _P, _P, _P, _I, _I, _P, _I, _I, _L, _P, _P, _P,
                                    _P, _P]
     L.orc_batch_learned_detect.argtypes = [_I, _I, _I, _P, _P, _P, _P, _D, _I, _I, _D, _I, _P, _P, _P, _P]
     L.orc_hybrid_trace.restype = ctypes.c_uint32
-    L.orc_hybrid_trace.argtypes = [_I, _I, _P, _P, _D, _I, _I, _I, _L, _P, _P, _P, ctypes.c_char_p, _I]
+    L.orc_hybrid_trace.argtypes = [_I, _I, _I, _P, _P, _D, _I, _I, _I, _L, _P, _P, _P, ctypes.c_char_p, _I]
     L.orc_batch_prune_features.argtypes = [_I, _I, _I, _P, _P, _P, _P]
     L.orc_path_terms.argtypes = [_I, _I, _P, _P, _P, _P]
     L.orc_mlp_forward.argtypes = [_P, _P, _I, _P]
@@ -230,8 +230,9 @@ def kbest(R, z, P: int, K: int, k_sched=None, r2: float = math.inf, J: int = 1,
 
 
 def hybrid(R, z, P: int, W: int, Kw: int, r2=math.inf, k_sched=None,
-           master_off: bool = False, budget: int = 0):
-    """Hybrid SD-K-best in deterministic rounds (Sec. VI).  r2: scalar or [B]."""
+           master_off: bool = False, budget: int = 0, J: int = 1):
+    """Hybrid SD-K-best in deterministic rounds (Sec. VI).  r2: scalar or [B];
+    J real levels per step (2: one complex symbol, P^2 children)."""
     R = _c(R, np.float64)
     z = _c(z, np.float64)
     B, n = z.shape
@@ -245,14 +246,14 @@ def hybrid(R, z, P: int, W: int, Kw: int, r2=math.inf, k_sched=None,
     mg = np.zeros((B, 3))
     fl = np.zeros(B, np.uint32)
     ctr = np.zeros((B, 4), np.int64)
-    lib().orc_batch_hybrid(B, n, P, _p(R), _p(z), _p(r2a), int(W), int(Kw), _p(ks), stride,
+    lib().orc_batch_hybrid(B, n, P, int(J), _p(R), _p(z), _p(r2a), int(W), int(Kw), _p(ks), stride,
                            int(bool(master_off)), int(budget), _p(x), _p(pd), _p(mg), _p(fl),
                            _p(ctr))
     return dict(x=x, pd=pd, margin=mg, flags=fl, counters=ctr)
 
 
 def hybrid_trace(R, z, P: int, W: int, Kw: int, r2: float = math.inf, master_off: bool = False,
-                 budget: int = 0):
+                 budget: int = 0, J: int = 1):
     """One frame (R [n,n], z [n]) of the hybrid with its round-by-round text
     trace.  Returns (trace lines, x [n], pd, flags, counters [4])."""
     R = _c(R, np.float64)
@@ -263,7 +264,7 @@ def hybrid_trace(R, z, P: int, W: int, Kw: int, r2: float = math.inf, master_off
     ctr = np.zeros(4, np.int64)
     cap = 1 << 20
     buf = ctypes.create_string_buffer(cap)
-    fl = lib().orc_hybrid_trace(n, P, _p(R), _p(z), float(r2), int(W), int(Kw), int(bool(master_off)),
+    fl = lib().orc_hybrid_trace(n, P, int(J), _p(R), _p(z), float(r2), int(W), int(Kw), int(bool(master_off)),
                                 int(budget), _p(x), ctypes.byref(pd), _p(ctr), buf, cap)
     return buf.value.decode().splitlines(), x, pd.value, int(fl), ctr
 

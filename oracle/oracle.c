@@ -636,12 +636,22 @@ typedef struct {
     int c;
 } hcand_t;
 
-static uint32_t hybrid_search(int n, int P, const double* R, const double* z, double r2, int W, int Kw,
+/* digits of child c (top level most significant) into levels k_hi .. k_hi-J+1 */
+static void set_digits(int* path, int P, int k_hi, int J, int c)
+{
+    for (int q = J - 1; q >= 0; --q) {
+        path[k_hi - q] = c % P;
+        c /= P;
+    }
+}
+
+static uint32_t hybrid_search(int n, int P, int J, const double* R, const double* z, double r2, int W, int Kw,
                               const int* k_sched, int master_off, int64_t budget, int* x_out,
                               double* pd_out, double* margin_out, int64_t* counters, trace_t* T)
 {
     const int kmax = Kw < 1 ? 1 : Kw; /* Kw is the capacity; schedule values are clamped to it */
-    const int cap = n * P + 8;
+    const int PC = ipow(P, J);        /* children per step: J real levels */
+    const int cap = (n / J + 1) * PC + 8;
     int* qt = (int*)malloc(sizeof(int) * cap);
     double* qpd = (double*)malloc(sizeof(double) * cap);
     int* qpath = (int*)malloc(sizeof(int) * (size_t)cap * n);
@@ -655,12 +665,13 @@ static uint32_t hybrid_search(int n, int P, const double* R, const double* z, do
     int* wpath = (int*)calloc((size_t)nw * kmax * n, sizeof(int));
     double* npd = (double*)calloc((size_t)kmax, sizeof(double));
     int* npath = (int*)calloc((size_t)kmax * n, sizeof(int));
-    cand_t* cand = (cand_t*)malloc(sizeof(cand_t) * (size_t)kmax * P);
-    /* round candidates: at most P from the master and kmax per worker */
-    hcand_t* hc = (hcand_t*)malloc(sizeof(hcand_t) * (size_t)(P + nw * kmax));
-    int* leafbuf = (int*)malloc(sizeof(int) * (size_t)(P + nw * kmax) * n);
+    cand_t* cand = (cand_t*)malloc(sizeof(cand_t) * (size_t)kmax * PC);
+    /* round candidates: at most PC from the master and kmax per worker */
+    hcand_t* hc = (hcand_t*)malloc(sizeof(hcand_t) * (size_t)(PC + nw * kmax));
+    int* leafbuf = (int*)malloc(sizeof(int) * (size_t)(PC + nw * kmax) * n);
     int* cur = (int*)malloc(sizeof(int) * n);
-    child_t ch[8];
+    int* tmp = (int*)malloc(sizeof(int) * n);
+    child_t* ch = (child_t*)malloc(sizeof(child_t) * (size_t)PC);
     int64_t expanded = 0, evaluated = 0, rounds = 0, stale = 0;
     uint32_t flags = 0;
     double best = INFINITY;
@@ -717,27 +728,25 @@ static uint32_t hybrid_search(int n, int P, const double* R, const double* z, do
                 memcpy(cur, qpath + (size_t)slot * n, sizeof(int) * n);
                 ++expanded;
                 tr(T, "master expand depth %d pd %.6g\n", t, pd);
-                int k = n - 1 - t;
-                double b = centre(n, P, R, z, k, cur);
-                for (int c = 0; c < P; ++c) {
-                    double e = b - R[k * n + k] * amp(P, c);
-                    ch[c].pd = pd + e * e;
+                int k = n - 1 - t; /* the step fixes levels k .. k-J+1 */
+                for (int c = 0; c < PC; ++c) {
+                    ch[c].pd = child_pd(n, P, R, z, k, J, c, cur, pd, tmp);
                     ch[c].c = c;
-                    ++evaluated;
+                    evaluated += J;
                 }
-                qsort(ch, (size_t)P, sizeof(child_t), cmp_child);
+                qsort(ch, (size_t)PC, sizeof(child_t), cmp_child);
                 int nk = 0;
-                for (int i = 0; i < P; ++i) {
+                for (int i = 0; i < PC; ++i) {
                     if (isfinite(r2r)) note_gap(margin_out, ch[i].pd, r2r);
                     if (ch[i].pd < r2r) nk = i + 1;
                 }
                 for (int i = 0; i + 1 < nk; ++i) note_gap(margin_out, ch[i].pd, ch[i + 1].pd);
-                for (int i = 0; i < nk; ++i) tr(T, "  child %d pd %.6g%s\n", ch[i].c, ch[i].pd, t + 1 == n ? " leaf" : "");
-                if (t + 1 == n) {
+                for (int i = 0; i < nk; ++i) tr(T, "  child %d pd %.6g%s\n", ch[i].c, ch[i].pd, t + J == n ? " leaf" : "");
+                if (t + J == n) {
                     for (int i = 0; i < nk; ++i) {
                         int* lp = leafbuf + (size_t)nh * n;
                         memcpy(lp, cur, sizeof(int) * n);
-                        lp[k] = ch[i].c;
+                        set_digits(lp, P, k, J, ch[i].c);
                         hc[nh].pd = ch[i].pd;
                         hc[nh].src = 0;
                         hc[nh].rank = i;
@@ -748,10 +757,10 @@ static uint32_t hybrid_search(int n, int P, const double* R, const double* z, do
                     for (int i = nk - 1; i >= 0; --i) {
                         head = (head - 1 + cap) % cap;
                         ++size;
-                        qt[head] = t + 1;
+                        qt[head] = t + J;
                         qpd[head] = ch[i].pd;
                         memcpy(qpath + (size_t)head * n, cur, sizeof(int) * n);
-                        qpath[(size_t)head * n + k] = ch[i].c;
+                        set_digits(qpath + (size_t)head * n, P, k, J, ch[i].c);
                     }
                 }
                 break;
@@ -783,8 +792,8 @@ static uint32_t hybrid_search(int n, int P, const double* R, const double* z, do
         /* 3. busy workers advance one K-best level */
         for (int w = 0; w < W; ++w) {
             if (!wbusy[w]) continue;
-            int t = wt[w], k = n - 1 - t;
-            int Kt = k_sched ? k_sched[k] : Kw;
+            int t = wt[w], k = n - 1 - t; /* the step fixes levels k .. k-J+1; K_t read at the lowest */
+            int Kt = k_sched ? k_sched[k - J + 1] : Kw;
             if (Kt > kmax) Kt = kmax;
             if (Kt < 1) Kt = 1;
             double* spd = wpd + (size_t)w * kmax;
@@ -792,11 +801,9 @@ static uint32_t hybrid_search(int n, int P, const double* R, const double* z, do
             int m = 0;
             for (int r = 0; r < wcnt[w]; ++r) {
                 ++expanded;
-                double b = centre(n, P, R, z, k, sp + (size_t)r * n);
-                for (int c = 0; c < P; ++c) {
-                    double e = b - R[k * n + k] * amp(P, c);
-                    double pd = spd[r] + e * e;
-                    ++evaluated;
+                for (int c = 0; c < PC; ++c) {
+                    double pd = child_pd(n, P, R, z, k, J, c, sp + (size_t)r * n, spd[r], tmp);
+                    evaluated += J;
                     if (isfinite(r2r)) note_gap(margin_out, pd, r2r);
                     if (pd < r2r) {
                         cand[m].pd = pd;
@@ -813,20 +820,20 @@ static uint32_t hybrid_search(int n, int P, const double* R, const double* z, do
             }
             qsort(cand, (size_t)m, sizeof(cand_t), cmp_cand);
             int keep = Kt < m ? Kt : m;
-            if (m > keep && t + 1 < n) note_gap(margin_out, cand[keep - 1].pd, cand[keep].pd);
+            if (m > keep && t + J < n) note_gap(margin_out, cand[keep - 1].pd, cand[keep].pd);
             for (int i = 0; i < keep; ++i)
                 tr(T, "worker %d depth %d keeps parent %d child %d pd %.6g%s\n", w, t, cand[i].parent, cand[i].c,
-                   cand[i].pd, t + 1 == n ? " leaf" : "");
+                   cand[i].pd, t + J == n ? " leaf" : "");
             for (int i = 0; i < keep; ++i) {
                 memcpy(npath + (size_t)i * n, sp + (size_t)cand[i].parent * n, sizeof(int) * n);
-                npath[(size_t)i * n + k] = cand[i].c;
+                set_digits(npath + (size_t)i * n, P, k, J, cand[i].c);
                 npd[i] = cand[i].pd;
             }
             memcpy(sp, npath, sizeof(int) * (size_t)keep * n);
             memcpy(spd, npd, sizeof(double) * keep);
             wcnt[w] = keep;
-            wt[w] = t + 1;
-            if (t + 1 == n) {
+            wt[w] = t + J;
+            if (t + J == n) {
                 for (int i = 0; i < keep; ++i) {
                     int* lp = leafbuf + (size_t)nh * n;
                     memcpy(lp, sp + (size_t)i * n, sizeof(int) * n);
@@ -891,19 +898,23 @@ static uint32_t hybrid_search(int n, int P, const double* R, const double* z, do
     free(hc);
     free(leafbuf);
     free(cur);
+    free(tmp);
+    free(ch);
     return flags;
 }
 
-/* An empty sphere is searched again with r2 = +inf (reading of Sec. III-B). */
-uint32_t orc_hybrid(int n, int P, const double* R, const double* z, double r2, int W, int Kw,
+/* An empty sphere is searched again with r2 = +inf (reading of Sec. III-B).
+ * J real levels per step (1 or 2; n a multiple of J). */
+uint32_t orc_hybrid(int n, int P, int J, const double* R, const double* z, double r2, int W, int Kw,
                     const int* k_sched, int master_off, int64_t budget, int* x_out, double* pd_out,
                     double* margin_out, int64_t* counters)
 {
-    uint32_t f = hybrid_search(n, P, R, z, r2, W, Kw, k_sched, master_off, budget, x_out, pd_out,
+    if (J < 1 || n % J != 0) return 0;
+    uint32_t f = hybrid_search(n, P, J, R, z, r2, W, Kw, k_sched, master_off, budget, x_out, pd_out,
                                margin_out, counters, NULL);
     if ((f & ORC_EMPTY_SPHERE) && isfinite(r2)) {
         double m2[3];
-        f = hybrid_search(n, P, R, z, INFINITY, W, Kw, k_sched, master_off, budget, x_out, pd_out,
+        f = hybrid_search(n, P, J, R, z, INFINITY, W, Kw, k_sched, master_off, budget, x_out, pd_out,
                           margin_out ? m2 : NULL, counters, NULL) | ORC_EMPTY_SPHERE;
         if (margin_out) merge_margin(margin_out, m2);
     }
@@ -914,13 +925,14 @@ uint32_t orc_hybrid(int n, int P, const double* R, const double* z, double r2, i
  * (at most cap bytes, NUL-terminated): the round-start radius and pool
  * size, every pop (expanded or stale) with its depth and pd, the children
  * kept, the workers' hand-offs and levels, and each radius update. */
-uint32_t orc_hybrid_trace(int n, int P, const double* R, const double* z, double r2, int W, int Kw,
+uint32_t orc_hybrid_trace(int n, int P, int J, const double* R, const double* z, double r2, int W, int Kw,
                           int master_off, int64_t budget, int* x_out, double* pd_out, int64_t* counters,
                           char* buf, int cap)
 {
     trace_t T = {buf, (size_t)(cap > 0 ? cap : 0), 0};
     if (cap > 0) buf[0] = 0;
-    return hybrid_search(n, P, R, z, r2, W, Kw, NULL, master_off, budget, x_out, pd_out, NULL, counters, &T);
+    if (J < 1 || n % J != 0) return 0;
+    return hybrid_search(n, P, J, R, z, r2, W, Kw, NULL, master_off, budget, x_out, pd_out, NULL, counters, &T);
 }
 
 /* ------------------------------------------------------------------ */
@@ -1193,7 +1205,7 @@ void orc_batch_kbest(int B, int n, int P, const double* R, const double* z, int 
     }
 }
 
-void orc_batch_hybrid(int B, int n, int P, const double* R, const double* z, const double* r2, int W,
+void orc_batch_hybrid(int B, int n, int P, int J, const double* R, const double* z, const double* r2, int W,
                       int Kw, const int* k_sched, int k_sched_stride, int master_off,
                       int64_t budget, int* x_out, double* pd_out, double* margin_out,
                       uint32_t* flags, int64_t* counters)
@@ -1201,7 +1213,7 @@ void orc_batch_hybrid(int B, int n, int P, const double* R, const double* z, con
 #pragma omp parallel for schedule(dynamic, 1)
     for (int b = 0; b < B; ++b) {
         int64_t ctr[ORC_NCOUNTERS] = {0, 0, 0, 0};
-        uint32_t f = orc_hybrid(n, P, R + (size_t)b * n * n, z + (size_t)b * n, r2 ? r2[b] : INFINITY, W, Kw,
+        uint32_t f = orc_hybrid(n, P, J, R + (size_t)b * n * n, z + (size_t)b * n, r2 ? r2[b] : INFINITY, W, Kw,
                                 k_sched ? k_sched + (size_t)b * k_sched_stride : NULL, master_off,
                                 budget, x_out + (size_t)b * n, pd_out ? pd_out + b : NULL,
                                 margin_out ? margin_out + (size_t)b * 3 : NULL, ctr);

@@ -97,13 +97,16 @@ uint32_t orc_kbest(int n, int P, const double* R, const double* z, int K, const 
                    int64_t* counters);
 
 /* Hybrid SD-K-best (Sec. VI) in deterministic rounds; W workers each keep
- * Kw survivors (or k_sched[k] clamped to [1, Kw] when k_sched is not NULL).  master_off hands
- * the root to worker 0 and never expands (the K-best special case). */
-uint32_t orc_hybrid(int n, int P, const double* R, const double* z, double r2, int W, int Kw,
+ * Kw survivors (or k_sched[k] clamped to [1, Kw] when k_sched is not NULL,
+ * k the lowest level a step fixes).  Each step fixes J real levels (1 or 2:
+ * P^J children, the digit of the top level most significant; Sec. IV-B
+ * grouping).  master_off hands the root to worker 0 and never expands (the
+ * K-best special case). */
+uint32_t orc_hybrid(int n, int P, int J, const double* R, const double* z, double r2, int W, int Kw,
                     const int* k_sched, int master_off, int64_t budget, int* x_out, double* pd_out,
                     double* margin_out, int64_t* counters);
 /* The same search for one frame with a text trace of its rounds in buf. */
-uint32_t orc_hybrid_trace(int n, int P, const double* R, const double* z, double r2, int W, int Kw,
+uint32_t orc_hybrid_trace(int n, int P, int J, const double* R, const double* z, double r2, int W, int Kw,
                           int master_off, int64_t budget, int* x_out, double* pd_out, int64_t* counters,
                           char* buf, int cap);
 
@@ -166,7 +169,7 @@ void orc_batch_kbest(int B, int n, int P, const double* R, const double* z, int 
                      const int* force_path, int* x_out, double* pd_out, double* margin_out,
                      int* rank_out, double* fgap_out, double* rgap_out, uint32_t* flags,
                      int64_t* counters);
-void orc_batch_hybrid(int B, int n, int P, const double* R, const double* z, const double* r2, int W,
+void orc_batch_hybrid(int B, int n, int P, int J, const double* R, const double* z, const double* r2, int W,
                       int Kw, const int* k_sched, int k_sched_stride, int master_off,
                       int64_t budget, int* x_out, double* pd_out, double* margin_out,
                       uint32_t* flags, int64_t* counters);

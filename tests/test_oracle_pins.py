@@ -495,6 +495,47 @@ def test_hybrid_round_schedule_golden_trace(orc):
     assert list(h["x"][0]) == [1, 1, 0, 1] and list(h["counters"][0]) == [9, 18, 5, 1]
 
 
+def test_hybrid_complex_levels_golden_trace(orc):
+    """The hybrid with J = 2 real levels per step (one complex symbol, P^2
+    children) on the frame of the real-level trace, traced by hand (the
+    derivation is in the golden file).  It fails if a child's digits are
+    stored with the lower level first, if the lower level's centre misses
+    the step's own upper symbol, if leaves are detected one level early, or
+    if a child counts one evaluation instead of J."""
+    path = __file__.replace("test_oracle_pins.py", "golden/hybrid_trace_2x2_4qam_j2_w1_k1.txt")
+    gold = [l for l in open(path).read().splitlines() if l and not l.startswith("#")]
+    c = orc.pam_scale(2)
+    lines, x, pd, fl, ctr = orc.hybrid_trace(_TRACE_RT / c, _TRACE_Z, 2, 1, 1, J=2)
+    assert lines == gold
+    assert list(x) == [1, 1, 0, 1] and abs(pd - 1.55) < 1e-12
+    assert list(ctr) == [4, 32, 3, 1] and (fl & orc.CERTIFIED) and (fl & orc.FOUND)
+    h = orc.hybrid((_TRACE_RT / c)[None], _TRACE_Z[None], 2, 1, 1, J=2)
+    assert list(h["x"][0]) == [1, 1, 0, 1] and list(h["counters"][0]) == [4, 32, 3, 1]
+
+
+@pytest.mark.parametrize("M,q,snr", [(2, 16, 4.0), (3, 4, 2.0), (2, 64, 12.0)])
+def test_hybrid_complex_levels_special_cases(orc, M, q, snr):
+    """J = 2: with no workers the master alone is an exact SD (the brute-force
+    ML metric); with the master off, worker 0 runs the complex-level K-best
+    (orc.kbest with J = 2: the same points and node counters)."""
+    from paper_2002_09561_amd.framegen import gen_frames
+
+    f = gen_frames(M, M, q, snr, 40, seed=77 + M)
+    R, z, _ = orc.qr(f.H, f.y)
+    P = math.isqrt(q)
+    h = orc.hybrid(R, z, P, 0, 1, J=2)
+    assert np.all(h["flags"] & orc.CERTIFIED)
+    s_bf, _ = orc.brute_force(f.H, f.y, q)
+    mh = orc.metric(f.H, f.y, orc.x_to_sym(h["x"], P), q)
+    mb = orc.metric(f.H, f.y, s_bf, q)
+    assert np.allclose(mh, mb, rtol=1e-12)
+    for K in (1, 3, 8):
+        hk = orc.hybrid(R, z, P, 1, K, master_off=True, J=2)
+        kb = orc.kbest(R, z, P, K, J=2)
+        assert np.array_equal(hk["x"], kb["x"])
+        assert np.array_equal(hk["counters"][:, :2], kb["counters"][:, :2])
+
+
 def test_hybrid_trace_no_workers_is_best_first_sd(orc):
     """With no workers the trace is the Best-FS SD of Alg. 1 on the same
     tree: the master alone walks down the best children (0.49, 0.65, 0.74,
