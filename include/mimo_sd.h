@@ -79,6 +79,7 @@ extern "C" {
 #define MIMO_MAX_K 256    /* K-best survivors: K * pam <= 1024 */
 #define MIMO_MAX_WORKERS 15
 #define MIMO_HYB_MAX_CAND 64 /* hybrid worker: k_worker * pam <= 64 */
+#define MIMO_HYB_MAX_CAND_CPLX 256 /* complex-level hybrid worker: k_worker * pam^2 <= 256 */
 
 #define MIMO_MLP_IN 4
 #define MIMO_MLP_HIDDEN 128
@@ -246,6 +247,27 @@ int32_t sd_hybrid_detect(const float* R, const float* z, int32_t B, int32_t n_tx
                          const int32_t* k_sched, int32_t k_sched_stride, int32_t master_off,
                          int64_t node_budget, int32_t* sym, float* pd, uint32_t* flags,
                          int64_t* counters, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Hybrid SD / K-best on the complex-symbol tree (Sec. VI with the tree of
+ * Sec. III-B: one complex symbol, |Omega| = pam^2 children, per node).  The
+ * rounds, arguments, outputs and error behaviour are those of
+ * sd_hybrid_detect, with one step fixing the real and imaginary levels
+ * 2m + 1, 2m of complex symbol m together: the master expands a node into
+ * pam^2 children (pd plus the two squared distances, upper level first),
+ * pool depths and worker steps are complex levels, a worker keeps
+ * k_sched[2m] (the step's lower real level) or k_worker survivors of its
+ * k_worker * pam^2 candidates, ordered by (pd, parent rank, child index
+ * c = ih * pam + il, ih the real part's PAM index).  counters[1] counts
+ * real-level evaluations: 2 pam^2 per expansion.
+ * Limits: 0 <= n_workers <= MIMO_MAX_WORKERS, 1 <= k_worker <= 64,
+ * k_worker * pam^2 <= MIMO_HYB_MAX_CAND_CPLX (256).
+ * ------------------------------------------------------------------- */
+int32_t sd_hybrid_detect_complex(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam,
+                                 const float* radius2, int32_t n_workers, int32_t k_worker,
+                                 const int32_t* k_sched, int32_t k_sched_stride, int32_t master_off,
+                                 int64_t node_budget, int32_t* sym, float* pd, uint32_t* flags,
+                                 int64_t* counters, void* stream);
 
 /* ---------------------------------------------------------------------
  * Exact sphere decoding with the frame's tree spread over the wavefronts

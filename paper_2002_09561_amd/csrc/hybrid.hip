@@ -53,13 +53,14 @@ __device__ inline void wave_sync()
 }
 
 struct HybLayout {
-    int nw, stride, nd;  // words per path, padded stride, depths (n + 1)
+    int nw, stride, nd;  // words per path, padded stride, depths (steps of J levels: n / J + 1)
     size_t o_mpath, o_bpath, o_ppd, o_pc, o_lo, o_hi, o_mask, o_wst, o_wpath, o_wpd, o_sel, o_cand, o_sc, total;
-    __host__ __device__ HybLayout(int n, int W, int Kw, int P)
+    // P: children per step (pam^J)
+    __host__ __device__ HybLayout(int n, int W, int Kw, int P, int J = 1)
     {
         nw = (n + 3) / 4;
         stride = nw + 1;
-        nd = n + 1;
+        nd = n / J + 1;
         const int Wc = W > 0 ? W : 1;
         size_t o = 0;
         o_mpath = o; o += 4 * nw;
@@ -82,9 +83,220 @@ struct HybLayout {
 // scalar slots (int32 unless noted)
 enum { SC_R2 = 0, SC_FOUND, SC_PSIZE, SC_DONE, SC_FLAGS, SC_EXP_LO, SC_EXP_HI, SC_ROUNDS, SC_STALE, SC_WEXP };
 
+__device__ inline int get_byte(const uint32_t* p, int j) { return (int)((p[j >> 2] >> (8 * (j & 3))) & 0xffu); }
+
+__device__ inline uint32_t put_byte(uint32_t v, int lev, int c)
+{
+    const int sh = 8 * (lev & 3);
+    return (v & ~(0xffu << sh)) | ((uint32_t)c << sh);
+}
+
+// the two digits of complex child c (real part, level lev + 1, most
+// significant) into the bytes of the even level lev and lev + 1 of one word
 template <int P>
+__device__ inline uint32_t put_pair(uint32_t v, int lev, int c)
+{
+    const int sh = 8 * (lev & 3);
+    return (v & ~(0xffffu << sh)) | ((uint32_t)(c % P) << sh) | ((uint32_t)(c / P) << (sh + 8));
+}
+
+// Master expansion of a node at step depth d (child c of its parent step)
+// on the complex-level tree: the children fix levels kh = lev - 1 and
+// kl = lev - 2 at once.  Both centres come from the levels above kh
+// (R[kl][kh] is the structural zero of the interleaved model); child
+// (ih, il) has pd + e_h^2 + e_l^2 (Eq. (inc) twice, the upper level first).
+// The children inside the radius are ranked by (pd, index) with one in-wave
+// sort and stored at depth d + 1, or the best leaf is offered.
+template <int P>
+__device__ void master_expand_pair(int n, const float* Rf, const float* zf, float cs, float r2r, int d, int c, float pd,
+                                   uint32_t* mpath, float* ppd, int* pc, int* plo, int* phi, uint32_t* pmask, int* sc,
+                                   float* cpd, int* cinfo, int* cok, int lane)
+{
+    constexpr int PC = P * P;
+    const int lev = n - 2 * d;  // lowest level of the node's own step (n for the root)
+    const int kh = lev - 1, kl = lev - 2;
+    const float* rh = Rf + r_row_off(n, kh);
+    const float* rl = Rf + r_row_off(n, kl);
+    float ah = 0.f, al = 0.f, sh = 0.f, sl = 0.f;
+    for (int j = lev + lane; j < n; j += WAVE) {
+        const int sym = j == lev ? c % P : (j == lev + 1 ? c / P : get_byte(mpath, j));
+        const float xh = cs * rh[j - kh], xl = cs * rl[j - kl];
+        ah = fmaf(xh, (float)sym, ah);
+        al = fmaf(xl, (float)sym, al);
+        sh += xh;
+        sl += xl;
+    }
+    ah = wave_sum(ah);
+    al = wave_sum(al);
+    sh = wave_sum(sh);
+    sl = wave_sum(sl);
+    const float bh = zf[kh] - (2.f * ah - (float)(P - 1) * sh);
+    const float bl = zf[kl] - (2.f * al - (float)(P - 1) * sl);
+    const float dh = cs * rh[0], dl = cs * rl[0];
+    if (!__builtin_isfinite(bh) || !__builtin_isfinite(bl) || !__builtin_isfinite(dh) || !__builtin_isfinite(dl)) {
+        if (lane == 0) {  // uniform: NaN or inf in R or z
+            sc[SC_DONE] = 1;
+            sc[SC_FLAGS] |= MIMO_FLAG_NONFINITE_INPUT;
+        }
+        return;
+    }
+    uint64_t key[1] = {~0ull};
+    if (lane < PC) {
+        const float eh = fmaf(-dh, (float)(2 * (lane / P) - (P - 1)), bh);
+        const float el = fmaf(-dl, (float)(2 * (lane % P) - (P - 1)), bl);
+        const float pdc = fmaf(el, el, fmaf(eh, eh, pd));
+        if (pdc < r2r) key[0] = ((uint64_t)__float_as_uint(pdc) << 32) | (uint32_t)lane;
+    }
+    bitonic_sort<1>(key, lane);
+    const int nk = __popcll(__ballot(key[0] != ~0ull));
+    const float kpd = __uint_as_float((uint32_t)(key[0] >> 32));
+    const int kc = (int)(uint32_t)key[0];
+    if (kl == 0) {
+        if (lane == 0 && nk > 0) {
+            cpd[0] = kpd;
+            cinfo[0] = kc;
+            cok[0] = 1;
+        }
+    } else if (nk > 0) {
+        const int dn = d + 1;
+        if (lane < nk) {
+            ppd[dn * PC + lane] = kpd;
+            pc[dn * PC + lane] = kc;
+        }
+        if (lane == 0) {
+            plo[dn] = 0;
+            phi[dn] = nk;
+            pmask[dn >> 5] |= 1u << (dn & 31);
+            sc[SC_PSIZE] += nk;
+        }
+    }
+    if (lane == 0) {
+        if (d > 0) mpath[lev >> 2] = put_pair<P>(mpath[lev >> 2], lev, c);  // the popped node joins the path
+        uint32_t lo = (uint32_t)sc[SC_EXP_LO] + 1u;
+        if (lo == 0u) sc[SC_EXP_HI] += 1;
+        sc[SC_EXP_LO] = (int)lo;
+    }
+}
+
+// One K-best step of a worker on the complex-level tree: each survivor s is
+// given 64 / 2^ceil(log2 cnt) lanes for its two dot products; candidate
+// m = s P^2 + c (c = ih P + il) sits at sort position m of 64 E keys
+// ordered by (pd bits, m), i.e. (pd, parent rank, child) as in the oracle.
+template <int P, int E>
+__device__ void worker_step_pair(int n, const float* Rf, const float* zf, float cs, float r2r, const int32_t* ks,
+                                 int Kw, int w, int depth, int cnt, int buf, int* st, uint32_t* wp, float* wq, int* sel,
+                                 int nw, int stride, int* sc, float* cpd, int* cinfo, int* cok, int lane)
+{
+    constexpr int PC = P * P;
+    const int kh = n - 2 * depth - 1, kl = kh - 1;
+    const uint32_t* pcur = wp + buf * Kw * stride;
+    uint32_t* pnxt = wp + (buf ^ 1) * Kw * stride;
+    const float* scur = wq + buf * Kw;
+    float* snxt = wq + (buf ^ 1) * Kw;
+    int Kt = ks ? ks[kl] : Kw;  // K_t of the step's lower level
+    Kt = Kt > Kw ? Kw : (Kt < 1 ? 1 : Kt);
+    const float* rh = Rf + r_row_off(n, kh);
+    const float* rl = Rf + r_row_off(n, kl);
+    float sh = 0.f, sl = 0.f;
+    for (int j = kh + 1 + lane; j < n; j += WAVE) {
+        sh += cs * rh[j - kh];
+        sl += cs * rl[j - kl];
+    }
+    sh = wave_sum(sh);
+    sl = wave_sum(sl);
+    const int lg = 6 - (cnt <= 1 ? 0 : 32 - __clz(cnt - 1));  // log2 of the lanes per survivor
+    const int G = 1 << lg, s = lane >> lg, g = lane & (G - 1);
+    float ah = 0.f, al = 0.f;
+    if (s < cnt) {
+        const uint32_t* prow = pcur + s * stride;
+        for (int wd = (kh + 1) / 4 + g; wd < nw; wd += G) {
+            const uint32_t dw = prow[wd];
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) {
+                const int j = 4 * wd + bb;
+                if (j > kh && j < n) {
+                    const float v = (float)((dw >> (8 * bb)) & 0xffu);
+                    ah = fmaf(cs * rh[j - kh], v, ah);
+                    al = fmaf(cs * rl[j - kl], v, al);
+                }
+            }
+        }
+    }
+    for (int m = 1; m < G; m <<= 1) {
+        ah += shfl_xor_f(ah, m);
+        al += shfl_xor_f(al, m);
+    }
+    const float bh = zf[kh] - (2.f * ah - (float)(P - 1) * sh);
+    const float bl = zf[kl] - (2.f * al - (float)(P - 1) * sl);
+    const float dh = cs * rh[0], dl = cs * rl[0];
+    // a NaN or infinity in R or z: the frame's search stops after this round
+    const bool bad = __ballot(!__builtin_isfinite(dh) || !__builtin_isfinite(dl) ||
+                              (s < cnt && (!__builtin_isfinite(bh) || !__builtin_isfinite(bl)))) != 0;
+    if (bad && lane == 0) {
+        sc[SC_DONE] = 1;
+        atomicOr(reinterpret_cast<unsigned int*>(&sc[SC_FLAGS]), MIMO_FLAG_NONFINITE_INPUT);
+    }
+    uint64_t key[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int m = e * WAVE + lane, sm = m / PC, cc = m % PC;
+        const int src = (sm < cnt ? sm : 0) << lg;
+        const float bhs = shfl_f(bh, src), bls = shfl_f(bl, src);
+        key[e] = ~0ull;
+        if (sm < cnt && !bad) {
+            const float eh = fmaf(-dh, (float)(2 * (cc / P) - (P - 1)), bhs);
+            const float el = fmaf(-dl, (float)(2 * (cc % P) - (P - 1)), bls);
+            const float pdc = fmaf(el, el, fmaf(eh, eh, scur[sm]));
+            if (pdc < r2r) key[e] = ((uint64_t)__float_as_uint(pdc) << 32) | (uint32_t)m;
+        }
+    }
+    bitonic_sort<E>(key, lane);
+    int nvalid = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) nvalid += __popcll(__ballot(key[e] != ~0ull));
+    if (lane == 0) atomicAdd(&sc[SC_WEXP], cnt);
+    if (nvalid == 0) {
+        if (lane == 0) st[0] = 0;
+        return;
+    }
+    const int keep = Kt < nvalid ? Kt : nvalid;  // <= Kw <= 64: the first 64 sort positions
+    if (lane < keep) {
+        snxt[lane] = __uint_as_float((uint32_t)(key[0] >> 32));
+        sel[lane] = (int)(uint32_t)key[0];
+    }
+    wave_sync();
+    const int w0 = kl / 4;
+    for (int i = 0; i < keep; ++i) {
+        const int m = sel[i];
+        const uint32_t* src = pcur + (m / PC) * stride;
+        uint32_t* dst = pnxt + i * stride;
+        for (int wd = w0 + lane; wd < nw; wd += WAVE) {
+            uint32_t v = src[wd];
+            if (wd == w0) v = put_pair<P>(v, kl, m % PC);
+            dst[wd] = v;
+        }
+    }
+    if (lane == 0) {
+        st[2] = keep;
+        st[3] = buf ^ 1;
+        st[1] = depth + 1;
+        if (kl == 0) {  // leaves: offer the best survivor
+            cpd[1 + w] = snxt[0];
+            cinfo[1 + w] = buf ^ 1;
+            cok[1 + w] = 1;
+            st[0] = 0;
+        }
+    }
+}
+
+// P: PAM points per real level; J: real levels per step (2: one complex
+// symbol, P^2 children; the levels 2m+1, 2m of a step have the structural
+// zero R[2m][2m+1] of the interleaved model, so both centres come from the
+// levels above the step).  Pool depths count steps.
+template <int P, int J, int E>
 __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
 {
+    constexpr int PC = J == 1 ? P : P * P;  // children per step
     extern __shared__ unsigned char smem_hy[];
     const int frame = blockIdx.x;
     if (a.rerun) {  // uniform over the workgroup
@@ -93,7 +305,7 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
     }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int n = a.n, W = a.W, Kw = a.Kw;
-    const HybLayout Lo(n, W, Kw, P);
+    const HybLayout Lo(n, W, Kw, PC, J);
     const int nw = Lo.nw, stride = Lo.stride;
     uint32_t* mpath = reinterpret_cast<uint32_t*>(smem_hy + Lo.o_mpath);
     uint32_t* bpath = reinterpret_cast<uint32_t*>(smem_hy + Lo.o_bpath);
@@ -194,14 +406,14 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                     const int i = plo[dd]++;
                     if (plo[dd] == phi[dd]) pmask[dd >> 5] &= ~(1u << (dd & 31));
                     sc[SC_PSIZE] -= 1;
-                    const float v = ppd[dd * P + i];
+                    const float v = ppd[dd * PC + i];
                     if (v >= r2r) {
                         ++stale;
                         continue;
                     }
                     ok = 1;
                     d = dd;
-                    c = pc[dd * P + i];
+                    c = pc[dd * PC + i];
                     pd = v;
                     break;
                 }
@@ -213,6 +425,10 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                 c = __shfl(c, 0, WAVE);
                 pd = __shfl(pd, 0, WAVE);
             }
+            if constexpr (J == 2) {
+                if (ok) master_expand_pair<P>(n, Rf, zf, cs, r2r, d, c, pd, mpath, ppd, pc, plo, phi, pmask, sc, cpd,
+                                              cinfo, cok, lane);
+            } else {
             const int lev = n - d;  // level of the node's own symbol (n for the root)
             const int k = lev - 1;  // level its children fix
             float b = 0.f, rkk = 0.f;
@@ -282,6 +498,7 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                     sc[SC_EXP_LO] = (int)lo;
                 }
             }
+            }
         }
         __syncthreads();
 
@@ -301,7 +518,7 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                     const int i = --phi[dd];
                     if (plo[dd] == phi[dd]) pmask[dd >> 5] &= ~(1u << (dd & 31));
                     sc[SC_PSIZE] -= 1;
-                    const float v = ppd[dd * P + i];
+                    const float v = ppd[dd * PC + i];
                     if (v >= r2r) {
                         ++stale;
                         continue;
@@ -309,7 +526,7 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                     st[0] = 1;
                     st[4] = 1;
                     st[5] = dd;
-                    st[6] = pc[dd * P + i];
+                    st[6] = pc[dd * PC + i];
                     reinterpret_cast<float*>(st)[7] = v;
                     break;
                 }
@@ -326,14 +543,14 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                 uint32_t* wp = wpath + (size_t)w * 2 * Kw * stride;
                 float* wq = wpd + (size_t)w * 2 * Kw;
                 int* sel = wsel + (size_t)w * Kw;
-                if (st[4]) {  // new node: survivor 0 = master prefix + its symbol
-                    const int d = st[5], lev = n - d;
+                if (st[4]) {  // new node: survivor 0 = master prefix + its symbol(s)
+                    const int d = st[5], lev = n - d * J;
                     uint32_t* dst = wp;  // buffer 0, survivor 0
                     for (int i = lane; i < nw; i += WAVE) {
                         uint32_t v = mpath[i];
-                        if (d > 0 && i == (lev >> 2)) {
-                            const int sh = 8 * (lev & 3);
-                            v = (v & ~(0xffu << sh)) | ((uint32_t)st[6] << sh);
+                        if (d > 0 && i == (lev >> 2)) {  // J = 2: lev is even, lev + 1 in the same word
+                            if constexpr (J == 2) v = put_pair<P>(v, lev, st[6]);
+                            else v = put_byte(v, lev, st[6]);
                         }
                         dst[i] = v;
                     }
@@ -347,6 +564,10 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                     wave_sync();
                 }
                 const int depth = st[1], cnt = st[2], buf = st[3];
+                if constexpr (J == 2) {
+                    worker_step_pair<P, E>(n, Rf, zf, cs, r2r, ks, Kw, w, depth, cnt, buf, st, wp, wq, sel, nw, stride,
+                                           sc, cpd, cinfo, cok, lane);
+                } else {
                 const int k = n - depth - 1;
                 uint32_t* pcur = wp + buf * Kw * stride;
                 uint32_t* pnxt = wp + (buf ^ 1) * Kw * stride;
@@ -426,6 +647,7 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                         }
                     }
                 }
+                }
             }
         }
         __syncthreads();
@@ -440,9 +662,10 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
             if (best >= 0 && cpd[best] < *sc_r2) {
                 *sc_r2 = cpd[best];
                 sc[SC_FOUND] = 1;
-                if (best == 0) {
+                if (best == 0) {  // the master's leaf: its path plus the child's digit(s) at the bottom
                     for (int i = 0; i < nw; ++i) bpath[i] = mpath[i];
-                    bpath[0] = (bpath[0] & ~0xffu) | (uint32_t)cinfo[0];
+                    if constexpr (J == 2) bpath[0] = put_pair<P>(bpath[0], 0, cinfo[0]);
+                    else bpath[0] = put_byte(bpath[0], 0, cinfo[0]);
                 } else {
                     const int w = best - 1;
                     const uint32_t* src = wpath + ((size_t)w * 2 + cinfo[best]) * Kw * stride;
@@ -477,12 +700,12 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
             int64_t* c = a.counters + (size_t)frame * 4;
             if (a.rerun) {
                 c[0] += e;
-                c[1] += e * P;
+                c[1] += e * PC * J;
                 c[2] += sc[SC_ROUNDS];
                 c[3] += sc[SC_STALE];
             } else {
                 c[0] = e;
-                c[1] = e * P;
+                c[1] = e * PC * J;
                 c[2] = sc[SC_ROUNDS];
                 c[3] = sc[SC_STALE];
             }
@@ -501,21 +724,84 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
     }
 }
 
-template <int P>
-static int32_t launch_hybrid(const HybArgs& a, int B, hipStream_t st)
+template <int P, int J, int E>
+static int32_t launch_hybrid(const HybArgs& a, int B, hipStream_t st, const char* name)
 {
-    const HybLayout Lo(a.n, a.W, a.Kw, P);
+    constexpr int PC = J == 1 ? P : P * P;
+    const HybLayout Lo(a.n, a.W, a.Kw, PC, J);
     if (Lo.total > 160 * 1024)
-        return fail(MIMO_ERR_UNSUPPORTED, "sd_hybrid_detect: %zu bytes of LDS needed (n_workers * k_worker too large)",
+        return fail(MIMO_ERR_UNSUPPORTED, "%s: %zu bytes of LDS needed (n_workers * k_worker too large)", name,
                     Lo.total);
     if (Lo.total > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)hybrid_kernel<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)Lo.total);
-        if (e != hipSuccess) return fail(MIMO_ERR_HIP, "sd_hybrid_detect: LDS attribute: %s", hipGetErrorString(e));
+        hipError_t e = hipFuncSetAttribute((const void*)hybrid_kernel<P, J, E>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lo.total);
+        if (e != hipSuccess) return fail(MIMO_ERR_HIP, "%s: LDS attribute: %s", name, hipGetErrorString(e));
     }
     const int threads = WAVE * (1 + a.W);
-    hipLaunchKernelGGL(hybrid_kernel<P>, dim3(B), dim3(threads), Lo.total, st, a);
-    return check_launch("sd_hybrid_detect");
+    hipLaunchKernelGGL((hybrid_kernel<P, J, E>), dim3(B), dim3(threads), Lo.total, st, a);
+    return check_launch(name);
+}
+
+template <int J>
+static int32_t launch_hybrid_pam(const HybArgs& a, int pam, int B, hipStream_t st, const char* name)
+{
+    if constexpr (J == 1) {
+        switch (pam) {
+        case 2: return launch_hybrid<2, 1, 1>(a, B, st, name);
+        case 4: return launch_hybrid<4, 1, 1>(a, B, st, name);
+        default: return launch_hybrid<8, 1, 1>(a, B, st, name);
+        }
+    } else {  // 64 E sort keys for the k_worker * pam^2 candidates of a worker step
+        const int cand = a.Kw * pam * pam;
+        const int E = cand <= 64 ? 1 : (cand <= 128 ? 2 : 4);
+        switch (pam * 4 + E) {
+        case 9: return launch_hybrid<2, 2, 1>(a, B, st, name);
+        case 10: return launch_hybrid<2, 2, 2>(a, B, st, name);
+        case 12: return launch_hybrid<2, 2, 4>(a, B, st, name);
+        case 17: return launch_hybrid<4, 2, 1>(a, B, st, name);
+        case 18: return launch_hybrid<4, 2, 2>(a, B, st, name);
+        case 20: return launch_hybrid<4, 2, 4>(a, B, st, name);
+        case 33: return launch_hybrid<8, 2, 1>(a, B, st, name);
+        case 34: return launch_hybrid<8, 2, 2>(a, B, st, name);
+        default: return launch_hybrid<8, 2, 4>(a, B, st, name);
+        }
+    }
+}
+
+template <int J>
+static int32_t hybrid_entry(const char* name, const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam,
+                            const float* radius2, int32_t n_workers, int32_t k_worker, const int32_t* k_sched,
+                            int32_t k_sched_stride, int32_t master_off, int64_t node_budget, int32_t* sym, float* pd,
+                            uint32_t* flags, int64_t* counters, void* stream)
+{
+    if (B < 0) return fail(MIMO_ERR_INVALID_ARG, "%s: B < 0", name);
+    if (pam != 2 && pam != 4 && pam != 8) return fail(MIMO_ERR_INVALID_ARG, "%s: pam must be 2, 4 or 8", name);
+    if (n_tx < 1) return fail(MIMO_ERR_INVALID_ARG, "%s: n_tx < 1", name);
+    if (n_tx > MIMO_MAX_TX) return fail(MIMO_ERR_UNSUPPORTED, "%s: n_tx > %d", name, MIMO_MAX_TX);
+    if (n_workers < 0 || n_workers > MIMO_MAX_WORKERS)
+        return fail(MIMO_ERR_INVALID_ARG, "%s: 0 <= n_workers <= %d", name, MIMO_MAX_WORKERS);
+    if (J == 1 && (k_worker < 1 || k_worker * pam > MIMO_HYB_MAX_CAND))
+        return fail(MIMO_ERR_INVALID_ARG, "%s: need k_worker >= 1 and k_worker * pam <= %d", name,
+                    MIMO_HYB_MAX_CAND);
+    if (J == 2 && (k_worker < 1 || k_worker > 64 || k_worker * pam * pam > MIMO_HYB_MAX_CAND_CPLX))
+        return fail(MIMO_ERR_INVALID_ARG, "%s: need 1 <= k_worker <= 64 and k_worker * pam^2 <= %d", name,
+                    MIMO_HYB_MAX_CAND_CPLX);
+    if (master_off && n_workers < 1) return fail(MIMO_ERR_INVALID_ARG, "%s: master_off needs a worker", name);
+    if (node_budget < 0) return fail(MIMO_ERR_INVALID_ARG, "%s: node_budget < 0", name);
+    const int n = 2 * n_tx;
+    if (k_sched && k_sched_stride != 0 && k_sched_stride != n)
+        return fail(MIMO_ERR_INVALID_ARG, "%s: k_sched_stride must be 0 or n = %d", name, n);
+    if (B == 0) return MIMO_OK;
+    if (!R || !z || !sym || !pd || !flags) return fail(MIMO_ERR_INVALID_ARG, "%s: null pointer", name);
+    HybArgs a{R, z, n, n_workers, k_worker, k_sched, k_sched_stride, radius2, master_off, node_budget,
+              sym, pd, flags, counters, 0};
+    hipStream_t st = (hipStream_t)stream;
+    const int32_t rc = launch_hybrid_pam<J>(a, pam, B, st, name);
+    if (rc || !radius2) return rc;
+    // frames whose finite radius left no leaf: again with r2 = +inf
+    a.radius2 = nullptr;
+    a.rerun = 1;
+    return launch_hybrid_pam<J>(a, pam, B, st, name);
 }
 
 }  // namespace mimo
@@ -526,39 +812,16 @@ extern "C" int32_t sd_hybrid_detect(const float* R, const float* z, int32_t B, i
                                     int64_t node_budget, int32_t* sym, float* pd, uint32_t* flags,
                                     int64_t* counters, void* stream)
 {
-    using namespace mimo;
-    if (B < 0) return fail(MIMO_ERR_INVALID_ARG, "sd_hybrid_detect: B < 0");
-    if (pam != 2 && pam != 4 && pam != 8) return fail(MIMO_ERR_INVALID_ARG, "sd_hybrid_detect: pam must be 2, 4 or 8");
-    if (n_tx < 1) return fail(MIMO_ERR_INVALID_ARG, "sd_hybrid_detect: n_tx < 1");
-    if (n_tx > MIMO_MAX_TX) return fail(MIMO_ERR_UNSUPPORTED, "sd_hybrid_detect: n_tx > %d", MIMO_MAX_TX);
-    if (n_workers < 0 || n_workers > MIMO_MAX_WORKERS)
-        return fail(MIMO_ERR_INVALID_ARG, "sd_hybrid_detect: 0 <= n_workers <= %d", MIMO_MAX_WORKERS);
-    if (k_worker < 1 || k_worker * pam > MIMO_HYB_MAX_CAND)
-        return fail(MIMO_ERR_INVALID_ARG, "sd_hybrid_detect: need k_worker >= 1 and k_worker * pam <= %d",
-                    MIMO_HYB_MAX_CAND);
-    if (master_off && n_workers < 1) return fail(MIMO_ERR_INVALID_ARG, "sd_hybrid_detect: master_off needs a worker");
-    if (node_budget < 0) return fail(MIMO_ERR_INVALID_ARG, "sd_hybrid_detect: node_budget < 0");
-    const int n = 2 * n_tx;
-    if (k_sched && k_sched_stride != 0 && k_sched_stride != n)
-        return fail(MIMO_ERR_INVALID_ARG, "sd_hybrid_detect: k_sched_stride must be 0 or n = %d", n);
-    if (B == 0) return MIMO_OK;
-    if (!R || !z || !sym || !pd || !flags) return fail(MIMO_ERR_INVALID_ARG, "sd_hybrid_detect: null pointer");
-    HybArgs a{R, z, n, n_workers, k_worker, k_sched, k_sched_stride, radius2, master_off, node_budget,
-              sym, pd, flags, counters, 0};
-    hipStream_t st = (hipStream_t)stream;
-    int32_t rc;
-    switch (pam) {
-    case 2: rc = launch_hybrid<2>(a, B, st); break;
-    case 4: rc = launch_hybrid<4>(a, B, st); break;
-    default: rc = launch_hybrid<8>(a, B, st); break;
-    }
-    if (rc || !radius2) return rc;
-    // frames whose finite radius left no leaf: again with r2 = +inf
-    a.radius2 = nullptr;
-    a.rerun = 1;
-    switch (pam) {
-    case 2: return launch_hybrid<2>(a, B, st);
-    case 4: return launch_hybrid<4>(a, B, st);
-    default: return launch_hybrid<8>(a, B, st);
-    }
+    return mimo::hybrid_entry<1>("sd_hybrid_detect", R, z, B, n_tx, pam, radius2, n_workers, k_worker, k_sched,
+                                 k_sched_stride, master_off, node_budget, sym, pd, flags, counters, stream);
+}
+
+extern "C" int32_t sd_hybrid_detect_complex(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam,
+                                            const float* radius2, int32_t n_workers, int32_t k_worker,
+                                            const int32_t* k_sched, int32_t k_sched_stride, int32_t master_off,
+                                            int64_t node_budget, int32_t* sym, float* pd, uint32_t* flags,
+                                            int64_t* counters, void* stream)
+{
+    return mimo::hybrid_entry<2>("sd_hybrid_detect_complex", R, z, B, n_tx, pam, radius2, n_workers, k_worker,
+                                 k_sched, k_sched_stride, master_off, node_budget, sym, pd, flags, counters, stream);
 }

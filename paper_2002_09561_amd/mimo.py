@@ -42,6 +42,8 @@ SIGNATURES = {
     "kbest_fallback": ([_P, _P, _I32, _I32, _I32, _I32, _P, _F, _P, _P, _P, _P, _P], _I32),
     "sd_hybrid_detect": ([_P, _P, _I32, _I32, _I32, _P, _I32, _I32, _P, _I32, _I32, _I64, _P, _P, _P, _P,
                           _P], _I32),
+    "sd_hybrid_detect_complex": ([_P, _P, _I32, _I32, _I32, _P, _I32, _I32, _P, _I32, _I32, _I64, _P, _P, _P, _P,
+                          _P], _I32),
     "sd_parallel_detect": ([_P, _P, _I32, _I32, _I32, _P, _I64, _I32, _P, _P, _P, _P, _P], _I32),
     "mimo_metric": ([_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P], _I32),
     "mimo_error_count": ([_P, _P, _I32, _I32, _I32, _P, _P], _I32),
@@ -269,16 +271,20 @@ def kbest_rank_labels(R, z, n_tx: int, pam: int, K: int, force_sym, stream=None)
 
 
 def sd_hybrid_detect(R, z, n_tx: int, pam: int, n_workers: int, k_worker: int, radius2=None, k_sched=None,
-                     master_off=False, node_budget: int = 0, want_counters=False, out=None, stream=None):
+                     master_off=False, node_budget: int = 0, want_counters=False, out=None, stream=None,
+                     complex_levels=False):
+    """Hybrid SD / K-best.  complex_levels=True runs sd_hybrid_detect_complex:
+    one complex symbol (pam^2 children) per tree step."""
     B = z.shape[0]
     n = 2 * n_tx
     sym, pd, flags, ctr = out if out is not None else _det_outputs(B, n_tx, z.device, want_counters)
     ks, stride = _sched(k_sched, n)
-    _check(load().sd_hybrid_detect(_ptr(R, torch.float32, "R"), _ptr(z, torch.float32, "z"), B, n_tx, pam,
-                                   _ptr(radius2, torch.float32, "radius2"), n_workers, k_worker,
-                                   _ptr(ks, torch.int32, "k_sched"), stride, int(bool(master_off)),
-                                   int(node_budget), _ptr(sym), _ptr(pd), _ptr(flags), _ptr(ctr),
-                                   _stream(stream)))
+    fn = load().sd_hybrid_detect_complex if complex_levels else load().sd_hybrid_detect
+    _check(fn(_ptr(R, torch.float32, "R"), _ptr(z, torch.float32, "z"), B, n_tx, pam,
+              _ptr(radius2, torch.float32, "radius2"), n_workers, k_worker,
+              _ptr(ks, torch.int32, "k_sched"), stride, int(bool(master_off)),
+              int(node_budget), _ptr(sym), _ptr(pd), _ptr(flags), _ptr(ctr),
+              _stream(stream)))
     return (sym, pd, flags, ctr) if want_counters else (sym, pd, flags)
 
 

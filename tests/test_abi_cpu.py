@@ -146,6 +146,19 @@ def test_grouped_kbest_host_checks(lib):
     assert g(P, P, 2, 8, 8, 16, 2, P, 0, P, P, P, P, P, P) == -1        # null pointers
 
 
+def test_complex_hybrid_host_checks(lib):
+    P = None
+    g = lib.sd_hybrid_detect_complex
+    assert g(P, P, 1, 4, 8, P, 2, 5, P, 0, 0, 0, P, P, P, P, P) == -1      # 5 * 64 candidates > 256
+    assert "pam^2" in _err(lib)
+    assert g(P, P, 1, 4, 2, P, 2, 65, P, 0, 0, 0, P, P, P, P, P) == -1     # k_worker > 64
+    assert g(P, P, 1, 4, 4, P, 16, 1, P, 0, 0, 0, P, P, P, P, P) == -1     # n_workers > 15
+    assert g(P, P, 1, 4, 4, P, 0, 1, P, 0, 1, 0, P, P, P, P, P) == -1      # master_off without a worker
+    assert g(P, P, 1, 4, 4, P, 1, 1, ctypes.c_void_p(1), 3, 0, 0, P, P, P, P, P) == -1  # schedule stride
+    assert g(P, P, 0, 4, 8, P, 2, 4, P, 0, 0, 0, P, P, P, P, P) == 0       # empty batch (4 * 64 allowed)
+    assert g(P, P, 2, 4, 8, P, 2, 4, P, 0, 0, 0, P, P, P, P, P) == -1      # null pointers
+
+
 def test_parallel_sd_host_checks(lib):
     P = None
     g = lib.sd_parallel_detect

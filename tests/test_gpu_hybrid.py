@@ -24,7 +24,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _run(gpu, orc, N, M, q, snr, B, W, Kw, seed, master_off=False, budget=0, sched=None, radius=None,
-         frames=None):
+         frames=None, J=1):
     import torch
 
     f = frames if frames is not None else gen_frames(N, M, q, snr, B, seed=seed)
@@ -34,13 +34,14 @@ def _run(gpu, orc, N, M, q, snr, B, W, Kw, seed, master_off=False, budget=0, sch
     R, z = gpu.qr_preprocess(H, y)
     ks = None if sched is None else torch.from_numpy(sched.astype(np.int32)).cuda()
     r2 = None if radius is None else torch.from_numpy(radius.astype(np.float32)).cuda()
-    print(f"hybrid {M}x{M} {q}-QAM {snr} dB B={len(f)} W={W} Kw={Kw} off={master_off} budget={budget}", flush=True)
+    print(f"hybrid J={J} {M}x{M} {q}-QAM {snr} dB B={len(f)} W={W} Kw={Kw} off={master_off} budget={budget}",
+          flush=True)
     sym, pd, flags, ctr = gpu.sd_hybrid_detect(R, z, M, P, W, Kw, radius2=r2, k_sched=ks, master_off=master_off,
-                                               node_budget=budget, want_counters=True)
+                                               node_budget=budget, want_counters=True, complex_levels=J == 2)
     torch.cuda.synchronize()
     Ro, zo, _ = orc.qr(f.H, f.y)
     r2o = math.inf if radius is None else radius.astype(np.float32).astype(np.float64)
-    out = orc.hybrid(Ro, zo, P, W, Kw, r2=r2o, k_sched=sched, master_off=master_off, budget=budget)
+    out = orc.hybrid(Ro, zo, P, W, Kw, r2=r2o, k_sched=sched, master_off=master_off, budget=budget, J=J)
     out["R"], out["z"] = Ro, zo
     return f, P, out, sym.cpu().numpy(), pd.cpu().numpy(), flags.cpu().numpy(), ctr.cpu().numpy()
 
@@ -137,6 +138,90 @@ def test_hybrid_radius_and_empty_sphere(gpu, orc):
     f, P, out, sym, pd, flags, ctr = _run(gpu, orc, M, M, 16, 10.0, B, 2, 2, seed=3500, radius=radius, frames=f)
     assert np.any(out["flags"] & 2) and np.all(out["flags"] & 1) and np.all(flags & 1)
     _check(f, P, out, sym, pd, flags, ctr, "radius")
+
+
+# ----------------------------------------------------------------- complex-symbol tree (one complex level per step)
+@pytest.mark.parametrize("M,q,snr,B", [(4, 16, 8.0, 200), (6, 64, 16.0, 100), (8, 4, 4.0, 150), (2, 64, 10.0, 200)])
+def test_hybrid_complex_exact_sd_parity(gpu, orc, M, q, snr, B):
+    """n_workers = 0 on the complex-symbol tree: the exact Best-FS SD with
+    |Omega| children per node; same ML points, and the oracle's counters
+    (2 |Omega| real-level evaluations per expansion) on frames without ties."""
+    f, P, out, sym, pd, flags, ctr = _run(gpu, orc, M, M, q, snr, B, 0, 1, seed=3600 + M, J=2)
+    check_ml(orc, f"complex SD {M}x{M}", P, sym, out, f.H, f.y, q)
+    assert np.all(flags & 8)
+    clean = out["margin"][:, 0] > near_tie_tol(_eps(out, P, sym, pd))
+    assert np.array_equal(ctr[clean], out["counters"][clean])
+    assert np.all(ctr[:, 1] == ctr[:, 0] * 2 * q)
+    if M <= 4:
+        sb, _ = orc.brute_force(f.H, f.y, q)
+        check_ml(orc, "complex SD vs brute force", P, sym, {"x": orc_x(sb, P)}, f.H, f.y, q)
+
+
+@pytest.mark.parametrize("q,W,Kw", [(16, 1, 1), (16, 3, 2), (16, 15, 4), (16, 5, 16), (64, 15, 1), (64, 4, 2),
+                                    (64, 2, 4), (4, 3, 64), (4, 7, 24)])
+def test_hybrid_complex_parity(gpu, orc, q, W, Kw):
+    """Workers on the complex-symbol tree, k_worker * |Omega| from 16 to 256
+    candidates per step (one to four sort registers per lane)."""
+    M = 8 if q == 64 else 10
+    f, P, out, sym, pd, flags, ctr = _run(gpu, orc, M, M, q, 12.0 if q == 16 else (18.0 if q == 64 else 5.0), 100,
+                                          W, Kw, seed=3700 + q + W, budget=200000, J=2)
+    _check(f, P, out, sym, pd, flags, ctr, f"complex hybrid {q}-QAM W={W} Kw={Kw}")
+
+
+def test_hybrid_complex_paper_shape(gpu, orc):
+    """16x16 64-QAM on the complex tree, 15 workers with 4 survivors each."""
+    f, P, out, sym, pd, flags, ctr = _run(gpu, orc, 16, 16, 64, 20.0, 48, 15, 4, seed=3800, budget=300000, J=2)
+    _check(f, P, out, sym, pd, flags, ctr, "complex hybrid 16x16 64-QAM W=15 Kw=4", max_frac=0.25)
+
+
+def test_hybrid_complex_master_off_is_kbest(gpu, orc):
+    """Master off: worker 0 runs the complex-level K-best from the root."""
+    f, P, out, sym, pd, flags, ctr = _run(gpu, orc, 12, 12, 16, 12.0, 100, 1, 16, seed=3900, master_off=True, J=2)
+    _check(f, P, out, sym, pd, flags, ctr, "complex master off")
+    kb = orc.kbest(out["R"], out["z"], P, 16, J=2)
+    check_kbest_run(orc, "complex master off vs K-best", P, 16, sym, pd, kb, out["R"], out["z"], J=2)
+    assert np.all(ctr[:, 0] == sum(min(16, 16 ** t) for t in range(12)))
+
+
+def test_hybrid_complex_schedule_budget_radius(gpu, orc):
+    """Per-frame schedules (read at the step's lower real level), a node
+    budget, and per-frame radii around the ML metric with the empty-sphere
+    re-run, on the complex tree."""
+    B, M = 80, 10
+    rng = np.random.default_rng(21)
+    sched = rng.integers(1, 5, size=(B, 2 * M)).astype(np.int32)
+    f, P, out, sym, pd, flags, ctr = _run(gpu, orc, M, M, 16, 6.0, B, 4, 4, seed=4000, sched=sched, budget=300,
+                                          J=2)
+    _check(f, P, out, sym, pd, flags, ctr, "complex budget + schedule")
+    assert np.any(flags & 4)
+    f = gen_frames(8, 8, 16, 10.0, 60, seed=4100)
+    Ro, zo, _ = orc.qr(f.H, f.y)
+    ml = orc.sesd(Ro, zo, 4)[1]
+    radius = ml * np.random.default_rng(22).uniform(0.7, 3.0, size=60)
+    f, P, out, sym, pd, flags, ctr = _run(gpu, orc, 8, 8, 16, 10.0, 60, 2, 2, seed=4100, radius=radius, frames=f,
+                                          J=2)
+    assert np.any(out["flags"] & 2) and np.all(out["flags"] & 1) and np.all(flags & 1)
+    _check(f, P, out, sym, pd, flags, ctr, "complex radius")
+
+
+def test_hybrid_complex_nonfinite(gpu, orc):
+    """A NaN in R or an infinity in z stops its frame with NONFINITE_INPUT
+    (sym 0, pd +inf) on the complex tree; the other frames are detected."""
+    import torch
+
+    M, B = 6, 6
+    f = gen_frames(M, M, 16, 12.0, B, seed=4200)
+    R, z = gpu.qr_preprocess(torch.from_numpy(f.H).cuda(), torch.from_numpy(f.y).cuda())
+    R[1, 4] = float("nan")
+    z[3, 0] = float("inf")
+    for W in (0, 3):
+        sym, pd, flags = gpu.sd_hybrid_detect(R, z, M, 4, W, 2, complex_levels=True)
+        fl, p, s = flags.cpu().numpy(), pd.cpu().numpy(), sym.cpu().numpy()
+        for b in (1, 3):
+            assert fl[b] & gpu.FLAG_NONFINITE_INPUT and not fl[b] & gpu.FLAG_FOUND
+            assert np.isinf(p[b]) and np.all(s[b] == 0)
+        for b in (0, 2, 4, 5):
+            assert fl[b] & gpu.FLAG_FOUND and np.isfinite(p[b])
 
 
 # ----------------------------------------------------------------- 100x100 64-QAM, as the benchmark runs it
