@@ -79,7 +79,7 @@ extern "C" {
 #define MIMO_MAX_K 256    /* K-best survivors: K * pam <= 1024 */
 #define MIMO_MAX_WORKERS 15
 #define MIMO_HYB_MAX_CAND 64 /* hybrid worker: k_worker * pam <= 64 */
-#define MIMO_HYB_MAX_CAND_CPLX 256 /* complex-level hybrid worker: k_worker * pam^2 <= 256 */
+#define MIMO_HYB_MAX_CAND_CPLX 512 /* complex-level hybrid worker: k_worker * pam^2 <= 512 */
 
 #define MIMO_MLP_IN 4
 #define MIMO_MLP_HIDDEN 128
@@ -158,7 +158,7 @@ int32_t kbest_detect(const float* R, const float* z, int32_t B, int32_t n_tx, in
  * counters[b][1] = real-level evaluations (2 per child).  From 512
  * candidates per level (K pam^2) or 128 real levels on, the launch is the
  * grouped kernel of kbest_detect_grouped (J = 2).
- * Limits: 1 <= K <= 64, K * pam^2 <= 1024.
+ * Limits: 1 <= K <= 64, K * pam^2 <= 2048 (K <= 32 at 64-QAM).
  * ------------------------------------------------------------------- */
 int32_t kbest_detect_complex(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam,
                              int32_t K, const int32_t* k_sched, int32_t k_sched_stride,
@@ -178,7 +178,7 @@ int32_t kbest_detect_complex(const float* R, const float* z, int32_t B, int32_t 
  * flags and the counters (counters[b][1] = J real-level evaluations per
  * child) are those of kbest_detect / kbest_detect_complex; only the order of
  * the FP32 sums in a centre differs.  Arguments and outputs as kbest_detect.
- * Limits: J in {1, 2}, 1 <= K <= 64, K * pam^J <= 1024, n_tx <= 128.
+ * Limits: J in {1, 2}, 1 <= K <= 64, K * pam^J <= 2048, n_tx <= 128.
  * ------------------------------------------------------------------- */
 int32_t kbest_detect_grouped(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam,
                              int32_t K, int32_t J, const int32_t* k_sched, int32_t k_sched_stride,
@@ -258,10 +258,11 @@ int32_t sd_hybrid_detect(const float* R, const float* z, int32_t B, int32_t n_tx
  * pool depths and worker steps are complex levels, a worker keeps
  * k_sched[2m] (the step's lower real level) or k_worker survivors of its
  * k_worker * pam^2 candidates, ordered by (pd, parent rank, child index
- * c = ih * pam + il, ih the real part's PAM index).  counters[1] counts
+ * c = ih * pam + il: ih the PAM index at level 2m + 1, the
+ * imaginary part, il the real part's).  counters[1] counts
  * real-level evaluations: 2 pam^2 per expansion.
  * Limits: 0 <= n_workers <= MIMO_MAX_WORKERS, 1 <= k_worker <= 64,
- * k_worker * pam^2 <= MIMO_HYB_MAX_CAND_CPLX (256).
+ * k_worker * pam^2 <= MIMO_HYB_MAX_CAND_CPLX (512: 8 survivors at 64-QAM).
  * ------------------------------------------------------------------- */
 int32_t sd_hybrid_detect_complex(const float* R, const float* z, int32_t B, int32_t n_tx, int32_t pam,
                                  const float* radius2, int32_t n_workers, int32_t k_worker,

@@ -91,8 +91,8 @@ __device__ inline uint32_t put_byte(uint32_t v, int lev, int c)
     return (v & ~(0xffu << sh)) | ((uint32_t)c << sh);
 }
 
-// the two digits of complex child c (real part, level lev + 1, most
-// significant) into the bytes of the even level lev and lev + 1 of one word
+// the two digits of complex child c into the bytes of the even level lev
+// (real part, c % P) and lev + 1 (imaginary part, c / P) of one word
 template <int P>
 __device__ inline uint32_t put_pair(uint32_t v, int lev, int c)
 {
@@ -753,17 +753,28 @@ static int32_t launch_hybrid_pam(const HybArgs& a, int pam, int B, hipStream_t s
         }
     } else {  // 64 E sort keys for the k_worker * pam^2 candidates of a worker step
         const int cand = a.Kw * pam * pam;
-        const int E = cand <= 64 ? 1 : (cand <= 128 ? 2 : 4);
-        switch (pam * 4 + E) {
-        case 9: return launch_hybrid<2, 2, 1>(a, B, st, name);
-        case 10: return launch_hybrid<2, 2, 2>(a, B, st, name);
-        case 12: return launch_hybrid<2, 2, 4>(a, B, st, name);
-        case 17: return launch_hybrid<4, 2, 1>(a, B, st, name);
-        case 18: return launch_hybrid<4, 2, 2>(a, B, st, name);
-        case 20: return launch_hybrid<4, 2, 4>(a, B, st, name);
-        case 33: return launch_hybrid<8, 2, 1>(a, B, st, name);
-        case 34: return launch_hybrid<8, 2, 2>(a, B, st, name);
-        default: return launch_hybrid<8, 2, 4>(a, B, st, name);
+        const int E = cand <= 64 ? 1 : (cand <= 128 ? 2 : (cand <= 256 ? 4 : 8));
+        switch (pam) {
+        case 2:  // at most 64 * 4 candidates
+            switch (E) {
+            case 1: return launch_hybrid<2, 2, 1>(a, B, st, name);
+            case 2: return launch_hybrid<2, 2, 2>(a, B, st, name);
+            default: return launch_hybrid<2, 2, 4>(a, B, st, name);
+            }
+        case 4:
+            switch (E) {
+            case 1: return launch_hybrid<4, 2, 1>(a, B, st, name);
+            case 2: return launch_hybrid<4, 2, 2>(a, B, st, name);
+            case 4: return launch_hybrid<4, 2, 4>(a, B, st, name);
+            default: return launch_hybrid<4, 2, 8>(a, B, st, name);
+            }
+        default:
+            switch (E) {
+            case 1: return launch_hybrid<8, 2, 1>(a, B, st, name);
+            case 2: return launch_hybrid<8, 2, 2>(a, B, st, name);
+            case 4: return launch_hybrid<8, 2, 4>(a, B, st, name);
+            default: return launch_hybrid<8, 2, 8>(a, B, st, name);
+            }
         }
     }
 }

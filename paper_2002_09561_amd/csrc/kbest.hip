@@ -1171,8 +1171,8 @@ extern "C" int32_t kbest_detect_complex(const float* R, const float* z, int32_t 
     using namespace mimo;
     int32_t rc = validate_common("kbest_detect_complex", B, n_tx, pam, K);
     if (rc) return rc;
-    if (K > 64 || K * pam * pam > 1024)
-        return fail(MIMO_ERR_UNSUPPORTED, "kbest_detect_complex: K <= 64 and K * pam^2 <= 1024");
+    if (K > 64 || K * pam * pam > 2048)
+        return fail(MIMO_ERR_UNSUPPORTED, "kbest_detect_complex: K <= 64 and K * pam^2 <= 2048");
     const int n = 2 * n_tx;
     if (k_sched && k_sched_stride != 0 && k_sched_stride != n)
         return fail(MIMO_ERR_INVALID_ARG, "kbest_detect_complex: k_sched_stride must be 0 or n = %d", n);

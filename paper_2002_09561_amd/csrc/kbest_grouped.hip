@@ -53,7 +53,7 @@ typedef uint32_t gk_u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t gk_u32x2 __attribute__((ext_vector_type(2)));
 
 constexpr int GK_LEVELS = 16;       // levels per group = rows of one matrix-core tile
-constexpr int GK_CAND_MAX = 1024;   // K pam^J candidates per step
+constexpr int GK_CAND_MAX = 2048;   // K pam^J candidates per step (beyond 1024: pam^J = 64 only)
 constexpr uint32_t GK_UNFIXED = 0x08080808u;
 
 template <int P, int J, int E>
@@ -544,6 +544,9 @@ static int32_t dispatch_grouped_pj(const KbestArgs& a, int B, hipStream_t st)
     }
     if constexpr (16 * WAVE / PC <= 64) {
         if (need <= 1024) return launch_grouped<P, J, 16>(a, B, st);
+    }
+    if constexpr (32 * WAVE / PC <= 64) {  // 64-QAM on the complex tree: K <= 32
+        if (need <= 2048) return launch_grouped<P, J, 32>(a, B, st);
     }
     return fail(MIMO_ERR_UNSUPPORTED, "kbest_detect_grouped: K * pam^J beyond the instantiations");
 }

@@ -138,7 +138,8 @@ def test_grouped_kbest_host_checks(lib):
     assert g(P, P, 1, 8, 4, 16, 3, P, 0, P, P, P, P, P, P) == -1        # J not 1 or 2
     assert "J" in _err(lib)
     assert g(P, P, 1, 8, 4, 65, 1, P, 0, P, P, P, P, P, P) == -2        # K > 64
-    assert g(P, P, 1, 8, 8, 32, 2, P, 0, P, P, P, P, P, P) == -2        # 32 * 64 candidates
+    assert g(P, P, 1, 8, 8, 33, 2, P, 0, P, P, P, P, P, P) == -2        # 33 * 64 candidates > 2048
+    assert lib.kbest_detect_complex(P, P, 1, 8, 8, 33, P, 0, P, P, P, P, P, P) == -2  # the same limit
     assert g(P, P, 1, 129, 4, 16, 1, P, 0, P, P, P, P, P, P) == -2      # n_tx > 128
     assert g(P, P, 1, 8, 3, 16, 1, P, 0, P, P, P, P, P, P) == -1        # pam
     assert g(P, P, 1, 8, 4, 16, 2, ctypes.c_void_p(1), 5, P, P, P, P, P, P) == -1  # schedule stride
@@ -149,13 +150,13 @@ def test_grouped_kbest_host_checks(lib):
 def test_complex_hybrid_host_checks(lib):
     P = None
     g = lib.sd_hybrid_detect_complex
-    assert g(P, P, 1, 4, 8, P, 2, 5, P, 0, 0, 0, P, P, P, P, P) == -1      # 5 * 64 candidates > 256
+    assert g(P, P, 1, 4, 8, P, 2, 9, P, 0, 0, 0, P, P, P, P, P) == -1      # 9 * 64 candidates > 512
     assert "pam^2" in _err(lib)
     assert g(P, P, 1, 4, 2, P, 2, 65, P, 0, 0, 0, P, P, P, P, P) == -1     # k_worker > 64
     assert g(P, P, 1, 4, 4, P, 16, 1, P, 0, 0, 0, P, P, P, P, P) == -1     # n_workers > 15
     assert g(P, P, 1, 4, 4, P, 0, 1, P, 0, 1, 0, P, P, P, P, P) == -1      # master_off without a worker
     assert g(P, P, 1, 4, 4, P, 1, 1, ctypes.c_void_p(1), 3, 0, 0, P, P, P, P, P) == -1  # schedule stride
-    assert g(P, P, 0, 4, 8, P, 2, 4, P, 0, 0, 0, P, P, P, P, P) == 0       # empty batch (4 * 64 allowed)
+    assert g(P, P, 0, 4, 8, P, 2, 8, P, 0, 0, 0, P, P, P, P, P) == 0       # empty batch (8 * 64 allowed)
     assert g(P, P, 2, 4, 8, P, 2, 4, P, 0, 0, 0, P, P, P, P, P) == -1      # null pointers
 
 

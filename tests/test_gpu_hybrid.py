@@ -157,21 +157,24 @@ def test_hybrid_complex_exact_sd_parity(gpu, orc, M, q, snr, B):
         check_ml(orc, "complex SD vs brute force", P, sym, {"x": orc_x(sb, P)}, f.H, f.y, q)
 
 
-@pytest.mark.parametrize("q,W,Kw", [(16, 1, 1), (16, 3, 2), (16, 15, 4), (16, 5, 16), (64, 15, 1), (64, 4, 2),
-                                    (64, 2, 4), (4, 3, 64), (4, 7, 24)])
+@pytest.mark.parametrize("q,W,Kw", [(16, 1, 1), (16, 3, 2), (16, 15, 4), (16, 5, 16), (16, 3, 32), (64, 15, 1),
+                                    (64, 4, 2), (64, 2, 4), (64, 3, 7), (4, 3, 64), (4, 7, 24)])
 def test_hybrid_complex_parity(gpu, orc, q, W, Kw):
-    """Workers on the complex-symbol tree, k_worker * |Omega| from 16 to 256
-    candidates per step (one to four sort registers per lane)."""
+    """Workers on the complex-symbol tree, k_worker * |Omega| from 16 to 512
+    candidates per step (one to eight sort registers per lane)."""
     M = 8 if q == 64 else 10
     f, P, out, sym, pd, flags, ctr = _run(gpu, orc, M, M, q, 12.0 if q == 16 else (18.0 if q == 64 else 5.0), 100,
                                           W, Kw, seed=3700 + q + W, budget=200000, J=2)
     _check(f, P, out, sym, pd, flags, ctr, f"complex hybrid {q}-QAM W={W} Kw={Kw}")
 
 
-def test_hybrid_complex_paper_shape(gpu, orc):
-    """16x16 64-QAM on the complex tree, 15 workers with 4 survivors each."""
-    f, P, out, sym, pd, flags, ctr = _run(gpu, orc, 16, 16, 64, 20.0, 48, 15, 4, seed=3800, budget=300000, J=2)
-    _check(f, P, out, sym, pd, flags, ctr, "complex hybrid 16x16 64-QAM W=15 Kw=4", max_frac=0.25)
+@pytest.mark.parametrize("Kw", [1, 2, 6, 8])
+def test_hybrid_complex_paper_shape(gpu, orc, Kw):
+    """16x16 64-QAM on the complex tree with the paper's worker survivor
+    counts k in {1, 2, 6, 8} and 15 workers (the paper runs 19)."""
+    f, P, out, sym, pd, flags, ctr = _run(gpu, orc, 16, 16, 64, 20.0, 48, 15, Kw, seed=3800 + Kw, budget=300000,
+                                          J=2)
+    _check(f, P, out, sym, pd, flags, ctr, f"complex hybrid 16x16 64-QAM W=15 Kw={Kw}", max_frac=0.25)
 
 
 def test_hybrid_complex_master_off_is_kbest(gpu, orc):

@@ -59,18 +59,21 @@ def orc_sym(x, P):
 
 @pytest.mark.parametrize("M,q,snr,B,K", [(4, 16, 10.0, 300, 10), (16, 16, 12.0, 200, 10), (16, 64, 18.0, 150, 10),
                                          (8, 64, 20.0, 100, 16), (32, 16, 14.0, 60, 64), (5, 4, 3.0, 100, 1),
-                                         (6, 4, 2.0, 100, 24), (100, 64, 24.0, 6, 10)])
+                                         (6, 4, 2.0, 100, 24), (100, 64, 24.0, 6, 10), (12, 64, 20.0, 60, 32),
+                                         (10, 64, 16.0, 60, 24)])
 def test_kbest_complex_parity(gpu, orc, M, q, snr, B, K):
     f, P, out, sym, pd, flags, ctr = _run(gpu, orc, M, q, snr, B, K, seed=8000 + M * 7 + K)
     _check(orc, P, out, sym, pd, flags, ctr, f"complex K-best {M}x{M} {q}-QAM K={K}")
 
 
-def test_kbest_complex_node_count_is_papers(gpu, orc):
+@pytest.mark.parametrize("K,nodes", [(10, 151), (32, 481)])
+def test_kbest_complex_node_count_is_papers(gpu, orc, K, nodes):
     """Survivors expanded per frame = 1 + (M - 1) K for K <= |Omega|: at
-    16x16 64-QAM with K = 10 that is the 151 visited nodes the paper prints."""
-    f, P, out, sym, pd, flags, ctr = _run(gpu, orc, 16, 64, 20.0, 50, 10, seed=8100)
-    assert np.all(ctr[:, 0] == 151)
-    assert np.all(out["counters"][:, 0] == 151)
+    16x16 64-QAM, 151 for K = 10 and 481 for K = 32, the visited-node
+    counts the paper prints (K = 32 has 2048 candidates per level)."""
+    f, P, out, sym, pd, flags, ctr = _run(gpu, orc, 16, 64, 20.0, 50, K, seed=8100 + K)
+    assert np.all(ctr[:, 0] == nodes)
+    assert np.all(out["counters"][:, 0] == nodes)
 
 
 def test_kbest_complex_full_K_is_ml(gpu, orc):
