@@ -55,8 +55,9 @@ __device__ inline void wave_sync()
 struct HybLayout {
     int nw, stride, nd;  // words per path, padded stride, depths (steps of J levels: n / J + 1)
     size_t o_mpath, o_bpath, o_ppd, o_pc, o_lo, o_hi, o_mask, o_wst, o_wpath, o_wpd, o_sel, o_cand, o_sc, total;
+    size_t o_r, o_z, o_rs;  // staged c R, z and row sums (when stage)
     // P: children per step (pam^J)
-    __host__ __device__ HybLayout(int n, int W, int Kw, int P, int J = 1)
+    __host__ __device__ HybLayout(int n, int W, int Kw, int P, int J, int stage)
     {
         nw = (n + 3) / 4;
         stride = nw + 1;
@@ -76,12 +77,18 @@ struct HybLayout {
         o_sel = o; o += 4 * (size_t)Wc * Kw;
         o_cand = o; o += 4 * 3 * (Wc + 1);      // pd, ok, info per source
         o_sc = o; o += 64;                      // scalars
+        o_r = o_z = o_rs = o;
+        if (stage) {
+            o_r = o; o += 4 * (size_t)r_packed_size(n);
+            o_z = o; o += 4 * (size_t)n;
+            o_rs = o; o += 4 * (size_t)n;
+        }
         total = o;
     }
 };
 
 // scalar slots (int32 unless noted)
-enum { SC_R2 = 0, SC_FOUND, SC_PSIZE, SC_DONE, SC_FLAGS, SC_EXP_LO, SC_EXP_HI, SC_ROUNDS, SC_STALE, SC_WEXP };
+enum { SC_R2 = 0, SC_FOUND, SC_PSIZE, SC_DONE, SC_FLAGS, SC_EXP_LO, SC_EXP_HI, SC_ROUNDS, SC_STALE, SC_WEXP, SC_BUSY };
 
 __device__ inline int get_byte(const uint32_t* p, int j) { return (int)((p[j >> 2] >> (8 * (j & 3))) & 0xffu); }
 
@@ -100,6 +107,82 @@ __device__ inline uint32_t put_pair(uint32_t v, int lev, int c)
     return (v & ~(0xffffu << sh)) | ((uint32_t)(c % P) << sh) | ((uint32_t)(c / P) << (sh + 8));
 }
 
+// entry t of row k of c R: staged rows are scaled already
+template <bool ST>
+__device__ __forceinline__ float rget(const float* rk, int t, float cs)
+{
+    if constexpr (ST) return rk[t];
+    else return cs * rk[t];
+}
+
+// sum of c R_kj over j > k: the staged sum, or lane-strided partial sums
+// reduced over the wave (the staged sums are made the same way)
+template <bool ST>
+__device__ __forceinline__ float row_sum(const float* rk, int k, int n, const float* rs, float cs, int lane)
+{
+    if constexpr (ST) {
+        return rs[k];
+    } else {
+        float v = 0.f;
+        for (int t = 1 + lane; t < n - k; t += WAVE) v += cs * rk[t];
+        return wave_sum(v);
+    }
+}
+
+// Copy the keep selected survivors' paths (sel[i] = parent rank * PC +
+// child) to the next buffer from word w0 on, the child's digit(s) put at
+// level lev; all (survivor, word) pairs at once over the lanes
+template <int P, int J>
+__device__ inline void gather_paths(const uint32_t* pcur, uint32_t* pnxt, const int* sel, int keep, int lev, int nw,
+                                    int stride, int lane)
+{
+    constexpr int PC = J == 1 ? P : P * P;
+    const int w0 = lev >> 2, nwd = nw - w0, total = keep * nwd;
+    const float inv = 1.0f / (float)nwd;  // (idx + 0.5) / nwd is q + 1/2 / nwd or more from the integers
+    for (int idx = lane; idx < total; idx += WAVE) {
+        const int i = (int)(((float)idx + 0.5f) * inv);
+        const int wd = w0 + idx - i * nwd;
+        const int m = sel[i];
+        uint32_t v = pcur[(m / PC) * stride + wd];
+        if (wd == w0) {
+            if constexpr (J == 2) v = put_pair<P>(v, lev, m % PC);
+            else v = put_byte(v, lev, m % PC);
+        }
+        pnxt[i * stride + wd] = v;
+    }
+}
+
+// smallest 64-bit key over the wave (every lane gets it)
+__device__ inline uint64_t wave_min_key(uint64_t v, int lane)
+{
+#pragma unroll
+    for (int m = 1; m < WAVE; m <<= 1) {
+        const uint64_t o = xor_lanes_u64(v, m, lane);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+// deepest (largest) / shallowest non-empty pool depth from the 9 mask
+// words, read by the lanes of one wave (the pool holds a node)
+__device__ inline int pool_deepest(const uint32_t* pmask, int lane)
+{
+    const uint32_t mk = lane < 9 ? pmask[lane] : 0u;
+    const uint64_t nz = __ballot(mk != 0u);
+    const int q = 63 - __clzll((long long)nz);
+    const uint32_t mq = (uint32_t)__shfl((int)mk, q, WAVE);
+    return 32 * q + 31 - __clz(mq);
+}
+
+__device__ inline int pool_shallowest(const uint32_t* pmask, int lane)
+{
+    const uint32_t mk = lane < 9 ? pmask[lane] : 0u;
+    const uint64_t nz = __ballot(mk != 0u);
+    const int q = __ffsll((long long)nz) - 1;
+    const uint32_t mq = (uint32_t)__shfl((int)mk, q, WAVE);
+    return 32 * q + __ffs(mq) - 1;
+}
+
 // Master expansion of a node at step depth d (child c of its parent step)
 // on the complex-level tree: the children fix levels kh = lev - 1 and
 // kl = lev - 2 at once.  Both centres come from the levels above kh
@@ -107,10 +190,10 @@ __device__ inline uint32_t put_pair(uint32_t v, int lev, int c)
 // (ih, il) has pd + e_h^2 + e_l^2 (Eq. (inc) twice, the upper level first).
 // The children inside the radius are ranked by (pd, index) with one in-wave
 // sort and stored at depth d + 1, or the best leaf is offered.
-template <int P>
-__device__ void master_expand_pair(int n, const float* Rf, const float* zf, float cs, float r2r, int d, int c, float pd,
-                                   uint32_t* mpath, float* ppd, int* pc, int* plo, int* phi, uint32_t* pmask, int* sc,
-                                   float* cpd, int* cinfo, int* cok, int lane)
+template <int P, bool ST>
+__device__ void master_expand_pair(int n, const float* Rf, const float* zf, const float* rs, float cs, float r2r, int d,
+                                   int c, float pd, uint32_t* mpath, float* ppd, int* pc, int* plo, int* phi,
+                                   uint32_t* pmask, int* sc, float* cpd, int* cinfo, int* cok, int lane)
 {
     constexpr int PC = P * P;
     const int lev = n - 2 * d;  // lowest level of the node's own step (n for the root)
@@ -120,19 +203,26 @@ __device__ void master_expand_pair(int n, const float* Rf, const float* zf, floa
     float ah = 0.f, al = 0.f, sh = 0.f, sl = 0.f;
     for (int j = lev + lane; j < n; j += WAVE) {
         const int sym = j == lev ? c % P : (j == lev + 1 ? c / P : get_byte(mpath, j));
-        const float xh = cs * rh[j - kh], xl = cs * rl[j - kl];
+        const float xh = rget<ST>(rh, j - kh, cs), xl = rget<ST>(rl, j - kl, cs);
         ah = fmaf(xh, (float)sym, ah);
         al = fmaf(xl, (float)sym, al);
-        sh += xh;
-        sl += xl;
+        if constexpr (!ST) {
+            sh += xh;
+            sl += xl;
+        }
     }
     ah = wave_sum(ah);
     al = wave_sum(al);
-    sh = wave_sum(sh);
-    sl = wave_sum(sl);
+    if constexpr (ST) {  // R[kl][kh] is the structural zero: it adds nothing to the staged sum of row kl
+        sh = rs[kh];
+        sl = rs[kl];
+    } else {
+        sh = wave_sum(sh);
+        sl = wave_sum(sl);
+    }
     const float bh = zf[kh] - (2.f * ah - (float)(P - 1) * sh);
     const float bl = zf[kl] - (2.f * al - (float)(P - 1) * sl);
-    const float dh = cs * rh[0], dl = cs * rl[0];
+    const float dh = rget<ST>(rh, 0, cs), dl = rget<ST>(rl, 0, cs);
     if (!__builtin_isfinite(bh) || !__builtin_isfinite(bl) || !__builtin_isfinite(dh) || !__builtin_isfinite(dl)) {
         if (lane == 0) {  // uniform: NaN or inf in R or z
             sc[SC_DONE] = 1;
@@ -182,10 +272,11 @@ __device__ void master_expand_pair(int n, const float* Rf, const float* zf, floa
 // given 64 / 2^ceil(log2 cnt) lanes for its two dot products; candidate
 // m = s P^2 + c (c = ih P + il) sits at sort position m of 64 E keys
 // ordered by (pd bits, m), i.e. (pd, parent rank, child) as in the oracle.
-template <int P, int E>
-__device__ void worker_step_pair(int n, const float* Rf, const float* zf, float cs, float r2r, const int32_t* ks,
-                                 int Kw, int w, int depth, int cnt, int buf, int* st, uint32_t* wp, float* wq, int* sel,
-                                 int nw, int stride, int* sc, float* cpd, int* cinfo, int* cok, int lane)
+template <int P, int E, bool ST>
+__device__ void worker_step_pair(int n, const float* Rf, const float* zf, const float* rs, float cs, float r2r,
+                                 const int32_t* ks, int Kw, int w, int depth, int cnt, int buf, int* st, uint32_t* wp,
+                                 float* wq, int* sel, int nw, int stride, int* sc, float* cpd, int* cinfo, int* cok,
+                                 int lane)
 {
     constexpr int PC = P * P;
     const int kh = n - 2 * depth - 1, kl = kh - 1;
@@ -197,13 +288,20 @@ __device__ void worker_step_pair(int n, const float* Rf, const float* zf, float 
     Kt = Kt > Kw ? Kw : (Kt < 1 ? 1 : Kt);
     const float* rh = Rf + r_row_off(n, kh);
     const float* rl = Rf + r_row_off(n, kl);
-    float sh = 0.f, sl = 0.f;
-    for (int j = kh + 1 + lane; j < n; j += WAVE) {
-        sh += cs * rh[j - kh];
-        sl += cs * rl[j - kl];
+    float sh, sl;
+    if constexpr (ST) {  // the structural zero R[kl][kh] adds nothing to the staged sum of row kl
+        sh = rs[kh];
+        sl = rs[kl];
+    } else {
+        sh = 0.f;
+        sl = 0.f;
+        for (int j = kh + 1 + lane; j < n; j += WAVE) {
+            sh += cs * rh[j - kh];
+            sl += cs * rl[j - kl];
+        }
+        sh = wave_sum(sh);
+        sl = wave_sum(sl);
     }
-    sh = wave_sum(sh);
-    sl = wave_sum(sl);
     const int lg = 6 - (cnt <= 1 ? 0 : 32 - __clz(cnt - 1));  // log2 of the lanes per survivor
     const int G = 1 << lg, s = lane >> lg, g = lane & (G - 1);
     float ah = 0.f, al = 0.f;
@@ -211,13 +309,23 @@ __device__ void worker_step_pair(int n, const float* Rf, const float* zf, float 
         const uint32_t* prow = pcur + s * stride;
         for (int wd = (kh + 1) / 4 + g; wd < nw; wd += G) {
             const uint32_t dw = prow[wd];
+            const int j0 = 4 * wd;
+            if (j0 > kh && j0 + 4 <= n) {  // the whole word lies above the step
 #pragma unroll
-            for (int bb = 0; bb < 4; ++bb) {
-                const int j = 4 * wd + bb;
-                if (j > kh && j < n) {
+                for (int bb = 0; bb < 4; ++bb) {
                     const float v = (float)((dw >> (8 * bb)) & 0xffu);
-                    ah = fmaf(cs * rh[j - kh], v, ah);
-                    al = fmaf(cs * rl[j - kl], v, al);
+                    ah = fmaf(rget<ST>(rh, j0 + bb - kh, cs), v, ah);
+                    al = fmaf(rget<ST>(rl, j0 + bb - kl, cs), v, al);
+                }
+            } else {
+#pragma unroll
+                for (int bb = 0; bb < 4; ++bb) {
+                    const int j = j0 + bb;
+                    if (j > kh && j < n) {
+                        const float v = (float)((dw >> (8 * bb)) & 0xffu);
+                        ah = fmaf(rget<ST>(rh, j - kh, cs), v, ah);
+                        al = fmaf(rget<ST>(rl, j - kl, cs), v, al);
+                    }
                 }
             }
         }
@@ -228,7 +336,7 @@ __device__ void worker_step_pair(int n, const float* Rf, const float* zf, float 
     }
     const float bh = zf[kh] - (2.f * ah - (float)(P - 1) * sh);
     const float bl = zf[kl] - (2.f * al - (float)(P - 1) * sl);
-    const float dh = cs * rh[0], dl = cs * rl[0];
+    const float dh = rget<ST>(rh, 0, cs), dl = rget<ST>(rl, 0, cs);
     // a NaN or infinity in R or z: the frame's search stops after this round
     const bool bad = __ballot(!__builtin_isfinite(dh) || !__builtin_isfinite(dl) ||
                               (s < cnt && (!__builtin_isfinite(bh) || !__builtin_isfinite(bl)))) != 0;
@@ -250,32 +358,44 @@ __device__ void worker_step_pair(int n, const float* Rf, const float* zf, float 
             if (pdc < r2r) key[e] = ((uint64_t)__float_as_uint(pdc) << 32) | (uint32_t)m;
         }
     }
-    bitonic_sort<E>(key, lane);
     int nvalid = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) nvalid += __popcll(__ballot(key[e] != ~0ull));
     if (lane == 0) atomicAdd(&sc[SC_WEXP], cnt);
     if (nvalid == 0) {
-        if (lane == 0) st[0] = 0;
+        if (lane == 0) {
+            st[0] = 0;
+            atomicAnd(reinterpret_cast<unsigned int*>(&sc[SC_BUSY]), ~(1u << w));
+        }
         return;
     }
-    const int keep = Kt < nvalid ? Kt : nvalid;  // <= Kw <= 64: the first 64 sort positions
+    const int keep = Kt < nvalid ? Kt : nvalid;  // <= Kw <= 64
+    // the keep smallest keys in order, lane i holding the i-th: by repeated
+    // wave minima when keep is small against the sort network's depth
+    // (about (6 + E) against E s (s + 1) / 2 exchanges per key, s = log2(64 E)),
+    // else by sorting all 64 E keys
+    constexpr int S = E == 1 ? 6 : (E == 2 ? 7 : (E == 4 ? 8 : 9));
+    uint64_t res = ~0ull;
+    if (keep * (6 + E) < E * S * (S + 1) / 2) {
+        for (int i = 0; i < keep; ++i) {
+            uint64_t m = key[0];
+#pragma unroll
+            for (int e = 1; e < E; ++e) m = key[e] < m ? key[e] : m;
+            m = wave_min_key(m, lane);
+#pragma unroll
+            for (int e = 0; e < E; ++e) key[e] = key[e] == m ? ~0ull : key[e];  // keys are distinct
+            res = lane == i ? m : res;
+        }
+    } else {
+        bitonic_sort<E>(key, lane);
+        res = key[0];
+    }
     if (lane < keep) {
-        snxt[lane] = __uint_as_float((uint32_t)(key[0] >> 32));
-        sel[lane] = (int)(uint32_t)key[0];
+        snxt[lane] = __uint_as_float((uint32_t)(res >> 32));
+        sel[lane] = (int)(uint32_t)res;
     }
     wave_sync();
-    const int w0 = kl / 4;
-    for (int i = 0; i < keep; ++i) {
-        const int m = sel[i];
-        const uint32_t* src = pcur + (m / PC) * stride;
-        uint32_t* dst = pnxt + i * stride;
-        for (int wd = w0 + lane; wd < nw; wd += WAVE) {
-            uint32_t v = src[wd];
-            if (wd == w0) v = put_pair<P>(v, kl, m % PC);
-            dst[wd] = v;
-        }
-    }
+    gather_paths<P, 2>(pcur, pnxt, sel, keep, kl, nw, stride, lane);
     if (lane == 0) {
         st[2] = keep;
         st[3] = buf ^ 1;
@@ -285,6 +405,7 @@ __device__ void worker_step_pair(int n, const float* Rf, const float* zf, float 
             cinfo[1 + w] = buf ^ 1;
             cok[1 + w] = 1;
             st[0] = 0;
+            atomicAnd(reinterpret_cast<unsigned int*>(&sc[SC_BUSY]), ~(1u << w));
         }
     }
 }
@@ -292,8 +413,11 @@ __device__ void worker_step_pair(int n, const float* Rf, const float* zf, float 
 // P: PAM points per real level; J: real levels per step (2: one complex
 // symbol, P^2 children; the levels 2m+1, 2m of a step have the structural
 // zero R[2m][2m+1] of the interleaved model, so both centres come from the
-// levels above the step).  Pool depths count steps.
-template <int P, int J, int E>
+// levels above the step).  Pool depths count steps.  E: 64-key sort
+// registers per lane of a complex-level worker.  ST: the frame's c R (c the
+// PAM spacing), z and the sums of c R right of the diagonal of each row are
+// copied to LDS first and every level reads them there.
+template <int P, int J, int E, bool ST>
 __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
 {
     constexpr int PC = J == 1 ? P : P * P;  // children per step
@@ -305,7 +429,7 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
     }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int n = a.n, W = a.W, Kw = a.Kw;
-    const HybLayout Lo(n, W, Kw, PC, J);
+    const HybLayout Lo(n, W, Kw, PC, J, ST);
     const int nw = Lo.nw, stride = Lo.stride;
     uint32_t* mpath = reinterpret_cast<uint32_t*>(smem_hy + Lo.o_mpath);
     uint32_t* bpath = reinterpret_cast<uint32_t*>(smem_hy + Lo.o_bpath);
@@ -324,9 +448,27 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
     int* sc = reinterpret_cast<int*>(smem_hy + Lo.o_sc);
     float* sc_r2 = reinterpret_cast<float*>(sc + SC_R2);
 
+    const float cs = pam_scale(P);
     const float* Rf = a.R + (size_t)frame * r_packed_size(n);
     const float* zf = a.z + (size_t)frame * n;
-    const float cs = pam_scale(P);
+    const float* rs = nullptr;  // staged row sums
+    if constexpr (ST) {  // every level reads c R, z and the row sums from LDS from here on
+        float* Rs = reinterpret_cast<float*>(smem_hy + Lo.o_r);
+        float* zs = reinterpret_cast<float*>(smem_hy + Lo.o_z);
+        float* rss = reinterpret_cast<float*>(smem_hy + Lo.o_rs);
+        const int rsz = (int)r_packed_size(n);
+        for (int i = threadIdx.x; i < rsz; i += blockDim.x) Rs[i] = cs * Rf[i];
+        for (int i = threadIdx.x; i < n; i += blockDim.x) zs[i] = zf[i];
+        __syncthreads();
+        const int nwave = blockDim.x / WAVE;
+        for (int k = wave; k < n; k += nwave) {  // uniform per wave
+            const float v = row_sum<false>(Rs + r_row_off(n, k), k, n, nullptr, 1.f, lane);
+            if (lane == 0) rss[k] = v;
+        }
+        Rf = Rs;
+        zf = zs;
+        rs = rss;
+    }
     const int32_t* ks = a.k_sched ? a.k_sched + (size_t)frame * a.k_sched_stride : nullptr;
 
     // ---- init
@@ -352,6 +494,7 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
         sc[SC_ROUNDS] = 0;
         sc[SC_STALE] = 0;
         sc[SC_WEXP] = 0;
+        sc[SC_BUSY] = a.master_off && W >= 1 ? 1 : 0;
         if (a.master_off) {
             sc[SC_PSIZE] = 0;
             if (W >= 1) {  // worker 0 starts at the root
@@ -375,8 +518,7 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
 
     for (;;) {
         // ---- termination (uniform: every thread reads the same LDS state)
-        int busy_any = 0;
-        for (int w = 0; w < W; ++w) busy_any |= wst[8 * w];
+        const int busy_any = sc[SC_BUSY];
         const int64_t expanded = ((int64_t)(uint32_t)sc[SC_EXP_HI] << 32) | (uint32_t)sc[SC_EXP_LO];
         if (sc[SC_DONE]) break;  // non-finite input seen
         if (sc[SC_PSIZE] == 0 && !busy_any) {
@@ -394,40 +536,34 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
         if (wave == 0 && !a.master_off) {
             int ok = 0, d = 0, c = 0;
             float pd = 0.f;
-            if (lane == 0) {
-                int stale = 0;
-                while (sc[SC_PSIZE] > 0) {
-                    int dd = 0;
-                    for (int q = 8; q >= 0; --q)
-                        if (pmask[q]) {
-                            dd = 32 * q + 31 - __clz(pmask[q]);
-                            break;
-                        }
-                    const int i = plo[dd]++;
-                    if (plo[dd] == phi[dd]) pmask[dd >> 5] &= ~(1u << (dd & 31));
-                    sc[SC_PSIZE] -= 1;
-                    const float v = ppd[dd * PC + i];
-                    if (v >= r2r) {
-                        ++stale;
-                        continue;
-                    }
+            // pop left-most nodes (deepest depth, best sibling) until one lies
+            // inside the radius; the siblings of a depth are sorted by pd, so
+            // when the best is outside, the whole depth is (each one counts
+            // as a discarded pop)
+            while (sc[SC_PSIZE] > 0) {  // uniform over wave 0
+                const int dd = pool_deepest(pmask, lane);
+                const int lo = plo[dd], hi = phi[dd];
+                const float v = ppd[dd * PC + lo];
+                const int take = v >= r2r ? hi - lo : 1;
+                wave_sync();
+                if (lane == 0) {
+                    plo[dd] = lo + take;
+                    if (lo + take == hi) pmask[dd >> 5] &= ~(1u << (dd & 31));
+                    sc[SC_PSIZE] -= take;
+                    if (v >= r2r) sc[SC_STALE] += take;
+                }
+                wave_sync();
+                if (v < r2r) {
                     ok = 1;
                     d = dd;
-                    c = pc[dd * PC + i];
+                    c = pc[dd * PC + lo];
                     pd = v;
                     break;
                 }
-                sc[SC_STALE] += stale;
-            }
-            ok = __shfl(ok, 0, WAVE);
-            if (ok) {
-                d = __shfl(d, 0, WAVE);
-                c = __shfl(c, 0, WAVE);
-                pd = __shfl(pd, 0, WAVE);
             }
             if constexpr (J == 2) {
-                if (ok) master_expand_pair<P>(n, Rf, zf, cs, r2r, d, c, pd, mpath, ppd, pc, plo, phi, pmask, sc, cpd,
-                                              cinfo, cok, lane);
+                if (ok) master_expand_pair<P, ST>(n, Rf, zf, rs, cs, r2r, d, c, pd, mpath, ppd, pc, plo, phi, pmask, sc,
+                                                  cpd, cinfo, cok, lane);
             } else {
             const int lev = n - d;  // level of the node's own symbol (n for the root)
             const int k = lev - 1;  // level its children fix
@@ -438,14 +574,15 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                 for (int t = 1 + lane; t < n - k; t += WAVE) {
                     const int j = k + t;
                     const int sym = (j == lev) ? c : (int)((mpath[j >> 2] >> (8 * (j & 3))) & 0xffu);
-                    const float r = cs * rk[t];
+                    const float r = rget<ST>(rk, t, cs);
                     acc = fmaf(r, (float)sym, acc);
-                    rsum += r;
+                    if constexpr (!ST) rsum += r;
                 }
                 acc = wave_sum(acc);
-                rsum = wave_sum(rsum);
+                if constexpr (ST) rsum = rs[k];  // the same sums, made once
+                else rsum = wave_sum(rsum);
                 b = zf[k] - (2.f * acc - (float)(P - 1) * rsum);
-                rkk = cs * rk[0];
+                rkk = rget<ST>(rk, 0, cs);
                 if (!__builtin_isfinite(b) || !__builtin_isfinite(rkk)) {  // uniform: NaN or inf in R or z
                     if (lane == 0) {
                         sc[SC_DONE] = 1;
@@ -464,7 +601,7 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                 int rank = 0;
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
-                    const float o = shfl_f(pdc, q);
+                    const float o = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pdc), q));
                     rank += (o < pdc) || (o == pdc && q < lane);
                 }
                 const bool keep = lane < P && pdc < r2r;
@@ -502,36 +639,49 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
         }
         __syncthreads();
 
-        // ---- B: idle workers take right-most nodes
-        if (threadIdx.x == 0) {
-            int stale = 0;
-            for (int w = 0; w < W; ++w) {
-                int* st = wst + 8 * w;
-                if (st[0]) continue;
+        // ---- B: idle workers, in order, take right-most nodes (shallowest
+        // depth, worst sibling) while the pool holds two or more; the nodes
+        // outside the radius at the right end of a depth are a run of the
+        // sorted siblings and are discarded together, one pop each, as far
+        // as the pool may shrink
+        if (wave == 0) {
+            uint64_t idle = ~(uint64_t)(uint32_t)sc[SC_BUSY] & ((1ull << W) - 1ull);
+            while (idle) {  // uniform over wave 0
+                const int w = __ffsll((long long)idle) - 1;
+                idle &= idle - 1;
+                bool given = false;
                 while (sc[SC_PSIZE] >= 2) {
-                    int dd = 0;
-                    for (int q = 0; q < 9; ++q)
-                        if (pmask[q]) {
-                            dd = 32 * q + __ffs(pmask[q]) - 1;
-                            break;
+                    const int dd = pool_shallowest(pmask, lane);
+                    const int lo = plo[dd], hi = phi[dd];
+                    const float vi = lane < hi - lo ? ppd[dd * PC + lo + lane] : 0.f;
+                    const int nst = __popcll(__ballot(lane < hi - lo && vi >= r2r));
+                    const int psz = sc[SC_PSIZE];
+                    const int npop = nst > 0 ? (nst < psz - 1 ? nst : psz - 1) : 1;
+                    wave_sync();
+                    if (lane == 0) {
+                        phi[dd] = hi - npop;
+                        if (lo == hi - npop) pmask[dd >> 5] &= ~(1u << (dd & 31));
+                        sc[SC_PSIZE] = psz - npop;
+                        if (nst > 0) {
+                            sc[SC_STALE] += npop;
+                        } else {
+                            int* st = wst + 8 * w;
+                            st[0] = 1;
+                            sc[SC_BUSY] |= 1 << w;
+                            st[4] = 1;
+                            st[5] = dd;
+                            st[6] = pc[dd * PC + hi - 1];
+                            reinterpret_cast<float*>(st)[7] = ppd[dd * PC + hi - 1];
                         }
-                    const int i = --phi[dd];
-                    if (plo[dd] == phi[dd]) pmask[dd >> 5] &= ~(1u << (dd & 31));
-                    sc[SC_PSIZE] -= 1;
-                    const float v = ppd[dd * PC + i];
-                    if (v >= r2r) {
-                        ++stale;
-                        continue;
                     }
-                    st[0] = 1;
-                    st[4] = 1;
-                    st[5] = dd;
-                    st[6] = pc[dd * PC + i];
-                    reinterpret_cast<float*>(st)[7] = v;
-                    break;
+                    wave_sync();
+                    if (nst == 0) {
+                        given = true;
+                        break;
+                    }
                 }
+                if (!given) break;  // fewer than two nodes: none for the later workers either
             }
-            sc[SC_STALE] += stale;
         }
         __syncthreads();
 
@@ -565,8 +715,8 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                 }
                 const int depth = st[1], cnt = st[2], buf = st[3];
                 if constexpr (J == 2) {
-                    worker_step_pair<P, E>(n, Rf, zf, cs, r2r, ks, Kw, w, depth, cnt, buf, st, wp, wq, sel, nw, stride,
-                                           sc, cpd, cinfo, cok, lane);
+                    worker_step_pair<P, E, ST>(n, Rf, zf, rs, cs, r2r, ks, Kw, w, depth, cnt, buf, st, wp, wq, sel, nw,
+                                               stride, sc, cpd, cinfo, cok, lane);
                 } else {
                 const int k = n - depth - 1;
                 uint32_t* pcur = wp + buf * Kw * stride;
@@ -577,26 +727,32 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                 Kt = Kt > Kw ? Kw : (Kt < 1 ? 1 : Kt);
                 const float* rk = Rf + r_row_off(n, k);
                 // row sum (uniform) and per-survivor dot products: P lanes per survivor
-                float rsum = 0.f;
-                for (int t = 1 + lane; t < n - k; t += WAVE) rsum += cs * rk[t];
-                rsum = wave_sum(rsum);
+                const float rsum = row_sum<ST>(rk, k, n, rs, cs, lane);
                 const int s = lane / P, cc = lane % P;
                 float acc = 0.f;
                 if (s < cnt) {
                     const uint32_t* prow = pcur + s * stride;
                     for (int wd = (k + 1) / 4 + cc; wd < nw; wd += P) {
                         const uint32_t dw = prow[wd];
+                        const int j0 = 4 * wd;
+                        if (j0 > k && j0 + 4 <= n) {  // the whole word lies above level k
 #pragma unroll
-                        for (int bb = 0; bb < 4; ++bb) {
-                            const int j = 4 * wd + bb;
-                            if (j > k && j < n) acc = fmaf(cs * rk[j - k], (float)((dw >> (8 * bb)) & 0xffu), acc);
+                            for (int bb = 0; bb < 4; ++bb)
+                                acc = fmaf(rget<ST>(rk, j0 + bb - k, cs), (float)((dw >> (8 * bb)) & 0xffu), acc);
+                        } else {
+#pragma unroll
+                            for (int bb = 0; bb < 4; ++bb) {
+                                const int j = j0 + bb;
+                                if (j > k && j < n)
+                                    acc = fmaf(rget<ST>(rk, j - k, cs), (float)((dw >> (8 * bb)) & 0xffu), acc);
+                            }
                         }
                     }
                 }
 #pragma unroll
                 for (int m = 1; m < P; m <<= 1) acc += shfl_xor_f(acc, m);
                 const float b = zf[k] - (2.f * acc - (float)(P - 1) * rsum);
-                const float rkk = cs * rk[0];
+                const float rkk = rget<ST>(rk, 0, cs);
                 // a NaN or infinity in R or z: the frame's search stops after this round
                 const bool bad = __ballot(!__builtin_isfinite(rkk) || (s < cnt && !__builtin_isfinite(b))) != 0;
                 if (bad && lane == 0) {
@@ -613,7 +769,10 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                 const int nvalid = __popcll(__ballot(key[0] != ~0ull));
                 if (lane == 0) atomicAdd(&sc[SC_WEXP], cnt);
                 if (nvalid == 0) {
-                    if (lane == 0) st[0] = 0;
+                    if (lane == 0) {
+                        st[0] = 0;
+                        atomicAnd(reinterpret_cast<unsigned int*>(&sc[SC_BUSY]), ~(1u << w));
+                    }
                 } else {
                     const int keep = Kt < nvalid ? Kt : nvalid;
                     if (lane < keep) {
@@ -621,20 +780,7 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                         sel[lane] = (int)(uint32_t)key[0];
                     }
                     wave_sync();
-                    const int w0 = k / 4;
-                    for (int i = 0; i < keep; ++i) {
-                        const int m = sel[i];
-                        const uint32_t* src = pcur + (m / P) * stride;
-                        uint32_t* dst = pnxt + i * stride;
-                        for (int wd = w0 + lane; wd < nw; wd += WAVE) {
-                            uint32_t v = src[wd];
-                            if (wd == w0) {
-                                const int sh = 8 * (k & 3);
-                                v = (v & ~(0xffu << sh)) | ((uint32_t)(m % P) << sh);
-                            }
-                            dst[wd] = v;
-                        }
-                    }
+                    gather_paths<P, 1>(pcur, pnxt, sel, keep, k, nw, stride, lane);
                     if (lane == 0) {
                         st[2] = keep;
                         st[3] = buf ^ 1;
@@ -644,6 +790,7 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                             cinfo[1 + w] = buf ^ 1;
                             cok[1 + w] = 1;
                             st[0] = 0;
+                            atomicAnd(reinterpret_cast<unsigned int*>(&sc[SC_BUSY]), ~(1u << w));
                         }
                     }
                 }
@@ -652,27 +799,34 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
         }
         __syncthreads();
 
-        // ---- D: merge offers, shrink the radius once
-        if (threadIdx.x == 0) {
-            int best = -1;
-            for (int q = 0; q <= W; ++q) {
-                if (!cok[q]) continue;
-                if (best < 0 || cpd[q] < cpd[best]) best = q;
-            }
-            if (best >= 0 && cpd[best] < *sc_r2) {
-                *sc_r2 = cpd[best];
-                sc[SC_FOUND] = 1;
-                if (best == 0) {  // the master's leaf: its path plus the child's digit(s) at the bottom
-                    for (int i = 0; i < nw; ++i) bpath[i] = mpath[i];
-                    if constexpr (J == 2) bpath[0] = put_pair<P>(bpath[0], 0, cinfo[0]);
-                    else bpath[0] = put_byte(bpath[0], 0, cinfo[0]);
-                } else {
-                    const int w = best - 1;
-                    const uint32_t* src = wpath + ((size_t)w * 2 + cinfo[best]) * Kw * stride;
-                    for (int i = 0; i < nw; ++i) bpath[i] = src[i];
+        // ---- D: merge offers (the smallest pd, the lowest source on ties),
+        // shrink the radius once
+        if (wave == 0) {
+            const bool offer = lane <= W && cok[lane <= W ? lane : 0];
+            const uint64_t okey = offer ? ((uint64_t)__float_as_uint(cpd[lane]) << 32) | (uint32_t)lane : ~0ull;
+            const uint64_t bkey = wave_min_key(okey, lane);
+            const float bpd = __uint_as_float((uint32_t)(bkey >> 32));
+            if (bkey != ~0ull && bpd < *sc_r2) {  // uniform
+                const int best = (int)(uint32_t)bkey;
+                const uint32_t* src = best == 0 ? mpath
+                                                : wpath + ((size_t)(best - 1) * 2 + cinfo[best]) * Kw * stride;
+                for (int i = lane; i < nw; i += WAVE) {
+                    uint32_t v = src[i];
+                    if (best == 0 && i == 0) {  // the master's leaf: its path plus the child's digit(s) at the bottom
+                        if constexpr (J == 2) v = put_pair<P>(v, 0, cinfo[0]);
+                        else v = put_byte(v, 0, cinfo[0]);
+                    }
+                    bpath[i] = v;
+                }
+                wave_sync();
+                if (lane == 0) {
+                    *sc_r2 = bpd;
+                    sc[SC_FOUND] = 1;
                 }
             }
-            for (int q = 0; q <= W; ++q) cok[q] = 0;
+            if (lane <= W) cok[lane] = 0;
+        }
+        if (threadIdx.x == 0) {
             uint32_t lo = (uint32_t)sc[SC_EXP_LO];
             const uint32_t add = (uint32_t)sc[SC_WEXP];
             const uint32_t nlo = lo + add;
@@ -728,17 +882,20 @@ template <int P, int J, int E>
 static int32_t launch_hybrid(const HybArgs& a, int B, hipStream_t st, const char* name)
 {
     constexpr int PC = J == 1 ? P : P * P;
-    const HybLayout Lo(a.n, a.W, a.Kw, PC, J);
+    // c R, z and the row sums in LDS when they fit beside the pool and the worker buffers
+    const bool stage = HybLayout(a.n, a.W, a.Kw, PC, J, 1).total <= 160 * 1024;
+    const HybLayout Lo(a.n, a.W, a.Kw, PC, J, stage);
     if (Lo.total > 160 * 1024)
         return fail(MIMO_ERR_UNSUPPORTED, "%s: %zu bytes of LDS needed (n_workers * k_worker too large)", name,
                     Lo.total);
+    const void* fn = stage ? (const void*)hybrid_kernel<P, J, E, true> : (const void*)hybrid_kernel<P, J, E, false>;
     if (Lo.total > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)hybrid_kernel<P, J, E>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lo.total);
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lo.total);
         if (e != hipSuccess) return fail(MIMO_ERR_HIP, "%s: LDS attribute: %s", name, hipGetErrorString(e));
     }
     const int threads = WAVE * (1 + a.W);
-    hipLaunchKernelGGL((hybrid_kernel<P, J, E>), dim3(B), dim3(threads), Lo.total, st, a);
+    if (stage) hipLaunchKernelGGL((hybrid_kernel<P, J, E, true>), dim3(B), dim3(threads), Lo.total, st, a);
+    else hipLaunchKernelGGL((hybrid_kernel<P, J, E, false>), dim3(B), dim3(threads), Lo.total, st, a);
     return check_launch(name);
 }
 
