@@ -88,7 +88,7 @@ struct HybLayout {
 };
 
 // scalar slots (int32 unless noted)
-enum { SC_R2 = 0, SC_FOUND, SC_PSIZE, SC_DONE, SC_FLAGS, SC_EXP_LO, SC_EXP_HI, SC_ROUNDS, SC_STALE, SC_WEXP, SC_BUSY };
+enum { SC_R2 = 0, SC_FOUND, SC_PSIZE, SC_DONE, SC_FLAGS, SC_EXP_LO, SC_EXP_HI, SC_ROUNDS, SC_STALE, SC_WEXP, SC_BUSY, SC_NEWW };
 
 __device__ inline int get_byte(const uint32_t* p, int j) { return (int)((p[j >> 2] >> (8 * (j & 3))) & 0xffu); }
 
@@ -130,15 +130,15 @@ __device__ __forceinline__ float row_sum(const float* rk, int k, int n, const fl
 }
 
 // Copy the keep selected survivors' paths (sel[i] = parent rank * PC +
-// child) to the next buffer from word w0 on, the child's digit(s) put at
-// level lev; all (survivor, word) pairs at once over the lanes
+// child) to the next buffer from word w0 = lev / 4 on, the child's digit(s)
+// put at level lev; all (survivor, word) pairs at once over the lanes
 template <int P, int J>
 __device__ inline void gather_paths(const uint32_t* pcur, uint32_t* pnxt, const int* sel, int keep, int lev, int nw,
                                     int stride, int lane)
 {
     constexpr int PC = J == 1 ? P : P * P;
     const int w0 = lev >> 2, nwd = nw - w0, total = keep * nwd;
-    const float inv = 1.0f / (float)nwd;  // (idx + 0.5) / nwd is q + 1/2 / nwd or more from the integers
+    const float inv = 1.0f / (float)nwd;  // (idx + 0.5) / nwd is 1/2 / nwd or more from the integers
     for (int idx = lane; idx < total; idx += WAVE) {
         const int i = (int)(((float)idx + 0.5f) * inv);
         const int wd = w0 + idx - i * nwd;
@@ -170,7 +170,7 @@ __device__ inline int pool_deepest(const uint32_t* pmask, int lane)
     const uint32_t mk = lane < 9 ? pmask[lane] : 0u;
     const uint64_t nz = __ballot(mk != 0u);
     const int q = 63 - __clzll((long long)nz);
-    const uint32_t mq = (uint32_t)__shfl((int)mk, q, WAVE);
+    const uint32_t mq = (uint32_t)__builtin_amdgcn_readlane((int)mk, q);
     return 32 * q + 31 - __clz(mq);
 }
 
@@ -179,7 +179,7 @@ __device__ inline int pool_shallowest(const uint32_t* pmask, int lane)
     const uint32_t mk = lane < 9 ? pmask[lane] : 0u;
     const uint64_t nz = __ballot(mk != 0u);
     const int q = __ffsll((long long)nz) - 1;
-    const uint32_t mq = (uint32_t)__shfl((int)mk, q, WAVE);
+    const uint32_t mq = (uint32_t)__builtin_amdgcn_readlane((int)mk, q);
     return 32 * q + __ffs(mq) - 1;
 }
 
@@ -226,7 +226,7 @@ __device__ void master_expand_pair(int n, const float* Rf, const float* zf, cons
     if (!__builtin_isfinite(bh) || !__builtin_isfinite(bl) || !__builtin_isfinite(dh) || !__builtin_isfinite(dl)) {
         if (lane == 0) {  // uniform: NaN or inf in R or z
             sc[SC_DONE] = 1;
-            sc[SC_FLAGS] |= MIMO_FLAG_NONFINITE_INPUT;
+            atomicOr(reinterpret_cast<unsigned int*>(&sc[SC_FLAGS]), MIMO_FLAG_NONFINITE_INPUT);
         }
         return;
     }
@@ -284,7 +284,7 @@ __device__ void worker_step_pair(int n, const float* Rf, const float* zf, const 
     uint32_t* pnxt = wp + (buf ^ 1) * Kw * stride;
     const float* scur = wq + buf * Kw;
     float* snxt = wq + (buf ^ 1) * Kw;
-    int Kt = ks ? ks[kl] : Kw;  // K_t of the step's lower level
+    int Kt = ks ? __builtin_amdgcn_readfirstlane(ks[kl]) : Kw;  // K_t of the step's lower level
     Kt = Kt > Kw ? Kw : (Kt < 1 ? 1 : Kt);
     const float* rh = Rf + r_row_off(n, kh);
     const float* rl = Rf + r_row_off(n, kl);
@@ -495,6 +495,7 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
         sc[SC_STALE] = 0;
         sc[SC_WEXP] = 0;
         sc[SC_BUSY] = a.master_off && W >= 1 ? 1 : 0;
+        sc[SC_NEWW] = 0;
         if (a.master_off) {
             sc[SC_PSIZE] = 0;
             if (W >= 1) {  // worker 0 starts at the root
@@ -530,10 +531,125 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
             break;
         }
         const float r2r = *sc_r2;
+        const uint32_t busy0 = (uint32_t)busy_any;  // the workers busy at the round start
         __syncthreads();  // everyone has read the round-start state
 
-        // ---- A: master
-        if (wave == 0 && !a.master_off) {
+        // one K-best step of worker w (a node handed over this round is set up first)
+        auto worker_advance = [&](const int w) {
+            int* st = wst + 8 * w;
+            uint32_t* wp = wpath + (size_t)w * 2 * Kw * stride;
+            float* wq = wpd + (size_t)w * 2 * Kw;
+            int* sel = wsel + (size_t)w * Kw;
+            if (st[4]) {  // new node: survivor 0 = master prefix + its symbol(s)
+                const int d = st[5], lev = n - d * J;
+                uint32_t* dst = wp;  // buffer 0, survivor 0
+                for (int i = lane; i < nw; i += WAVE) {
+                    uint32_t v = mpath[i];
+                    if (d > 0 && i == (lev >> 2)) {  // J = 2: lev is even, lev + 1 in the same word
+                        if constexpr (J == 2) v = put_pair<P>(v, lev, st[6]);
+                        else v = put_byte(v, lev, st[6]);
+                    }
+                    dst[i] = v;
+                }
+                if (lane == 0) {
+                    wq[0] = reinterpret_cast<float*>(st)[7];
+                    st[1] = d;
+                    st[2] = 1;
+                    st[3] = 0;
+                    st[4] = 0;
+                }
+                wave_sync();
+            }
+            const int depth = __builtin_amdgcn_readfirstlane(st[1]), cnt = __builtin_amdgcn_readfirstlane(st[2]),
+                      buf = __builtin_amdgcn_readfirstlane(st[3]);
+            if constexpr (J == 2) {
+                worker_step_pair<P, E, ST>(n, Rf, zf, rs, cs, r2r, ks, Kw, w, depth, cnt, buf, st, wp, wq, sel, nw,
+                                           stride, sc, cpd, cinfo, cok, lane);
+            } else {
+            const int k = n - depth - 1;
+            uint32_t* pcur = wp + buf * Kw * stride;
+            uint32_t* pnxt = wp + (buf ^ 1) * Kw * stride;
+            float* scur = wq + buf * Kw;
+            float* snxt = wq + (buf ^ 1) * Kw;
+            int Kt = ks ? __builtin_amdgcn_readfirstlane(ks[k]) : Kw;
+            Kt = Kt > Kw ? Kw : (Kt < 1 ? 1 : Kt);
+            const float* rk = Rf + r_row_off(n, k);
+            // row sum (uniform) and per-survivor dot products: P lanes per survivor
+            const float rsum = row_sum<ST>(rk, k, n, rs, cs, lane);
+            const int s = lane / P, cc = lane % P;
+            float acc = 0.f;
+            if (s < cnt) {
+                const uint32_t* prow = pcur + s * stride;
+                for (int wd = (k + 1) / 4 + cc; wd < nw; wd += P) {
+                    const uint32_t dw = prow[wd];
+                    const int j0 = 4 * wd;
+                    if (j0 > k && j0 + 4 <= n) {  // the whole word lies above level k
+#pragma unroll
+                        for (int bb = 0; bb < 4; ++bb)
+                            acc = fmaf(rget<ST>(rk, j0 + bb - k, cs), (float)((dw >> (8 * bb)) & 0xffu), acc);
+                    } else {
+#pragma unroll
+                        for (int bb = 0; bb < 4; ++bb) {
+                            const int j = j0 + bb;
+                            if (j > k && j < n)
+                                acc = fmaf(rget<ST>(rk, j - k, cs), (float)((dw >> (8 * bb)) & 0xffu), acc);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int m = 1; m < P; m <<= 1) acc += shfl_xor_f(acc, m);
+            const float b = zf[k] - (2.f * acc - (float)(P - 1) * rsum);
+            const float rkk = rget<ST>(rk, 0, cs);
+            // a NaN or infinity in R or z: the frame's search stops after this round
+            const bool bad = __ballot(!__builtin_isfinite(rkk) || (s < cnt && !__builtin_isfinite(b))) != 0;
+            if (bad && lane == 0) {
+                sc[SC_DONE] = 1;
+                atomicOr(reinterpret_cast<unsigned int*>(&sc[SC_FLAGS]), MIMO_FLAG_NONFINITE_INPUT);
+            }
+            uint64_t key[1] = {~0ull};
+            if (s < cnt && !bad) {
+                const float ee = fmaf(-rkk, (float)(2 * cc - (P - 1)), b);
+                const float pdc = fmaf(ee, ee, scur[s]);
+                if (pdc < r2r) key[0] = ((uint64_t)__float_as_uint(pdc) << 32) | (uint32_t)lane;
+            }
+            bitonic_sort<1>(key, lane);
+            const int nvalid = __popcll(__ballot(key[0] != ~0ull));
+            if (lane == 0) atomicAdd(&sc[SC_WEXP], cnt);
+            if (nvalid == 0) {
+                if (lane == 0) {
+                    st[0] = 0;
+                    atomicAnd(reinterpret_cast<unsigned int*>(&sc[SC_BUSY]), ~(1u << w));
+                }
+            } else {
+                const int keep = Kt < nvalid ? Kt : nvalid;
+                if (lane < keep) {
+                    snxt[lane] = __uint_as_float((uint32_t)(key[0] >> 32));
+                    sel[lane] = (int)(uint32_t)key[0];
+                }
+                wave_sync();
+                gather_paths<P, 1>(pcur, pnxt, sel, keep, k, nw, stride, lane);
+                if (lane == 0) {
+                    st[2] = keep;
+                    st[3] = buf ^ 1;
+                    st[1] = depth + 1;
+                    if (k == 0) {  // leaves: offer the best survivor
+                        cpd[1 + w] = snxt[0];
+                        cinfo[1 + w] = buf ^ 1;
+                        cok[1 + w] = 1;
+                        st[0] = 0;
+                        atomicAnd(reinterpret_cast<unsigned int*>(&sc[SC_BUSY]), ~(1u << w));
+                    }
+                }
+            }
+            }
+        };
+
+        // ---- A: the master expands a node, while the workers busy since an
+        // earlier round advance (C for them: neither reads what the other writes)
+        if (wave >= 1 && wave <= W) {
+            if ((busy0 >> (wave - 1)) & 1u) worker_advance(wave - 1);
+        } else if (wave == 0 && !a.master_off) {
             int ok = 0, d = 0, c = 0;
             float pd = 0.f;
             // pop left-most nodes (deepest depth, best sibling) until one lies
@@ -542,8 +658,8 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
             // as a discarded pop)
             while (sc[SC_PSIZE] > 0) {  // uniform over wave 0
                 const int dd = pool_deepest(pmask, lane);
-                const int lo = plo[dd], hi = phi[dd];
-                const float v = ppd[dd * PC + lo];
+                const int lo = __builtin_amdgcn_readfirstlane(plo[dd]), hi = __builtin_amdgcn_readfirstlane(phi[dd]);
+                const float v = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(ppd[dd * PC + lo])));
                 const int take = v >= r2r ? hi - lo : 1;
                 wave_sync();
                 if (lane == 0) {
@@ -586,7 +702,7 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                 if (!__builtin_isfinite(b) || !__builtin_isfinite(rkk)) {  // uniform: NaN or inf in R or z
                     if (lane == 0) {
                         sc[SC_DONE] = 1;
-                        sc[SC_FLAGS] |= MIMO_FLAG_NONFINITE_INPUT;
+                        atomicOr(reinterpret_cast<unsigned int*>(&sc[SC_FLAGS]), MIMO_FLAG_NONFINITE_INPUT);
                     }
                     ok = 0;
                 }
@@ -645,14 +761,15 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
         // sorted siblings and are discarded together, one pop each, as far
         // as the pool may shrink
         if (wave == 0) {
-            uint64_t idle = ~(uint64_t)(uint32_t)sc[SC_BUSY] & ((1ull << W) - 1ull);
+            uint64_t idle = ~(uint64_t)busy0 & ((1ull << W) - 1ull);  // idle at the round start
             while (idle) {  // uniform over wave 0
                 const int w = __ffsll((long long)idle) - 1;
                 idle &= idle - 1;
                 bool given = false;
                 while (sc[SC_PSIZE] >= 2) {
                     const int dd = pool_shallowest(pmask, lane);
-                    const int lo = plo[dd], hi = phi[dd];
+                    const int lo = __builtin_amdgcn_readfirstlane(plo[dd]);
+                    const int hi = __builtin_amdgcn_readfirstlane(phi[dd]);
                     const float vi = lane < hi - lo ? ppd[dd * PC + lo + lane] : 0.f;
                     const int nst = __popcll(__ballot(lane < hi - lo && vi >= r2r));
                     const int psz = sc[SC_PSIZE];
@@ -668,6 +785,7 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                             int* st = wst + 8 * w;
                             st[0] = 1;
                             sc[SC_BUSY] |= 1 << w;
+                            sc[SC_NEWW] |= 1 << w;
                             st[4] = 1;
                             st[5] = dd;
                             st[6] = pc[dd * PC + hi - 1];
@@ -685,119 +803,12 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
         }
         __syncthreads();
 
-        // ---- C: busy workers advance one level
-        if (wave >= 1 && wave <= W) {
-            const int w = wave - 1;
-            int* st = wst + 8 * w;
-            if (st[0]) {
-                uint32_t* wp = wpath + (size_t)w * 2 * Kw * stride;
-                float* wq = wpd + (size_t)w * 2 * Kw;
-                int* sel = wsel + (size_t)w * Kw;
-                if (st[4]) {  // new node: survivor 0 = master prefix + its symbol(s)
-                    const int d = st[5], lev = n - d * J;
-                    uint32_t* dst = wp;  // buffer 0, survivor 0
-                    for (int i = lane; i < nw; i += WAVE) {
-                        uint32_t v = mpath[i];
-                        if (d > 0 && i == (lev >> 2)) {  // J = 2: lev is even, lev + 1 in the same word
-                            if constexpr (J == 2) v = put_pair<P>(v, lev, st[6]);
-                            else v = put_byte(v, lev, st[6]);
-                        }
-                        dst[i] = v;
-                    }
-                    if (lane == 0) {
-                        wq[0] = reinterpret_cast<float*>(st)[7];
-                        st[1] = d;
-                        st[2] = 1;
-                        st[3] = 0;
-                        st[4] = 0;
-                    }
-                    wave_sync();
-                }
-                const int depth = st[1], cnt = st[2], buf = st[3];
-                if constexpr (J == 2) {
-                    worker_step_pair<P, E, ST>(n, Rf, zf, rs, cs, r2r, ks, Kw, w, depth, cnt, buf, st, wp, wq, sel, nw,
-                                               stride, sc, cpd, cinfo, cok, lane);
-                } else {
-                const int k = n - depth - 1;
-                uint32_t* pcur = wp + buf * Kw * stride;
-                uint32_t* pnxt = wp + (buf ^ 1) * Kw * stride;
-                float* scur = wq + buf * Kw;
-                float* snxt = wq + (buf ^ 1) * Kw;
-                int Kt = ks ? ks[k] : Kw;
-                Kt = Kt > Kw ? Kw : (Kt < 1 ? 1 : Kt);
-                const float* rk = Rf + r_row_off(n, k);
-                // row sum (uniform) and per-survivor dot products: P lanes per survivor
-                const float rsum = row_sum<ST>(rk, k, n, rs, cs, lane);
-                const int s = lane / P, cc = lane % P;
-                float acc = 0.f;
-                if (s < cnt) {
-                    const uint32_t* prow = pcur + s * stride;
-                    for (int wd = (k + 1) / 4 + cc; wd < nw; wd += P) {
-                        const uint32_t dw = prow[wd];
-                        const int j0 = 4 * wd;
-                        if (j0 > k && j0 + 4 <= n) {  // the whole word lies above level k
-#pragma unroll
-                            for (int bb = 0; bb < 4; ++bb)
-                                acc = fmaf(rget<ST>(rk, j0 + bb - k, cs), (float)((dw >> (8 * bb)) & 0xffu), acc);
-                        } else {
-#pragma unroll
-                            for (int bb = 0; bb < 4; ++bb) {
-                                const int j = j0 + bb;
-                                if (j > k && j < n)
-                                    acc = fmaf(rget<ST>(rk, j - k, cs), (float)((dw >> (8 * bb)) & 0xffu), acc);
-                            }
-                        }
-                    }
-                }
-#pragma unroll
-                for (int m = 1; m < P; m <<= 1) acc += shfl_xor_f(acc, m);
-                const float b = zf[k] - (2.f * acc - (float)(P - 1) * rsum);
-                const float rkk = rget<ST>(rk, 0, cs);
-                // a NaN or infinity in R or z: the frame's search stops after this round
-                const bool bad = __ballot(!__builtin_isfinite(rkk) || (s < cnt && !__builtin_isfinite(b))) != 0;
-                if (bad && lane == 0) {
-                    sc[SC_DONE] = 1;
-                    atomicOr(reinterpret_cast<unsigned int*>(&sc[SC_FLAGS]), MIMO_FLAG_NONFINITE_INPUT);
-                }
-                uint64_t key[1] = {~0ull};
-                if (s < cnt && !bad) {
-                    const float ee = fmaf(-rkk, (float)(2 * cc - (P - 1)), b);
-                    const float pdc = fmaf(ee, ee, scur[s]);
-                    if (pdc < r2r) key[0] = ((uint64_t)__float_as_uint(pdc) << 32) | (uint32_t)lane;
-                }
-                bitonic_sort<1>(key, lane);
-                const int nvalid = __popcll(__ballot(key[0] != ~0ull));
-                if (lane == 0) atomicAdd(&sc[SC_WEXP], cnt);
-                if (nvalid == 0) {
-                    if (lane == 0) {
-                        st[0] = 0;
-                        atomicAnd(reinterpret_cast<unsigned int*>(&sc[SC_BUSY]), ~(1u << w));
-                    }
-                } else {
-                    const int keep = Kt < nvalid ? Kt : nvalid;
-                    if (lane < keep) {
-                        snxt[lane] = __uint_as_float((uint32_t)(key[0] >> 32));
-                        sel[lane] = (int)(uint32_t)key[0];
-                    }
-                    wave_sync();
-                    gather_paths<P, 1>(pcur, pnxt, sel, keep, k, nw, stride, lane);
-                    if (lane == 0) {
-                        st[2] = keep;
-                        st[3] = buf ^ 1;
-                        st[1] = depth + 1;
-                        if (k == 0) {  // leaves: offer the best survivor
-                            cpd[1 + w] = snxt[0];
-                            cinfo[1 + w] = buf ^ 1;
-                            cok[1 + w] = 1;
-                            st[0] = 0;
-                            atomicAnd(reinterpret_cast<unsigned int*>(&sc[SC_BUSY]), ~(1u << w));
-                        }
-                    }
-                }
-                }
-            }
+        // ---- C for the workers given a node this round
+        const uint32_t fresh = (uint32_t)sc[SC_NEWW];
+        if (fresh) {  // uniform
+            if (wave >= 1 && wave <= W && ((fresh >> (wave - 1)) & 1u)) worker_advance(wave - 1);
+            __syncthreads();
         }
-        __syncthreads();
 
         // ---- D: merge offers (the smallest pd, the lowest source on ties),
         // shrink the radius once
@@ -827,6 +838,7 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
             if (lane <= W) cok[lane] = 0;
         }
         if (threadIdx.x == 0) {
+            sc[SC_NEWW] = 0;
             uint32_t lo = (uint32_t)sc[SC_EXP_LO];
             const uint32_t add = (uint32_t)sc[SC_WEXP];
             const uint32_t nlo = lo + add;
