@@ -22,6 +22,8 @@
 // A-C use the radius of the start of the round.
 #include "common.hpp"
 
+#include <utility>
+
 namespace mimo {
 
 struct HybArgs {
@@ -894,18 +896,31 @@ template <int P, int J, int E>
 static int32_t launch_hybrid(const HybArgs& a, int B, hipStream_t st, const char* name)
 {
     constexpr int PC = J == 1 ? P : P * P;
-    // c R, z and the row sums in LDS when they fit beside the pool and the worker buffers
-    const bool stage = HybLayout(a.n, a.W, a.Kw, PC, J, 1).total <= 160 * 1024;
-    const HybLayout Lo(a.n, a.W, a.Kw, PC, J, stage);
-    if (Lo.total > 160 * 1024)
-        return fail(MIMO_ERR_UNSUPPORTED, "%s: %zu bytes of LDS needed (n_workers * k_worker too large)", name,
-                    Lo.total);
-    const void* fn = stage ? (const void*)hybrid_kernel<P, J, E, true> : (const void*)hybrid_kernel<P, J, E, false>;
-    if (Lo.total > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lo.total);
-        if (e != hipSuccess) return fail(MIMO_ERR_HIP, "%s: LDS attribute: %s", name, hipGetErrorString(e));
-    }
     const int threads = WAVE * (1 + a.W);
+    const HybLayout Ls(a.n, a.W, a.Kw, PC, J, 1), Lu(a.n, a.W, a.Kw, PC, J, 0);
+    if (Lu.total > 160 * 1024)
+        return fail(MIMO_ERR_UNSUPPORTED, "%s: %zu bytes of LDS needed (n_workers * k_worker too large)", name,
+                    Lu.total);
+    const void* fs = (const void*)hybrid_kernel<P, J, E, true>;
+    const void* fu = (const void*)hybrid_kernel<P, J, E, false>;
+    for (const auto& [f, L] : {std::pair<const void*, size_t>{fs, Ls.total}, {fu, Lu.total}}) {
+        if (L > 64 * 1024 && L <= 160 * 1024) {
+            hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L);
+            if (e != hipSuccess) return fail(MIMO_ERR_HIP, "%s: LDS attribute: %s", name, hipGetErrorString(e));
+        }
+    }
+    // c R, z and the row sums in LDS when they fit and keep at least half of
+    // the workgroups a CU holds without them (measured: staging wins at 1 of
+    // 2 workgroups per CU, loses at 1 of 4)
+    bool stage = false;
+    if (Ls.total <= 160 * 1024) {
+        int occ_s = 0, occ_u = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_s, fs, threads, Ls.total) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_u, fu, threads, Lu.total) != hipSuccess)
+            return fail(MIMO_ERR_HIP, "%s: occupancy query failed", name);
+        stage = occ_s >= 1 && 2 * occ_s >= occ_u;
+    }
+    const HybLayout& Lo = stage ? Ls : Lu;
     if (stage) hipLaunchKernelGGL((hybrid_kernel<P, J, E, true>), dim3(B), dim3(threads), Lo.total, st, a);
     else hipLaunchKernelGGL((hybrid_kernel<P, J, E, false>), dim3(B), dim3(threads), Lo.total, st, a);
     return check_launch(name);
