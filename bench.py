@@ -82,7 +82,7 @@ def parse():
                    help="ablation leg: plain K-best with this K plus the same fallback (0: the learned mean K_t, rounded)")
     p.add_argument("--K", type=int, default=0, help="plain K-best survivors (0: the workload's matched-BER setting)")
     p.add_argument("--workers", type=int, default=3,
-                   help="hybrid workers (SD-K-best legs; errors measured equal for 3 to 15 at 100x100 64-QAM)")
+                   help="hybrid workers (SD-K-best legs; error counts measured equal for 3 to 15 at 100x100 64-QAM)")
     p.add_argument("--k-worker", type=int, default=8)
     p.add_argument("--margin", type=float, default=None)
     p.add_argument("--beta", type=float, default=None)
