@@ -276,16 +276,20 @@ def test_exact_sd_100x100_warm_start(gpu, orc):
     assert agree[same].mean() >= 0.9
 
 
-def test_paper_hybrid_100x100(gpu, orc):
-    """The benchmark's paper-hybrid leg: 15 workers keeping 8 survivors, no
-    radius, no budget, on a sample of its frames."""
+@pytest.mark.parametrize("W", [3, 15])
+def test_paper_hybrid_100x100(gpu, orc, W):
+    """The benchmark's paper-hybrid leg: 3 workers keeping 8 survivors (the
+    benchmark's setting; R read from global memory, the staged copy would
+    leave too few workgroups per CU) and 15 (R staged in LDS), no radius, no
+    budget, on a sample of its frames."""
     f = _c5_frames(5)
-    f2, P, out, sym, pd, flags, ctr = _run(gpu, orc, 100, 100, 64, 0.0, len(f), 15, 8, seed=0, frames=f)
+    f2, P, out, sym, pd, flags, ctr = _run(gpu, orc, 100, 100, 64, 0.0, len(f), W, 8, seed=0, frames=f)
     assert np.all(flags & 8) and np.all(out["flags"] & 8)
-    _check(f, P, out, sym, pd, flags, ctr, "paper hybrid 100x100 W=15 Kw=8", max_frac=0.35)
+    _check(f, P, out, sym, pd, flags, ctr, f"paper hybrid 100x100 W={W} Kw=8", max_frac=0.35)
 
 
-def test_learned_hybrid_100x100(gpu, orc):
+@pytest.mark.parametrize("W", [3, 15])
+def test_learned_hybrid_100x100(gpu, orc, W):
     """The learned-pruning hybrid: the SD master with K-best workers whose
     per-level survivor counts come from the network (k_sched, capped at the
     workers' K_w = 8), on a sample of the benchmark's frames."""
@@ -305,6 +309,6 @@ def test_learned_hybrid_100x100(gpu, orc):
     s2 = torch.from_numpy((10.0 ** (-snr / 10)).astype(np.float32)).cuda()
     ks = learned.schedule(w.cuda(), R, z, s2, 100, P, meta["margin"], meta["k_min"], meta["k_max"])
     sched = ks.cpu().numpy().reshape(len(f), 200)
-    f2, P, out, sym, pd, flags, ctr = _run(gpu, orc, 100, 100, 64, 0.0, len(f), 15, 8, seed=0, frames=f,
+    f2, P, out, sym, pd, flags, ctr = _run(gpu, orc, 100, 100, 64, 0.0, len(f), W, 8, seed=0, frames=f,
                                            sched=sched)
-    _check(f, P, out, sym, pd, flags, ctr, "learned hybrid 100x100 W=15 Kw=8", max_frac=0.35)
+    _check(f, P, out, sym, pd, flags, ctr, f"learned hybrid 100x100 W={W} Kw=8", max_frac=0.35)
