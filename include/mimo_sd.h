@@ -395,9 +395,9 @@ int32_t prune_mlp_loss_grad(const float* w, const float* X, const float* y, int6
 /* Allocation-free variant of prune_mlp_loss_grad, for callers that cannot
  * allocate device memory (code under hipGraph capture, serving or training
  * loops, harnesses that forbid allocation).  Same arguments and results
- * (bit for bit) without the workspace: the per-state activations, deltas and
- * loss partials live in a static device array sized for
- * MIMO_MLP_NOALLOC_MAX_S states (about 16.8 MB), which each GPU the library
+ * (bit for bit) without the workspace: the per-state activations, deltas,
+ * loss partials and partial gradient tiles live in a static device array
+ * sized for MIMO_MLP_NOALLOC_MAX_S states (about 19.7 MB), which each GPU the library
  * runs on holds until the process ends.  S > MIMO_MLP_NOALLOC_MAX_S returns
  * MIMO_ERR_UNSUPPORTED.  Every call on a GPU uses that GPU's one array, so
  * calls that overlap on one GPU (other streams, other host threads) race;

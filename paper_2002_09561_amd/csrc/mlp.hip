@@ -21,8 +21,11 @@
 // Training (loss and gradient) runs one thread per state in FP32: the weights
 // are read at wave-uniform addresses, so they arrive as scalar operands, and
 // the backward pass writes the per-state activations and deltas
-// feature-major ([128][S]); a second kernel reduces the weight gradients over
-// the states in a fixed order (deterministic).
+// feature-major ([128][S]).  The weight gradients are then products over the
+// states, G_[W2|b2] = D2 [H1^T | 1], G_[W1|b1] = D1 [X | 1] and
+// G_[W3|b3] = dout [H2^T | 1], taken in 16 x 16 tiles on the matrix cores
+// (FP32 MFMA 16x16x4) over fixed chunks of states, and the chunks' partial
+// tiles are summed in chunk order: the result does not depend on scheduling.
 #include <mutex>
 
 #include "common.hpp"
@@ -267,41 +270,123 @@ __global__ void __launch_bounds__(256) mlp_backward_states(const float* __restri
     if (threadIdx.x == 0) lpart[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-// gradient reduction: one thread per parameter, states summed in order
-__global__ void __launch_bounds__(256) mlp_backward_reduce(const float* __restrict__ X, int64_t S,
-                                                           const float* __restrict__ H1, const float* __restrict__ H2,
-                                                           const float* __restrict__ D2, const float* __restrict__ D1,
-                                                           const float* __restrict__ dout,
-                                                           const float* __restrict__ lpart, int nlpart,
-                                                           float* __restrict__ grad, float* __restrict__ loss)
+// Weight-gradient tiles.  Tile t < 72: rows 16 (t / 9) .. of D2, columns
+// 16 (t % 9) .. of [H1^T | 1] (column 128 the ones); t < 80: rows 16 (t - 72)
+// .. of D1, columns [X | 1] (column 4 the ones); t < 89: row 0 is dout,
+// columns 16 (t - 80) .. of [H2^T | 1].  Entries past the sources are zero.
+constexpr int GT_W2 = 0, GT_W1 = 72, GT_W3 = 80, GT_N = 89;
+constexpr int G_CHUNK_MIN = 256;  // states per chunk, at least
+constexpr int G_CHUNKS_MAX = 64;
+
+__host__ __device__ constexpr int grad_chunks(int64_t S)
+{
+    const int64_t c = (S + G_CHUNK_MIN - 1) / G_CHUNK_MIN;
+    return (int)(c < 1 ? 1 : (c > G_CHUNKS_MAX ? G_CHUNKS_MAX : c));
+}
+
+// states per chunk: a multiple of 16 (four MFMA k-steps per load round)
+__host__ __device__ inline int64_t grad_chunk_len(int64_t S)
+{
+    const int C = grad_chunks(S);
+    const int64_t L = (S + C - 1) / C;
+    return (L + 15) & ~(int64_t)15;
+}
+
+// row r of the A operand of tile t at state s
+__device__ __forceinline__ float grad_a(int t, int r, int64_t s, int64_t S, const float* __restrict__ D2,
+                                        const float* __restrict__ D1, const float* __restrict__ dout)
+{
+    if (s >= S) return 0.f;
+    if (t < GT_W1) return D2[(int64_t)(16 * (t / 9) + r) * S + s];
+    if (t < GT_W3) return D1[(int64_t)(16 * (t - GT_W1) + r) * S + s];
+    return r == 0 ? dout[s] : 0.f;
+}
+
+// column c of the B operand of tile t at state s
+__device__ __forceinline__ float grad_b(int t, int c, int64_t s, int64_t S, const float* __restrict__ H1,
+                                        const float* __restrict__ X, const float* __restrict__ H2)
+{
+    if (s >= S) return 0.f;
+    if (t < GT_W1) {
+        const int j = 16 * (t % 9) + c;
+        return j < HID ? H1[(int64_t)j * S + s] : (j == HID ? 1.f : 0.f);
+    }
+    if (t < GT_W3) return c < NIN ? X[s * NIN + c] : (c == NIN ? 1.f : 0.f);
+    const int j = 16 * (t - GT_W3) + c;
+    return j < HID ? H2[(int64_t)j * S + s] : (j == HID ? 1.f : 0.f);
+}
+
+typedef float f32x4g __attribute__((ext_vector_type(4)));
+
+// one wavefront per (tile, chunk): the chunk's partial 16 x 16 tile.  Lane l
+// feeds row / column l % 16 at states s0 + 4 (l / 16) + e of the e-th of four
+// MFMA k-steps (the same states for A and B, so each step sums over them)
+__global__ void __launch_bounds__(256) mlp_grad_tiles(int64_t S, const float* __restrict__ X,
+                                                      const float* __restrict__ H1, const float* __restrict__ H2,
+                                                      const float* __restrict__ D2, const float* __restrict__ D1,
+                                                      const float* __restrict__ dout, float* __restrict__ part)
+{
+    const int job = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x >> 6);
+    const int C = grad_chunks(S);
+    if (job >= GT_N * C) return;  // uniform per wavefront
+    const int lane = threadIdx.x & 63;
+    const int t = job % GT_N, c = job / GT_N;
+    const int64_t L = grad_chunk_len(S), s_beg = (int64_t)c * L, s_end = s_beg + L;
+    const int rc = lane & 15, kq = lane >> 4;
+    f32x4g acc = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t s0 = s_beg; s0 < s_end; s0 += 16) {
+        float a[4], b[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t s = s0 + 4 * kq + e;
+            a[e] = grad_a(t, rc, s, S, D2, D1, dout);
+            b[e] = grad_b(t, rc, s, S, H1, X, H2);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b[e], acc, 0, 0, 0);
+    }
+    // lane l holds rows 4 (l / 16) + i of column l % 16
+    float* out = part + ((size_t)c * GT_N + t) * 256;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) out[(4 * kq + i) * 16 + rc] = acc[i];
+}
+
+// one thread per parameter (and one for the loss): its tile entry summed
+// over the chunks in order
+__global__ void __launch_bounds__(256) mlp_grad_sum(int64_t S, const float* __restrict__ part,
+                                                    const float* __restrict__ lpart, int nlpart,
+                                                    float* __restrict__ grad, float* __restrict__ loss)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= MIMO_MLP_NPARAM + 1) return;
-    float acc = 0.f;
-    if (p < OB1) {  // W1[i][j] = sum_s D1[i][s] X[s][j]
-        const int i = p / NIN, j = p % NIN;
-        for (int64_t s = 0; s < S; ++s) acc = fmaf(D1[(int64_t)i * S + s], X[s * NIN + j], acc);
-    } else if (p < OW2) {
-        const int i = p - OB1;
-        for (int64_t s = 0; s < S; ++s) acc += D1[(int64_t)i * S + s];
-    } else if (p < OB2) {
-        const int i = (p - OW2) / HID, j = (p - OW2) % HID;
-        const float* a = D2 + (int64_t)i * S;
-        const float* b = H1 + (int64_t)j * S;
-        for (int64_t s = 0; s < S; ++s) acc = fmaf(a[s], b[s], acc);
-    } else if (p < OW3) {
-        const int i = p - OB2;
-        for (int64_t s = 0; s < S; ++s) acc += D2[(int64_t)i * S + s];
-    } else if (p < OB3) {
-        const int j = p - OW3;
-        for (int64_t s = 0; s < S; ++s) acc = fmaf(dout[s], H2[(int64_t)j * S + s], acc);
-    } else if (p == OB3) {
-        for (int64_t s = 0; s < S; ++s) acc += dout[s];
-    } else {  // p == NPARAM: the loss
+    if (p > MIMO_MLP_NPARAM) return;
+    if (p == MIMO_MLP_NPARAM) {
+        float acc = 0.f;
         for (int b = 0; b < nlpart; ++b) acc += lpart[b];
         *loss = acc / (float)S;
         return;
     }
+    int t, r, col;
+    if (p < OB1) {  // W1[i][j]
+        const int i = p / NIN;
+        t = GT_W1 + i / 16, r = i % 16, col = p % NIN;
+    } else if (p < OW2) {  // b1[i]
+        const int i = p - OB1;
+        t = GT_W1 + i / 16, r = i % 16, col = NIN;
+    } else if (p < OB2) {  // W2[i][j]
+        const int i = (p - OW2) / HID, j = (p - OW2) % HID;
+        t = GT_W2 + 9 * (i / 16) + j / 16, r = i % 16, col = j % 16;
+    } else if (p < OW3) {  // b2[i]
+        const int i = p - OB2;
+        t = GT_W2 + 9 * (i / 16) + 8, r = i % 16, col = 0;
+    } else if (p < OB3) {  // W3[j]
+        const int j = p - OW3;
+        t = GT_W3 + j / 16, r = 0, col = j % 16;
+    } else {  // b3
+        t = GT_W3 + 8, r = 0, col = 0;
+    }
+    const int C = grad_chunks(S);
+    float acc = 0.f;
+    for (int c = 0; c < C; ++c) acc += part[((size_t)c * GT_N + t) * 256 + r * 16 + col];
     grad[p] = acc;
 }
 
@@ -344,9 +429,12 @@ extern "C" int32_t prune_mlp_schedule(const float* w, const float* X, int64_t S,
 
 extern "C" size_t prune_mlp_workspace_bytes(int64_t S)
 {
+    using namespace mimo;
     if (S < 0) S = 0;
     const int64_t nblk = (S + 255) / 256;
-    return sizeof(float) * (size_t)(4 * HID * S + S + nblk + 64);
+    // activations and deltas, dout, loss partials (padded to 64 floats), then the partial tiles
+    const int64_t head = (4 * HID * S + S + nblk + 64 + 63) & ~(int64_t)63;
+    return sizeof(float) * (size_t)(head + (int64_t)grad_chunks(S) * GT_N * 256);
 }
 
 namespace mimo {
@@ -368,8 +456,13 @@ static int32_t mlp_loss_grad_ws(const char* who, const float* w, const float* X,
                        lpart);
     int32_t rc = check_launch(who);
     if (rc) return rc;
-    hipLaunchKernelGGL(mlp_backward_reduce, dim3((MIMO_MLP_NPARAM + 1 + 255) / 256), dim3(256), 0, st, X, S, H1, H2,
-                       D2, D1, dout, lpart, nblk, grad, loss);
+    float* part = f + ((4 * HID * S + S + nblk + 64 + 63) & ~(int64_t)63);
+    const int jobs = GT_N * grad_chunks(S);
+    hipLaunchKernelGGL(mlp_grad_tiles, dim3((jobs + 3) / 4), dim3(256), 0, st, S, X, H1, H2, D2, D1, dout, part);
+    rc = check_launch(who);
+    if (rc) return rc;
+    hipLaunchKernelGGL(mlp_grad_sum, dim3((MIMO_MLP_NPARAM + 1 + 255) / 256), dim3(256), 0, st, S, part, lpart, nblk,
+                       grad, loss);
     return check_launch(who);
 }
 
@@ -387,8 +480,10 @@ static int32_t mlp_loss_grad_check(const char* who, const float* w, const float*
 // for the life of the process.  Host code never passes the array's name to
 // a kernel (on the host it is only a stand-in for the symbol): the device
 // address is looked up once per device with that device current and kept.
-constexpr size_t NOALLOC_FLOATS = (size_t)4 * HID * MIMO_MLP_NOALLOC_MAX_S + MIMO_MLP_NOALLOC_MAX_S +
-                                  (MIMO_MLP_NOALLOC_MAX_S + 255) / 256 + 64;
+constexpr size_t NOALLOC_FLOATS =
+    (((size_t)4 * HID * MIMO_MLP_NOALLOC_MAX_S + MIMO_MLP_NOALLOC_MAX_S + (MIMO_MLP_NOALLOC_MAX_S + 255) / 256 + 64 +
+      63) & ~(size_t)63) +
+    (size_t)grad_chunks(MIMO_MLP_NOALLOC_MAX_S) * GT_N * 256;
 static __device__ __align__(256) float scratch[NOALLOC_FLOATS];
 
 constexpr int MAX_DEVICES = 64;

@@ -68,12 +68,14 @@ def test_mlp_forward_parity(gpu, orc):
     assert np.array_equal(out7, out[:7])
 
 
-def test_mlp_loss_grad_parity(gpu, orc):
+@pytest.mark.parametrize("S", [777, 20000])
+def test_mlp_loss_grad_parity(gpu, orc, S):
+    """Loss and gradient against the FP64 oracle: 777 states (4 chunks of the
+    gradient products, the last one ragged) and 20000 (the 64-chunk cap)."""
     import torch
 
     w = _params(3).astype(np.float32).astype(np.float64)
     rng = np.random.default_rng(4)
-    S = 777
     X = rng.normal(size=(S, 4)).astype(np.float32).astype(np.float64)
     y = (rng.normal(size=S) * 2).astype(np.float32).astype(np.float64)
     loss_o, g_o = orc.mlp_loss_grad(w, X, y, 0.95)
