@@ -24,10 +24,11 @@ and the matched-BER statistics are paired per frame against it.
 
 Other workloads (`--workload`): c2 (16x16 16-QAM, 4-20 dB, plain K-best
 K = 64 and the hybrid), c4 (32x32 16-QAM, 12-20 dB, learned vs plain),
-uneven (1e5 mixed frames in persistent launches), and sdkbest (16x16 64-QAM,
+uneven (1e5 mixed frames in persistent launches), sdkbest (16x16 64-QAM,
 18-28 dB: the SD-K-best and K-best settings of the paper's Sec. VII figures
 on the complex-symbol tree, with symbol error rates and visited-node counts
-beside the values the paper prints).
+beside the values the paper prints), and train (training steps of the
+learned survivor count's network on level states of 32x32 16-QAM frames).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]; prints one JSON line.
 """
@@ -73,7 +74,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--workload", default="c5", choices=["c5", "c2", "c4", "uneven", "sdkbest"])
+    p.add_argument("--workload", default="c5", choices=["c5", "c2", "c4", "uneven", "sdkbest", "train"])
+    p.add_argument("--train-batch", type=int, default=4096, help="states per training step (--workload train)")
     p.add_argument("--frames", type=int, default=0, help="frames per SNR point (0: the workload's)")
     p.add_argument("--snrs", default=None)
     p.add_argument("--detector", default="auto",
@@ -427,6 +429,108 @@ def sdkbest_main(args):
     print(json.dumps(out), flush=True)
 
 
+# ------------------------------------------------------------ training the learned survivor count
+# algorithmic FP32 flops per state of one training step: forward (4x128,
+# 128x128, 128x1 products), the backward delta through W2, and the weight
+# gradients (two flops per multiply-add; biases one add each)
+MLP_FWD_FLOPS = 2 * (4 * 128 + 128 * 128 + 128)
+MLP_TRAIN_FLOPS = MLP_FWD_FLOPS + 2 * 128 * 128 + 2 * (4 * 128 + 128 * 128 + 128) + (128 + 128 + 1)
+
+
+def train_main(args):
+    """One step = the pinball-loss gradient of a batch of level states
+    (prune_mlp_loss_grad: per-state forward and backward, then the weight
+    gradients as products over the states on the matrix cores) and an Adam
+    step.  The states are those the learned detector is trained on: the
+    per-level features of 32x32 16-QAM frames at 12-20 dB, labelled by the
+    GPU's exact SD (learned.training_states), shuffled once and resident in
+    HBM; step i takes the next contiguous batch."""
+    import torch
+
+    from paper_2002_09561_amd import learned, mimo
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    mimo.load()
+    M, QAM, snrs = 32, 16, [12.0, 14.0, 16.0, 18.0, 20.0]
+    frames = args.frames or 1000
+    t_gen = time.perf_counter()
+    X, y, st = learned.training_states(M, QAM, snrs, frames, args.seed, log=lambda *a, **k: None)
+    S, bs = X.shape[0], args.train_batch
+    if S < 2 * bs:
+        raise SystemExit(f"{S} states for batches of {bs}: raise --frames")
+    g = torch.Generator(device="cpu")
+    g.manual_seed(args.seed)
+    perm = torch.randperm(S, generator=g).cuda()
+    X, y = X[perm].contiguous(), y[perm].contiguous()
+    w = torch.from_numpy(learned.init_weights(args.seed)).cuda()
+    m, v = torch.zeros_like(w), torch.zeros_like(w)
+    ws = torch.empty(mimo.mlp_workspace_bytes(bs), device="cuda", dtype=torch.uint8)
+    grad, loss = torch.empty_like(w), torch.empty(1, device="cuda")
+    nb = S // bs
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    ev = {"loss_grad": [], "adam": []}
+    state = {"t": 0}
+
+    def step(record):
+        i = state["t"] % nb
+        state["t"] += 1
+        xb, yb = X[i * bs:(i + 1) * bs], y[i * bs:(i + 1) * bs]
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)] if record else None
+        if record:
+            e[0].record()
+        mimo.mlp_loss_grad(w, xb, yb, 0.95, ws=ws, grad=grad, loss=loss)
+        if record:
+            e[1].record()
+        mimo.mlp_adam_step(w, m, v, grad, state["t"], 1e-3)
+        if record:
+            e[2].record()
+            ev["loss_grad"].append((e[0], e[1]))
+            ev["adam"].append((e[1], e[2]))
+
+    for _ in range(max(1, args.warmup)):
+        step(False)
+    loss0 = float(loss.item())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kms = {k: sum(a.elapsed_time(b) for a, b in v) / len(v) for k, v in ev.items()}
+    flops = MLP_TRAIN_FLOPS * bs
+    achieved = flops / (kms["loss_grad"] * 1e-3) / 1e12
+    out = {"metric": "MLP training states/s (pinball-loss gradient + Adam), 32x32 16-QAM level states, one MI355X",
+           "value": round(bs * args.steps / dt, 1), "unit": "states/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "MLP 4-128-128-1 training steps on 32x32 16-QAM level states, 12-20 dB",
+                      "states": S, "batch": bs, "certified_frames": st["certified"], "frames": st["frames"]},
+           "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
+                        "kernel": "prune_mlp_loss_grad (mlp_backward_states, mlp_grad_tiles, mlp_grad_sum)",
+                        "avg_launch_ms": round(kms["loss_grad"], 4),
+                        "algorithmic_flops_per_launch": flops},
+           "kernel_avg_ms": {k: round(x, 4) for k, x in kms.items()},
+           "loss": {"after_warmup": loss0, "end": float(loss.item())}, "setup_s": round(t_gen, 1)}
+    if not args.no_cpu_baseline:
+        import oracle
+
+        n = min(bs, 2048)
+        w64 = w.cpu().numpy().astype(np.float64)
+        x64, y64 = X[:n].cpu().numpy().astype(np.float64), y[:n].cpu().numpy().astype(np.float64)
+        done, tc = 0, time.perf_counter()
+        while time.perf_counter() - tc < args.cpu_baseline_seconds:
+            oracle.mlp_loss_grad(w64, x64, y64, 0.95)
+            done += n
+        tc = time.perf_counter() - tc
+        out["cpu_baseline"] = {"value": round(done / tc, 1), "unit": "states/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the oracle's FP64 loss and gradient on {n} of the states, repeated for "
+                                         f"{tc:.1f} s (single-threaded C)"}
+    print(json.dumps(out), flush=True)
+
+
 # ------------------------------------------------------------ the sweep workloads
 def main():
     args = parse()
@@ -438,6 +542,8 @@ def main():
         return uneven_main(args)
     if args.workload == "sdkbest":
         return sdkbest_main(args)
+    if args.workload == "train":
+        return train_main(args)
     import torch
 
     from paper_2002_09561_amd import learned, mimo

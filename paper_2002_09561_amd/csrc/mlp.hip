@@ -18,9 +18,9 @@
 //   * layer 3, biases and ReLU in FP32 on the vector ALUs.
 // The hidden units of layer 1 are computed in a permuted order so that its
 // result registers are already laid out as layer 2's B operand.
-// Training (loss and gradient) runs one thread per state in FP32: the weights
-// are read at wave-uniform addresses, so they arrive as scalar operands, and
-// the backward pass writes the per-state activations and deltas
+// Training (loss and gradient) runs in FP32 on the matrix cores (FP32 MFMA
+// 16x16x4), 16 states per wavefront: the forward pass, the loss and the
+// deltas back through W2, with the per-state activations and deltas written
 // feature-major ([128][S]).  The weight gradients are then products over the
 // states, G_[W2|b2] = D2 [H1^T | 1], G_[W1|b1] = D1 [X | 1] and
 // G_[W3|b3] = dout [H2^T | 1], taken in 16 x 16 tiles on the matrix cores
@@ -215,59 +215,138 @@ static int32_t launch_mlp_infer(int64_t S, hipStream_t st, const float* w, const
     return check_launch(SCHED ? "prune_mlp_schedule" : "prune_mlp_forward");
 }
 
-// per state: activations and deltas, feature-major in the workspace
-__global__ void __launch_bounds__(256) mlp_backward_states(const float* __restrict__ w, const float* __restrict__ X,
-                                                           const float* __restrict__ y, int64_t S, float tau,
-                                                           float* __restrict__ H1, float* __restrict__ H2,
-                                                           float* __restrict__ D2, float* __restrict__ D1,
-                                                           float* __restrict__ dout, float* __restrict__ lpart)
+// per state: activations and deltas, feature-major in the workspace, on the
+// matrix cores (FP32 MFMA 16x16x4).  A wavefront takes 16 states, lane l
+// feeding state l % 16: layer 1 is W1 [X^T] (K = 4), layer 2 W2 H1^T and the
+// delta through it W2^T D2^T (K = 128, 32 k-steps per 16 rows); a
+// wavefront's H1^T, then its D2^T, pass through LDS (128 x 16 floats) to
+// become the B operand.  Lane l holds rows 16 rb + 4 (l / 16) + i of each
+// 16-row block rb, column l % 16.  The loss of a workgroup's 64 states is
+// summed in a fixed order into lpart[blockIdx.x].
+constexpr int BK_WAVES = 4, BK_STATES = 16 * BK_WAVES;
+
+__host__ __device__ constexpr int64_t loss_parts(int64_t S) { return (S + BK_STATES - 1) / BK_STATES; }
+
+typedef float f32x4b __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(64 * BK_WAVES) mlp_backward_mfma(const float* __restrict__ w,
+                                                                  const float* __restrict__ X,
+                                                                  const float* __restrict__ y, int64_t S, float tau,
+                                                                  float* __restrict__ H1, float* __restrict__ H2,
+                                                                  float* __restrict__ D2, float* __restrict__ D1,
+                                                                  float* __restrict__ dout,
+                                                                  float* __restrict__ lpart)
 {
-    __shared__ float red[4];
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    float loss = 0.f;
-    if (s < S) {
-        float x[NIN], h1[HID];
+    __shared__ float tb[BK_WAVES][HID][16];
+    __shared__ float red[BK_WAVES];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 15, kq = lane >> 4;
+    const int64_t s = (int64_t)blockIdx.x * BK_STATES + 16 * wave + col;
+    const bool live = s < S;
+    float (*T)[16] = tb[wave];
+
+    // layer 1: a1 = W1 x + b1 (one k-step, K = the 4 features)
+    f32x4b a1[8];
+    {
+        const float xb = live ? X[s * NIN + kq] : 0.f;
 #pragma unroll
-        for (int j = 0; j < NIN; ++j) x[j] = X[s * NIN + j];
-        mlp_layer1(w, x, h1);
-        float out = w[OB3];
-        uint32_t m2[HID / 32] = {0, 0, 0, 0};
-#pragma unroll 2
-        for (int i = 0; i < HID; ++i) {
-            float a = w[OB2 + i];
+        for (int rb = 0; rb < 8; ++rb) {
+            f32x4b c;
 #pragma unroll
-            for (int j = 0; j < HID; ++j) a = fmaf(w[OW2 + i * HID + j], h1[j], a);
-            const float h = fmaxf(a, 0.f);
-            if (a > 0.f) m2[i >> 5] |= 1u << (i & 31);
-            H2[(int64_t)i * S + s] = h;
-            out = fmaf(w[OW3 + i], h, out);
-        }
-        const float r = y[s] - out;
-        loss = r > 0.f ? tau * r : (tau - 1.f) * r;
-        const float dz = (r > 0.f ? -tau : 1.f - tau) / (float)S;
-        dout[s] = dz;
-        float d1[HID];
-#pragma unroll
-        for (int j = 0; j < HID; ++j) d1[j] = 0.f;
-#pragma unroll 2
-        for (int i = 0; i < HID; ++i) {
-            const float d2 = ((m2[i >> 5] >> (i & 31)) & 1u) ? dz * w[OW3 + i] : 0.f;
-            D2[(int64_t)i * S + s] = d2;
-#pragma unroll
-            for (int j = 0; j < HID; ++j) d1[j] = fmaf(w[OW2 + i * HID + j], d2, d1[j]);
-        }
-#pragma unroll
-        for (int j = 0; j < HID; ++j) {
-            D1[(int64_t)j * S + s] = h1[j] > 0.f ? d1[j] : 0.f;
-            H1[(int64_t)j * S + s] = h1[j];
+            for (int i = 0; i < 4; ++i) c[i] = w[OB1 + 16 * rb + 4 * kq + i];
+            a1[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[OW1 + (16 * rb + col) * NIN + kq], xb, c, 0, 0, 0);
         }
     }
-    // deterministic loss partial per block
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) loss += __shfl_xor(loss, m, WAVE);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = loss;
+    for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * rb + 4 * kq + i;
+            const float h = fmaxf(a1[rb][i], 0.f);
+            T[r][col] = h;
+            if (live) H1[(int64_t)r * S + s] = h;
+        }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    // layer 2: a2 = W2 h1 + b2
+    f32x4b a2[8];
+#pragma unroll
+    for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a2[rb][i] = w[OB2 + 16 * rb + 4 * kq + i];
+    for (int q = 0; q < HID / 4; ++q) {
+        const float b = T[4 * q + kq][col];
+#pragma unroll
+        for (int rb = 0; rb < 8; ++rb)
+            a2[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[OW2 + (16 * rb + col) * HID + 4 * q + kq], b, a2[rb], 0,
+                                                          0, 0);
+    }
+    // ReLU, layer 3 (this lane's 32 rows, then the four row groups of the column)
+    float out = 0.f;
+#pragma unroll
+    for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * rb + 4 * kq + i;
+            const float h = fmaxf(a2[rb][i], 0.f);
+            if (live) H2[(int64_t)r * S + s] = h;
+            out = fmaf(w[OW3 + r], h, out);
+        }
+    out += __shfl_xor(out, 16, WAVE);
+    out += __shfl_xor(out, 32, WAVE);
+    out += w[OB3];
+    const float r = live ? y[s] - out : 0.f;
+    const float loss = live ? (r > 0.f ? tau * r : (tau - 1.f) * r) : 0.f;
+    const float dz = live ? (r > 0.f ? -tau : 1.f - tau) / (float)S : 0.f;
+    if (live && kq == 0) dout[s] = dz;
+
+    // delta of layer 2 (zero where the ReLU was off), into LDS for the delta through W2
+    __builtin_amdgcn_wave_barrier();  // every lane has read T for layer 2
+#pragma unroll
+    for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int rr = 16 * rb + 4 * kq + i;
+            const float d2 = a2[rb][i] > 0.f ? dz * w[OW3 + rr] : 0.f;
+            T[rr][col] = d2;
+            if (live) D2[(int64_t)rr * S + s] = d2;
+        }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // delta of layer 1: W2^T d2, masked by layer 1's ReLU
+    f32x4b d1[8];
+#pragma unroll
+    for (int rb = 0; rb < 8; ++rb) d1[rb] = f32x4b{0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < HID / 4; ++q) {
+        const float b = T[4 * q + kq][col];
+#pragma unroll
+        for (int rb = 0; rb < 8; ++rb)
+            d1[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[OW2 + (4 * q + kq) * HID + 16 * rb + col], b, d1[rb], 0,
+                                                          0, 0);
+    }
+    if (live) {
+#pragma unroll
+        for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int rr = 16 * rb + 4 * kq + i;
+                D1[(int64_t)rr * S + s] = a1[rb][i] > 0.f ? d1[rb][i] : 0.f;
+            }
+    }
+    // the workgroup's loss: columns 0..15 of each wavefront in order, then the wavefronts
+    float l = kq == 0 ? loss : 0.f;
+#pragma unroll
+    for (int m = 1; m < 16; m <<= 1) l += __shfl_xor(l, m, WAVE);
+    if (lane == 0) red[wave] = l;
     __syncthreads();
-    if (threadIdx.x == 0) lpart[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    if (threadIdx.x == 0) {
+        float t = 0.f;
+        for (int v = 0; v < BK_WAVES; ++v) t += red[v];
+        lpart[blockIdx.x] = t;
+    }
 }
 
 // Weight-gradient tiles.  Tile t < 72: rows 16 (t / 9) .. of D2, columns
@@ -431,7 +510,7 @@ extern "C" size_t prune_mlp_workspace_bytes(int64_t S)
 {
     using namespace mimo;
     if (S < 0) S = 0;
-    const int64_t nblk = (S + 255) / 256;
+    const int64_t nblk = loss_parts(S);
     // activations and deltas, dout, loss partials (padded to 64 floats), then the partial tiles
     const int64_t head = (4 * HID * S + S + nblk + 64 + 63) & ~(int64_t)63;
     return sizeof(float) * (size_t)(head + (int64_t)grad_chunks(S) * GT_N * 256);
@@ -451,9 +530,9 @@ static int32_t mlp_loss_grad_ws(const char* who, const float* w, const float* X,
     float* D1 = D2 + HID * S;
     float* dout = D1 + HID * S;
     float* lpart = dout + S;
-    const int nblk = (int)((S + 255) / 256);
-    hipLaunchKernelGGL(mlp_backward_states, dim3(nblk), dim3(256), 0, st, w, X, y, S, tau, H1, H2, D2, D1, dout,
-                       lpart);
+    const int nblk = (int)loss_parts(S);
+    hipLaunchKernelGGL(mlp_backward_mfma, dim3(nblk), dim3(64 * BK_WAVES), 0, st, w, X, y, S, tau, H1, H2, D2, D1,
+                       dout, lpart);
     int32_t rc = check_launch(who);
     if (rc) return rc;
     float* part = f + ((4 * HID * S + S + nblk + 64 + 63) & ~(int64_t)63);
@@ -481,7 +560,7 @@ static int32_t mlp_loss_grad_check(const char* who, const float* w, const float*
 // a kernel (on the host it is only a stand-in for the symbol): the device
 // address is looked up once per device with that device current and kept.
 constexpr size_t NOALLOC_FLOATS =
-    (((size_t)4 * HID * MIMO_MLP_NOALLOC_MAX_S + MIMO_MLP_NOALLOC_MAX_S + (MIMO_MLP_NOALLOC_MAX_S + 255) / 256 + 64 +
+    (((size_t)4 * HID * MIMO_MLP_NOALLOC_MAX_S + MIMO_MLP_NOALLOC_MAX_S + loss_parts(MIMO_MLP_NOALLOC_MAX_S) + 64 +
       63) & ~(size_t)63) +
     (size_t)grad_chunks(MIMO_MLP_NOALLOC_MAX_S) * GT_N * 256;
 static __device__ __align__(256) float scratch[NOALLOC_FLOATS];
