@@ -227,6 +227,17 @@ def test_hybrid_complex_nonfinite(gpu, orc):
             assert fl[b] & gpu.FLAG_FOUND and np.isfinite(p[b])
 
 
+@pytest.mark.parametrize("J,W", [(1, 3), (1, 15), (2, 3), (2, 15)])
+def test_hybrid_max_size(gpu, orc, J, W):
+    """The largest system, 128x128 (256 real levels, 129 pool depths on the
+    complex tree), 4-QAM at 10 dB with 8 survivors per worker: R read from
+    global memory (the staged copy does not fit beside 15 workers' paths, and
+    with 3 workers it would leave too few workgroups per CU)."""
+    f, P, out, sym, pd, flags, ctr = _run(gpu, orc, 128, 128, 4, 10.0, 6, W, 8, seed=4300 + 10 * J + W,
+                                          budget=300000, J=J)
+    _check(f, P, out, sym, pd, flags, ctr, f"hybrid J={J} 128x128 4-QAM W={W}", max_frac=0.5)
+
+
 # ----------------------------------------------------------------- 100x100 64-QAM, as the benchmark runs it
 def _c5_frames(B_per_snr, seed=2020):
     """A sample of the benchmark's own frames: the first B_per_snr frames of
