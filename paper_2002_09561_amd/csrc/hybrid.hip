@@ -58,6 +58,7 @@ struct HybLayout {
     int nw, stride, nd;  // words per path, padded stride, depths (steps of J levels: n / J + 1)
     size_t o_mpath, o_bpath, o_ppd, o_pc, o_lo, o_hi, o_mask, o_wst, o_wpath, o_wpd, o_sel, o_cand, o_sc, total;
     size_t o_r, o_z, o_rs;  // staged c R, z and row sums (when stage)
+    size_t o_rowb;          // else each worker's copy of the row(s) of c R its step reads: [W][J][n]
     // P: children per step (pam^J)
     __host__ __device__ HybLayout(int n, int W, int Kw, int P, int J, int stage)
     {
@@ -79,11 +80,13 @@ struct HybLayout {
         o_sel = o; o += 4 * (size_t)Wc * Kw;
         o_cand = o; o += 4 * 3 * (Wc + 1);      // pd, ok, info per source
         o_sc = o; o += 64;                      // scalars
-        o_r = o_z = o_rs = o;
+        o_r = o_z = o_rs = o_rowb = o;
         if (stage) {
             o_r = o; o += 4 * (size_t)r_packed_size(n);
             o_z = o; o += 4 * (size_t)n;
             o_rs = o; o += 4 * (size_t)n;
+        } else {
+            o_rowb = o; o += 4 * (size_t)Wc * J * n;
         }
         total = o;
     }
@@ -129,6 +132,53 @@ __device__ __forceinline__ float row_sum(const float* rk, int k, int n, const fl
         for (int t = 1 + lane; t < n - k; t += WAVE) v += cs * rk[t];
         return wave_sum(v);
     }
+}
+
+// Row k of R (entries t >= 1, lane-strided as copy_row_sum reads them) into
+// registers: the next level's row, loaded one round ahead so that the load
+// is in flight across the round's barriers.  pf_k records the row held.
+constexpr int PF_MAX = 4;  // 4 x 64 entries: rows of up to 256 levels
+__device__ inline void prefetch_row(const float* R, int n, int k, float (&pf)[PF_MAX], int lane)
+{
+    const float* rk = R + r_row_off(n, k);
+#pragma unroll
+    for (int i = 0; i < PF_MAX; ++i) {
+        const int t = 1 + lane + WAVE * i;
+        pf[i] = t < n - k ? rk[t] : 0.f;
+    }
+}
+
+// copy_row_sum from prefetched entries (bit-identical: the same values, lanes and order)
+__device__ inline float copy_row_sum_pf(const float* rk, int k, int n, float cs, float* dst, const float (&pf)[PF_MAX],
+                                        int lane)
+{
+    float v = 0.f;
+#pragma unroll
+    for (int i = 0; i < PF_MAX; ++i) {
+        const int t = 1 + lane + WAVE * i;
+        if (t < n - k) {
+            const float x = cs * pf[i];
+            dst[t] = x;
+            v += x;
+        }
+    }
+    if (lane == 0) dst[0] = cs * rk[0];
+    return wave_sum(v);
+}
+
+// Copy row k of R, scaled by c, into the worker's LDS buffer dst (entry t =
+// c R[k][k + t]) with coalesced loads, and return the sum of entries t >= 1
+// made as row_sum<false> makes it (the same lanes, order and reduction)
+__device__ inline float copy_row_sum(const float* rk, int k, int n, float cs, float* dst, int lane)
+{
+    float v = 0.f;
+    for (int t = 1 + lane; t < n - k; t += WAVE) {
+        const float x = cs * rk[t];
+        dst[t] = x;
+        v += x;
+    }
+    if (lane == 0) dst[0] = cs * rk[0];
+    return wave_sum(v);
 }
 
 // Copy the keep selected survivors' paths (sel[i] = parent rank * PC +
@@ -278,7 +328,7 @@ template <int P, int E, bool ST>
 __device__ void worker_step_pair(int n, const float* Rf, const float* zf, const float* rs, float cs, float r2r,
                                  const int32_t* ks, int Kw, int w, int depth, int cnt, int buf, int* st, uint32_t* wp,
                                  float* wq, int* sel, int nw, int stride, int* sc, float* cpd, int* cinfo, int* cok,
-                                 int lane)
+                                 float* rowb, int lane)
 {
     constexpr int PC = P * P;
     const int kh = n - 2 * depth - 1, kl = kh - 1;
@@ -294,15 +344,27 @@ __device__ void worker_step_pair(int n, const float* Rf, const float* zf, const 
     if constexpr (ST) {  // the structural zero R[kl][kh] adds nothing to the staged sum of row kl
         sh = rs[kh];
         sl = rs[kl];
-    } else {
+    } else {  // both rows into this worker's LDS buffers first, summed on the way (j > kh)
+        float* bh = rowb + (size_t)w * 2 * n;
+        float* bl = bh + n;
         sh = 0.f;
         sl = 0.f;
         for (int j = kh + 1 + lane; j < n; j += WAVE) {
-            sh += cs * rh[j - kh];
-            sl += cs * rl[j - kl];
+            const float xh = cs * rh[j - kh], xl = cs * rl[j - kl];
+            bh[j - kh] = xh;
+            bl[j - kl] = xl;
+            sh += xh;
+            sl += xl;
+        }
+        if (lane == 0) {
+            bh[0] = cs * rh[0];
+            bl[0] = cs * rl[0];
         }
         sh = wave_sum(sh);
         sl = wave_sum(sl);
+        wave_sync();
+        rh = bh;
+        rl = bl;
     }
     const int lg = 6 - (cnt <= 1 ? 0 : 32 - __clz(cnt - 1));  // log2 of the lanes per survivor
     const int G = 1 << lg, s = lane >> lg, g = lane & (G - 1);
@@ -316,8 +378,8 @@ __device__ void worker_step_pair(int n, const float* Rf, const float* zf, const 
 #pragma unroll
                 for (int bb = 0; bb < 4; ++bb) {
                     const float v = (float)((dw >> (8 * bb)) & 0xffu);
-                    ah = fmaf(rget<ST>(rh, j0 + bb - kh, cs), v, ah);
-                    al = fmaf(rget<ST>(rl, j0 + bb - kl, cs), v, al);
+                    ah = fmaf(rget<true>(rh, j0 + bb - kh, cs), v, ah);
+                    al = fmaf(rget<true>(rl, j0 + bb - kl, cs), v, al);
                 }
             } else {
 #pragma unroll
@@ -325,8 +387,8 @@ __device__ void worker_step_pair(int n, const float* Rf, const float* zf, const 
                     const int j = j0 + bb;
                     if (j > kh && j < n) {
                         const float v = (float)((dw >> (8 * bb)) & 0xffu);
-                        ah = fmaf(rget<ST>(rh, j - kh, cs), v, ah);
-                        al = fmaf(rget<ST>(rl, j - kl, cs), v, al);
+                        ah = fmaf(rget<true>(rh, j - kh, cs), v, ah);
+                        al = fmaf(rget<true>(rl, j - kl, cs), v, al);
                     }
                 }
             }
@@ -338,7 +400,7 @@ __device__ void worker_step_pair(int n, const float* Rf, const float* zf, const 
     }
     const float bh = zf[kh] - (2.f * ah - (float)(P - 1) * sh);
     const float bl = zf[kl] - (2.f * al - (float)(P - 1) * sl);
-    const float dh = rget<ST>(rh, 0, cs), dl = rget<ST>(rl, 0, cs);
+    const float dh = rget<true>(rh, 0, cs), dl = rget<true>(rl, 0, cs);
     // a NaN or infinity in R or z: the frame's search stops after this round
     const bool bad = __ballot(!__builtin_isfinite(dh) || !__builtin_isfinite(dl) ||
                               (s < cnt && (!__builtin_isfinite(bh) || !__builtin_isfinite(bl)))) != 0;
@@ -454,6 +516,7 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
     const float* Rf = a.R + (size_t)frame * r_packed_size(n);
     const float* zf = a.z + (size_t)frame * n;
     const float* rs = nullptr;  // staged row sums
+    float* rowb = reinterpret_cast<float*>(smem_hy + Lo.o_rowb);  // unstaged: the workers' row buffers
     if constexpr (ST) {  // every level reads c R, z and the row sums from LDS from here on
         float* Rs = reinterpret_cast<float*>(smem_hy + Lo.o_r);
         float* zs = reinterpret_cast<float*>(smem_hy + Lo.o_z);
@@ -473,6 +536,8 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
     }
     const int32_t* ks = a.k_sched ? a.k_sched + (size_t)frame * a.k_sched_stride : nullptr;
 
+    float pf[PF_MAX] = {0.f, 0.f, 0.f, 0.f};  // a worker's prefetched next row (R unstaged)
+    int pf_k = -1;
     // ---- init
     for (int i = threadIdx.x; i < Lo.nd; i += blockDim.x) {
         plo[i] = 0;
@@ -566,7 +631,7 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                       buf = __builtin_amdgcn_readfirstlane(st[3]);
             if constexpr (J == 2) {
                 worker_step_pair<P, E, ST>(n, Rf, zf, rs, cs, r2r, ks, Kw, w, depth, cnt, buf, st, wp, wq, sel, nw,
-                                           stride, sc, cpd, cinfo, cok, lane);
+                                           stride, sc, cpd, cinfo, cok, rowb, lane);
             } else {
             const int k = n - depth - 1;
             uint32_t* pcur = wp + buf * Kw * stride;
@@ -577,7 +642,19 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
             Kt = Kt > Kw ? Kw : (Kt < 1 ? 1 : Kt);
             const float* rk = Rf + r_row_off(n, k);
             // row sum (uniform) and per-survivor dot products: P lanes per survivor
-            const float rsum = row_sum<ST>(rk, k, n, rs, cs, lane);
+            float rsum;
+            if constexpr (ST) {
+                rsum = rs[k];
+            } else {  // the row into this worker's LDS buffer first (c R, summed on the way)
+                float* bk = rowb + (size_t)w * n;
+                rsum = pf_k == k ? copy_row_sum_pf(rk, k, n, cs, bk, pf, lane) : copy_row_sum(rk, k, n, cs, bk, lane);
+                wave_sync();
+                rk = bk;
+                if (k > 0) {  // the row of the next level, in flight until the next step
+                    prefetch_row(Rf, n, k - 1, pf, lane);
+                    pf_k = k - 1;
+                }
+            }
             const int s = lane / P, cc = lane % P;
             float acc = 0.f;
             if (s < cnt) {
@@ -588,13 +665,13 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                     if (j0 > k && j0 + 4 <= n) {  // the whole word lies above level k
 #pragma unroll
                         for (int bb = 0; bb < 4; ++bb)
-                            acc = fmaf(rget<ST>(rk, j0 + bb - k, cs), (float)((dw >> (8 * bb)) & 0xffu), acc);
+                            acc = fmaf(rget<true>(rk, j0 + bb - k, cs), (float)((dw >> (8 * bb)) & 0xffu), acc);
                     } else {
 #pragma unroll
                         for (int bb = 0; bb < 4; ++bb) {
                             const int j = j0 + bb;
                             if (j > k && j < n)
-                                acc = fmaf(rget<ST>(rk, j - k, cs), (float)((dw >> (8 * bb)) & 0xffu), acc);
+                                acc = fmaf(rget<true>(rk, j - k, cs), (float)((dw >> (8 * bb)) & 0xffu), acc);
                         }
                     }
                 }
@@ -602,7 +679,7 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
 #pragma unroll
             for (int m = 1; m < P; m <<= 1) acc += shfl_xor_f(acc, m);
             const float b = zf[k] - (2.f * acc - (float)(P - 1) * rsum);
-            const float rkk = rget<ST>(rk, 0, cs);
+            const float rkk = rget<true>(rk, 0, cs);
             // a NaN or infinity in R or z: the frame's search stops after this round
             const bool bad = __ballot(!__builtin_isfinite(rkk) || (s < cnt && !__builtin_isfinite(b))) != 0;
             if (bad && lane == 0) {
