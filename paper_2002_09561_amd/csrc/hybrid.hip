@@ -70,7 +70,7 @@ struct HybLayout {
         o_mpath = o; o += 4 * nw;
         o_bpath = o; o += 4 * nw;
         o_ppd = o; o += 4 * (size_t)nd * P;
-        o_pc = o; o += 4 * (size_t)nd * P;
+        o_pc = o; o += ((size_t)nd * P + 3) & ~(size_t)3;  // child index bytes
         o_lo = o; o += 4 * nd;
         o_hi = o; o += 4 * nd;
         o_mask = o; o += 4 * 9;
@@ -244,7 +244,7 @@ __device__ inline int pool_shallowest(const uint32_t* pmask, int lane)
 // sort and stored at depth d + 1, or the best leaf is offered.
 template <int P, bool ST>
 __device__ void master_expand_pair(int n, const float* Rf, const float* zf, const float* rs, float cs, float r2r, int d,
-                                   int c, float pd, uint32_t* mpath, float* ppd, int* pc, int* plo, int* phi,
+                                   int c, float pd, uint32_t* mpath, float* ppd, uint8_t* pc, int* plo, int* phi,
                                    uint32_t* pmask, int* sc, float* cpd, int* cinfo, int* cok, int lane)
 {
     constexpr int PC = P * P;
@@ -303,7 +303,7 @@ __device__ void master_expand_pair(int n, const float* Rf, const float* zf, cons
         const int dn = d + 1;
         if (lane < nk) {
             ppd[dn * PC + lane] = kpd;
-            pc[dn * PC + lane] = kc;
+            pc[dn * PC + lane] = (uint8_t)kc;
         }
         if (lane == 0) {
             plo[dn] = 0;
@@ -498,7 +498,7 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
     uint32_t* mpath = reinterpret_cast<uint32_t*>(smem_hy + Lo.o_mpath);
     uint32_t* bpath = reinterpret_cast<uint32_t*>(smem_hy + Lo.o_bpath);
     float* ppd = reinterpret_cast<float*>(smem_hy + Lo.o_ppd);
-    int* pc = reinterpret_cast<int*>(smem_hy + Lo.o_pc);
+    uint8_t* pc = smem_hy + Lo.o_pc;  // the pool's child indices (< 64)
     int* plo = reinterpret_cast<int*>(smem_hy + Lo.o_lo);
     int* phi = reinterpret_cast<int*>(smem_hy + Lo.o_hi);
     uint32_t* pmask = reinterpret_cast<uint32_t*>(smem_hy + Lo.o_mask);
@@ -811,7 +811,7 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                     const int dn = d + 1;
                     if (keep) {
                         ppd[dn * P + rank] = pdc;
-                        pc[dn * P + rank] = lane;
+                        pc[dn * P + rank] = (uint8_t)lane;
                     }
                     if (lane == 0) {
                         plo[dn] = 0;
