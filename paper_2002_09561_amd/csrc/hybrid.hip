@@ -4,7 +4,7 @@
 //
 // The master's list is a depth-first stack, so every pool node at depth d is
 // a child of the master's current path prefix at depth d-1.  The pool is
-// therefore kept as the master path (one byte per level) plus, per depth, a
+// therefore kept as the master path (a 4-bit digit per level) plus, per depth, a
 // short sorted list of remaining siblings (pd, symbol): the left-most node is
 // the best sibling of the deepest non-empty depth, the right-most node is
 // the worst sibling of the shallowest one.
@@ -54,6 +54,8 @@ __device__ inline void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+constexpr int HY_DPW = 8;  // path digits (levels) per 32-bit word
+
 struct HybLayout {
     int nw, stride, nd;  // words per path, padded stride, depths (steps of J levels: n / J + 1)
     size_t o_mpath, o_bpath, o_ppd, o_pc, o_lo, o_hi, o_mask, o_wst, o_wpath, o_wpd, o_sel, o_cand, o_sc, total;
@@ -62,7 +64,7 @@ struct HybLayout {
     // P: children per step (pam^J)
     __host__ __device__ HybLayout(int n, int W, int Kw, int P, int J, int stage)
     {
-        nw = (n + 3) / 4;
+        nw = (n + HY_DPW - 1) / HY_DPW;
         stride = nw + 1;
         nd = n / J + 1;
         const int Wc = W > 0 ? W : 1;
@@ -95,21 +97,22 @@ struct HybLayout {
 // scalar slots (int32 unless noted)
 enum { SC_R2 = 0, SC_FOUND, SC_PSIZE, SC_DONE, SC_FLAGS, SC_EXP_LO, SC_EXP_HI, SC_ROUNDS, SC_STALE, SC_WEXP, SC_BUSY, SC_NEWW };
 
-__device__ inline int get_byte(const uint32_t* p, int j) { return (int)((p[j >> 2] >> (8 * (j & 3))) & 0xffu); }
+// a path holds one 4-bit PAM index per level (P <= 8), eight levels per word
+__device__ inline int get_dig(const uint32_t* p, int j) { return (int)((p[j >> 3] >> (4 * (j & 7))) & 0xfu); }
 
-__device__ inline uint32_t put_byte(uint32_t v, int lev, int c)
+__device__ inline uint32_t put_dig(uint32_t v, int lev, int c)
 {
-    const int sh = 8 * (lev & 3);
-    return (v & ~(0xffu << sh)) | ((uint32_t)c << sh);
+    const int sh = 4 * (lev & 7);
+    return (v & ~(0xfu << sh)) | ((uint32_t)c << sh);
 }
 
-// the two digits of complex child c into the bytes of the even level lev
+// the two digits of complex child c into the nibbles of the even level lev
 // (real part, c % P) and lev + 1 (imaginary part, c / P) of one word
 template <int P>
 __device__ inline uint32_t put_pair(uint32_t v, int lev, int c)
 {
-    const int sh = 8 * (lev & 3);
-    return (v & ~(0xffffu << sh)) | ((uint32_t)(c % P) << sh) | ((uint32_t)(c / P) << (sh + 8));
+    const int sh = 4 * (lev & 7);
+    return (v & ~(0xffu << sh)) | ((uint32_t)(c % P) << sh) | ((uint32_t)(c / P) << (sh + 4));
 }
 
 // entry t of row k of c R: staged rows are scaled already
@@ -182,14 +185,14 @@ __device__ inline float copy_row_sum(const float* rk, int k, int n, float cs, fl
 }
 
 // Copy the keep selected survivors' paths (sel[i] = parent rank * PC +
-// child) to the next buffer from word w0 = lev / 4 on, the child's digit(s)
+// child) to the next buffer from word w0 = lev / 8 on, the child's digit(s)
 // put at level lev; all (survivor, word) pairs at once over the lanes
 template <int P, int J>
 __device__ inline void gather_paths(const uint32_t* pcur, uint32_t* pnxt, const int* sel, int keep, int lev, int nw,
                                     int stride, int lane)
 {
     constexpr int PC = J == 1 ? P : P * P;
-    const int w0 = lev >> 2, nwd = nw - w0, total = keep * nwd;
+    const int w0 = lev >> 3, nwd = nw - w0, total = keep * nwd;
     const float inv = 1.0f / (float)nwd;  // (idx + 0.5) / nwd is 1/2 / nwd or more from the integers
     for (int idx = lane; idx < total; idx += WAVE) {
         const int i = (int)(((float)idx + 0.5f) * inv);
@@ -198,7 +201,7 @@ __device__ inline void gather_paths(const uint32_t* pcur, uint32_t* pnxt, const 
         uint32_t v = pcur[(m / PC) * stride + wd];
         if (wd == w0) {
             if constexpr (J == 2) v = put_pair<P>(v, lev, m % PC);
-            else v = put_byte(v, lev, m % PC);
+            else v = put_dig(v, lev, m % PC);
         }
         pnxt[i * stride + wd] = v;
     }
@@ -254,7 +257,7 @@ __device__ void master_expand_pair(int n, const float* Rf, const float* zf, cons
     const float* rl = Rf + r_row_off(n, kl);
     float ah = 0.f, al = 0.f, sh = 0.f, sl = 0.f;
     for (int j = lev + lane; j < n; j += WAVE) {
-        const int sym = j == lev ? c % P : (j == lev + 1 ? c / P : get_byte(mpath, j));
+        const int sym = j == lev ? c % P : (j == lev + 1 ? c / P : get_dig(mpath, j));
         const float xh = rget<ST>(rh, j - kh, cs), xl = rget<ST>(rl, j - kl, cs);
         ah = fmaf(xh, (float)sym, ah);
         al = fmaf(xl, (float)sym, al);
@@ -313,7 +316,7 @@ __device__ void master_expand_pair(int n, const float* Rf, const float* zf, cons
         }
     }
     if (lane == 0) {
-        if (d > 0) mpath[lev >> 2] = put_pair<P>(mpath[lev >> 2], lev, c);  // the popped node joins the path
+        if (d > 0) mpath[lev >> 3] = put_pair<P>(mpath[lev >> 3], lev, c);  // the popped node joins the path
         uint32_t lo = (uint32_t)sc[SC_EXP_LO] + 1u;
         if (lo == 0u) sc[SC_EXP_HI] += 1;
         sc[SC_EXP_LO] = (int)lo;
@@ -371,22 +374,22 @@ __device__ void worker_step_pair(int n, const float* Rf, const float* zf, const 
     float ah = 0.f, al = 0.f;
     if (s < cnt) {
         const uint32_t* prow = pcur + s * stride;
-        for (int wd = (kh + 1) / 4 + g; wd < nw; wd += G) {
+        for (int wd = (kh + 1) / HY_DPW + g; wd < nw; wd += G) {
             const uint32_t dw = prow[wd];
-            const int j0 = 4 * wd;
-            if (j0 > kh && j0 + 4 <= n) {  // the whole word lies above the step
+            const int j0 = HY_DPW * wd;
+            if (j0 > kh && j0 + HY_DPW <= n) {  // the whole word lies above the step
 #pragma unroll
-                for (int bb = 0; bb < 4; ++bb) {
-                    const float v = (float)((dw >> (8 * bb)) & 0xffu);
+                for (int bb = 0; bb < HY_DPW; ++bb) {
+                    const float v = (float)((dw >> (4 * bb)) & 0xfu);
                     ah = fmaf(rget<true>(rh, j0 + bb - kh, cs), v, ah);
                     al = fmaf(rget<true>(rl, j0 + bb - kl, cs), v, al);
                 }
             } else {
 #pragma unroll
-                for (int bb = 0; bb < 4; ++bb) {
+                for (int bb = 0; bb < HY_DPW; ++bb) {
                     const int j = j0 + bb;
                     if (j > kh && j < n) {
-                        const float v = (float)((dw >> (8 * bb)) & 0xffu);
+                        const float v = (float)((dw >> (4 * bb)) & 0xfu);
                         ah = fmaf(rget<true>(rh, j - kh, cs), v, ah);
                         al = fmaf(rget<true>(rl, j - kl, cs), v, al);
                     }
@@ -612,9 +615,9 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                 uint32_t* dst = wp;  // buffer 0, survivor 0
                 for (int i = lane; i < nw; i += WAVE) {
                     uint32_t v = mpath[i];
-                    if (d > 0 && i == (lev >> 2)) {  // J = 2: lev is even, lev + 1 in the same word
+                    if (d > 0 && i == (lev >> 3)) {  // J = 2: lev is even, lev + 1 in the same word
                         if constexpr (J == 2) v = put_pair<P>(v, lev, st[6]);
-                        else v = put_byte(v, lev, st[6]);
+                        else v = put_dig(v, lev, st[6]);
                     }
                     dst[i] = v;
                 }
@@ -659,19 +662,19 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
             float acc = 0.f;
             if (s < cnt) {
                 const uint32_t* prow = pcur + s * stride;
-                for (int wd = (k + 1) / 4 + cc; wd < nw; wd += P) {
+                for (int wd = (k + 1) / HY_DPW + cc; wd < nw; wd += P) {
                     const uint32_t dw = prow[wd];
-                    const int j0 = 4 * wd;
-                    if (j0 > k && j0 + 4 <= n) {  // the whole word lies above level k
+                    const int j0 = HY_DPW * wd;
+                    if (j0 > k && j0 + HY_DPW <= n) {  // the whole word lies above level k
 #pragma unroll
-                        for (int bb = 0; bb < 4; ++bb)
-                            acc = fmaf(rget<true>(rk, j0 + bb - k, cs), (float)((dw >> (8 * bb)) & 0xffu), acc);
+                        for (int bb = 0; bb < HY_DPW; ++bb)
+                            acc = fmaf(rget<true>(rk, j0 + bb - k, cs), (float)((dw >> (4 * bb)) & 0xfu), acc);
                     } else {
 #pragma unroll
-                        for (int bb = 0; bb < 4; ++bb) {
+                        for (int bb = 0; bb < HY_DPW; ++bb) {
                             const int j = j0 + bb;
                             if (j > k && j < n)
-                                acc = fmaf(rget<true>(rk, j - k, cs), (float)((dw >> (8 * bb)) & 0xffu), acc);
+                                acc = fmaf(rget<true>(rk, j - k, cs), (float)((dw >> (4 * bb)) & 0xfu), acc);
                         }
                     }
                 }
@@ -768,7 +771,7 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                 float acc = 0.f, rsum = 0.f;
                 for (int t = 1 + lane; t < n - k; t += WAVE) {
                     const int j = k + t;
-                    const int sym = (j == lev) ? c : (int)((mpath[j >> 2] >> (8 * (j & 3))) & 0xffu);
+                    const int sym = (j == lev) ? c : get_dig(mpath, j);
                     const float r = rget<ST>(rk, t, cs);
                     acc = fmaf(r, (float)sym, acc);
                     if constexpr (!ST) rsum += r;
@@ -822,8 +825,7 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                 }
                 if (lane == 0) {
                     if (d > 0) {  // the popped node's symbol joins the master path
-                        const int sh = 8 * (lev & 3);
-                        mpath[lev >> 2] = (mpath[lev >> 2] & ~(0xffu << sh)) | ((uint32_t)c << sh);
+                        mpath[lev >> 3] = put_dig(mpath[lev >> 3], lev, c);
                     }
                     uint32_t lo = (uint32_t)sc[SC_EXP_LO] + 1u;
                     if (lo == 0u) sc[SC_EXP_HI] += 1;
@@ -904,7 +906,7 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
                     uint32_t v = src[i];
                     if (best == 0 && i == 0) {  // the master's leaf: its path plus the child's digit(s) at the bottom
                         if constexpr (J == 2) v = put_pair<P>(v, 0, cinfo[0]);
-                        else v = put_byte(v, 0, cinfo[0]);
+                        else v = put_dig(v, 0, cinfo[0]);
                     }
                     bpath[i] = v;
                 }
@@ -960,8 +962,8 @@ __global__ void __launch_bounds__(1024) hybrid_kernel(HybArgs a)
         for (int m = threadIdx.x; m < n / 2; m += blockDim.x) {
             int v = 0;
             if (found) {
-                const int ire = (bpath[(2 * m) >> 2] >> (8 * ((2 * m) & 3))) & 0xff;
-                const int iim = (bpath[(2 * m + 1) >> 2] >> (8 * ((2 * m + 1) & 3))) & 0xff;
+                const int ire = get_dig(bpath, 2 * m);
+                const int iim = get_dig(bpath, 2 * m + 1);
                 v = ire * P + iim;
             }
             a.sym[(size_t)frame * (n / 2) + m] = v;
