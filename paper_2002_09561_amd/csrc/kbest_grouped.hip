@@ -62,18 +62,36 @@ struct GroupedShape {
     static constexpr int KCAP = WAVE * E / PC;                     // survivor capacity
     static constexpr int L = WAVE / KCAP;                          // lanes per survivor
     static constexpr int NT = KCAP >= 16 ? KCAP / 16 : 1;          // survivor tiles of 16 columns
-    static constexpr int CST = KCAP >= 16 ? KCAP : 16;             // row stride of C in LDS
 };
 
-// LDS of one frame: compaction keys, segment words [G][KCAP][2], C [16][CST],
-// in-group rows [16][16], diagonal [16], z [16], selected pds [KCAP],
-// selected candidates [KCAP], segment parents [G][KCAP] (bytes)
+// LDS of one frame: compaction keys, segment words [G][KCAP][2], in-group
+// rows [16][16], diagonal [16], z [16], selected pds [KCAP], selected
+// candidates [KCAP], segment parents [G][KCAP] (bytes).  The interference C
+// of a group stays in the matrix-core result registers.
 __host__ __device__ inline size_t gk_lds_bytes(int kcap, int G)
 {
-    const int cst = kcap >= 16 ? kcap : 16;
     const size_t segw = ((size_t)2 * G * kcap + 3) & ~(size_t)3;  // whole 16-byte units
-    return sizeof(uint64_t) * 2 * WAVE + sizeof(uint32_t) * segw + sizeof(float) * 16 * cst +
-           sizeof(float) * (256 + 32) + sizeof(float) * kcap + sizeof(int32_t) * kcap + (size_t)G * kcap;
+    return sizeof(uint64_t) * 2 * WAVE + sizeof(uint32_t) * segw + sizeof(float) * (256 + 32) +
+           sizeof(float) * kcap + sizeof(int32_t) * kcap + (size_t)G * kcap;
+}
+
+// Entry (r, col) of the group's interference C held in the result registers
+// of the matrix product: column tile col / 16, in lane 16 (r / 4) + col % 16,
+// element r % 4 (r is uniform, col this lane's own).  One lane permute per
+// column tile, then this lane's tile is kept.
+template <int NT>
+__device__ __forceinline__ float gk_cread(const gk_f32x4 (&c)[NT], int r, int col, int lane)
+{
+    const int i = r & 3;
+    const int src = (((r >> 2) << 4) | (col & 15)) << 2;
+    float v = 0.f;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const float e = i == 0 ? c[t][0] : (i == 1 ? c[t][1] : (i == 2 ? c[t][2] : c[t][3]));
+        const float x = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(e)));
+        v = (col >> 4) == t ? x : v;
+    }
+    return v;
 }
 
 // exact three-way bf16 split of an FP32 value by truncation: hi keeps the
@@ -231,7 +249,7 @@ template <int P, int J, int E>
 __device__ __forceinline__ void kbest_frame_grouped(const KbestArgs& a, int frame, unsigned char* lds)
 {
     using S = GroupedShape<P, J, E>;
-    constexpr int PC = S::PC, KCAP = S::KCAP, L = S::L, NT = S::NT, CST = S::CST;
+    constexpr int PC = S::PC, KCAP = S::KCAP, L = S::L, NT = S::NT;
     static_assert(KCAP >= 1 && KCAP <= 64, "one survivor per lane at most, one at least");
     static_assert(J == 1 || J == 2, "one or two real levels per step");
     static_assert(E * L == PC, "a survivor's lanes hold its children over the E blocks");
@@ -241,8 +259,7 @@ __device__ __forceinline__ void kbest_frame_grouped(const KbestArgs& a, int fram
     const int G = (n + GK_LEVELS - 1) / GK_LEVELS;
     uint64_t* skey = reinterpret_cast<uint64_t*>(lds);
     uint32_t* segb = reinterpret_cast<uint32_t*>(skey + 2 * WAVE);  // [G][KCAP][2]: 16 nibbles
-    float* cg = reinterpret_cast<float*>(segb + ((2 * G * KCAP + 3) & ~3));  // 16-byte aligned
-    float* rg = cg + 16 * CST;
+    float* rg = reinterpret_cast<float*>(segb + ((2 * G * KCAP + 3) & ~3));  // 16-byte aligned
     float* rd = rg + 256;
     float* zg = rd + 16;
     float* sn = zg + 16;
@@ -287,10 +304,10 @@ __device__ __forceinline__ void kbest_frame_grouped(const KbestArgs& a, int fram
             zg[lane] = k < n ? zf[k] : 0.f;
         }
         // interference of the levels above the group, for every survivor, on the matrix cores
-        if (h < G - 1) {
-            gk_f32x4 acc[NT];
+        gk_f32x4 acc[NT];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t] = gk_f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < NT; ++t) acc[t] = gk_f32x4{0.f, 0.f, 0.f, 0.f};
+        if (h < G - 1) {
             const int row = k0 + (lane & 15);                  // A row of this lane (every row exists)
             const int roff = (int)r_row_off(n, row) - row;     // (c R)[row][j] at roff + j
             const int nch = (n - GK_LEVELS * (h + 1) + 31) / 32;
@@ -351,14 +368,6 @@ __device__ __forceinline__ void kbest_frame_grouped(const KbestArgs& a, int fram
                 }
             }
             // lane l holds C rows 4 (l / 16) + i of survivor column 16 t + l % 16
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const int col = 16 * t + (lane & 15);
-                if (col < KCAP) {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) cg[(4 * (lane >> 4) + i) * CST + col] = acc[t][i];
-                }
-            }
         }
         kb_wave_sync();
 
@@ -387,8 +396,8 @@ __device__ __forceinline__ void kbest_frame_grouped(const KbestArgs& a, int fram
                 }
             }
             const bool above = h < G - 1;
-            const float bh = zg[r_hi] - ((above ? cg[r_hi * CST + orig] : 0.f) + dh);
-            const float bl = J == 2 ? zg[r_lo] - ((above ? cg[r_lo * CST + orig] : 0.f) + dl) : 0.f;
+            const float bh = zg[r_hi] - ((above ? gk_cread<NT>(acc, r_hi, orig, lane) : 0.f) + dh);
+            const float bl = J == 2 ? zg[r_lo] - ((above ? gk_cread<NT>(acc, r_lo, orig, lane) : 0.f) + dl) : 0.f;
             const float rkh = rd[r_hi], rkl = rd[r_lo];
             const bool live = s_own < cnt;
             // a NaN or infinity in R or z reaches every centre of the level
