@@ -62,17 +62,19 @@ struct GroupedShape {
     static constexpr int KCAP = WAVE * E / PC;                     // survivor capacity
     static constexpr int L = WAVE / KCAP;                          // lanes per survivor
     static constexpr int NT = KCAP >= 16 ? KCAP / 16 : 1;          // survivor tiles of 16 columns
+    static constexpr int CST = KCAP >= 16 ? KCAP : 16;             // row stride of C in LDS
 };
 
-// LDS of one frame: compaction keys, segment words [G][KCAP][2], in-group
-// rows [16][16], diagonal [16], z [16], selected pds [KCAP], selected
-// candidates [KCAP], segment parents [G][KCAP] (bytes).  The interference C
-// of a group stays in the matrix-core result registers.
-__host__ __device__ inline size_t gk_lds_bytes(int kcap, int G)
+// LDS of one frame: compaction keys, segment words [G][KCAP][2], C [16][CST]
+// unless the group's interference stays in the matrix-core result registers
+// (CR), in-group rows [16][16], diagonal [16], z [16], selected pds [KCAP],
+// selected candidates [KCAP], segment parents [G][KCAP] (bytes)
+__host__ __device__ inline size_t gk_lds_bytes(int kcap, int G, bool cr = false)
 {
+    const int cst = kcap >= 16 ? kcap : 16;
     const size_t segw = ((size_t)2 * G * kcap + 3) & ~(size_t)3;  // whole 16-byte units
-    return sizeof(uint64_t) * 2 * WAVE + sizeof(uint32_t) * segw + sizeof(float) * (256 + 32) +
-           sizeof(float) * kcap + sizeof(int32_t) * kcap + (size_t)G * kcap;
+    return sizeof(uint64_t) * 2 * WAVE + sizeof(uint32_t) * segw + (cr ? 0 : sizeof(float) * 16 * cst) +
+           sizeof(float) * (256 + 32) + sizeof(float) * kcap + sizeof(int32_t) * kcap + (size_t)G * kcap;
 }
 
 // Entry (r, col) of the group's interference C held in the result registers
@@ -245,11 +247,14 @@ __device__ __forceinline__ int gk_select(const uint32_t (&kh)[E], int nvalid, in
     return keep;
 }
 
-template <int P, int J, int E>
+// CR: the group's interference C stays in the matrix-core result registers
+// (read by lane permutes) instead of an LDS tile: fewer LDS bytes per frame,
+// more registers; the host picks the variant that holds more frames per CU.
+template <int P, int J, int E, bool CR>
 __device__ __forceinline__ void kbest_frame_grouped(const KbestArgs& a, int frame, unsigned char* lds)
 {
     using S = GroupedShape<P, J, E>;
-    constexpr int PC = S::PC, KCAP = S::KCAP, L = S::L, NT = S::NT;
+    constexpr int PC = S::PC, KCAP = S::KCAP, L = S::L, NT = S::NT, CST = S::CST;
     static_assert(KCAP >= 1 && KCAP <= 64, "one survivor per lane at most, one at least");
     static_assert(J == 1 || J == 2, "one or two real levels per step");
     static_assert(E * L == PC, "a survivor's lanes hold its children over the E blocks");
@@ -259,7 +264,8 @@ __device__ __forceinline__ void kbest_frame_grouped(const KbestArgs& a, int fram
     const int G = (n + GK_LEVELS - 1) / GK_LEVELS;
     uint64_t* skey = reinterpret_cast<uint64_t*>(lds);
     uint32_t* segb = reinterpret_cast<uint32_t*>(skey + 2 * WAVE);  // [G][KCAP][2]: 16 nibbles
-    float* rg = reinterpret_cast<float*>(segb + ((2 * G * KCAP + 3) & ~3));  // 16-byte aligned
+    float* cg = reinterpret_cast<float*>(segb + ((2 * G * KCAP + 3) & ~3));  // 16-byte aligned
+    float* rg = CR ? cg : cg + 16 * CST;
     float* rd = rg + 256;
     float* zg = rd + 16;
     float* sn = zg + 16;
@@ -368,6 +374,16 @@ __device__ __forceinline__ void kbest_frame_grouped(const KbestArgs& a, int fram
                 }
             }
             // lane l holds C rows 4 (l / 16) + i of survivor column 16 t + l % 16
+            if constexpr (!CR) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const int col = 16 * t + (lane & 15);
+                    if (col < KCAP) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) cg[(4 * (lane >> 4) + i) * CST + col] = acc[t][i];
+                    }
+                }
+            }
         }
         kb_wave_sync();
 
@@ -396,8 +412,18 @@ __device__ __forceinline__ void kbest_frame_grouped(const KbestArgs& a, int fram
                 }
             }
             const bool above = h < G - 1;
-            const float bh = zg[r_hi] - ((above ? gk_cread<NT>(acc, r_hi, orig, lane) : 0.f) + dh);
-            const float bl = J == 2 ? zg[r_lo] - ((above ? gk_cread<NT>(acc, r_lo, orig, lane) : 0.f) + dl) : 0.f;
+            float ch = 0.f, cl = 0.f;  // C at the survivor's origin (the levels above the group)
+            if (above) {
+                if constexpr (CR) {
+                    ch = gk_cread<NT>(acc, r_hi, orig, lane);
+                    if constexpr (J == 2) cl = gk_cread<NT>(acc, r_lo, orig, lane);
+                } else {
+                    ch = cg[r_hi * CST + orig];
+                    if constexpr (J == 2) cl = cg[r_lo * CST + orig];
+                }
+            }
+            const float bh = zg[r_hi] - (ch + dh);
+            const float bl = J == 2 ? zg[r_lo] - (cl + dl) : 0.f;
             const float rkh = rd[r_hi], rkl = rd[r_lo];
             const bool live = s_own < cnt;
             // a NaN or infinity in R or z reaches every centre of the level
@@ -518,20 +544,42 @@ __device__ __forceinline__ void kbest_frame_grouped(const KbestArgs& a, int fram
     }
 }
 
-template <int P, int J, int E>
+template <int P, int J, int E, bool CR>
 __global__ void __launch_bounds__(64) kbest_grouped_kernel(KbestArgs a)
 {
     extern __shared__ unsigned char smem_kbg[];
     if (kb_keep_first(a, blockIdx.x)) return;
-    kbest_frame_grouped<P, J, E>(a, blockIdx.x, smem_kbg);
+    kbest_frame_grouped<P, J, E, CR>(a, blockIdx.x, smem_kbg);
 }
 
+// C in registers where that holds more frames per CU (LDS-bound shapes:
+// many groups), else C in LDS (fewer instructions per level); the register
+// variant exists up to E = 8 blocks.  A fallback or re-run launch detects a
+// few flagged frames of the batch, for which occupancy does not matter: LDS.
 template <int P, int J, int E>
 static int32_t launch_grouped(const KbestArgs& a, int B, hipStream_t st)
 {
     using S = GroupedShape<P, J, E>;
     const int G = (a.n + GK_LEVELS - 1) / GK_LEVELS;
-    hipLaunchKernelGGL((kbest_grouped_kernel<P, J, E>), dim3(B), dim3(WAVE), gk_lds_bytes(S::KCAP, G), st, a);
+    const size_t lds_l = gk_lds_bytes(S::KCAP, G, false);
+    if constexpr (E <= 8) {
+        if (a.fb_sigma2 || a.rerun) {
+            hipLaunchKernelGGL((kbest_grouped_kernel<P, J, E, false>), dim3(B), dim3(WAVE), lds_l, st, a);
+            return check_launch("kbest_detect_grouped");
+        }
+        const size_t lds_r = gk_lds_bytes(S::KCAP, G, true);
+        int occ_r = 0, occ_l = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_r, (const void*)kbest_grouped_kernel<P, J, E, true>,
+                                                         WAVE, lds_r) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_l, (const void*)kbest_grouped_kernel<P, J, E, false>,
+                                                         WAVE, lds_l) != hipSuccess)
+            return fail(MIMO_ERR_HIP, "kbest_detect_grouped: occupancy query failed");
+        if (occ_r > occ_l) {
+            hipLaunchKernelGGL((kbest_grouped_kernel<P, J, E, true>), dim3(B), dim3(WAVE), lds_r, st, a);
+            return check_launch("kbest_detect_grouped");
+        }
+    }
+    hipLaunchKernelGGL((kbest_grouped_kernel<P, J, E, false>), dim3(B), dim3(WAVE), lds_l, st, a);
     return check_launch("kbest_detect_grouped");
 }
 
@@ -624,7 +672,7 @@ constexpr int UNEVEN_CAND_MAX = 256; // K * pam: four blocks of 64 candidates
 template <int P, int E>
 __device__ __forceinline__ void kbest_uneven_one(const KbestArgs& a, unsigned char* lds)
 {
-    kbest_frame_grouped<P, 1, E>(a, 0, lds);
+    kbest_frame_grouped<P, 1, E, false>(a, 0, lds);
 }
 
 __global__ void __launch_bounds__(64) kbest_uneven_kernel(const mimo_frame_desc* __restrict__ desc, int B,
