@@ -231,22 +231,6 @@ __device__ __forceinline__ int kb_select(const uint32_t (&kh)[E], int ncand, int
     return keep;
 }
 
-// Bitonic sort of one register of keys within groups of LIM lanes (LIM a
-// power of two <= 64), ascending in the group of lanes 0 .. LIM-1.
-template <int LIM>
-__device__ __forceinline__ void bitonic_sort_lim(uint64_t& key, int lane)
-{
-#pragma unroll
-    for (int size = 2; size <= LIM; size <<= 1) {
-#pragma unroll
-        for (int j = size >> 1; j > 0; j >>= 1) {
-            const uint64_t o = xor_lanes_u64(key, j, lane);
-            const bool take_max = ((lane & size) != 0) != ((lane & j) != 0);
-            key = ((o < key) != take_max) ? o : key;
-        }
-    }
-}
-
 // Selection by sorting, for at most 128 candidates (ES = 1 or 2 blocks of
 // 64): all candidate keys (pd bits, candidate index; invalid = ~0) are put
 // in order by one in-wave bitonic sort and the first `keep` survive; with one
@@ -271,7 +255,7 @@ __device__ __forceinline__ int kb_select_sort(const uint32_t (&kh)[E], int nvali
             if (e == fe) fh = __shfl(kh[e], fl, WAVE);
         if (fh != ~0u) fkey = ((uint64_t)fh << 32) | (uint32_t)fm;
     }
-    if constexpr (ES == 1) bitonic_sort_lim<LIM>(key[0], lane);
+    if constexpr (ES == 1) sort_lanes<LIM>(key[0], lane);
     else bitonic_sort<ES>(key, lane);
     int fpos = -1;
     if (fkey != ~0ull) {  // the forced candidate's rank = its sorted position
@@ -293,14 +277,6 @@ __device__ __forceinline__ int kb_select_sort(const uint32_t (&kh)[E], int nvali
     }
     *fpos_out = fpos;
     return keep;
-}
-
-// One compare-exchange stage with lane ^ j of a bitonic network on one
-// register of 64 keys (one per lane); keep_min: this lane keeps the smaller.
-__device__ __forceinline__ uint64_t kb_cx(uint64_t key, int j, bool keep_min, int lane)
-{
-    const uint64_t o = xor_lanes_u64(key, j, lane);
-    return ((o < key) == keep_min) ? o : key;
 }
 
 // Selection with a bound, when at least `keep` parents (groups of PC
@@ -365,9 +341,9 @@ __device__ __forceinline__ int kb_select_bounded(const uint32_t (&kh)[E], int nc
     uint64_t key[2];
     key[0] = lane < count ? skey[lane] : ~0ull;
     key[1] = WAVE + lane < count ? skey[WAVE + lane] : ~0ull;
-    if (count <= 16) bitonic_sort_lim<16>(key[0], lane);
-    else if (count <= 32) bitonic_sort_lim<32>(key[0], lane);
-    else if (count <= WAVE) bitonic_sort_lim<WAVE>(key[0], lane);
+    if (count <= 16) sort_lanes<16>(key[0], lane);
+    else if (count <= 32) sort_lanes<32>(key[0], lane);
+    else if (count <= WAVE) sort_lanes<WAVE>(key[0], lane);
     else bitonic_sort<2>(key, lane);
     const bool add_forced = fpos >= keep;  // it takes the last slot
     if (lane < keep) {
@@ -418,16 +394,12 @@ __device__ __forceinline__ int kb_select_merge(const uint32_t (&kh)[E], int ncan
             fpos = below;
         }
     }
-    // 1. sort every block (branch-free: all E blocks are full at nearly every
-    //    level, and a block of padding is sorted already)
+    // 1. sort every block, even ones ascending and odd ones descending
+    //    (branch-free: all E blocks are full at nearly every level)
 #pragma unroll
-    for (int size = 2; size <= WAVE; size <<= 1) {
-#pragma unroll
-        for (int j = size >> 1; j > 0; j >>= 1) {
-            const bool asc_min = ((lane & size) == 0) == ((lane & j) == 0);
-#pragma unroll
-            for (int e = 0; e < E; ++e) key[e] = kb_cx(key[e], j, asc_min != (bool)(e & 1), lane);
-        }
+    for (int e = 0; e < E; ++e) {
+        if (e & 1) sort_lanes<WAVE, true>(key[e], lane);
+        else sort_lanes<WAVE, false>(key[e], lane);
     }
     // 2. merge with truncation: (e, e + w) -> e, direction by the parity of e / 2w
 #pragma unroll
@@ -435,11 +407,8 @@ __device__ __forceinline__ int kb_select_merge(const uint32_t (&kh)[E], int ncan
 #pragma unroll
         for (int e = 0; e < E; e += 2 * w) {
             const uint64_t b = key[e + w];
-            uint64_t c = b < key[e] ? b : key[e];
-            const bool desc = ((e / (2 * w)) & 1) != 0;
-#pragma unroll
-            for (int j = WAVE / 2; j > 0; j >>= 1) c = kb_cx(c, j, ((lane & j) == 0) != desc, lane);
-            key[e] = c;
+            const uint64_t c = b < key[e] ? b : key[e];
+            key[e] = ((e / (2 * w)) & 1) ? merge_lanes<true>(c, lane) : merge_lanes<false>(c, lane);
         }
     }
     const bool add_forced = fpos >= keep;  // it takes the last slot

@@ -131,38 +131,31 @@ __device__ __forceinline__ uint32_t gk_nibbles4(uint32_t b)
 // ~0 and sort among themselves)
 __device__ __forceinline__ void gk_sort_upto(uint64_t& k, int count, int lane)
 {
-    if (count <= 16) bitonic_sort_lim<16>(k, lane);
-    else if (count <= 32) bitonic_sort_lim<32>(k, lane);
-    else bitonic_sort_lim<WAVE>(k, lane);
+    if (count <= 16) sort_lanes<16>(k, lane);
+    else if (count <= 32) sort_lanes<32>(k, lane);
+    else sort_lanes<WAVE>(k, lane);
 }
 
 // the 64 smallest of 64 * E keys (distinct), ascending in key[0]: every
 // block sorted (even ones ascending, odd ones descending), then pairs merged
 // with truncation (the lane-wise minimum of an ascending and a descending
-// block is a bitonic sequence of the 64 smallest of the pair, put in order by
-// six half-cleaner stages)
+// block is a bitonic sequence of the 64 smallest of the pair, put in order
+// by six half-cleaner stages)
 template <int E>
 __device__ __forceinline__ void gk_merge_select(uint64_t (&key)[E], int lane)
 {
 #pragma unroll
-    for (int size = 2; size <= WAVE; size <<= 1) {
-#pragma unroll
-        for (int j = size >> 1; j > 0; j >>= 1) {
-            const bool asc_min = ((lane & size) == 0) == ((lane & j) == 0);
-#pragma unroll
-            for (int e = 0; e < E; ++e) key[e] = kb_cx(key[e], j, asc_min != (bool)(e & 1), lane);
-        }
+    for (int e = 0; e < E; ++e) {
+        if (e & 1) sort_lanes<WAVE, true>(key[e], lane);
+        else sort_lanes<WAVE, false>(key[e], lane);
     }
 #pragma unroll
     for (int w = 1; w < E; w <<= 1) {
 #pragma unroll
         for (int e = 0; e < E; e += 2 * w) {
             const uint64_t b = key[e + w];
-            uint64_t c = b < key[e] ? b : key[e];
-            const bool desc = ((e / (2 * w)) & 1) != 0;
-#pragma unroll
-            for (int j = WAVE / 2; j > 0; j >>= 1) c = kb_cx(c, j, ((lane & j) == 0) != desc, lane);
-            key[e] = c;
+            const uint64_t c = b < key[e] ? b : key[e];
+            key[e] = ((e / (2 * w)) & 1) ? merge_lanes<true>(c, lane) : merge_lanes<false>(c, lane);
         }
     }
 }
@@ -212,16 +205,19 @@ __device__ __forceinline__ int gk_select(const uint32_t (&kh)[E], int nvalid, in
                 if (base <= WAVE) {
                     gk_sort_upto(k0, base, lane);
                 } else {
-                    uint64_t k1 = WAVE + lane < base ? skey[WAVE + lane] : ~0ull;
-                    bitonic_sort_lim<WAVE>(k0, lane);
-                    gk_sort_upto(k1, base - WAVE, lane);
-                    const int rl = (WAVE - 1 - lane) << 2;  // reversed: descending, padding first
-                    const uint32_t rlo = (uint32_t)__builtin_amdgcn_ds_bpermute(rl, (int)(uint32_t)k1);
-                    const uint32_t rhi = (uint32_t)__builtin_amdgcn_ds_bpermute(rl, (int)(uint32_t)(k1 >> 32));
-                    const uint64_t k1r = ((uint64_t)rhi << 32) | rlo;
-                    k0 = k1r < k0 ? k1r : k0;
-#pragma unroll
-                    for (int j = WAVE / 2; j > 0; j >>= 1) k0 = kb_cx(k0, j, (lane & j) == 0, lane);
+                    // the rest descending over the wave: in the top lim lanes
+                    // (lim = 16, 32 or 64 holds them), sorted as complements
+                    const int c1 = base - WAVE;
+                    const int lim = c1 <= 16 ? 16 : (c1 <= 32 ? 32 : WAVE);
+                    const int i1 = lane - (WAVE - lim);
+                    uint64_t k1 = i1 >= 0 && i1 < c1 ? ~skey[WAVE + i1] : 0ull;
+                    sort_lanes<WAVE>(k0, lane);
+                    if (lim == 16) sort_lanes<16>(k1, lane);
+                    else if (lim == 32) sort_lanes<32>(k1, lane);
+                    else sort_lanes<WAVE>(k1, lane);
+                    k1 = ~k1;
+                    k0 = k1 < k0 ? k1 : k0;  // the 64 smallest, a bitonic sequence
+                    k0 = merge_lanes(k0, lane);
                 }
                 res = k0;
                 done = true;
