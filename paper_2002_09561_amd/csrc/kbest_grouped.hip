@@ -168,8 +168,10 @@ __device__ __forceinline__ void gk_merge_select(uint64_t (&key)[E], int lane)
 // children, T, bounds the keep-th smallest key: the keys with pd bits <= T
 // (usually little more than keep) are compacted through LDS and sorted --
 // one register when at most 64, else the first 64 ascending and the rest
-// ascending then reversed, merged with truncation.  Otherwise all blocks
-// are sorted and merged.
+// descending, merged with truncation.  Beyond 128 such keys (a few levels in
+// a hundred at 64 survivors of 64-QAM) the 64th smallest of the first 128 is
+// the tighter bound of a second compaction.  Otherwise all blocks are sorted
+// and merged.
 template <int E>
 __device__ __forceinline__ int gk_select(const uint32_t (&kh)[E], int nvalid, int Kt, int cnt, uint32_t idx0, int L,
                                          int lane, float* sn, int32_t* sel, uint64_t* skey)
@@ -184,30 +186,40 @@ __device__ __forceinline__ int gk_select(const uint32_t (&kh)[E], int nvalid, in
         for (int e = 1; e < E; ++e) mn = min(mn, kh[e]);
         for (int j = 1; j < L; j <<= 1) mn = min(mn, xor_lanes(mn, j, lane));
         uint32_t t = lane / L < cnt ? mn : 0u;
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) t = max(t, xor_lanes(t, m, lane));
+        // the wave's largest: rows of 16 by DPP (quad exchanges, rotations
+        // by 4 and 8), then the four row results (uniform)
+        t = max(t, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)t, 0xB1, 0xF, 0xF, false));
+        t = max(t, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)t, 0x4E, 0xF, 0xF, false));
+        t = max(t, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)t, 0x124, 0xF, 0xF, false));
+        t = max(t, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)t, 0x128, 0xF, 0xF, false));
+        t = max(max((uint32_t)__builtin_amdgcn_readlane((int)t, 0), (uint32_t)__builtin_amdgcn_readlane((int)t, 16)),
+                max((uint32_t)__builtin_amdgcn_readlane((int)t, 32), (uint32_t)__builtin_amdgcn_readlane((int)t, 48)));
         // t = ~0u when an expanded survivor has no child inside the radius: no bound
         if (t != ~0u) {
-            int base = 0;
+            // a second pass when more than 128 keys lie below T: the 64th
+            // smallest of the first 128 bounds the keep-th smallest as well
+            for (int pass = 0; pass < 2; ++pass) {
+                int base = 0;
 #pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const bool take = kh[e] <= t;
-                const uint64_t bal = __ballot(take);
-                if (take) {
-                    const int slot = base + (int)__popcll(bal & below);
-                    if (slot < 2 * WAVE) skey[slot] = ((uint64_t)kh[e] << 32) | (idx0 + (uint32_t)(e * L));
+                for (int e = 0; e < E; ++e) {
+                    const bool take = kh[e] <= t;
+                    const uint64_t bal = __ballot(take);
+                    if (take) {
+                        const int slot = base + (int)__popcll(bal & below);
+                        if (slot < 2 * WAVE) skey[slot] = ((uint64_t)kh[e] << 32) | (idx0 + (uint32_t)(e * L));
+                    }
+                    base += (int)__popcll(bal);
                 }
-                base += (int)__popcll(bal);
-            }
-            if (base <= 2 * WAVE) {
+                if (base > 2 * WAVE && pass == 1) break;  // (not seen in practice) all blocks sorted below
+                const int nb = base < 2 * WAVE ? base : 2 * WAVE;
                 kb_wave_sync();
-                uint64_t k0 = lane < base ? skey[lane] : ~0ull;
-                if (base <= WAVE) {
-                    gk_sort_upto(k0, base, lane);
+                uint64_t k0 = lane < nb ? skey[lane] : ~0ull;
+                if (nb <= WAVE) {
+                    gk_sort_upto(k0, nb, lane);
                 } else {
                     // the rest descending over the wave: in the top lim lanes
                     // (lim = 16, 32 or 64 holds them), sorted as complements
-                    const int c1 = base - WAVE;
+                    const int c1 = nb - WAVE;
                     const int lim = c1 <= 16 ? 16 : (c1 <= 32 ? 32 : WAVE);
                     const int i1 = lane - (WAVE - lim);
                     uint64_t k1 = i1 >= 0 && i1 < c1 ? ~skey[WAVE + i1] : 0ull;
@@ -219,8 +231,13 @@ __device__ __forceinline__ int gk_select(const uint32_t (&kh)[E], int nvalid, in
                     k0 = k1 < k0 ? k1 : k0;  // the 64 smallest, a bitonic sequence
                     k0 = merge_lanes(k0, lane);
                 }
-                res = k0;
-                done = true;
+                if (base <= 2 * WAVE) {
+                    res = k0;
+                    done = true;
+                    break;
+                }
+                t = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(k0 >> 32), WAVE - 1);
+                kb_wave_sync();  // every lane has read skey before the next pass writes it
             }
         }
     }
