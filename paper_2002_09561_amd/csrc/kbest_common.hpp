@@ -279,6 +279,33 @@ __device__ __forceinline__ int kb_select_sort(const uint32_t (&kh)[E], int nvali
     return keep;
 }
 
+// The 64 smallest of the nb <= 128 keys in skey[0 .. nb-1], ascending over
+// the lanes (~0 past nb): with at most 64, one register sorted in the
+// smallest lane groups that hold them; else the first 64 ascending and the
+// rest descending over the wave (in its top 16, 32 or 64 lanes, sorted as
+// complements), merged with truncation.
+__device__ __forceinline__ uint64_t kb_top64(const uint64_t* skey, int nb, int lane)
+{
+    uint64_t k0 = lane < nb ? skey[lane] : ~0ull;
+    if (nb <= WAVE) {
+        if (nb <= 16) sort_lanes<16>(k0, lane);
+        else if (nb <= 32) sort_lanes<32>(k0, lane);
+        else sort_lanes<WAVE>(k0, lane);
+        return k0;
+    }
+    const int c1 = nb - WAVE;
+    const int lim = c1 <= 16 ? 16 : (c1 <= 32 ? 32 : WAVE);
+    const int i1 = lane - (WAVE - lim);
+    uint64_t k1 = i1 >= 0 && i1 < c1 ? ~skey[WAVE + i1] : 0ull;
+    sort_lanes<WAVE>(k0, lane);
+    if (lim == 16) sort_lanes<16>(k1, lane);
+    else if (lim == 32) sort_lanes<32>(k1, lane);
+    else sort_lanes<WAVE>(k1, lane);
+    k1 = ~k1;
+    k0 = k1 < k0 ? k1 : k0;  // the 64 smallest, a bitonic sequence
+    return merge_lanes(k0, lane);
+}
+
 // Selection with a bound, when at least `keep` parents (groups of PC
 // candidates) were expanded.  Each parent's smallest child exists, so the
 // largest of those minima, T, is at least the keep-th smallest pd: no
@@ -286,8 +313,9 @@ __device__ __forceinline__ int kb_select_sort(const uint32_t (&kh)[E], int nvali
 // compacted through LDS (skey, 128 entries) and sorted with the smallest
 // network that holds them; the result is that of sorting all candidates.
 // At high SNR a parent's second child lies far above the best children of
-// the others, so about `keep` candidates remain.  Returns -1 (nothing
-// written) when more than 128 remain.
+// the others, so about `keep` candidates remain; when more than 128 do, the
+// 64th smallest of the first 128 is the tighter bound of a second pass.
+// Returns -1 (nothing written) when more than 128 remain after it.
 template <int E, int PC>
 __device__ __forceinline__ int kb_select_bounded(const uint32_t (&kh)[E], int ncand, int keep, int fm, int lane,
                                                  float* sn, int32_t* sel, uint64_t* skey, int* fpos_out)
@@ -303,11 +331,6 @@ __device__ __forceinline__ int kb_select_bounded(const uint32_t (&kh)[E], int nc
     }
 #pragma unroll
     for (int j = 1; j < WAVE; j <<= 1) t = max(t, xor_lanes(t, j, lane));
-    int count = 0;
-#pragma unroll
-    for (int e = 0; e < E; ++e)
-        if (e * WAVE < ncand) count += __popcll(__ballot(kh[e] != ~0u && kh[e] <= t));
-    if (count > 2 * WAVE) return -1;
     uint64_t fkey = ~0ull;
     int fpos = -1;
     if (fm >= 0) {  // label mode: the forced candidate's rank among all candidates
@@ -327,27 +350,32 @@ __device__ __forceinline__ int kb_select_bounded(const uint32_t (&kh)[E], int nc
             fpos = below;
         }
     }
-    int base = 0;
+    // a second pass when more than 128 candidates lie below T: the 64th
+    // smallest of the first 128 bounds the keep-th smallest as well
+    uint64_t res = ~0ull;
+    for (int pass = 0; pass < 2; ++pass) {
+        int base = 0;
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        if (e * WAVE >= ncand) continue;
-        const bool take = kh[e] != ~0u && kh[e] <= t;
-        const uint64_t bal = __ballot(take);
-        if (take) skey[base + (int)__popcll(bal & ((1ull << lane) - 1ull))] =
-            ((uint64_t)kh[e] << 32) | (uint32_t)(e * WAVE + lane);
-        base += (int)__popcll(bal);
+        for (int e = 0; e < E; ++e) {
+            if (e * WAVE >= ncand) continue;
+            const bool take = kh[e] != ~0u && kh[e] <= t;
+            const uint64_t bal = __ballot(take);
+            if (take) {
+                const int slot = base + (int)__popcll(bal & ((1ull << lane) - 1ull));
+                if (slot < 2 * WAVE) skey[slot] = ((uint64_t)kh[e] << 32) | (uint32_t)(e * WAVE + lane);
+            }
+            base += (int)__popcll(bal);
+        }
+        if (base > 2 * WAVE && pass == 1) return -1;  // nothing written to sn and sel
+        kb_wave_sync();
+        res = kb_top64(skey, base < 2 * WAVE ? base : 2 * WAVE, lane);
+        if (base <= 2 * WAVE) break;
+        t = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(res >> 32), WAVE - 1);
+        kb_wave_sync();  // every lane has read skey before the next pass writes it
     }
-    kb_wave_sync();
-    uint64_t key[2];
-    key[0] = lane < count ? skey[lane] : ~0ull;
-    key[1] = WAVE + lane < count ? skey[WAVE + lane] : ~0ull;
-    if (count <= 16) sort_lanes<16>(key[0], lane);
-    else if (count <= 32) sort_lanes<32>(key[0], lane);
-    else if (count <= WAVE) sort_lanes<WAVE>(key[0], lane);
-    else bitonic_sort<2>(key, lane);
     const bool add_forced = fpos >= keep;  // it takes the last slot
     if (lane < keep) {
-        const uint64_t k = (add_forced && lane == keep - 1) ? fkey : key[0];
+        const uint64_t k = (add_forced && lane == keep - 1) ? fkey : res;
         sn[lane] = __uint_as_float((uint32_t)(k >> 32));
         sel[lane] = (int32_t)(uint32_t)k;
     }

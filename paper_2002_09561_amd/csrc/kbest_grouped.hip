@@ -211,26 +211,8 @@ __device__ __forceinline__ int gk_select(const uint32_t (&kh)[E], int nvalid, in
                     base += (int)__popcll(bal);
                 }
                 if (base > 2 * WAVE && pass == 1) break;  // (not seen in practice) all blocks sorted below
-                const int nb = base < 2 * WAVE ? base : 2 * WAVE;
                 kb_wave_sync();
-                uint64_t k0 = lane < nb ? skey[lane] : ~0ull;
-                if (nb <= WAVE) {
-                    gk_sort_upto(k0, nb, lane);
-                } else {
-                    // the rest descending over the wave: in the top lim lanes
-                    // (lim = 16, 32 or 64 holds them), sorted as complements
-                    const int c1 = nb - WAVE;
-                    const int lim = c1 <= 16 ? 16 : (c1 <= 32 ? 32 : WAVE);
-                    const int i1 = lane - (WAVE - lim);
-                    uint64_t k1 = i1 >= 0 && i1 < c1 ? ~skey[WAVE + i1] : 0ull;
-                    sort_lanes<WAVE>(k0, lane);
-                    if (lim == 16) sort_lanes<16>(k1, lane);
-                    else if (lim == 32) sort_lanes<32>(k1, lane);
-                    else sort_lanes<WAVE>(k1, lane);
-                    k1 = ~k1;
-                    k0 = k1 < k0 ? k1 : k0;  // the 64 smallest, a bitonic sequence
-                    k0 = merge_lanes(k0, lane);
-                }
+                const uint64_t k0 = kb_top64(skey, base < 2 * WAVE ? base : 2 * WAVE, lane);
                 if (base <= 2 * WAVE) {
                     res = k0;
                     done = true;
