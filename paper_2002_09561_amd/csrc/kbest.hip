@@ -1058,17 +1058,19 @@ static int32_t dispatch_kbest_p(const KbestArgs& a, int B, hipStream_t st)
 // gfx950 for K <= 64 at every measured shape but two, which keep the
 // row-recompute kernels: at most 8 survivors of 64-QAM at 64 < n <= 208
 // (two frames per wavefront), and K pam > 64 at n <= 8.  With a per-level
-// schedule the row-recompute kernels are kept too: they evaluate and sort
-// only the candidate blocks the level's survivors fill, while the grouped
-// kernel's lanes hold every survivor's children in all E blocks (32x32
-// 16-QAM, cap 64 and mean K_t 14: 2.77 ms grouped against about 2.3 ms).
-// Label mode (forced path and rank output) is served by the row-recompute
-// kernels only.
+// schedule it is faster too (32x32 16-QAM with the learned schedule, cap 64
+// and mean K_t 14: 1.77 against 2.30 ms; 1.06-2.7x at 10x10 to 64x64 with
+// caps 16 and 64), except for a cap of 9 to 16 survivors of 64-QAM: its two
+// blocks of children per lane allow no bound, so both are sorted at every
+// level, while the row-recompute kernels sort only the blocks the level's
+// survivors fill (16x16, K_t 2-6: 0.41 against 0.27 ms).  Label mode (forced
+// path and rank output) is served by the row-recompute kernels only.
 static bool grouped_real_preferred(const KbestArgs& a, int pam)
 {
-    if (a.force_sym || a.k_sched || a.K > 64) return false;
+    if (a.force_sym || a.K > 64) return false;
     if (pam == 8 && a.K <= 8 && a.n > 64 && a.n <= 208 && !a.fb_sigma2 && !a.rerun) return false;
     if (a.n <= 8 && a.K * pam > 64) return false;
+    if (a.k_sched && pam == 8 && a.K > 8 && a.K <= 16) return false;
     return true;
 }
 
