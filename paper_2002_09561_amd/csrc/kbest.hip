@@ -1063,7 +1063,7 @@ static int32_t dispatch_kbest_p(const KbestArgs& a, int B, hipStream_t st)
 // caps 16 and 64), except for a cap of 9 to 16 survivors of 64-QAM: its two
 // blocks of children per lane allow no bound, so both are sorted at every
 // level, while the row-recompute kernels sort only the blocks the level's
-// survivors fill (16x16, K_t 2-6: 0.41 against 0.27 ms).  Label mode (forced
+// survivors fill (16x16, K_t 2-6: 0.32 against 0.27 ms).  Label mode (forced
 // path and rank output) is served by the row-recompute kernels only.
 static bool grouped_real_preferred(const KbestArgs& a, int pam)
 {

@@ -163,9 +163,10 @@ __device__ __forceinline__ void gk_merge_select(uint64_t (&key)[E], int lane)
 // Selection of the keep = min(K_t, nvalid) smallest keys (pd bits, s PC + c)
 // -- i.e. (pd, parent rank, child), the survivors being kept in order --
 // written in order to sn (pd) and sel (candidate index).  Lane (s, q) holds
-// children c = e L + q of survivor s in block e.  With four blocks or more
-// and at least keep survivors expanded, the largest of their smallest
-// children, T, bounds the keep-th smallest key: the keys with pd bits <= T
+// children c = e L + q of survivor s in block e.  With at least keep
+// survivors expanded (and more candidates than one sort over 32 lanes
+// holds), the largest of their smallest children, T, bounds the keep-th
+// smallest key: the keys with pd bits <= T
 // (usually little more than keep) are compacted through LDS and sorted --
 // one register when at most 64, else the first 64 ascending and the rest
 // descending, merged with truncation.  Beyond 128 such keys (a few levels in
@@ -180,7 +181,7 @@ __device__ __forceinline__ int gk_select(const uint32_t (&kh)[E], int nvalid, in
     const uint64_t below = (1ull << lane) - 1ull;
     uint64_t res;  // the keep smallest keys, ascending in lanes 0 .. keep-1
     bool done = false;
-    if (E >= 4 && cnt >= keep) {  // (one or two blocks are sorted directly)
+    if ((E >= 2 || cnt * L > 32) && cnt >= keep) {  // (else one sort over at most 32 lanes)
         uint32_t mn = kh[0];
 #pragma unroll
         for (int e = 1; e < E; ++e) mn = min(mn, kh[e]);
