@@ -74,6 +74,9 @@ def _check(orc, label, P, out, forced, Ro, zo, res):
     (128, 4, 8.0, 4, 16),      # the largest size: 16 groups
     (7, 64, 16.0, 100, 1),     # K = 1: successive cancellation
     (100, 64, 24.0, 6, 64),    # plain K = 64 at 100x100 64-QAM
+    (12, 64, 20.0, 80, 16),    # two blocks of children per lane (64-QAM, 9-16 survivors): the bound
+    (20, 16, 14.0, 60, 32),    # two blocks (16-QAM, 17-32 survivors)
+    (48, 4, 6.0, 30, 64),      # two blocks (4-QAM, 33-64 survivors)
 ])
 def test_grouped_real_levels_parity(gpu, orc, M, q, snr, B, K):
     f, P, out, forced, Ro, zo, res = _case(gpu, orc, M, q, snr, B, K, 1, seed=9000 + 3 * M + K)
