@@ -98,6 +98,8 @@ def parse():
     p.add_argument("--seed", type=int, default=2020)
     p.add_argument("--no-graph", action="store_true", help="skip the hipGraph-replayed timing")
     p.add_argument("--uneven-frames", type=int, default=100000)
+    p.add_argument("--no-extra", action="store_true",
+                   help="c5: skip the uneven-batch and 32x32 figures added to the line")
     return p.parse_args()
 
 
@@ -247,11 +249,11 @@ def certify_ml(idx, frames, B, P, qam, budget=20_000_000):
 
 
 # ------------------------------------------------------------ uneven batches
-def uneven_main(args):
+def uneven_run(args):
     """Config: 1e5 frames, M = N drawn from {10, 16, 32, 64}, QAM from {4, 16,
     64}, SNR uniform 8-24 dB; QR and K-best each in one persistent launch,
     K per class and grids from the autotuner's cache; the step is captured in
-    a hipGraph and replayed."""
+    a hipGraph and replayed.  Returns the result line as a dict."""
     import torch
 
     from paper_2002_09561_amd import autotune, mimo, uneven
@@ -292,7 +294,7 @@ def uneven_main(args):
                       "kbest_grid": tune["kbest_grid"], "graph": True},
            "kernel_ms": {"qr_uneven": round(a.elapsed_time(b), 4), "kbest_uneven": round(b.elapsed_time(c), 4)},
            "symbol_error_rate": float(ub.symbol_errors()) / int(fr.n_tx.sum())}
-    print(json.dumps(out), flush=True)
+    return out
 
 
 # ------------------------------------------------------------ SD-K-best on the complex-symbol tree
@@ -539,11 +541,57 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload == "uneven":
-        return uneven_main(args)
+        print(json.dumps(uneven_run(args)), flush=True)
+        return
     if args.workload == "sdkbest":
         return sdkbest_main(args)
     if args.workload == "train":
         return train_main(args)
+    out = sweep_run(args)
+    if args.workload == "c5" and not args.no_extra:
+        out["other_workloads"] = extra_workloads(args)
+    print(json.dumps(out), flush=True)
+
+
+def extra_workloads(args):
+    """Two more configurations in the same run, throughput and errors only:
+    the uneven batch (10^5 mixed frames, persistent launches, graph-replayed)
+    and 32x32 16-QAM (learned against plain K-best and the ablation; no
+    exact-SD reference, CPU baseline or graph replay).  A failure is reported
+    in place of the numbers rather than ending the run."""
+    import copy
+
+    res = {}
+    a = copy.copy(args)
+    a.workload, a.steps, a.warmup = "uneven", max(3, args.steps), 1
+    try:
+        u = uneven_run(a)
+        res["uneven"] = {k: u[k] for k in ("metric", "value", "unit", "steps", "ms_per_step", "kernel_ms",
+                                           "symbol_error_rate")}
+        res["uneven"]["workload"] = u["config"]["workload"]
+    except Exception as e:  # noqa: BLE001 - reported in the line
+        res["uneven"] = {"error": repr(e)}
+    a = copy.copy(args)
+    a.workload, a.steps, a.warmup = "c4", 3, 1
+    a.no_ml, a.no_cpu_baseline, a.no_graph, a.copy_probe_mib = True, True, True, 0
+    a.frames, a.snrs, a.K, a.fixed_k, a.detector, a.margin, a.beta = 0, None, 0, 0, "auto", None, None
+    try:
+        c = sweep_run(a)
+        res["c4"] = {k: c[k] for k in ("metric", "value", "unit", "steps", "ms_per_step", "kernel_avg_ms", "errors")}
+        res["c4"]["workload"] = c["config"]["workload"]
+        for leg in ("plain_kbest", "ablation_fixed_k"):
+            if leg in c:
+                res["c4"][leg] = {k: c[leg][k] for k in ("detector", "frames_per_s", "symbol_errors") if k in c[leg]}
+    except Exception as e:  # noqa: BLE001
+        res["c4"] = {"error": repr(e)}
+    return res
+
+
+def sweep_run(args):
+    """The c5 / c2 / c4 workloads: frames over an SNR sweep, the headline
+    detector timed per step, the comparison legs, the exact-SD reference and
+    matched-BER statistics, the CPU baseline.  Returns the result line as a
+    dict."""
     import torch
 
     from paper_2002_09561_amd import learned, mimo
@@ -950,7 +998,7 @@ def main():
         legs = [l for l in ("kbest", "hybrid") if l != det and (l in wl["legs"] or l == "kbest")]
         out["cpu_baseline"] = cpu_baseline(frames, w, det if det in ("learned", "kbest") else "kbest", K, meta_run,
                                            args.cpu_baseline_seconds, legs, args.workers, args.k_worker)
-    print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":
