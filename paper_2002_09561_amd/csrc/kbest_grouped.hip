@@ -671,7 +671,10 @@ __device__ __forceinline__ void kbest_uneven_one(const KbestArgs& a, unsigned ch
     kbest_frame_grouped<P, 1, E, false>(a, 0, lds);
 }
 
-__global__ void __launch_bounds__(64) kbest_uneven_kernel(const mimo_frame_desc* __restrict__ desc, int B,
+// At most 128 registers (four waves per SIMD): the eight inlined variants
+// would otherwise take 148 (three waves), and with 11.4 KB of LDS per frame
+// the CU holds 14 frames; 5 registers spill to scratch outside the hot loops.
+__global__ void __launch_bounds__(64, 4) kbest_uneven_kernel(const mimo_frame_desc* __restrict__ desc, int B,
                                                           const float* __restrict__ R, const float* __restrict__ z,
                                                           int32_t* __restrict__ sym, float* __restrict__ pd,
                                                           uint32_t* __restrict__ flags, int* __restrict__ counter)
