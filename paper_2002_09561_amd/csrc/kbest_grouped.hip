@@ -540,12 +540,16 @@ __device__ __forceinline__ void kbest_frame_grouped(const KbestArgs& a, int fram
     }
 }
 
-// With 32 sort registers per lane (2048 candidates per complex level) the
-// kernel would take 196 registers, two waves per SIMD; capped at 168 for
-// three (15 registers spill to scratch): K = 32 at 16x16 64-QAM 3.75 ->
-// 2.70 ms per 6x10^4 frames.
+// Register caps where registers, not LDS, bound the waves per SIMD: with 32
+// sort registers per lane (2048 candidates per complex level) the kernel
+// would take 196 registers, two waves; capped at 168 for three (15 spill to
+// scratch): K = 32 at 16x16 64-QAM 3.75 -> 2.70 ms per 6x10^4 frames.  With
+// 16 (1024 candidates), 124 registers, four waves; capped for five (14
+// spill): K = 10 at 16x16 64-QAM 0.98 -> 0.92 ms, at 100x100 3.97 -> 3.79 ms
+// per 5x10^4 frames.  (The same cap on the two-frames-per-wave kernel, 84 ->
+// 80 registers for six waves, made it slower.)
 template <int P, int J, int E, bool CR>
-__global__ void __launch_bounds__(64, (E >= 32 ? 3 : 1)) kbest_grouped_kernel(KbestArgs a)
+__global__ void __launch_bounds__(64, (E >= 32 ? 3 : (E == 16 ? 5 : 1))) kbest_grouped_kernel(KbestArgs a)
 {
     extern __shared__ unsigned char smem_kbg[];
     if (kb_keep_first(a, blockIdx.x)) return;
