@@ -86,6 +86,9 @@ def parse():
     p.add_argument("--workers", type=int, default=3,
                    help="hybrid workers (SD-K-best legs; error counts measured equal for 3 to 15 at 100x100 64-QAM)")
     p.add_argument("--k-worker", type=int, default=8)
+    p.add_argument("--hybrid-budget", type=int, default=20000,
+                   help="learned hybrid: node expansions per frame (0: none); a frame that reaches it keeps its best "
+                        "leaf only if the fallback's bound accepts it, else plain K-best detects it again")
     p.add_argument("--margin", type=float, default=None)
     p.add_argument("--beta", type=float, default=None)
     p.add_argument("--no-compare", action="store_true", help="skip the comparison legs")
@@ -695,7 +698,8 @@ def sweep_run(args):
         elif detector == "learned_hybrid":
             schedule(record)
             timed("hybrid", record, lambda: mimo.sd_hybrid_detect(o["R"], o["z"], M, P, args.workers, args.k_worker,
-                                                                  k_sched=o["ks"], out=out3))
+                                                                  k_sched=o["ks"], node_budget=args.hybrid_budget,
+                                                                  out=out3))
             fallback_and_metric(record, out3)
         else:
             schedule(record)
@@ -732,6 +736,12 @@ def sweep_run(args):
             ks = o["ks"].cpu().numpy()
             extra["mean_k_t"] = float(ks.mean())
             extra["ks"] = ks
+        if detector == "learned_hybrid" and args.hybrid_budget > 0:
+            # the fallback rewrites the flags of the frames it detects again:
+            # the budget's share from one more (untimed) hybrid call
+            fb = mimo.sd_hybrid_detect(o["R"], o["z"], M, P, args.workers, args.k_worker, k_sched=o["ks"],
+                                       node_budget=args.hybrid_budget)[2]
+            extra["budget_exhausted_fraction"] = float(((fb & mimo.FLAG_BUDGET_EXHAUSTED) != 0).float().mean())
         return dt, counts, kavg, extra
 
     frames_per_step = B * len(snrs)
@@ -808,8 +818,8 @@ def sweep_run(args):
     names = {"kbest": ("plain_kbest", f"K-best K={K}"),
              "hybrid": ("paper_hybrid", f"SD-K-best, {args.workers} workers x {args.k_worker} survivors"),
              "learned_hybrid": ("learned_hybrid", f"SD-K-best, {args.workers} workers, learned per-level "
-                                                  f"survivor counts (capped at {args.k_worker}), plain K-best "
-                                                  f"K={K} fallback")}
+                                                  f"survivor counts (capped at {args.k_worker}), node budget "
+                                                  f"{args.hybrid_budget or 'none'}, plain K-best K={K} fallback")}
     if not args.no_compare:
         for other in wl["legs"]:
             if other == det or (other == "learned_hybrid" and w is None):
@@ -826,6 +836,9 @@ def sweep_run(args):
             if "mean_k_t" in oextra:
                 out[key]["mean_k_t"] = round(oextra["mean_k_t"], 3)
                 out[key]["fallback_fraction"] = round(oextra["fallback_fraction"], 5)
+            if "budget_exhausted_fraction" in oextra:
+                out[key]["node_budget"] = args.hybrid_budget
+                out[key]["budget_exhausted_fraction"] = round(oextra["budget_exhausted_fraction"], 6)
     if kroof:
         out["kbest_roofline"] = kroof
     # ---------------- ablation: the learned detector's fallback with a constant K
