@@ -158,3 +158,39 @@ def test_grouped_nonfinite_frame(gpu, orc):
             assert np.isinf(p[b]) and np.all(s[b] == 0)
         for b in (0, 2, 5):
             assert fl[b] == mimo.FLAG_FOUND and np.isfinite(p[b])
+
+
+def test_grouped_near_singular_channel(gpu, orc):
+    """Columns 4 and 9 of H are made nearly parallel to their left
+    neighbours (difference 0.05 times a Gaussian vector), so two diagonal
+    entries of R are small and at their levels every survivor's children lie
+    close together: most of the 512 candidates fall below the bound T.  (An
+    FP64 simulation of this K-best puts more than 128 below T at 44% of the
+    levels; at 29% more than 128 remain below the second bound as well.)  So
+    both the second compaction and the sort of every block run here; the
+    result must match the oracle under the near-tie rule, and the counters on
+    frames without a near tie."""
+    import torch
+
+    M, q, B, K = 12, 64, 40, 64
+    P = math.isqrt(q)
+    f = gen_frames(M, M, q, 24.0, B, seed=9900)
+    rng = np.random.default_rng(9901)
+    H = f.H.copy()
+    for c in (4, 9):
+        d = (rng.standard_normal((B, M)) + 1j * rng.standard_normal((B, M))) / np.sqrt(2)
+        H[:, :, c] = (H[:, :, c - 1] + 0.05 * d).astype(np.complex64)
+    y = f.y
+    print(f"grouped K-best near-singular {M}x{M} {q}-QAM B={B} K={K}", flush=True)
+    R, z = gpu.qr_preprocess(torch.from_numpy(H).cuda(), torch.from_numpy(y).cuda())
+    sym, pd, flags, ctr = gpu.kbest_detect_grouped(R, z, M, P, K, J=1, want_counters=True)
+    Ro, zo, _ = orc.qr(H, y)
+    out = orc.kbest(Ro, zo, P, K)
+
+    def forced(mask, xf):
+        return orc.kbest(Ro[mask], zo[mask], P, K, force_path=xf)["fgap"]
+
+    res = (_np(sym), _np(pd), _np(flags), _np(ctr))
+    _check(orc, f"grouped J=1 near-singular {M}x{M} {q}-QAM K={K}", P, out, forced, Ro, zo, res)
+    expect = sum(min(K, P ** t) for t in range(2 * M))
+    assert np.all(res[3][:, 0] == expect)
