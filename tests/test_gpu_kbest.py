@@ -621,3 +621,31 @@ def test_empty_sphere_rerun_all_variants(gpu, orc, variant):
     else:
         assert np.array_equal(s1, s0) and np.array_equal(p1, p0)
     assert np.all(c1[1:, 0] > c0[1:, 0]) and np.all(c1[1:, 0] < 2 * c0[1:, 0] + 1)
+
+
+def test_kbest_scheduled_near_singular_channel(gpu, orc):
+    """Scheduled 64-QAM K-best with a cap of 16 survivors (the row-recompute
+    kernel with two blocks of candidates) on channels with two nearly
+    parallel column pairs: at the small diagonal entries' levels most
+    candidates fall below the bound, so the second compaction of
+    kb_select_bounded and the sort of every block both run."""
+    import torch
+
+    M, q, B, K = 12, 64, 40, 16
+    P = math.isqrt(q)
+    f = gen_frames(M, M, q, 24.0, B, seed=9910)
+    rng = np.random.default_rng(9911)
+    H = f.H.copy()
+    for c in (4, 9):
+        d = (rng.standard_normal((B, M)) + 1j * rng.standard_normal((B, M))) / np.sqrt(2)
+        H[:, :, c] = (H[:, :, c - 1] + 0.05 * d).astype(np.complex64)
+    sched = rng.integers(9, K + 1, (B, 2 * M)).astype(np.int32)
+    print(f"scheduled K-best near-singular {M}x{M} {q}-QAM B={B} cap {K}", flush=True)
+    R, z = gpu.qr_preprocess(torch.from_numpy(H).cuda(), torch.from_numpy(f.y).cuda())
+    sym, pd, flags, ctr = gpu.kbest_detect(R, z, M, P, K, k_sched=torch.from_numpy(sched).cuda(),
+                                           want_counters=True)
+    Ro, zo, _ = orc.qr(H, f.y)
+    out = orc.kbest(Ro, zo, P, K, k_sched=sched)
+    _, tol, _ = check_kbest_run(orc, "scheduled near-singular", P, K, _np(sym), _np(pd), out, Ro, zo, k_sched=sched)
+    clean = out["margin"][:, 0] > tol
+    assert np.array_equal(_np(ctr)[clean, :2], out["counters"][clean, :2])
