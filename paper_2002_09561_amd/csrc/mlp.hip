@@ -430,6 +430,83 @@ __global__ void __launch_bounds__(256) mlp_grad_tiles(int64_t S, const float* __
     for (int i = 0; i < 4; ++i) out[(4 * kq + i) * 16 + rc] = acc[i];
 }
 
+// Tiles in groups of up to three that share an operand: a W2 tile row block
+// (the same 16 rows of D2) over three column blocks, three W1 tiles (the same
+// [X | 1] columns), three W3 tiles (the same dout row).  The shared operand
+// is loaded once per k-step for the group, instead of once per tile.
+constexpr int GT_G = 30;              // 24 W2 groups, 3 W1, 3 W3
+constexpr int64_t G_GROUP_MIN_LEN = 512;  // states per chunk from which the groups are launched
+
+__device__ __forceinline__ void grad_group(int g, int& t0, int& nt, bool& share_a)
+{
+    if (g < 24) {  // W2: row block g / 3, column blocks 3 (g % 3) .. + 2
+        t0 = GT_W2 + 9 * (g / 3) + 3 * (g % 3);
+        nt = 3;
+        share_a = true;
+    } else if (g < 27) {  // W1: tiles 72-74, 75-77, 78-79
+        t0 = GT_W1 + 3 * (g - 24);
+        nt = GT_W3 - t0 < 3 ? GT_W3 - t0 : 3;
+        share_a = false;
+    } else {  // W3: tiles 80-82, 83-85, 86-88
+        t0 = GT_W3 + 3 * (g - 27);
+        nt = 3;
+        share_a = true;
+    }
+}
+
+// one wavefront per (tile group, chunk): the chunk's partial 16 x 16 tiles.
+// Lane l feeds row / column l % 16 at states s0 + 4 (l / 16) + e of the e-th
+// of four MFMA k-steps (the same states for A and B, so each step sums over
+// them); every tile takes the same products in the same order as alone.
+__global__ void __launch_bounds__(256) mlp_grad_tile_groups(int64_t S, const float* __restrict__ X,
+                                                            const float* __restrict__ H1, const float* __restrict__ H2,
+                                                            const float* __restrict__ D2, const float* __restrict__ D1,
+                                                            const float* __restrict__ dout, float* __restrict__ part)
+{
+    const int job = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x >> 6);
+    const int C = grad_chunks(S);
+    if (job >= GT_G * C) return;  // uniform per wavefront
+    const int lane = threadIdx.x & 63;
+    const int g = job % GT_G, c = job / GT_G;
+    int t0, nt;
+    bool share_a;
+    grad_group(g, t0, nt, share_a);
+    const int64_t L = grad_chunk_len(S), s_beg = (int64_t)c * L, s_end = s_beg + L;
+    const int rc = lane & 15, kq = lane >> 4;
+    f32x4g acc[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc[k] = f32x4g{0.f, 0.f, 0.f, 0.f};
+    for (int64_t s0 = s_beg; s0 < s_end; s0 += 16) {
+        float sh[4], own[3][4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t s = s0 + 4 * kq + e;
+            sh[e] = share_a ? grad_a(t0, rc, s, S, D2, D1, dout) : grad_b(t0, rc, s, S, H1, X, H2);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                if (k < nt) own[k][e] = share_a ? grad_b(t0 + k, rc, s, S, H1, X, H2) : grad_a(t0 + k, rc, s, S, D2, D1, dout);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (k < nt) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    acc[k] = share_a ? __builtin_amdgcn_mfma_f32_16x16x4f32(sh[e], own[k][e], acc[k], 0, 0, 0)
+                                     : __builtin_amdgcn_mfma_f32_16x16x4f32(own[k][e], sh[e], acc[k], 0, 0, 0);
+            }
+        }
+    }
+    // lane l holds rows 4 (l / 16) + i of column l % 16
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (k < nt) {
+            float* out = part + ((size_t)c * GT_N + t0 + k) * 256;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) out[(4 * kq + i) * 16 + rc] = acc[k][i];
+        }
+    }
+}
+
 // one thread per parameter (and one for the loss): its tile entry summed
 // over the chunks in order
 __global__ void __launch_bounds__(256) mlp_grad_sum(int64_t S, const float* __restrict__ part,
@@ -536,8 +613,17 @@ static int32_t mlp_loss_grad_ws(const char* who, const float* w, const float* X,
     int32_t rc = check_launch(who);
     if (rc) return rc;
     float* part = f + ((4 * HID * S + S + nblk + 64 + 63) & ~(int64_t)63);
-    const int jobs = GT_N * grad_chunks(S);
-    hipLaunchKernelGGL(mlp_grad_tiles, dim3((jobs + 3) / 4), dim3(256), 0, st, S, X, H1, H2, D2, D1, dout, part);
+    // long chunks: tile groups (fewer loads); short ones: one tile per
+    // wavefront (three times the wavefronts to hide the loads' latency).
+    // Both give the same partial tiles.
+    if (grad_chunk_len(S) >= G_GROUP_MIN_LEN) {
+        const int jobs = GT_G * grad_chunks(S);
+        hipLaunchKernelGGL(mlp_grad_tile_groups, dim3((jobs + 3) / 4), dim3(256), 0, st, S, X, H1, H2, D2, D1, dout,
+                           part);
+    } else {
+        const int jobs = GT_N * grad_chunks(S);
+        hipLaunchKernelGGL(mlp_grad_tiles, dim3((jobs + 3) / 4), dim3(256), 0, st, S, X, H1, H2, D2, D1, dout, part);
+    }
     rc = check_launch(who);
     if (rc) return rc;
     hipLaunchKernelGGL(mlp_grad_sum, dim3((MIMO_MLP_NPARAM + 1 + 255) / 256), dim3(256), 0, st, S, part, lpart, nblk,
