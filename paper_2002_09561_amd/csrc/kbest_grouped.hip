@@ -211,7 +211,7 @@ __device__ __forceinline__ int gk_select(const uint32_t (&kh)[E], int nvalid, in
                     }
                     base += (int)__popcll(bal);
                 }
-                if (base > 2 * WAVE && pass == 1) break;  // (not seen in practice) all blocks sorted below
+                if (base > 2 * WAVE && pass == 1) break;  // (rare on random channels, common on near-singular ones) all blocks sorted below
                 kb_wave_sync();
                 const uint64_t k0 = kb_top64(skey, base < 2 * WAVE ? base : 2 * WAVE, lane);
                 if (base <= 2 * WAVE) {
